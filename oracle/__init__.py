@@ -1,0 +1,322 @@
+"""CPU oracle for randomized rank-1 lattice QMC of sector integrands and amplitudes.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library (``paper_2305_19768_amd``); both consume the seeded arrays of
+``workloads`` and nothing else.
+
+Heavy loops live in ``qmc_oracle.c`` (plain scalar C, FP64, Neumaier sums, no FMA
+contraction).  The statistics and the lattice-size allocation are written out here
+in numpy, each following the passage of arXiv:2305.19768 named in its docstring.
+
+Parity status of each function (what pins it, in ``tests/test_oracle_pins.py``):
+  points            lattice identities (permutation columns, z_1 = 1) and exactness on
+                    trigonometric polynomials (character-sum identity)
+  transform         closed-form properties (phi(0), phi(1), symmetry, phi' = w, int w = 1)
+  integrand/sums    closed-form integrals (1-loop massless bubble log^m F moments, separable
+                    and mixed-monomial integrals with known values), Gauss-Legendre in 1-3 D,
+                    convergence order
+  neumaier          exact results of ill-conditioned sums
+  p2                truncated dual-lattice sum on small n, Korobov-space identities
+  estimate/amplitude/eps_rel  textbook mean/variance, propagation of independent variances
+  allocate          constraint + stationarity residuals, brute-force constrained minimum
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libqmc_oracle.so")
+_lib = None
+
+TRANSFORM_CODES = {"none": 0, "baker": 1, "korobov1": 2, "korobov2": 3, "korobov3": 4,
+                   "korobov4": 5, "korobov5": 6, "korobov6": 7}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.or_points.argtypes = [ctypes.c_uint64, ctypes.c_int, _u64p, _dp, ctypes.c_uint64,
+                                ctypes.c_uint64, _dp]
+        L.or_points.restype = None
+        L.or_transform.argtypes = [ctypes.c_int, ctypes.c_uint64, _dp, _dp, _dp]
+        L.or_transform.restype = None
+        L.or_integrand.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_int, _u8p,
+                                   _dp, _i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, _dp, ctypes.c_uint64, _dp, _dp]
+        L.or_integrand.restype = ctypes.c_int
+        L.or_sums.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_int, _u8p, _dp,
+                              _i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              _dp, ctypes.c_int, ctypes.c_uint64, _u64p, _dp, ctypes.c_int,
+                              ctypes.c_int, _dp, _dp, _i64p]
+        L.or_sums.restype = ctypes.c_int
+        L.or_neumaier.argtypes = [_dp, ctypes.c_uint64]
+        L.or_neumaier.restype = ctypes.c_double
+        L.or_p2.argtypes = [ctypes.c_uint64, ctypes.c_int, _u64p]
+        L.or_p2.restype = ctypes.c_double
+        L.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.or_splitmix64.restype = ctypes.c_uint64
+        _lib = L
+    return _lib
+
+
+def _p(a, typ):
+    return a.ctypes.data_as(typ)
+
+
+# ------------------------------------------------------------------ lattice
+
+def korobov_vector(n: int, a: int, d: int) -> np.ndarray:
+    """Korobov generating vector z = (1, a, a^2, ..., a^(d-1)) mod n."""
+    return np.array([pow(int(a), j, int(n)) for j in range(d)], dtype=np.uint64)
+
+
+def points(n: int, z: Sequence[int], delta: Sequence[float], i0: int = 0,
+           count: Optional[int] = None) -> np.ndarray:
+    """Shifted lattice points y_i = frac(i z / n + Delta), i = i0 .. i0+count-1.
+
+    Rank-1 lattice rule of the paper's Sec. 2.2 (definition of Q_{n,z}); k_j = i z_j mod n
+    is exact, q_j = k_j / n is the IEEE quotient, the shift wraps by one exact subtraction.
+    """
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    delta = np.ascontiguousarray(delta, dtype=np.float64)
+    d = len(z)
+    count = n - i0 if count is None else count
+    out = np.empty((count, d), dtype=np.float64)
+    lib().or_points(n, d, _p(z, _u64p), _p(delta, _dp), i0, count, _p(out, _dp))
+    return out
+
+
+def transform(kind: str, y) -> tuple:
+    """Periodizing transform x = phi(y) and its derivative w = phi'(y), per coordinate."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    x = np.empty_like(y)
+    w = np.empty_like(y)
+    lib().or_transform(TRANSFORM_CODES[kind], y.size, _p(y, _dp), _p(x, _dp), _p(w, _dp))
+    return x, w
+
+
+class _SectorArrays:
+    """Contiguous copies of a sector's tables, kept alive across C calls."""
+
+    def __init__(self, sec):
+        self.d = int(sec.d)
+        self.u_exp = np.ascontiguousarray(sec.u_exp, dtype=np.uint8).reshape(-1)
+        self.u_coef = np.ascontiguousarray(sec.u_coef, dtype=np.float64)
+        self.f_exp = np.ascontiguousarray(sec.f_exp, dtype=np.uint8).reshape(-1)
+        self.f_coef = np.ascontiguousarray(sec.f_coef, dtype=np.float64)
+        self.x_pow2 = np.ascontiguousarray(sec.x_pow2, dtype=np.int32)
+        self.logc = np.ascontiguousarray(sec.logc, dtype=np.float64)
+        self.K, self.M = self.logc.shape[0], self.logc.shape[1] - 1
+        self.n_u, self.n_f = len(self.u_coef), len(self.f_coef)
+        self.u_pow, self.f_pow2 = int(sec.u_pow), int(sec.f_pow2)
+        self.transform = TRANSFORM_CODES[sec.transform]
+
+    def head(self):
+        return (self.d, self.n_u, _p(self.u_exp, _u8p), _p(self.u_coef, _dp), self.n_f,
+                _p(self.f_exp, _u8p), _p(self.f_coef, _dp), _p(self.x_pow2, _i32p),
+                self.u_pow, self.f_pow2, self.K, self.M, _p(self.logc, _dp))
+
+
+def integrand(sec, x) -> np.ndarray:
+    """f_k(x) = x^p U^a F^b sum_m c_{k,m} (log F)^m for each order k, at points x [count, d]."""
+    A = _SectorArrays(sec)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, A.d)
+    out = np.empty((x.shape[0], A.K), dtype=np.float64)
+    lib().or_integrand(*A.head(), x.shape[0], _p(x, _dp), _p(out, _dp))
+    return out
+
+
+class OracleNonFinite(RuntimeError):
+    pass
+
+
+def sector_sums(sec, shifts, n: Optional[int] = None, a: Optional[int] = None,
+                z: Optional[Sequence[int]] = None, shift_range=None, threads: int = 1):
+    """Per-shift lattice estimates of one sector.
+
+    Returns (Q, S) with Q[l, k] = (1/n) sum_i W f_k and S[l, k] = (1/n) sum_i |W f_k|,
+    summed with Neumaier compensation (the per-shift sums of Sec. 2.1).
+    """
+    A = _SectorArrays(sec)
+    n = int(sec.n if n is None else n)
+    if z is None:
+        z = korobov_vector(n, sec.a if a is None else a, A.d)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+    m = shifts.shape[0]
+    l0, l1 = (0, m) if shift_range is None else shift_range
+    Q = np.empty((l1 - l0, A.K))
+    S = np.empty((l1 - l0, A.K))
+    L = lib()
+
+    def run(lo, hi):
+        bad = np.zeros(2, dtype=np.int64)
+        q = np.empty((hi - lo, A.K))
+        s = np.empty((hi - lo, A.K))
+        rc = L.or_sums(*A.head(), A.transform, n, _p(z, _u64p), _p(shifts, _dp), lo, hi,
+                       _p(q, _dp), _p(s, _dp), _p(bad, _i64p))
+        if rc == 1:
+            raise OracleNonFinite(f"non-finite sample at shift {bad[0]}, index {bad[1]}")
+        if rc != 0:
+            raise ValueError("invalid sector")
+        Q[lo - l0:hi - l0] = q
+        S[lo - l0:hi - l0] = s
+
+    if threads <= 1 or l1 - l0 == 1:
+        run(l0, l1)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda l: run(l, l + 1), range(l0, l1)))
+    return Q, S
+
+
+def problem_sums(problem, threads: int = 1, sectors=None):
+    """Q[s] (m x K) and S[s] for every sector of a workloads.Problem."""
+    idx = range(len(problem.sectors)) if sectors is None else sectors
+    out_q, out_s = [], []
+    for s in idx:
+        sec = problem.sectors[s]
+        q, a = sector_sums(sec, problem.shifts[s], threads=threads)
+        out_q.append(q)
+        out_s.append(a)
+    return out_q, out_s
+
+
+def neumaier(v) -> float:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().or_neumaier(_p(v, _dp), v.size)
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    return int(lib().or_splitmix64(seed & (2**64 - 1), counter & (2**64 - 1)))
+
+
+def seeded_shifts(seed: int, sector: int, m: int, d: int) -> np.ndarray:
+    """Shift Delta_{s,l,j} = (splitmix64(seed, (s << 32) | (l << 8) | j) >> 11) * 2^-53."""
+    out = np.empty((m, d))
+    for l in range(m):
+        for j in range(d):
+            c = (sector << 32) | (l << 8) | j
+            out[l, j] = (splitmix64(seed, c) >> 11) * 2.0 ** -53
+    return out
+
+
+# ---------------------------------------------------------------- P_2 search
+
+def p2(n: int, z: Sequence[int]) -> float:
+    """P_2 figure of merit (Korobov space, alpha = 2, unit product weights; Sec. 2.2)."""
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    return float(lib().or_p2(n, len(z), _p(z, _u64p)))
+
+
+def korobov_search(n: int, d: int, candidates: Sequence[int], rel_tie: float = 1e-12,
+                   threads: int = 1):
+    """Korobov parameter a minimising P_2 over the candidates.
+
+    Candidates within a relative rel_tie of the minimum count as tied and the smallest
+    a wins (P_2(a) = P_2(n - a) and P_2 is invariant under coordinate reversal, so exact
+    ties are common).  Returns (a, p2 values).
+    """
+    cands = [int(c) for c in candidates]
+
+    def f(a):
+        return p2(n, korobov_vector(n, a, d))
+
+    if threads > 1:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            vals = list(ex.map(f, cands))
+    else:
+        vals = [f(a) for a in cands]
+    vmin = min(vals)
+    tied = [a for a, v in zip(cands, vals) if v <= vmin * (1.0 + rel_tie)]
+    return min(tied), np.array(vals)
+
+
+# --------------------------------------------------------------- statistics
+
+def estimate(Q):
+    """Mean over the m shift estimates and its standard error sqrt(var/m), var unbiased.
+
+    Error from the shifts as in the caption of the precision-by-lattice figure (Sec. 2.1.3).
+    Q has shape [m, ...]; returns (mean, err) of shape [...].
+    """
+    Q = np.asarray(Q, dtype=np.float64)
+    m = Q.shape[0]
+    mean = Q.sum(axis=0) / m
+    var = ((Q - mean) ** 2).sum(axis=0) / (m - 1)
+    return mean, np.sqrt(var / m)
+
+
+def integral_values(problem, means: List[np.ndarray], errs: List[np.ndarray]):
+    """Integral I_c = sum of its sectors; variances of independent sectors add."""
+    K = problem.K
+    val = np.zeros((problem.n_integrals, K))
+    var = np.zeros((problem.n_integrals, K))
+    for s, sec in enumerate(problem.sectors):
+        val[sec.integral] += means[s]
+        var[sec.integral] += errs[s] ** 2
+    return val, np.sqrt(var)
+
+
+def amplitude(coef, ival, ierr, ival_im=None, ierr_im=None):
+    """A_k = sum_i C_i I_{i,k} with var(A_k) = sum_i |C_i|^2 var(I_{i,k}) (Sec. 2.1.3, Eq. 4).
+
+    For complex C and I, Re and Im of each integral are independent, so
+    var(Re A) = sum (Re C)^2 var(Re I) + (Im C)^2 var(Im I) and likewise for Im A.
+    Returns (re, im, err_re, err_im), each of shape [K].
+    """
+    C = np.asarray(coef, dtype=np.complex128)
+    ir = np.asarray(ival, dtype=np.float64)
+    ii = np.zeros_like(ir) if ival_im is None else np.asarray(ival_im, dtype=np.float64)
+    er = np.asarray(ierr, dtype=np.float64)
+    ei = np.zeros_like(er) if ierr_im is None else np.asarray(ierr_im, dtype=np.float64)
+    cr, ci = C.real[:, None], C.imag[:, None]
+    re = (cr * ir - ci * ii).sum(axis=0)
+    im = (cr * ii + ci * ir).sum(axis=0)
+    var_re = (cr ** 2 * er ** 2 + ci ** 2 * ei ** 2).sum(axis=0)
+    var_im = (cr ** 2 * ei ** 2 + ci ** 2 * er ** 2).sum(axis=0)
+    return re, im, np.sqrt(var_re), np.sqrt(var_im)
+
+
+def eps_rel(re, im, dre, dim):
+    """epsilon_rel = sqrt((dR^2 + dI^2) / (R^2 + I^2)) (Sec. 3.3, timing notes)."""
+    return np.sqrt((np.asarray(dre) ** 2 + np.asarray(dim) ** 2) /
+                   (np.asarray(re) ** 2 + np.asarray(im) ** 2))
+
+
+# --------------------------------------------------------------- allocation
+
+def allocate(c2, w, tau, V, alpha: float = 2.0):
+    """Lattice sizes minimising T = sum tau_i n_i subject to sum |C_i|^2 w_i / n_i^alpha = V.
+
+    Lagrange solution of Sec. 2.1.3 (Eq. adaptive-solution), read with one consistent unit
+    index i (the printed equation mixes the sum and free indices):
+        lambda = (1/alpha) [ (1/V) sum_i (|C_i|^2 w_i tau_i^alpha)^(1/(alpha+1)) ]^((alpha+1)/alpha)
+        n_i    = (alpha w_i lambda |C_i|^2 / tau_i)^(1/(alpha+1))
+    Units with zero |C_i|^2 w_i get n_i = 0.  Returns (n [real], lambda).
+    """
+    c2 = np.asarray(c2, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    tau = np.asarray(tau, dtype=np.float64)
+    s = np.sum((c2 * w * tau ** alpha) ** (1.0 / (alpha + 1.0)))
+    lam = (1.0 / alpha) * (s / V) ** ((alpha + 1.0) / alpha)
+    n = (alpha * w * lam * c2 / tau) ** (1.0 / (alpha + 1.0))
+    return n, lam

@@ -1,0 +1,284 @@
+/*
+ * qmc_oracle.c -- plain, slow, obviously correct CPU reference for randomized
+ * rank-1 lattice quasi-Monte Carlo over sector-decomposed Feynman-parameter
+ * integrands (arXiv:2305.19768, Sec. 2.1 "Disteval" and Sec. 2.2 "Median QMC rules").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this file.  It shares no code, header,
+ * table or constant with the HIP library; the two only consume the same seeded
+ * inputs.
+ *
+ * Compile: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (x86-64 SSE2
+ * doubles; no FMA contraction, so every rounding step below is the one written).
+ *
+ * Every routine follows one definition, in the order the mathematics states it:
+ *   - lattice rule Q_{n,z}(f) = (1/n) sum_i f({i z / n + Delta}) with random shift
+ *     Delta (Sec. 2.2, definition of Q_{n,z} next to the median rule, Eq. "median");
+ *   - periodizing transforms korobov_r / baker (named in Sec. 3.3 timing notes; the
+ *     formulas are the standard ones: korobov_r is the regularized incomplete beta
+ *     I_y(r+1, r+1) with density (2r+1)!/(r!)^2 y^r (1-y)^r, baker is the tent map);
+ *   - integrand x^p U^a F^b sum_m c_{k,m} (log F)^m per epsilon order;
+ *   - per-shift sums with Neumaier compensation;
+ *   - the P_2 figure of merit of a lattice (Korobov space, alpha = 2, unit product
+ *     weights; Sec. 2.2 first paragraph names this criterion for the CBC vectors).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_NONFINITE 1
+#define OR_INVAL 2
+
+/* ---------------------------------------------------------------- lattice */
+
+/* (a * b) mod n, exact for all 64-bit inputs. */
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t n)
+{
+    if (a < 0x100000000ull && b < 0x100000000ull)
+        return (a * b) % n;
+    return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) % (unsigned __int128)n);
+}
+
+/* y_j = frac(k_j / n + Delta_j), k_j = i z_j mod n (exact integer product). */
+static void lattice_point(uint64_t n, int d, const uint64_t *z, const double *delta,
+                          uint64_t i, double *y)
+{
+    for (int j = 0; j < d; ++j) {
+        uint64_t k = mulmod(i, z[j], n);
+        double q = (double)k / (double)n;        /* IEEE round-to-nearest quotient */
+        double v = q + delta[j];
+        if (v >= 1.0)
+            v = v - 1.0;                         /* exact: v in [1, 2) */
+        y[j] = v;
+    }
+}
+
+void or_points(uint64_t n, int d, const uint64_t *z, const double *delta, uint64_t i0,
+               uint64_t count, double *y_out)
+{
+    for (uint64_t t = 0; t < count; ++t)
+        lattice_point(n, d, z, delta, i0 + t, y_out + t * (uint64_t)d);
+}
+
+/* -------------------------------------------------------------- transform */
+
+static double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i)
+        r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+static double ipow(double x, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; ++i)
+        r *= x;
+    return r;
+}
+
+/* kind: 0 = none, 1 = baker, r + 1 = korobov_r (r = 1..6). */
+static void transform1(int kind, double y, double *x, double *w)
+{
+    if (kind == 0) {
+        *x = y;
+        *w = 1.0;
+    } else if (kind == 1) {
+        *x = 1.0 - fabs(2.0 * y - 1.0);
+        *w = 1.0;
+    } else {
+        int r = kind - 1;
+        int N = 2 * r + 1;
+        /* phi(y) = sum_{j=r+1}^{2r+1} C(2r+1, j) y^j (1-y)^(2r+1-j) */
+        double phi = 0.0;
+        for (int j = r + 1; j <= N; ++j)
+            phi += binom(N, j) * ipow(y, j) * ipow(1.0 - y, N - j);
+        /* phi'(y) = (2r+1)!/(r!)^2 y^r (1-y)^r = (2r+1) C(2r, r) y^r (1-y)^r */
+        double dens = (double)N * binom(2 * r, r) * ipow(y, r) * ipow(1.0 - y, r);
+        *x = phi;
+        *w = dens;
+    }
+}
+
+void or_transform(int kind, uint64_t count, const double *y, double *x, double *w)
+{
+    for (uint64_t t = 0; t < count; ++t)
+        transform1(kind, y[t], &x[t], &w[t]);
+}
+
+/* -------------------------------------------------------------- integrand */
+
+typedef struct {
+    int d, n_u, n_f, u_pow, f_pow2, K, M;
+    const uint8_t *u_exp;
+    const double *u_coef;
+    const uint8_t *f_exp;
+    const double *f_coef;
+    const int32_t *x_pow2;
+    const double *logc;
+} integrand_t;
+
+static double poly(int d, int nmono, const uint8_t *exps, const double *coef, const double *x)
+{
+    double s = 0.0;
+    for (int t = 0; t < nmono; ++t) {
+        double v = coef[t];
+        for (int j = 0; j < d; ++j)
+            v *= ipow(x[j], exps[t * d + j]);
+        s += v;
+    }
+    return s;
+}
+
+/* out[k] = x^p U^a F^b sum_m logc[k][m] L^m, L = log F. */
+static void integrand(const integrand_t *g, const double *x, double *out)
+{
+    double U = poly(g->d, g->n_u, g->u_exp, g->u_coef, x);
+    double F = poly(g->d, g->n_f, g->f_exp, g->f_coef, x);
+    double base = 1.0;
+    for (int j = 0; j < g->d; ++j)
+        if (g->x_pow2[j] != 0)
+            base *= pow(x[j], 0.5 * (double)g->x_pow2[j]);
+    if (g->u_pow != 0)
+        base *= pow(U, (double)g->u_pow);
+    if (g->f_pow2 != 0)
+        base *= pow(F, 0.5 * (double)g->f_pow2);
+    double L = (g->M > 0) ? log(F) : 0.0;
+    for (int k = 0; k < g->K; ++k) {
+        double s = 0.0;
+        for (int m = 0; m <= g->M; ++m)
+            s += g->logc[k * (g->M + 1) + m] * ipow(L, m);
+        out[k] = base * s;
+    }
+}
+
+int or_integrand(int d, int n_u, const uint8_t *u_exp, const double *u_coef, int n_f,
+                 const uint8_t *f_exp, const double *f_coef, const int32_t *x_pow2,
+                 int u_pow, int f_pow2, int K, int M, const double *logc,
+                 uint64_t count, const double *x, double *out)
+{
+    integrand_t g = {d, n_u, n_f, u_pow, f_pow2, K, M, u_exp, u_coef, f_exp, f_coef,
+                     x_pow2, logc};
+    for (uint64_t t = 0; t < count; ++t)
+        integrand(&g, x + t * (uint64_t)d, out + t * (uint64_t)K);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------- sums */
+
+typedef struct {
+    double s, c;
+} neumaier_t;
+
+static void neumaier_add(neumaier_t *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/*
+ * Shift estimates for one sector, shifts l0..l1-1.
+ *   q_out[(l-l0)*K + k]   = (1/n) sum_i W(y_i) f_k(x(y_i))       (Neumaier)
+ *   abs_out[(l-l0)*K + k] = (1/n) sum_i |W(y_i) f_k(x(y_i))|
+ * A sample with W == 0 contributes 0 and the integrand is not evaluated there.
+ * Returns OR_NONFINITE and writes the first offending (shift, index) to bad[0..1]
+ * if a contribution is not finite.
+ */
+int or_sums(int d, int n_u, const uint8_t *u_exp, const double *u_coef, int n_f,
+            const uint8_t *f_exp, const double *f_coef, const int32_t *x_pow2, int u_pow,
+            int f_pow2, int K, int M, const double *logc, int transform, uint64_t n,
+            const uint64_t *z, const double *shifts, int l0, int l1, double *q_out,
+            double *abs_out, int64_t *bad)
+{
+    if (d < 1 || d > 16 || K < 1 || K > 16 || n < 1)
+        return OR_INVAL;
+    integrand_t g = {d, n_u, n_f, u_pow, f_pow2, K, M, u_exp, u_coef, f_exp, f_coef,
+                     x_pow2, logc};
+    double y[16], x[16], fk[16];
+    for (int l = l0; l < l1; ++l) {
+        neumaier_t acc[16], aab[16];
+        memset(acc, 0, sizeof acc);
+        memset(aab, 0, sizeof aab);
+        for (uint64_t i = 0; i < n; ++i) {
+            lattice_point(n, d, z, shifts + (size_t)l * d, i, y);
+            double W = 1.0;
+            for (int j = 0; j < d; ++j) {
+                double w;
+                transform1(transform, y[j], &x[j], &w);
+                W *= w;
+            }
+            if (W == 0.0)
+                continue;
+            integrand(&g, x, fk);
+            for (int k = 0; k < K; ++k) {
+                double v = W * fk[k];
+                if (!isfinite(v)) {
+                    if (bad) {
+                        bad[0] = l;
+                        bad[1] = (int64_t)i;
+                    }
+                    return OR_NONFINITE;
+                }
+                neumaier_add(&acc[k], v);
+                neumaier_add(&aab[k], fabs(v));
+            }
+        }
+        for (int k = 0; k < K; ++k) {
+            q_out[(l - l0) * K + k] = (acc[k].s + acc[k].c) / (double)n;
+            if (abs_out)
+                abs_out[(l - l0) * K + k] = (aab[k].s + aab[k].c) / (double)n;
+        }
+    }
+    return OR_OK;
+}
+
+/* Neumaier sum of an array (exposed so the compensation itself can be pinned). */
+double or_neumaier(const double *v, uint64_t count)
+{
+    neumaier_t a = {0.0, 0.0};
+    for (uint64_t t = 0; t < count; ++t)
+        neumaier_add(&a, v[t]);
+    return a.s + a.c;
+}
+
+/* --------------------------------------------------------------------- P2 */
+
+/*
+ * P_2(z) = -1 + (1/n) sum_{k=0}^{n-1} prod_j [1 + 2 pi^2 B_2({k z_j / n})],
+ * B_2(x) = x^2 - x + 1/6: the squared worst-case error of the lattice rule in the
+ * Korobov space of smoothness alpha = 2 with unit product weights.
+ */
+double or_p2(uint64_t n, int d, const uint64_t *z)
+{
+    const double two_pi2 = 2.0 * M_PI * M_PI;
+    neumaier_t acc = {0.0, 0.0};
+    for (uint64_t k = 0; k < n; ++k) {
+        double prod = 1.0;
+        for (int j = 0; j < d; ++j) {
+            uint64_t r = mulmod(k, z[j], n);
+            double x = (double)r / (double)n;
+            double b2 = x * x - x + 1.0 / 6.0;
+            prod *= 1.0 + two_pi2 * b2;
+        }
+        neumaier_add(&acc, prod);
+    }
+    return -1.0 + (acc.s + acc.c) / (double)n;
+}
+
+/* splitmix64 (Steele, Lea, Flood, OOPSLA 2014): state += golden gamma, then the
+ * variant-13 finalizer of MurmurHash3.  Counter-based use: value of counter c is
+ * mix(seed + (c + 1) * gamma). */
+uint64_t or_splitmix64(uint64_t seed, uint64_t counter)
+{
+    uint64_t x = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
