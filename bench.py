@@ -1,0 +1,200 @@
+"""Benchmark: integrand evaluations per second of randomized rank-1 lattice QMC on MI355X.
+
+Workload (one step = one pass of the whole hot path over it): the two-loop-like
+synthetic integral -- 40 sectors, d uniform in 4..6, U with 4-8 and F with 10-30
+monomials, epsilon orders -2..0 with log^m F (m <= 2), per-sector prime lattice sizes
+log-uniform in [1e5, 1e7], 32 random shifts -- integrated in FP64: lattice points,
+korobov3 transform, integrand, compensated per-shift sums, shift means and errors.
+One evaluation = one (lattice point, shift) sample of one sector, all orders.
+
+Prints one JSON line.  `roofline` reports the integrand kernel against the FP64 vector
+peak (the path is ALU-bound; it reads no per-sample data from memory): algorithmic
+flops per launch (convention in `algorithmic_flops`) over the kernel time measured
+with HIP events on the launch stream.  `cpu_baseline` times the CPU oracle on a
+bounded sample of the same workload (every sector, one shift).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qmc_integrate_kernel_two_loop_traffic.json")
+
+
+def algorithmic_flops(sec, m: int) -> float:
+    """Algorithmic flops of one evaluation of a sector (what the method computes, not
+    what the kernel executes).  Convention: add, multiply = 1; FMA = 2; division, square
+    root and log = 1 each.  Per evaluation:
+      lattice    d adds (q + Delta) and d divisions k/n shared by the m shifts;
+      korobov3   14 per coordinate (y(1-y), its cube, the factor 140, a 3-FMA Horner,
+                 y^4 and the product), plus d-1 for W; baker 3, none 0;
+      U, F       per monomial of total degree g: g multiplications by variables, one by
+                 the coefficient, one add;
+      base       one multiplication per unit of |integer exponent| of U and F and of x_j,
+                 one square root if a half-integer exponent occurs, one division if a
+                 negative exponent occurs;
+      log F      1 if any order uses it;
+      orders     per order: 2 max_log (Horner in log F) + 1 (base times polynomial) +
+                 1 (weight) + 1 (accumulate).
+    """
+    import numpy as np
+    d = sec.d
+    f = d + d / m
+    if sec.transform.startswith("korobov"):
+        f += 14 * d + (d - 1)
+    elif sec.transform == "baker":
+        f += 3 * d
+    for e in (np.asarray(sec.u_exp), np.asarray(sec.f_exp)):
+        g = e.reshape(len(e), d).sum(axis=1)
+        f += float(np.sum(g + 2))
+    xp = np.asarray(sec.x_pow2)
+    f += abs(int(sec.u_pow)) + abs(int(sec.f_pow2)) // 2 + int(np.sum(np.abs(xp) // 2))
+    if (xp % 2).any() or sec.f_pow2 % 2:
+        f += 1
+    if sec.u_pow < 0 or sec.f_pow2 < 0 or (xp < 0).any():
+        f += 1
+    M = sec.M
+    if M > 0:
+        f += 1
+    f += sec.K * (2 * M + 3)
+    return f
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("qmc_kernels.hip", "qmc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2305_19768_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(problem, threads: int):
+    """CPU oracle on every sector with one shift (a bounded sample of the workload)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    from oracle import build as ob
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    order = sorted(range(len(problem.sectors)), key=lambda s: -problem.sectors[s].n)
+
+    def run(s):
+        oracle.sector_sums(problem.sectors[s], problem.shifts[s], shift_range=(0, 1))
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, order))
+    dt = time.perf_counter() - t0
+    evals = int(sum(s.n for s in problem.sectors))
+    return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"all {len(problem.sectors)} sectors x 1 of {problem.m} shifts "
+                      f"({evals} evaluations, FP64 scalar C, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the lattice QMC "
+                                   "path has no multi-GPU mode (--gpus must be 1)"}))
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import __graft_entry__ as g
+    g._ensure_built()
+    import paper_2305_19768_amd as qmc
+
+    torch.cuda.set_device(0)
+    prob = workloads.two_loop_integral(seed=0)
+    t0 = time.perf_counter()
+    plan = qmc.Plan(prob)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    S, m, K = plan.S, plan.m, plan.K
+    out = (torch.empty((S, m, K), dtype=torch.float64, device="cuda"),
+           torch.empty((S, K), dtype=torch.float64, device="cuda"),
+           torch.empty((S, K), dtype=torch.float64, device="cuda"))
+    for _ in range(args.warmup):
+        plan.integrate(out=out, check=False)
+    torch.cuda.synchronize()
+    plan.check_status()
+    print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    plan.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.integrate(out=out, check=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, launches = plan.read_timing()
+    plan.enable_timing(False)
+    plan.check_status()
+
+    if args.copy_probe:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    evals = prob.evals()
+    value = evals * args.steps / elapsed
+    flops_launch = sum(algorithmic_flops(sec, m) * sec.n * m for sec in prob.sectors)
+    k_s = kernel_ms / max(launches, 1) / 1e3
+    achieved = flops_launch / k_s / 1e12
+    traffic = measured_traffic()
+    result = {
+        "metric": "integrand evals/s (FP64 vs FP32) and wall time to 1e-4 rel. amplitude error",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded two-loop-like sectors; the paper's integrands are not "
+                "available)",
+        "config": {"workload": "two_loop_integral: 40 sectors, d 4..6, n 1e5..1e7 prime, "
+                               "32 shifts, orders eps^-2..eps^0, korobov3, FP64",
+                   "sectors": S, "shifts": m, "orders": K, "evals_per_step": evals,
+                   "lattice_points_per_step": int(sum(s.n for s in prob.sectors))},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic, "kernel": "qmc_integrate_kernel<3,2>",
+                     "kernel_ms": kernel_ms / max(launches, 1),
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "flops_per_eval": flops_launch / evals},
+        "plan_seconds": plan_s,
+    }
+    if not args.no_cpu:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        result["cpu_baseline"] = cpu_baseline(prob, threads)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

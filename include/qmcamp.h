@@ -1,0 +1,236 @@
+/*
+ * qmcamp.h -- C ABI of the MI355X (gfx950) randomized rank-1 lattice QMC library
+ * for sector-decomposed Feynman-parameter integrals and weighted sums of them
+ * (amplitudes), after arXiv:2305.19768 (pySecDec 1.6), Sec. 2.1 and 2.2.
+ *
+ * The problem statement follows the paper's: a set of integrals, each a sum of
+ * sectors; each sector an integrand over the unit cube expanded in epsilon up to a
+ * fixed order; a rank-1 lattice of size n with generating vector z per sector, m
+ * random shifts; weighted sums A = sum_i C_i I_i; value and error estimate out
+ * (Sec. 2.1.1 usage, Sec. 2.1.3 adaptive weighted sums, Sec. 2.4 coefficients).
+ *
+ * Conventions
+ *   - Plain C types only.  Pointers are host pointers unless the name starts with
+ *     "dev_"; device pointers are HIP device addresses (e.g. a torch tensor's
+ *     data_ptr()).  "stream" is a hipStream_t passed as void* (NULL = legacy stream).
+ *   - The library copies every host input it needs during the call; the caller may
+ *     free host buffers as soon as a call returns.
+ *   - The library allocates no device memory: all device storage is the caller's
+ *     workspace bound with qmc_bind_workspace() plus the caller's output buffers.
+ *   - Errors are negative qmc_status codes; qmc_last_error() returns a thread-local
+ *     message describing the most recent failure.  Argument checks happen before
+ *     any launch, so a QMC_E_INVAL call has no device side effects.
+ *   - Calls on one plan are not thread-safe; distinct plans are independent.
+ */
+#ifndef QMCAMP_H
+#define QMCAMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QMC_OK = 0,
+    QMC_E_INVAL = -1,      /* invalid argument; nothing was launched */
+    QMC_E_NOMEM = -2,      /* host allocation failed or workspace too small */
+    QMC_E_DEVICE = -3,     /* a HIP runtime call failed */
+    QMC_E_NONFINITE = -4,  /* a per-shift sum is not finite; see qmc_query_status */
+    QMC_E_TIMEOUT = -5,    /* amp_evaluate stopped at its time limit (results valid, flagged) */
+    QMC_E_STATE = -7       /* call out of order (e.g. no workspace bound) */
+} qmc_status;
+
+/* Periodizing transforms (the paper's "korobov3" default and "baker", Sec. 3.3). */
+enum {
+    QMC_TRANSFORM_NONE = 0,     /* x = y, w = 1 (tests only) */
+    QMC_TRANSFORM_BAKER = 1,    /* tent map x = 1 - |2y - 1|, w = 1 */
+    QMC_TRANSFORM_KOROBOV1 = 2, /* korobov_r = QMC_TRANSFORM_KOROBOV1 + r - 1, r = 1..6: */
+    QMC_TRANSFORM_KOROBOV3 = 4, /*   x = I_y(r+1, r+1), w = (2r+1)!/(r!)^2 (y(1-y))^r    */
+    QMC_TRANSFORM_KOROBOV6 = 7
+};
+
+enum { QMC_PREC_FP64 = 0, QMC_PREC_FP32 = 1 };
+
+#define QMC_MAX_DIM 8      /* Feynman parameters per sector after the delta constraint */
+#define QMC_MAX_ORDERS 4   /* epsilon orders per sector */
+#define QMC_MAX_LOG 4      /* highest power of log F per order */
+#define QMC_MAX_DEG 3      /* total degree of U and F (one- and two-loop graphs) */
+#define QMC_MAX_SHIFTS 64
+
+/*
+ * One sector integrand, expanded in epsilon (Sec. 2.3 and 3: sector-decomposed
+ * parameter integrals, all orders up to the finite one are integrated):
+ *
+ *   f_k(x) = prod_j x_j^(x_pow2[j]/2) * U(x)^u_pow * F(x)^(f_pow2/2)
+ *            * sum_{m=0}^{max_log} logc[k][m] * (log F(x))^m ,   k = 0 .. n_orders-1
+ *
+ * U and F are sums of monomials c * prod_j x_j^e_j with total degree <= QMC_MAX_DEG;
+ * their monomials are rows u_off .. u_off+n_u-1 (f_off .. f_off+n_f-1) of the
+ * problem's mono_exp / mono_coef arrays.  Repeated exponent rows are summed.
+ */
+typedef struct {
+    int32_t d;                        /* 1 .. QMC_MAX_DIM */
+    int32_t integral;                 /* index of the integral this sector belongs to */
+    int32_t n_u, n_f;                 /* number of monomials of U and F (n_f >= 1) */
+    int64_t u_off, f_off;             /* first monomial row of U and F */
+    int32_t x_pow2[QMC_MAX_DIM];      /* twice the exponent of x_j, |x_pow2| <= 16 */
+    int32_t u_pow;                    /* exponent of U, |u_pow| <= 8 */
+    int32_t f_pow2;                   /* twice the exponent of F, |f_pow2| <= 16 */
+    int32_t transform;                /* QMC_TRANSFORM_* */
+    int32_t reserved0;
+    double logc[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
+    uint64_t n;                       /* default lattice size (prime or any n >= 2) */
+    uint64_t a;                       /* default Korobov parameter, z = (1, a, a^2, ...) mod n */
+} qmc_sector_desc;
+
+typedef struct {
+    int32_t n_sectors;                /* >= 1 */
+    int32_t n_orders;                 /* K, 1 .. QMC_MAX_ORDERS */
+    int32_t order_lo;                 /* epsilon power of order 0 (informational) */
+    int32_t max_log;                  /* 0 .. QMC_MAX_LOG */
+    int32_t n_integrals;              /* >= 1; every sector's integral < n_integrals */
+    int32_t reserved0;
+    const qmc_sector_desc *sectors;   /* [n_sectors] */
+    const uint8_t *mono_exp;          /* [rows][QMC_MAX_DIM] exponents, row-major */
+    const double *mono_coef;          /* [rows] coefficients */
+    int64_t n_mono_rows;
+} qmc_problem;
+
+typedef struct {
+    int32_t m;                        /* random shifts per sector, 2 .. QMC_MAX_SHIFTS */
+    int32_t precision;                /* QMC_PREC_FP64 (default) or QMC_PREC_FP32 */
+    uint64_t seed;                    /* seed of the built-in shift generator */
+    uint64_t n_max;                   /* largest lattice size any call will use (sizes the
+                                         workspace); 0 = max of the sectors' n */
+    int32_t block;                    /* threads per workgroup (64..1024, multiple of 64);
+                                         0 = tuned default */
+    int32_t shift_tile;               /* shifts per workgroup, 1..16, divides m; 0 = tuned */
+    int32_t shifts_per_pass;          /* shifts evaluated per lattice point in one pass:
+                                         1, 2 or 4, divides shift_tile; 0 = tuned */
+    int32_t reserved0;
+} qmc_options;
+
+typedef struct qmc_plan_s *qmc_plan_t;
+
+/*
+ * qmc_plan -- validate a problem and pack it for the device (the per-integrand
+ * hoisting of Sec. 2.1: everything that does not depend on the lattice point is
+ * prepared once).  Copies the host tables; computes each sector's dense nested-Horner
+ * coefficient table for U and F; derives the shifts from opt->seed.  Host only: no
+ * HIP call is made.  On success *out owns the plan (free with qmc_plan_free).
+ * Errors: QMC_E_INVAL (bad dimension, degree > QMC_MAX_DEG, exponent out of range,
+ * offsets outside the monomial arrays, non-finite coefficient, m out of range),
+ * QMC_E_NOMEM.
+ */
+qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t *out);
+
+/* Bytes of device workspace qmc_bind_workspace needs for this plan (0 on NULL). */
+size_t qmc_workspace_bytes(qmc_plan_t plan);
+
+/*
+ * qmc_bind_workspace -- hand the plan a caller-owned device buffer of at least
+ * qmc_workspace_bytes() bytes (256-byte aligned) and upload the packed tables on
+ * `stream`.  The buffer must stay valid until the plan is freed or rebound.
+ * Errors: QMC_E_INVAL (NULL / misaligned), QMC_E_NOMEM (too small), QMC_E_DEVICE.
+ */
+qmc_status qmc_bind_workspace(qmc_plan_t plan, void *dev_workspace, size_t bytes, void *stream);
+
+/*
+ * qmc_set_shifts -- replace the shifts with caller values: host array
+ * shifts[s][l][j], s < n_sectors, l < m, j < QMC_MAX_DIM (only j < d_s is read),
+ * each in [0, 1).  Copied to the workspace on `stream`.
+ * Built-in shifts (used until this is called): Delta_{s,l,j} =
+ * (splitmix64(seed, (s << 32) | (l << 8) | j) >> 11) * 2^-53, where splitmix64(seed, c)
+ * is the (c+1)-th output of Steele-Lea-Flood's SplitMix64 started from state `seed`.
+ * Errors: QMC_E_INVAL (value outside [0,1) or not finite), QMC_E_STATE, QMC_E_DEVICE.
+ */
+qmc_status qmc_set_shifts(qmc_plan_t plan, const double *shifts, void *stream);
+
+/*
+ * qmc_integrate -- randomized rank-1 lattice rule for every sector (Sec. 2.1 and the
+ * definition of Q_{n,z} in Sec. 2.2), on the device, asynchronous on `stream`:
+ *
+ *   Q[s][l][k] = (1/n_s) sum_{i=0}^{n_s-1} W(y) f_k(phi(y)),
+ *   y_j = frac((i z_j mod n_s) / n_s + Delta_{s,l,j}),  z = (1, a_s, a_s^2, ...) mod n_s,
+ *   x_j = phi(y_j), W = prod_j phi'(y_j)  (samples with W = 0 contribute 0);
+ *   mean[s][k] = (1/m) sum_l Q[s][l][k];  err[s][k] = sqrt(sum_l (Q - mean)^2 / ((m-1) m)).
+ *
+ * n, a: host arrays [n_sectors] of lattice sizes and Korobov parameters, or NULL for
+ * the sectors' defaults.  Requires 2 <= n_s <= n_max, n_s < 2^53, gcd(a_s^j, n_s) = 1
+ * for j < d_s (checked on the host before launch: QMC_E_INVAL).
+ * Outputs (device, caller-owned, float64): dev_q [n_sectors][m][K] (may be NULL),
+ * dev_mean and dev_err [n_sectors][K].  Sums are compensated (TwoSum) within each
+ * thread, across the wavefront and across workgroups, in a fixed order, so results
+ * are bitwise reproducible.  Non-finite sums are reported by qmc_query_status, not
+ * here (the call does not synchronize).
+ */
+qmc_status qmc_integrate(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, void *stream,
+                         double *dev_q, double *dev_mean, double *dev_err);
+
+/*
+ * qmc_query_status -- synchronize `stream` and report the device status word of the
+ * last qmc_integrate: QMC_OK, or QMC_E_NONFINITE with *sector, *shift, *order set to
+ * the first non-finite sum in (sector, shift, order) order.
+ */
+qmc_status qmc_query_status(qmc_plan_t plan, void *stream, int32_t *sector, int32_t *shift,
+                            int32_t *order);
+
+/*
+ * qmc_korobov_p2 -- figure of merit of Korobov lattices on the device:
+ *   dev_p2[c] = -1 + (1/n) sum_{k<n} prod_{j<d} [1 + 2 pi^2 B2({k a_c^j / n})],
+ *   B2(x) = x^2 - x + 1/6,
+ * the worst-case error criterion (Korobov space alpha = 2, unit product weights) the
+ * paper names for its lattices (Sec. 2.2).  candidates: host array [n_cand] of a,
+ * 1 <= a < n.  Uses the plan's workspace as scratch (the plan must be bound; needs
+ * n_cand <= 65536 and 2 <= n < 2^53).  Asynchronous on `stream`.
+ */
+qmc_status qmc_korobov_p2(qmc_plan_t plan, uint64_t n, int32_t d, const uint64_t *candidates,
+                          int32_t n_cand, void *stream, double *dev_p2);
+
+/*
+ * qmc_korobov_search -- synchronous argmin of qmc_korobov_p2 over the candidates with
+ * ties (relative 1e-12 of the minimum) broken towards the smallest a.  *a_out receives
+ * the chosen parameter, *p2_out (may be NULL) its figure of merit.
+ */
+qmc_status qmc_korobov_search(qmc_plan_t plan, uint64_t n, int32_t d, const uint64_t *candidates,
+                              int32_t n_cand, void *stream, uint64_t *a_out, double *p2_out);
+
+/*
+ * qmc_lattice_points -- the lattice-point step of qmc_integrate on its own, for
+ * verification: dev_y[t][j] = y_j of point i = i0 + t, t < count, j < d, with
+ *   k_j = i z_j mod n,  q_j = RN(k_j / n),  y_j = RN(q_j + shift[j]) (minus 1 if >= 1),
+ * z = (1, a, a^2, ...) mod n (rank-1 lattice rule of Sec. 2.2).  The device walks the
+ * points with the same per-thread stride arithmetic as the integration kernel.
+ * dev_y: device float64 [count][d].  Requires i0 + count <= n, shift in [0,1)^d, gcd
+ * conditions as qmc_integrate.  Asynchronous on `stream`.
+ */
+qmc_status qmc_lattice_points(uint64_t n, int32_t d, uint64_t a, const double *shift,
+                              uint64_t i0, uint64_t count, void *stream, double *dev_y);
+
+/*
+ * qmc_enable_timing / qmc_read_timing -- kernel timing for measurement: while enabled,
+ * every qmc_integrate records a HIP event pair on its stream around its main
+ * (integrand) kernel.  Enabling (or disabling) clears the record; at most 4096
+ * launches are recorded (QMC_E_STATE beyond).  qmc_read_timing synchronizes on the
+ * recorded events and returns the summed kernel time in milliseconds and the number
+ * of recorded launches (either pointer may be NULL).
+ */
+qmc_status qmc_enable_timing(qmc_plan_t plan, int32_t enable);
+qmc_status qmc_read_timing(qmc_plan_t plan, double *ms_total, int32_t *launches);
+
+/* Release a plan (host memory only; the workspace stays the caller's). NULL is a no-op. */
+void qmc_plan_free(qmc_plan_t plan);
+
+/* Thread-local description of the last failure ("" if none). */
+const char *qmc_last_error(void);
+
+/* Library version string. */
+const char *qmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMCAMP_H */

@@ -1,0 +1,177 @@
+"""MI355X (gfx950) randomized rank-1 lattice QMC for sector integrals and amplitudes.
+
+Thin ctypes binding of ``libqmcamp.so`` (C ABI in ``include/qmcamp.h``).  This module
+only marshals arguments: every step of the integration runs in the library's HIP
+kernels.  PyTorch provides device memory (the plan workspace and output tensors) and
+the stream.  There is no CPU fallback: importing fails loudly when the library is
+missing, and every call requires a HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from ._abi import (QMC_MAX_DIM, QMC_MAX_LOG, QMC_MAX_ORDERS, QMC_PREC_FP32, QMC_PREC_FP64,
+                   TRANSFORMS, QmcError, lib, options_struct, problem_struct)
+
+__all__ = ["Plan", "QmcError", "lib", "korobov_search", "lattice_points", "TRANSFORMS",
+           "QMC_PREC_FP64", "QMC_PREC_FP32"]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2305_19768_amd needs a HIP device (torch.cuda.is_available() "
+                           "is False); the library has no CPU path")
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    st = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise QmcError(rc, f"{what}: {lib().qmc_last_error().decode()}")
+
+
+class Plan:
+    """A packed problem bound to a device workspace.
+
+    ``problem`` is a ``workloads.Problem``-like object (sectors with monomial tables,
+    exponents, log coefficients, lattice size n and Korobov parameter a).
+    """
+
+    def __init__(self, problem, m: Optional[int] = None, precision: int = QMC_PREC_FP64,
+                 seed: int = 0, n_max: int = 0, block: int = 0, shift_tile: int = 0,
+                 shifts_per_pass: int = 0, use_problem_shifts: bool = True, device=None):
+        torch = _torch()
+        self.problem = problem
+        self.m = int(problem.m if m is None else m)
+        self.S = len(problem.sectors)
+        self.K = problem.K
+        self._keep, prob = problem_struct(problem)
+        opt = options_struct(self.m, precision, seed, n_max, block, shift_tile, shifts_per_pass)
+        h = ctypes.c_void_p()
+        _check(lib().qmc_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)), "qmc_plan")
+        self._h = h
+        nbytes = int(lib().qmc_workspace_bytes(h))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _check(lib().qmc_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                        ctypes.c_size_t(nbytes), _stream_ptr()),
+               "qmc_bind_workspace")
+        if use_problem_shifts and getattr(problem, "shifts", None) is not None:
+            self.set_shifts(problem.shifts)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().qmc_plan_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_shifts(self, shifts: Sequence[np.ndarray]):
+        arr = np.zeros((self.S, self.m, QMC_MAX_DIM), dtype=np.float64)
+        for s, sh in enumerate(shifts):
+            sh = np.asarray(sh, dtype=np.float64)
+            arr[s, :, :sh.shape[1]] = sh[:self.m]
+        _check(lib().qmc_set_shifts(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    _stream_ptr()), "qmc_set_shifts")
+        self._shift_host = arr   # keep alive until the copy is issued
+
+    def integrate(self, n: Optional[Sequence[int]] = None, a: Optional[Sequence[int]] = None,
+                  out=None, stream=None, check: bool = True):
+        """Runs the lattice rule on every sector.  Returns (q [S, m, K], mean [S, K],
+        err [S, K]) as float64 device tensors.  With check=True the stream is
+        synchronised and a non-finite sum raises QmcError."""
+        torch = _torch()
+        if out is None:
+            q = torch.empty((self.S, self.m, self.K), dtype=torch.float64, device=self.device)
+            mean = torch.empty((self.S, self.K), dtype=torch.float64, device=self.device)
+            err = torch.empty((self.S, self.K), dtype=torch.float64, device=self.device)
+        else:
+            q, mean, err = out
+        n_arr = None if n is None else np.ascontiguousarray(n, dtype=np.uint64)
+        a_arr = None if a is None else np.ascontiguousarray(a, dtype=np.uint64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.c_void_p
+        st = _stream_ptr(stream)
+        _check(lib().qmc_integrate(self._h, None if n_arr is None else n_arr.ctypes.data_as(u64p),
+                                   None if a_arr is None else a_arr.ctypes.data_as(u64p), st,
+                                   dp(q.data_ptr()) if q is not None else None,
+                                   dp(mean.data_ptr()), dp(err.data_ptr())), "qmc_integrate")
+        if check:
+            self.check_status(stream)
+        return q, mean, err
+
+    def check_status(self, stream=None):
+        sec, sh, order = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().qmc_query_status(self._h, _stream_ptr(stream), ctypes.byref(sec),
+                                      ctypes.byref(sh), ctypes.byref(order)), "qmc_query_status")
+
+    def enable_timing(self, on: bool = True):
+        """Record HIP events around the integrand kernel of each integrate() call."""
+        _check(lib().qmc_enable_timing(self._h, ctypes.c_int32(1 if on else 0)),
+               "qmc_enable_timing")
+
+    def read_timing(self):
+        """(summed kernel milliseconds, number of timed launches) since enable_timing."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int32()
+        _check(lib().qmc_read_timing(self._h, ctypes.byref(ms), ctypes.byref(cnt)),
+               "qmc_read_timing")
+        return float(ms.value), int(cnt.value)
+
+    def korobov_p2(self, n: int, d: int, candidates: Sequence[int], stream=None):
+        """P_2 figure of merit of the Korobov vectors (1, a, ..., a^(d-1)) mod n (device)."""
+        torch = _torch()
+        c = np.ascontiguousarray(candidates, dtype=np.uint64)
+        out = torch.empty(len(c), dtype=torch.float64, device=self.device)
+        _check(lib().qmc_korobov_p2(self._h, ctypes.c_uint64(n), ctypes.c_int32(d),
+                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    ctypes.c_int32(len(c)), _stream_ptr(stream),
+                                    ctypes.c_void_p(out.data_ptr())), "qmc_korobov_p2")
+        return out
+
+    def korobov_search(self, n: int, d: int, candidates: Sequence[int], stream=None):
+        """Korobov parameter minimising P_2 over the candidates (ties: smallest a)."""
+        c = np.ascontiguousarray(candidates, dtype=np.uint64)
+        a = ctypes.c_uint64()
+        p2 = ctypes.c_double()
+        _check(lib().qmc_korobov_search(self._h, ctypes.c_uint64(n), ctypes.c_int32(d),
+                                        c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                        ctypes.c_int32(len(c)), _stream_ptr(stream),
+                                        ctypes.byref(a), ctypes.byref(p2)), "qmc_korobov_search")
+        return int(a.value), float(p2.value)
+
+
+def korobov_search(plan: Plan, n: int, d: int, candidates: Sequence[int]):
+    return plan.korobov_search(n, d, candidates)
+
+
+def lattice_points(n: int, a: int, shift: Sequence[float], i0: int = 0,
+                   count: Optional[int] = None, stream=None):
+    """Shifted rank-1 lattice points computed on the device, float64 [count, d]."""
+    torch = _torch()
+    sh = np.ascontiguousarray(shift, dtype=np.float64)
+    d = len(sh)
+    count = n - i0 if count is None else count
+    out = torch.empty((count, d), dtype=torch.float64, device="cuda")
+    _check(lib().qmc_lattice_points(ctypes.c_uint64(n), ctypes.c_int32(d), ctypes.c_uint64(a),
+                                    sh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.c_uint64(i0), ctypes.c_uint64(count),
+                                    _stream_ptr(stream), ctypes.c_void_p(out.data_ptr())),
+           "qmc_lattice_points")
+    return out

@@ -1,0 +1,653 @@
+// qmc_api.cpp -- host planner and C ABI of the lattice QMC library (see include/qmcamp.h).
+//
+// The planner does, once per problem, the per-integrand work that does not depend
+// on the lattice point (the hoisting of Sec. 2.1 of arXiv:2305.19768): it validates
+// the sectors, converts the monomial lists of U and F into dense nested-Horner
+// tables (degree <= 3), splits every exponent into integer / half-integer parts and
+// numerator / denominator factors, and derives the random shifts.  Per call it
+// builds the lattice table (n, z = (1, a, a^2, ...) mod n, RN(1/n), workgroup
+// ranges) and launches the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qmc_internal.h"
+
+using namespace qmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qmc_status fail(qmc_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+qmc_status hip_fail(int e, const char *what) {
+  return fail(QMC_E_DEVICE, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t n) {
+  return (uint64_t)(((unsigned __int128)a * (unsigned __int128)b) % (unsigned __int128)n);
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014), counter-based: output number `counter` (0-based)
+// of the generator started from state `seed`.
+uint64_t splitmix64(uint64_t seed, uint64_t counter) {
+  uint64_t x = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int64_t kTargetBlocks = 16384;   // workgroups per launch the chunking aims at
+constexpr int32_t kP2MaxCand = 65536;
+constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
+
+}  // namespace
+
+struct qmc_plan_s {
+  // problem
+  int32_t S = 0, K = 0, M = 0, n_integrals = 0, d_max = 0;
+  std::vector<SectorDev> sec;
+  std::vector<double> coef;
+  std::vector<double> shifts;          // [S][m][QMC_MAX_DIM]
+  std::vector<uint64_t> n_default, a_default;
+  std::vector<int32_t> dims;
+  // options
+  int32_t m = 0, precision = 0, block = 256, tile = 8, spp = 2;
+  uint64_t n_max = 0;
+  // workspace layout (byte offsets)
+  size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
+         off_status = 0, off_partial = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
+         total = 0;
+  int64_t max_blocks = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  // per-call staging
+  std::vector<LatticeDev> lat;
+  std::vector<int64_t> begin;
+  std::vector<LatticeDev> lat_uploaded;
+  bool lat_valid = false;
+  // kernel timing (HIP events around the main kernel of each qmc_integrate)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // pairs: start, stop
+  size_t ev_used = 0;
+  ~qmc_plan_s() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+static void layout(qmc_plan_s *p) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const int tiles = (p->m + p->tile - 1) / p->tile;
+  p->max_blocks = kTargetBlocks + (int64_t)p->S * tiles + 64;
+  p->off_sec = take(sizeof(SectorDev) * p->S);
+  p->off_coef = take(sizeof(double) * p->coef.size());
+  p->off_shift = take(sizeof(double) * p->shifts.size());
+  p->off_lat = take(sizeof(LatticeDev) * p->S);
+  p->off_begin = take(sizeof(int64_t) * (p->S + 1));
+  p->off_q = take(sizeof(double) * (size_t)p->S * p->m * p->K);
+  p->off_status = take(256);
+  p->off_partial = take(sizeof(double) * 2 * (size_t)p->max_blocks * p->tile * p->K);
+  p->off_p2cand = take(sizeof(uint64_t) * kP2MaxCand);
+  p->off_p2part = take(sizeof(double) * kP2PartialDoubles);
+  p->off_p2vals = take(sizeof(double) * kP2MaxCand);
+  p->total = o;
+}
+
+// Position of each monomial in the dense nested-Horner layout (degree <= 3).
+static int dense_pos(int D, const uint8_t *e, int *deg_out) {
+  int var[3], g = 0;
+  for (int j = 0; j < D; ++j)
+    for (int t = 0; t < e[j]; ++t) {
+      if (g >= 3) return -1;
+      var[g++] = j;
+    }
+  *deg_out = g;
+  if (g == 0) return 0;
+  int p = 1;
+  for (int j = 0; j < D; ++j) {
+    if (g == 1 && var[0] == j) return p;
+    ++p;
+    for (int k = j; k < D; ++k) {
+      if (g == 2 && var[0] == j && var[1] == k) return p;
+      ++p;
+      for (int l = k; l < D; ++l) {
+        if (g == 3 && var[0] == j && var[1] == k && var[2] == l) return p;
+        ++p;
+      }
+    }
+  }
+  return -1;
+}
+
+static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t count,
+                            std::vector<double> &coef, int32_t *table_off, int32_t *deg_out,
+                            double *abs_sum, int s, const char *name) {
+  if (count < 0 || off < 0 || off + count > prob->n_mono_rows)
+    return fail(QMC_E_INVAL, "sector %d: %s monomial rows [%lld, %lld) outside [0, %lld)", s, name,
+                (long long)off, (long long)(off + count), (long long)prob->n_mono_rows);
+  const int len = dense_len(D);
+  const size_t base = coef.size();
+  coef.resize(base + len, 0.0);
+  *table_off = (int32_t)base;
+  int deg = 0;
+  double a = 0.0;
+  for (int32_t t = 0; t < count; ++t) {
+    const uint8_t *e = prob->mono_exp + (off + t) * QMC_MAX_DIM;
+    const double c = prob->mono_coef[off + t];
+    if (!std::isfinite(c)) return fail(QMC_E_INVAL, "sector %d: non-finite %s coefficient", s, name);
+    for (int j = D; j < QMC_MAX_DIM; ++j)
+      if (e[j] != 0)
+        return fail(QMC_E_INVAL, "sector %d: %s monomial uses x_%d beyond d = %d", s, name, j + 1, D);
+    int g;
+    const int pos = dense_pos(D, e, &g);
+    if (pos < 0)
+      return fail(QMC_E_INVAL, "sector %d: %s monomial of total degree > %d", s, name, QMC_MAX_DEG);
+    coef[base + pos] += c;
+    if (c != 0.0) deg = std::max(deg, g);
+    a += std::fabs(c);
+  }
+  *deg_out = std::max(deg, 1);
+  if (abs_sum) *abs_sum = a;
+  return QMC_OK;
+}
+
+static void split_pow2(int32_t e2, int32_t *num, int32_t *den, int32_t *half) {
+  const int32_t mag = e2 < 0 ? -e2 : e2;
+  *num = e2 > 0 ? mag / 2 : 0;
+  *den = e2 < 0 ? mag / 2 : 0;
+  *half = (mag & 1) ? (e2 > 0 ? 1 : -1) : 0;
+}
+
+extern "C" {
+
+const char *qmc_last_error(void) { return g_last_error.c_str(); }
+
+const char *qmc_version(void) { return "qmcamp 0.1 (gfx950)"; }
+
+qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t *out) {
+  g_last_error.clear();
+  if (!prob || !opt || !out) return fail(QMC_E_INVAL, "NULL argument");
+  *out = nullptr;
+  if (prob->n_sectors < 1 || !prob->sectors)
+    return fail(QMC_E_INVAL, "n_sectors must be >= 1 with a sector array");
+  if (prob->n_orders < 1 || prob->n_orders > QMC_MAX_ORDERS)
+    return fail(QMC_E_INVAL, "n_orders must be in [1, %d]", QMC_MAX_ORDERS);
+  if (prob->max_log < 0 || prob->max_log > QMC_MAX_LOG)
+    return fail(QMC_E_INVAL, "max_log must be in [0, %d]", QMC_MAX_LOG);
+  if (prob->n_integrals < 1) return fail(QMC_E_INVAL, "n_integrals must be >= 1");
+  if (prob->n_mono_rows < 0 || (prob->n_mono_rows > 0 && (!prob->mono_exp || !prob->mono_coef)))
+    return fail(QMC_E_INVAL, "monomial arrays missing");
+  if (opt->m < 2 || opt->m > QMC_MAX_SHIFTS)
+    return fail(QMC_E_INVAL, "m must be in [2, %d]", QMC_MAX_SHIFTS);
+  if (opt->precision != QMC_PREC_FP64 && opt->precision != QMC_PREC_FP32)
+    return fail(QMC_E_INVAL, "unknown precision %d", opt->precision);
+  if (opt->precision == QMC_PREC_FP32)
+    return fail(QMC_E_INVAL, "FP32 integrand form is not available in this build");
+  const int block = opt->block ? opt->block : 256;
+  const int tile = opt->shift_tile ? opt->shift_tile : std::min(opt->m, 8);
+  const int spp = opt->shifts_per_pass ? opt->shifts_per_pass : (tile % 2 == 0 ? 2 : 1);
+  if (!tile_supported(tile, spp, block))
+    return fail(QMC_E_INVAL, "unsupported launch shape: shift_tile %d, shifts_per_pass %d, block %d",
+                tile, spp, block);
+  if (opt->m % tile != 0)
+    return fail(QMC_E_INVAL, "m = %d is not a multiple of shift_tile = %d", opt->m, tile);
+
+  qmc_plan_s *p = new (std::nothrow) qmc_plan_s();
+  if (!p) return fail(QMC_E_NOMEM, "out of host memory");
+  p->S = prob->n_sectors;
+  p->K = prob->n_orders;
+  p->M = prob->max_log;
+  p->n_integrals = prob->n_integrals;
+  p->m = opt->m;
+  p->precision = opt->precision;
+  p->block = block;
+  p->tile = tile;
+  p->spp = spp;
+  p->sec.resize(p->S);
+  p->n_default.resize(p->S);
+  p->a_default.resize(p->S);
+  p->dims.resize(p->S);
+  uint64_t nmax = 0;
+  for (int s = 0; s < p->S; ++s) {
+    const qmc_sector_desc &in = prob->sectors[s];
+    SectorDev &sd = p->sec[s];
+    std::memset(&sd, 0, sizeof sd);
+    const int D = in.d;
+    if (D < 1 || D > QMC_MAX_DIM) {
+      delete p;
+      return fail(QMC_E_INVAL, "sector %d: d = %d outside [1, %d]", s, D, QMC_MAX_DIM);
+    }
+    if (in.integral < 0 || in.integral >= prob->n_integrals) {
+      delete p;
+      return fail(QMC_E_INVAL, "sector %d: integral %d outside [0, %d)", s, in.integral,
+                  prob->n_integrals);
+    }
+    if (in.transform < QMC_TRANSFORM_NONE || in.transform > QMC_TRANSFORM_KOROBOV6) {
+      delete p;
+      return fail(QMC_E_INVAL, "sector %d: unknown transform %d", s, in.transform);
+    }
+    if (in.n_f < 1) {
+      delete p;
+      return fail(QMC_E_INVAL, "sector %d: F needs at least one monomial", s);
+    }
+    if (in.u_pow < -8 || in.u_pow > 8 || in.f_pow2 < -16 || in.f_pow2 > 16) {
+      delete p;
+      return fail(QMC_E_INVAL, "sector %d: exponent of U or F out of range", s);
+    }
+    sd.d = D;
+    sd.transform = in.transform;
+    sd.integral = in.integral;
+    sd.n_orders = p->K;
+    sd.max_log = p->M;
+    p->dims[s] = D;
+    p->d_max = std::max(p->d_max, D);
+    qmc_status st;
+    if (in.n_u == 0) {
+      // U absent: constant 1
+      const size_t base = p->coef.size();
+      p->coef.resize(base + dense_len(D), 0.0);
+      p->coef[base] = 1.0;
+      sd.u_off = (int32_t)base;
+      sd.u_deg = 1;
+    } else if ((st = pack_poly(D, prob, in.u_off, in.n_u, p->coef, &sd.u_off, &sd.u_deg, nullptr,
+                               s, "U")) != QMC_OK) {
+      delete p;
+      return st;
+    }
+    if ((st = pack_poly(D, prob, in.f_off, in.n_f, p->coef, &sd.f_off, &sd.f_deg, &sd.f_abs, s,
+                        "F")) != QMC_OK) {
+      delete p;
+      return st;
+    }
+    int flags = 0;
+    for (int j = 0; j < QMC_MAX_DIM; ++j) {
+      const int32_t e2 = j < D ? in.x_pow2[j] : 0;
+      if (j >= D && in.x_pow2[j] != 0) {
+        delete p;
+        return fail(QMC_E_INVAL, "sector %d: x_pow2[%d] set beyond d", s, j);
+      }
+      if (e2 < -16 || e2 > 16) {
+        delete p;
+        return fail(QMC_E_INVAL, "sector %d: x_pow2[%d] = %d out of range", s, j, e2);
+      }
+      split_pow2(e2, &sd.x_num[j], &sd.x_den[j], &sd.x_half[j]);
+      if (e2 != 0) flags |= SF_XPOW;
+      if (sd.x_half[j] != 0) flags |= SF_HALF;
+      if (sd.x_den[j] != 0 || sd.x_half[j] < 0) flags |= SF_DEN;
+    }
+    sd.u_num = in.u_pow > 0 ? in.u_pow : 0;
+    sd.u_den = in.u_pow < 0 ? -in.u_pow : 0;
+    int32_t fh;
+    split_pow2(in.f_pow2, &sd.f_num, &sd.f_den, &fh);
+    sd.f_half = fh;
+    if (fh != 0) flags |= SF_HALF;
+    if (sd.u_den || sd.f_den || fh < 0) flags |= SF_DEN;
+    if (p->M > 0) flags |= SF_LOG;
+    sd.flags = flags;
+    for (int k = 0; k < QMC_MAX_ORDERS; ++k)
+      for (int mm = 0; mm <= QMC_MAX_LOG; ++mm) {
+        const double c = (k < p->K && mm <= p->M) ? in.logc[k][mm] : 0.0;
+        if (!std::isfinite(c)) {
+          delete p;
+          return fail(QMC_E_INVAL, "sector %d: non-finite logc[%d][%d]", s, k, mm);
+        }
+        sd.logc[k][mm] = c;
+      }
+    p->n_default[s] = in.n;
+    p->a_default[s] = in.a;
+    nmax = std::max<uint64_t>(nmax, in.n);
+  }
+  p->n_max = opt->n_max ? opt->n_max : nmax;
+  if (p->n_max < 2 || p->n_max >= (1ull << 53)) {
+    delete p;
+    return fail(QMC_E_INVAL, "n_max = %llu outside [2, 2^53)", (unsigned long long)p->n_max);
+  }
+  // built-in shifts
+  p->shifts.assign((size_t)p->S * p->m * QMC_MAX_DIM, 0.0);
+  for (int s = 0; s < p->S; ++s)
+    for (int l = 0; l < p->m; ++l)
+      for (int j = 0; j < QMC_MAX_DIM; ++j) {
+        const uint64_t c = ((uint64_t)s << 32) | ((uint64_t)l << 8) | (uint64_t)j;
+        p->shifts[((size_t)s * p->m + l) * QMC_MAX_DIM + j] =
+            (double)(splitmix64(opt->seed, c) >> 11) * 0x1.0p-53;
+      }
+  layout(p);
+  p->lat.resize(p->S);
+  p->begin.resize(p->S + 1);
+  *out = p;
+  return QMC_OK;
+}
+
+size_t qmc_workspace_bytes(qmc_plan_t p) { return p ? p->total : 0; }
+
+qmc_status qmc_bind_workspace(qmc_plan_t p, void *dev, size_t bytes, void *stream) {
+  g_last_error.clear();
+  if (!p || !dev) return fail(QMC_E_INVAL, "NULL plan or workspace");
+  if (((uintptr_t)dev & 255) != 0) return fail(QMC_E_INVAL, "workspace not 256-byte aligned");
+  if (bytes < p->total)
+    return fail(QMC_E_NOMEM, "workspace of %zu bytes, %zu needed", bytes, p->total);
+  p->ws = (char *)dev;
+  p->ws_bytes = bytes;
+  p->lat_valid = false;
+  hipStream_t st = (hipStream_t)stream;
+  int e;
+  if ((e = hipMemcpyAsync(p->ws + p->off_sec, p->sec.data(), sizeof(SectorDev) * p->S,
+                          hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "upload sectors");
+  if (!p->coef.empty() &&
+      (e = hipMemcpyAsync(p->ws + p->off_coef, p->coef.data(), sizeof(double) * p->coef.size(),
+                          hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "upload coefficients");
+  if ((e = hipMemcpyAsync(p->ws + p->off_shift, p->shifts.data(),
+                          sizeof(double) * p->shifts.size(), hipMemcpyHostToDevice, st)) !=
+      hipSuccess)
+    return hip_fail(e, "upload shifts");
+  if ((e = launch_status_reset((int32_t *)(p->ws + p->off_status), stream)) != hipSuccess)
+    return hip_fail(e, "status reset");
+  return QMC_OK;
+}
+
+qmc_status qmc_set_shifts(qmc_plan_t p, const double *shifts, void *stream) {
+  g_last_error.clear();
+  if (!p || !shifts) return fail(QMC_E_INVAL, "NULL argument");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  for (int s = 0; s < p->S; ++s)
+    for (int l = 0; l < p->m; ++l)
+      for (int j = 0; j < p->dims[s]; ++j) {
+        const double v = shifts[((size_t)s * p->m + l) * QMC_MAX_DIM + j];
+        if (!(v >= 0.0 && v < 1.0))
+          return fail(QMC_E_INVAL, "shift[%d][%d][%d] = %g outside [0, 1)", s, l, j, v);
+      }
+  for (int s = 0; s < p->S; ++s)
+    for (int l = 0; l < p->m; ++l)
+      for (int j = 0; j < QMC_MAX_DIM; ++j) {
+        const size_t at = ((size_t)s * p->m + l) * QMC_MAX_DIM + j;
+        p->shifts[at] = j < p->dims[s] ? shifts[at] : 0.0;
+      }
+  int e = hipMemcpyAsync(p->ws + p->off_shift, p->shifts.data(), sizeof(double) * p->shifts.size(),
+                         hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "upload shifts");
+  return QMC_OK;
+}
+
+qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_in, void *stream,
+                         double *dev_q, double *dev_mean, double *dev_err) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  if (!dev_mean || !dev_err) return fail(QMC_E_INVAL, "dev_mean and dev_err are required");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  const int tiles = p->m / p->tile;
+  // lattice table
+  __int128 total = 0;
+  for (int s = 0; s < p->S; ++s) {
+    const uint64_t n = n_in ? n_in[s] : p->n_default[s];
+    if (n < 2 || n > p->n_max || n >= (1ull << 53))
+      return fail(QMC_E_INVAL, "sector %d: n = %llu outside [2, n_max = %llu]", s,
+                  (unsigned long long)n, (unsigned long long)p->n_max);
+    const uint64_t a = (a_in ? a_in[s] : p->a_default[s]) % n;
+    LatticeDev &L = p->lat[s];
+    std::memset(&L, 0, sizeof L);
+    L.n = n;
+    L.n_d = (double)n;
+    L.inv_n = 1.0 / (double)n;
+    uint64_t z = 1 % n;
+    for (int j = 0; j < QMC_MAX_DIM; ++j) {
+      if (j < p->dims[s]) {
+        if (gcd_u64(z, n) != 1)
+          return fail(QMC_E_INVAL, "sector %d: z_%d = a^%d mod n = %llu shares a factor with n = %llu",
+                      s, j + 1, j, (unsigned long long)z, (unsigned long long)n);
+        L.z[j] = z;
+        L.dz[j] = mulmod_host((uint64_t)p->block % n, z, n);
+      }
+      z = mulmod_host(z, a, n);
+    }
+    total += (__int128)n * tiles;
+  }
+  // points per thread: enough that the launch has about kTargetBlocks workgroups
+  const __int128 per_block = (__int128)kTargetBlocks * p->block;
+  int64_t ppt = (int64_t)((total + per_block - 1) / per_block);
+  if (ppt < 1) ppt = 1;
+  const int64_t chunk = ppt * p->block;
+  int64_t b = 0;
+  for (int s = 0; s < p->S; ++s) {
+    LatticeDev &L = p->lat[s];
+    L.chunk = chunk;
+    L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
+    L.block_begin = b;
+    p->begin[s] = b;
+    b += (int64_t)L.n_chunks * tiles;
+  }
+  p->begin[p->S] = b;
+  if (b > p->max_blocks)
+    return fail(QMC_E_NOMEM, "launch needs %lld workgroups, workspace holds %lld", (long long)b,
+                (long long)p->max_blocks);
+  hipStream_t st = (hipStream_t)stream;
+  int e;
+  const bool same = p->lat_valid && p->lat_uploaded.size() == p->lat.size() &&
+                    std::memcmp(p->lat_uploaded.data(), p->lat.data(),
+                                sizeof(LatticeDev) * p->lat.size()) == 0;
+  if (!same) {
+    if ((e = hipMemcpyAsync(p->ws + p->off_lat, p->lat.data(), sizeof(LatticeDev) * p->S,
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+      return hip_fail(e, "upload lattice table");
+    if ((e = hipMemcpyAsync(p->ws + p->off_begin, p->begin.data(), sizeof(int64_t) * (p->S + 1),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+      return hip_fail(e, "upload workgroup table");
+    p->lat_uploaded = p->lat;
+    p->lat_valid = true;
+  }
+  LaunchArgs la;
+  std::memset(&la, 0, sizeof la);
+  la.sectors = (const SectorDev *)(p->ws + p->off_sec);
+  la.coef = (const double *)(p->ws + p->off_coef);
+  la.shifts = (const double *)(p->ws + p->off_shift);
+  la.lat = (const LatticeDev *)(p->ws + p->off_lat);
+  la.block_begin = (const int64_t *)(p->ws + p->off_begin);
+  la.partial = (double *)(p->ws + p->off_partial);
+  la.q = dev_q ? dev_q : (double *)(p->ws + p->off_q);
+  la.mean = dev_mean;
+  la.err = dev_err;
+  la.status = (int32_t *)(p->ws + p->off_status);
+  la.n_sectors = p->S;
+  la.m = p->m;
+  la.K = p->K;
+  la.shift_tile = p->tile;
+  la.shifts_per_pass = p->spp;
+  la.block = p->block;
+  la.total_blocks = b;
+  la.d_max = p->d_max;
+  la.precision = p->precision;
+  if (p->timing) {
+    if (p->ev_used + 2 > p->ev.size()) {
+      if (p->ev.size() >= 2 * 4096) return fail(QMC_E_STATE, "timing record full; re-enable timing");
+      for (int t = 0; t < 2; ++t) {
+        hipEvent_t h;
+        if ((e = hipEventCreate(&h)) != hipSuccess) return hip_fail(e, "create timing event");
+        p->ev.push_back(h);
+      }
+    }
+    la.ev_start = p->ev[p->ev_used];
+    la.ev_stop = p->ev[p->ev_used + 1];
+    p->ev_used += 2;
+  }
+  if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
+  if ((e = launch_integrate(la, stream)) != hipSuccess) return hip_fail(e, "integrate launch");
+  return QMC_OK;
+}
+
+qmc_status qmc_query_status(qmc_plan_t p, void *stream, int32_t *sector, int32_t *shift,
+                            int32_t *order) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  int32_t code = 0;
+  hipStream_t st = (hipStream_t)stream;
+  int e = hipMemcpyAsync(&code, p->ws + p->off_status, sizeof code, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "read status");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
+  if (code == INT32_MAX) return QMC_OK;
+  const int ko = code % QMC_MAX_ORDERS;
+  const int sl = code / QMC_MAX_ORDERS;
+  if (sector) *sector = sl / p->m;
+  if (shift) *shift = sl % p->m;
+  if (order) *order = ko;
+  return fail(QMC_E_NONFINITE, "non-finite sum: sector %d, shift %d, order %d", sl / p->m,
+              sl % p->m, ko);
+}
+
+qmc_status qmc_korobov_p2(qmc_plan_t p, uint64_t n, int32_t d, const uint64_t *cand,
+                          int32_t n_cand, void *stream, double *dev_p2) {
+  g_last_error.clear();
+  if (!p || !cand || !dev_p2) return fail(QMC_E_INVAL, "NULL argument");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (n < 2 || n >= (1ull << 53)) return fail(QMC_E_INVAL, "n = %llu outside [2, 2^53)",
+                                              (unsigned long long)n);
+  if (d < 1 || d > QMC_MAX_DIM) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  if (n_cand < 1 || n_cand > kP2MaxCand)
+    return fail(QMC_E_INVAL, "n_cand = %d outside [1, %d]", n_cand, kP2MaxCand);
+  for (int32_t c = 0; c < n_cand; ++c)
+    if (cand[c] < 1 || cand[c] >= n)
+      return fail(QMC_E_INVAL, "candidate %d: a = %llu outside [1, n)", c,
+                  (unsigned long long)cand[c]);
+  // workgroups per candidate: about 128 points per thread, within the partial buffer
+  int64_t chunks = (int64_t)((n + 256 * 128 - 1) / (256 * 128));
+  const int64_t cap = (int64_t)(kP2PartialDoubles / 2) / n_cand;
+  chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, std::min<int64_t>(cap, 65535)));
+  hipStream_t st = (hipStream_t)stream;
+  int e = hipMemcpyAsync(p->ws + p->off_p2cand, cand, sizeof(uint64_t) * n_cand,
+                         hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "upload candidates");
+  e = launch_korobov_p2(n, d, (const uint64_t *)(p->ws + p->off_p2cand), n_cand, (int32_t)chunks,
+                        (double *)(p->ws + p->off_p2part), dev_p2, stream);
+  if (e != hipSuccess) return hip_fail(e, "P2 launch");
+  return QMC_OK;
+}
+
+qmc_status qmc_korobov_search(qmc_plan_t p, uint64_t n, int32_t d, const uint64_t *cand,
+                              int32_t n_cand, void *stream, uint64_t *a_out, double *p2_out) {
+  if (!a_out) return fail(QMC_E_INVAL, "NULL a_out");
+  if (!p || !p->ws) return fail(p ? QMC_E_STATE : QMC_E_INVAL, "plan not bound");
+  double *dev_vals = (double *)(p->ws + p->off_p2vals);
+  qmc_status st = qmc_korobov_p2(p, n, d, cand, n_cand, stream, dev_vals);
+  if (st != QMC_OK) return st;
+  std::vector<double> v(n_cand);
+  hipStream_t hs = (hipStream_t)stream;
+  int e = hipMemcpyAsync(v.data(), dev_vals, sizeof(double) * n_cand, hipMemcpyDeviceToHost, hs);
+  if (e != hipSuccess) return hip_fail(e, "read P2 values");
+  if ((e = hipStreamSynchronize(hs)) != hipSuccess) return hip_fail(e, "synchronize");
+  double vmin = v[0];
+  for (double x : v) vmin = std::min(vmin, x);
+  uint64_t best = 0;
+  double bestv = 0.0;
+  bool have = false;
+  for (int32_t c = 0; c < n_cand; ++c)
+    if (v[c] <= vmin * (1.0 + 1e-12) && (!have || cand[c] < best)) {
+      best = cand[c];
+      bestv = v[c];
+      have = true;
+    }
+  *a_out = best;
+  if (p2_out) *p2_out = bestv;
+  return QMC_OK;
+}
+
+qmc_status qmc_enable_timing(qmc_plan_t p, int32_t enable) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  return QMC_OK;
+}
+
+qmc_status qmc_read_timing(qmc_plan_t p, double *ms_total, int32_t *launches) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  double tot = 0.0;
+  for (size_t t = 0; t + 1 < p->ev_used; t += 2) {
+    int e = hipEventSynchronize(p->ev[t + 1]);
+    if (e != hipSuccess) return hip_fail(e, "synchronize timing event");
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, p->ev[t], p->ev[t + 1])) != hipSuccess)
+      return hip_fail(e, "elapsed time");
+    tot += ms;
+  }
+  if (ms_total) *ms_total = tot;
+  if (launches) *launches = (int32_t)(p->ev_used / 2);
+  return QMC_OK;
+}
+
+qmc_status qmc_lattice_points(uint64_t n, int32_t d, uint64_t a, const double *shift,
+                              uint64_t i0, uint64_t count, void *stream, double *dev_y) {
+  g_last_error.clear();
+  if (!shift || !dev_y) return fail(QMC_E_INVAL, "NULL argument");
+  if (n < 2 || n >= (1ull << 53)) return fail(QMC_E_INVAL, "n = %llu outside [2, 2^53)",
+                                              (unsigned long long)n);
+  if (d < 1 || d > QMC_MAX_DIM) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  if (count == 0) return QMC_OK;
+  if (i0 >= n || count > n - i0) return fail(QMC_E_INVAL, "points [%llu, %llu) outside [0, n)",
+                                             (unsigned long long)i0,
+                                             (unsigned long long)(i0 + count));
+  PointsArgs pa;
+  std::memset(&pa, 0, sizeof pa);
+  pa.n = n;
+  pa.n_d = (double)n;
+  pa.inv_n = 1.0 / (double)n;
+  pa.d = d;
+  pa.i0 = i0;
+  pa.count = count;
+  pa.out = dev_y;
+  pa.steps = 16;
+  const uint64_t am = a % n;
+  uint64_t z = 1 % n;
+  for (int j = 0; j < d; ++j) {
+    if (gcd_u64(z, n) != 1)
+      return fail(QMC_E_INVAL, "z_%d = %llu shares a factor with n", j + 1, (unsigned long long)z);
+    if (!(shift[j] >= 0.0 && shift[j] < 1.0))
+      return fail(QMC_E_INVAL, "shift[%d] = %g outside [0, 1)", j, shift[j]);
+    pa.z[j] = z;
+    pa.dz[j] = mulmod_host(256 % n, z, n);
+    pa.delta[j] = shift[j];
+    z = mulmod_host(z, am, n);
+  }
+  const uint64_t per = 256ull * pa.steps;
+  const uint64_t grid = (count + per - 1) / per;
+  if (grid > 0x7fffffffull) return fail(QMC_E_INVAL, "too many points for one call");
+  int e = launch_points(pa, (unsigned)grid, stream);
+  if (e != hipSuccess) return hip_fail(e, "points launch");
+  return QMC_OK;
+}
+
+void qmc_plan_free(qmc_plan_t p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// qmc_internal.h -- device-side records shared by the host planner and the gfx950
+// kernels of the lattice QMC library.  Not part of the C ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/qmcamp.h"
+
+namespace qmc {
+
+// Monomial table of one polynomial in the dense nested-Horner layout for total
+// degree <= 3 in D variables:
+//   P(x) = c0 + sum_j x_j (c_j + sum_{k>=j} x_k (c_jk + sum_{l>=k} c_jkl x_l)),
+// stored as c0, then for each j: c_j, then for each k >= j: c_jk followed by the
+// c_jkl for l = k .. D-1.  Length C(D+3, 3).
+constexpr int dense_len(int D) { return (D + 1) * (D + 2) * (D + 3) / 6; }
+
+enum : int32_t {
+  SF_XPOW = 1,      // some x_j has a non-zero exponent
+  SF_HALF = 2,      // a half-integer exponent occurs (one square root per sample)
+  SF_DEN = 4,       // a negative exponent occurs (one division per sample)
+  SF_LOG = 8,       // max_log > 0: log F is needed
+};
+
+// Static per-sector record (plan time).  Read with uniform (scalar) loads.
+struct alignas(16) SectorDev {
+  int32_t d, transform, u_deg, f_deg;
+  int32_t u_off, f_off;            // offsets of the dense tables in the coefficient array
+  int32_t flags, max_log;
+  int32_t u_num, u_den, f_num, f_den;   // integer parts of the exponents of U and F
+  int32_t f_half, n_orders, integral, pad0;  // f_half: +1 numerator, -1 denominator, 0 none
+  int32_t x_num[QMC_MAX_DIM];
+  int32_t x_den[QMC_MAX_DIM];
+  int32_t x_half[QMC_MAX_DIM];     // +1 / -1 / 0 as f_half
+  double f_abs;                    // sum of |coefficients| of F (bound of sum |c m(x)| on the cube)
+  double pad1;
+  double logc[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
+};
+
+// Per-call lattice record of a sector.
+struct alignas(16) LatticeDev {
+  uint64_t n;
+  double n_d;                      // (double) n, exact (n < 2^53)
+  double inv_n;                    // RN(1/n)
+  int64_t block_begin;             // first workgroup of this sector in the launch
+  uint64_t z[QMC_MAX_DIM];         // generating vector
+  uint64_t dz[QMC_MAX_DIM];        // (workgroup size * z_j) mod n: lattice stride of a thread
+  int64_t chunk;                   // lattice points per workgroup
+  int32_t n_chunks;                // workgroups per shift tile
+  int32_t pad;
+};
+
+// Workgroup partials: per (shift in tile, order): (sum, compensation).
+// Status word: first non-finite (sector, shift, order), linearised, or INT32_MAX.
+
+// ---------------------------------------------------------------- launchers
+struct LaunchArgs {
+  const SectorDev *sectors;
+  const double *coef;
+  const double *shifts;            // [S][m][QMC_MAX_DIM]
+  const LatticeDev *lat;
+  const int64_t *block_begin;      // [S+1]
+  double *partial;                 // [blocks][tile][K][2]
+  double *q;                       // [S][m][K] (always written; workspace if caller passes NULL)
+  double *mean, *err;              // [S][K]
+  int32_t *status;
+  int32_t n_sectors, m, K, shift_tile, block, shifts_per_pass;
+  int64_t total_blocks;
+  int32_t d_max, precision;
+  void *ev_start, *ev_stop;        // optional hipEvent_t pair recorded around the main kernel
+};
+
+struct PointsArgs {
+  uint64_t n;
+  double n_d, inv_n;
+  uint64_t z[QMC_MAX_DIM], dz[QMC_MAX_DIM];
+  double delta[QMC_MAX_DIM];
+  int32_t d;
+  uint32_t steps;
+  uint64_t i0, count;
+  double *out;
+};
+
+// Returns a hipError_t value (0 = success).
+int launch_points(const PointsArgs &pa, unsigned grid, void *stream);
+int launch_integrate(const LaunchArgs &a, void *stream);
+int launch_status_reset(int32_t *status, void *stream);
+int launch_korobov_p2(uint64_t n, int32_t d, const uint64_t *dev_cand, int32_t n_cand,
+                      int32_t chunks, double *dev_partial, double *dev_p2, void *stream);
+
+// Launch shapes compiled into the library: shifts per workgroup (1..16), shifts per
+// pass (1, 2, 4; divides the tile), workgroup size (64..256, multiple of 64).
+bool tile_supported(int shift_tile, int shifts_per_pass, int block);
+
+}  // namespace qmc

@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: lattice points bit-exact; per-shift sums within 1e-12 relative, measured against
+max(|Q_oracle|, (1/n) sum |W f|) so that nearly cancelling sums are judged on their
+scale; means within the same bar; the shift standard error within 1e-9 relative (it
+is a difference of nearly equal numbers).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "one_loop_korobov.json")
+
+
+@pytest.fixture(scope="module")
+def qmc():
+    import __graft_entry__ as g
+    g._ensure_built()
+    import torch
+    import paper_2305_19768_amd as q
+    torch.cuda.set_device(0)
+    return q
+
+
+def _check_sums(q_gpu, Qo, So, tol=TOL, what=""):
+    scale = np.maximum(np.abs(Qo), So)
+    dev = np.abs(q_gpu - Qo)
+    ok = dev <= tol * scale
+    assert ok.all(), (f"{what}: max rel dev {np.max(dev / np.maximum(scale, 1e-300)):.3e} at "
+                      f"{np.argwhere(~ok)[:5].tolist()}")
+
+
+def _parity(qmc, prob, threads=8, **plan_kw):
+    plan = qmc.Plan(prob, **plan_kw)
+    q, mean, err = plan.integrate()
+    q, mean, err = q.cpu().numpy(), mean.cpu().numpy(), err.cpu().numpy()
+    for s, sec in enumerate(prob.sectors):
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], threads=threads)
+        print(f"sector {s}: d={sec.d} n={sec.n} K={sec.K} transform={sec.transform}", flush=True)
+        _check_sums(q[s], Qo, So, what=f"sector {s}")
+        mo, eo = oracle.estimate(Qo)
+        sc = np.maximum(np.abs(mo), So.mean(axis=0))
+        assert np.all(np.abs(mean[s] - mo) <= TOL * sc)
+        assert np.all(np.abs(err[s] - eo) <= 1e-9 * eo + TOL * sc)
+    return plan, q, mean, err
+
+
+# ------------------------------------------------------------------ lattice
+
+@pytest.mark.parametrize("n,a,d,i0,count", [
+    (65521, 14276, 3, 0, 65521),            # the one-loop sector's lattice, every point
+    (1009, 317, 8, 0, 1009),
+    (2, 1, 1, 0, 2),
+    (2147483647, 48271, 6, 2147483647 - 300000, 300000),   # ragged end of a 2^31-1 lattice
+    ((1 << 40) + 15, 1234567891, 4, 123456789, 20000),       # 128-bit products
+    (9007199254740881, 9007199254740000, 2, 9007199254740881 - 5000, 5000),   # n near 2^53
+])
+def test_lattice_points_bit_exact(qmc, n, a, d, i0, count):
+    rng = np.random.default_rng(n % 1000)
+    shift = W.uniform_shifts(rng, 1, d)[0]
+    y = qmc.lattice_points(n, a, shift, i0=i0, count=count).cpu().numpy()
+    z = oracle.korobov_vector(n, a, d)
+    yo = oracle.points(n, z, shift, i0=i0, count=count)
+    assert y.shape == yo.shape
+    assert np.array_equal(y.view(np.uint64), yo.view(np.uint64))
+
+
+# ---------------------------------------------------------- integration parity
+
+def test_one_loop_sector_with_p2_lattice(qmc):
+    gold = json.load(open(GOLDEN))
+    prob = W.one_loop_sector(seed=0, a=gold["a"])
+    assert prob.sectors[0].n == gold["n"]
+    _parity(qmc, prob)
+
+
+def test_two_loop_integral_parity(qmc):
+    prob = W.two_loop_integral(seed=0, n_scale=0.01)   # 40 sectors, n in [1e3, 1e5]
+    _parity(qmc, prob)
+
+
+@pytest.mark.parametrize("transform", ["none", "baker", "korobov1", "korobov2", "korobov3",
+                                       "korobov4", "korobov5", "korobov6"])
+def test_transforms(qmc, transform):
+    # half-integer and negative exponents; F > 0 on the closed cube so 'none' is finite
+    sec = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0)), (0.25, (0, 1, 1))],
+                          [(0.3, (0, 0, 0)), (0.7, (1, 1, 0)), (0.2, (0, 0, 2)), (0.4, (1, 0, 1))],
+                          x_pow2=[1, 0, 3], u_pow=-2, f_pow2=-3,
+                          logc=[[1, 0, 0], [0.5, -1, 0], [0, 0.25, 2]], n=20011, a=5467,
+                          transform=transform)
+    _parity(qmc, W.single_problem(sec, m=8, seed=1))
+
+
+@pytest.mark.parametrize("d,K,M", [(1, 1, 0), (2, 2, 1), (5, 3, 2), (7, 4, 4), (8, 2, 3),
+                                   (8, 4, 0)])
+def test_dimensions_orders_logs(qmc, d, K, M):
+    rng = np.random.default_rng(100 * d + 10 * K + M)
+    ue, uc = W.random_polynomial(rng, d, 5, 2)
+    fe, fc = W.random_polynomial(rng, d, 12, 3)
+    logc = rng.uniform(-1, 1, size=(K, M + 1))
+    sec = W.Sector(d=d, u_exp=ue, u_coef=uc, f_exp=fe, f_coef=fc,
+                   x_pow2=rng.integers(0, 3, size=d).astype(np.int32), u_pow=1, f_pow2=-4,
+                   logc=logc, n=10007, a=int(rng.integers(2, 10005)), transform="korobov3")
+    _parity(qmc, W.single_problem(sec, m=4, seed=d))
+
+
+@pytest.mark.parametrize("block,tile,spp,m", [(256, 8, 2, 16), (64, 1, 1, 2), (128, 4, 4, 8),
+                                              (192, 16, 4, 32), (256, 3, 1, 6), (64, 2, 2, 4)])
+def test_launch_shapes_agree(qmc, block, tile, spp, m):
+    prob = W.two_loop_integral(seed=3, n_sectors=6, n_scale=0.003, m=m)
+    _parity(qmc, prob, block=block, shift_tile=tile, shifts_per_pass=spp)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 63, 64, 65, 255, 257, 4099])
+def test_small_and_ragged_lattices(qmc, n):
+    a = 1 if n < 4 else next(c for c in range(2, n) if math.gcd(c, n) == 1)
+    prob = W.one_loop_sector(seed=2, n=n, m=4, a=a)
+    _parity(qmc, prob)
+
+
+def test_deterministic_and_seeded_shifts(qmc):
+    prob = W.two_loop_integral(seed=5, n_sectors=8, n_scale=0.01, m=8)
+    plan = qmc.Plan(prob, seed=1234, use_problem_shifts=False)
+    q1 = plan.integrate()[0].cpu().numpy()
+    q2 = plan.integrate()[0].cpu().numpy()
+    assert np.array_equal(q1.view(np.uint64), q2.view(np.uint64))
+    for s in (0, 5):
+        sh = oracle.seeded_shifts(1234, s, 8, prob.sectors[s].d)
+        Qo, So = oracle.sector_sums(prob.sectors[s], sh, threads=8)
+        _check_sums(q1[s], Qo, So, what=f"seeded sector {s}")
+
+
+def test_lattice_size_override(qmc):
+    prob = W.two_loop_integral(seed=4, n_sectors=4, n_scale=0.01, m=4)
+    plan = qmc.Plan(prob, n_max=50021)
+    n = [50021, 10007, 2003, 20011]
+    a = [1234, 4567, 89, 9999]
+    q = plan.integrate(n=n, a=a)[0].cpu().numpy()
+    for s, sec in enumerate(prob.sectors):
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], n=n[s], a=a[s], threads=4)
+        _check_sums(q[s], Qo, So)
+
+
+def test_nonfinite_sum_is_reported(qmc):
+    sec = W.custom_sector(2, [], [(1.0, (1, 0)), (1.0, (0, 1))], f_pow2=-2, n=101, a=7,
+                          transform="none")
+    prob = W.single_problem(sec, m=4)
+    prob.shifts[0][2] = 0.0          # shift 2 hits x = 0 where F = 0
+    plan = qmc.Plan(prob)
+    with pytest.raises(qmc.QmcError, match="sector 0, shift 2, order 0"):
+        plan.integrate()
+
+
+def test_invalid_lattice_rejected_before_launch(qmc):
+    prob = W.one_loop_sector(n=1009)
+    plan = qmc.Plan(prob)
+    with pytest.raises(qmc.QmcError, match="QMC_E_INVAL"):
+        plan.integrate(n=[1000], a=[10])          # gcd(10, 1000) != 1
+    with pytest.raises(qmc.QmcError, match="n_max"):
+        plan.integrate(n=[2003], a=[5])
+
+
+# ------------------------------------------------------------------- P_2
+
+def test_p2_values_match_oracle(qmc):
+    plan = qmc.Plan(W.one_loop_sector(n=1009))
+    rng = np.random.default_rng(0)
+    for n, d in [(1009, 3), (65521, 5), (100003, 8), (2, 1)]:
+        cands = [1] if n == 2 else [int(c) for c in rng.integers(1, n, size=6)]
+        g = plan.korobov_p2(n, d, cands).cpu().numpy()
+        o = np.array([oracle.p2(n, oracle.korobov_vector(n, c, d)) for c in cands])
+        assert np.allclose(g, o, rtol=1e-12, atol=1e-15)
+
+
+def test_p2_exhaustive_search_reproduces_golden(qmc):
+    gold = json.load(open(GOLDEN))
+    plan = qmc.Plan(W.one_loop_sector(n=1009))
+    n = gold["n"]
+    a, p2 = plan.korobov_search(n, gold["d"], list(range(1, (n - 1) // 2 + 1)))
+    assert a == gold["a"]
+    assert p2 == pytest.approx(gold["p2"], rel=1e-12)
+
+
+# --------------------------------------------------- full-size, sampled outputs
+
+def test_full_size_two_loop_integral_sampled(qmc):
+    """The benchmark workload at full size (40 sectors, n up to 1e7, 32 shifts): the
+    three smallest sectors are checked against the oracle on two shifts each, and every
+    sector's estimate is finite with a positive error."""
+    prob = W.two_loop_integral(seed=0)
+    plan = qmc.Plan(prob)
+    qg, mean, err = plan.integrate()
+    qg, mean, err = qg.cpu().numpy(), mean.cpu().numpy(), err.cpu().numpy()
+    assert np.all(np.isfinite(qg)) and np.all(err > 0)
+    order = np.argsort([s.n for s in prob.sectors])
+    for s in order[:3]:
+        sec = prob.sectors[s]
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], shift_range=(0, 2), threads=2)
+        _check_sums(qg[s, :2], Qo, So, what=f"full-size sector {s} (n={sec.n})")
+    # the spread across shifts is what the error estimate reports
+    assert np.allclose(err, qg.std(axis=1, ddof=1) / math.sqrt(prob.m), rtol=1e-9)

@@ -162,6 +162,8 @@ def random_polynomial(rng: np.random.Generator, d: int, count: int, deg: int,
 
 
 def _korobov_candidates(rng: np.random.Generator, n: int, count: int) -> np.ndarray:
+    if n < 4:
+        return np.ones(count, dtype=np.uint64)
     return rng.integers(2, n - 1, size=count, dtype=np.int64).astype(np.uint64)
 
 
