@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = library default)")
+    ap.add_argument("--tile", type=int, default=0, help="shifts per workgroup (0 = default)")
+    ap.add_argument("--spp", type=int, default=0, help="shifts per pass (0 = default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -134,7 +137,7 @@ def main():
     torch.cuda.set_device(0)
     prob = workloads.two_loop_integral(seed=0)
     t0 = time.perf_counter()
-    plan = qmc.Plan(prob)
+    plan = qmc.Plan(prob, block=args.block, shift_tile=args.tile, shifts_per_pass=args.spp)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     S, m, K = plan.S, plan.m, plan.K
@@ -184,11 +187,13 @@ def main():
                    "lattice_points_per_step": int(sum(s.n for s in prob.sectors))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "qmc_integrate_kernel<3,2>",
+                     "traffic": traffic, "kernel": "qmc_integrate_kernel<D,3,S> (d = 4, 5, 6)",
                      "kernel_ms": kernel_ms / max(launches, 1),
                      "algorithmic_flops_per_launch": flops_launch,
                      "flops_per_eval": flops_launch / evals},
         "plan_seconds": plan_s,
+        "launch": {"block": args.block or 256, "shift_tile": args.tile or 16,
+                   "shifts_per_pass": args.spp or 0},
     }
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

@@ -77,12 +77,13 @@ struct qmc_plan_s {
   std::vector<double> shifts;          // [S][m][QMC_MAX_DIM]
   std::vector<uint64_t> n_default, a_default;
   std::vector<int32_t> dims;
+  std::vector<int32_t> order;          // sectors in workgroup order: by dimension, then index
   // options
   int32_t m = 0, precision = 0, block = 256, tile = 8, spp = 2;
   uint64_t n_max = 0;
   // workspace layout (byte offsets)
   size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
-         off_status = 0, off_partial = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
+         off_status = 0, off_partial = 0, off_order = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
          total = 0;
   int64_t max_blocks = 0;
   char *ws = nullptr;
@@ -115,6 +116,7 @@ static void layout(qmc_plan_s *p) {
   p->off_shift = take(sizeof(double) * p->shifts.size());
   p->off_lat = take(sizeof(LatticeDev) * p->S);
   p->off_begin = take(sizeof(int64_t) * (p->S + 1));
+  p->off_order = take(sizeof(int32_t) * p->S);
   p->off_q = take(sizeof(double) * (size_t)p->S * p->m * p->K);
   p->off_status = take(256);
   p->off_partial = take(sizeof(double) * 2 * (size_t)p->max_blocks * p->tile * p->K);
@@ -215,7 +217,10 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
   if (opt->precision == QMC_PREC_FP32)
     return fail(QMC_E_INVAL, "FP32 integrand form is not available in this build");
   const int block = opt->block ? opt->block : 256;
-  const int tile = opt->shift_tile ? opt->shift_tile : std::min(opt->m, 8);
+  int tile = opt->shift_tile;
+  if (!tile)  // largest power of two <= 16 dividing m
+    for (tile = 16; tile > 1 && opt->m % tile != 0; tile >>= 1) {
+    }
   const int spp = opt->shifts_per_pass ? opt->shifts_per_pass : (tile % 2 == 0 ? 2 : 1);
   if (!tile_supported(tile, spp, block))
     return fail(QMC_E_INVAL, "unsupported launch shape: shift_tile %d, shifts_per_pass %d, block %d",
@@ -267,6 +272,7 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
     }
     sd.d = D;
     sd.transform = in.transform;
+    sd.w_scale = std::pow(140.0, D);   // exact: 140^8 < 2^53 * 2^16
     sd.integral = in.integral;
     sd.n_orders = p->K;
     sd.max_log = p->M;
@@ -314,6 +320,9 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
     if (fh != 0) flags |= SF_HALF;
     if (sd.u_den || sd.f_den || fh < 0) flags |= SF_DEN;
     if (p->M > 0) flags |= SF_LOG;
+    if (in.transform == QMC_TRANSFORM_KOROBOV3 && !(flags & (SF_XPOW | SF_HALF)) &&
+        p->M <= p->K - 1)
+      flags |= SF_FAST;
     sd.flags = flags;
     for (int k = 0; k < QMC_MAX_ORDERS; ++k)
       for (int mm = 0; mm <= QMC_MAX_LOG; ++mm) {
@@ -342,6 +351,10 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
         p->shifts[((size_t)s * p->m + l) * QMC_MAX_DIM + j] =
             (double)(splitmix64(opt->seed, c) >> 11) * 0x1.0p-53;
       }
+  p->order.resize(p->S);
+  for (int s = 0; s < p->S; ++s) p->order[s] = s;
+  std::stable_sort(p->order.begin(), p->order.end(),
+                   [&](int32_t x, int32_t y) { return p->dims[x] < p->dims[y]; });
   layout(p);
   p->lat.resize(p->S);
   p->begin.resize(p->S + 1);
@@ -373,6 +386,9 @@ qmc_status qmc_bind_workspace(qmc_plan_t p, void *dev, size_t bytes, void *strea
                           sizeof(double) * p->shifts.size(), hipMemcpyHostToDevice, st)) !=
       hipSuccess)
     return hip_fail(e, "upload shifts");
+  if ((e = hipMemcpyAsync(p->ws + p->off_order, p->order.data(), sizeof(int32_t) * p->S,
+                          hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "upload sector order");
   if ((e = launch_status_reset((int32_t *)(p->ws + p->off_status), stream)) != hipSuccess)
     return hip_fail(e, "status reset");
   return QMC_OK;
@@ -429,6 +445,7 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
                       s, j + 1, j, (unsigned long long)z, (unsigned long long)n);
         L.z[j] = z;
         L.dz[j] = mulmod_host((uint64_t)p->block % n, z, n);
+        L.ndz[j] = (double)(n - L.dz[j]);
       }
       z = mulmod_host(z, a, n);
     }
@@ -440,13 +457,25 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
   if (ppt < 1) ppt = 1;
   const int64_t chunk = ppt * p->block;
   int64_t b = 0;
-  for (int s = 0; s < p->S; ++s) {
+  DimLaunch dl[QMC_MAX_DIM];
+  int n_dl = 0;
+  for (int t = 0; t < p->S; ++t) {
+    const int s = p->order[t];
     LatticeDev &L = p->lat[s];
     L.chunk = chunk;
     L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
     L.block_begin = b;
-    p->begin[s] = b;
-    b += (int64_t)L.n_chunks * tiles;
+    p->begin[t] = b;
+    if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s]) {
+      dl[n_dl].d = p->dims[s];
+      dl[n_dl].base = b;
+      dl[n_dl].blocks = 0;
+      dl[n_dl].pad = 0;
+      ++n_dl;
+    }
+    const int64_t nb = (int64_t)L.n_chunks * tiles;
+    dl[n_dl - 1].blocks += nb;
+    b += nb;
   }
   p->begin[p->S] = b;
   if (b > p->max_blocks)
@@ -474,6 +503,9 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
   la.shifts = (const double *)(p->ws + p->off_shift);
   la.lat = (const LatticeDev *)(p->ws + p->off_lat);
   la.block_begin = (const int64_t *)(p->ws + p->off_begin);
+  la.order = (const int32_t *)(p->ws + p->off_order);
+  la.n_dim_launches = n_dl;
+  for (int t = 0; t < n_dl; ++t) la.dims[t] = dl[t];
   la.partial = (double *)(p->ws + p->off_partial);
   la.q = dev_q ? dev_q : (double *)(p->ws + p->off_q);
   la.mean = dev_mean;
@@ -637,6 +669,7 @@ qmc_status qmc_lattice_points(uint64_t n, int32_t d, uint64_t a, const double *s
       return fail(QMC_E_INVAL, "shift[%d] = %g outside [0, 1)", j, shift[j]);
     pa.z[j] = z;
     pa.dz[j] = mulmod_host(256 % n, z, n);
+    pa.ndz[j] = (double)(n - pa.dz[j]);
     pa.delta[j] = shift[j];
     z = mulmod_host(z, am, n);
   }

@@ -20,6 +20,8 @@ enum : int32_t {
   SF_HALF = 2,      // a half-integer exponent occurs (one square root per sample)
   SF_DEN = 4,       // a negative exponent occurs (one division per sample)
   SF_LOG = 8,       // max_log > 0: log F is needed
+  SF_FAST = 16,     // korobov3, no x powers, integer exponents of U and F,
+                    // max_log <= n_orders - 1 (log polynomials zero-padded to that degree)
 };
 
 // Static per-sector record (plan time).  Read with uniform (scalar) loads.
@@ -33,7 +35,7 @@ struct alignas(16) SectorDev {
   int32_t x_den[QMC_MAX_DIM];
   int32_t x_half[QMC_MAX_DIM];     // +1 / -1 / 0 as f_half
   double f_abs;                    // sum of |coefficients| of F (bound of sum |c m(x)| on the cube)
-  double pad1;
+  double w_scale;                  // korobov3: 140^d, the constant of W = 140^d prod (y(1-y))^3
   double logc[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
 };
 
@@ -45,6 +47,7 @@ struct alignas(16) LatticeDev {
   int64_t block_begin;             // first workgroup of this sector in the launch
   uint64_t z[QMC_MAX_DIM];         // generating vector
   uint64_t dz[QMC_MAX_DIM];        // (workgroup size * z_j) mod n: lattice stride of a thread
+  double ndz[QMC_MAX_DIM];         // n - dz_j as an exact double (the stride step subtracts it)
   int64_t chunk;                   // lattice points per workgroup
   int32_t n_chunks;                // workgroups per shift tile
   int32_t pad;
@@ -54,12 +57,19 @@ struct alignas(16) LatticeDev {
 // Status word: first non-finite (sector, shift, order), linearised, or INT32_MAX.
 
 // ---------------------------------------------------------------- launchers
+// Workgroups [base, base + blocks) of the launch numbering hold the sectors of dimension d.
+struct DimLaunch {
+  int64_t base, blocks;
+  int32_t d, pad;
+};
+
 struct LaunchArgs {
   const SectorDev *sectors;
   const double *coef;
   const double *shifts;            // [S][m][QMC_MAX_DIM]
   const LatticeDev *lat;
-  const int64_t *block_begin;      // [S+1]
+  const int64_t *block_begin;      // [S+1], in workgroup order (sectors ordered by dimension)
+  const int32_t *order;            // [S]: sector index of the s-th sector in workgroup order
   double *partial;                 // [blocks][tile][K][2]
   double *q;                       // [S][m][K] (always written; workspace if caller passes NULL)
   double *mean, *err;              // [S][K]
@@ -68,12 +78,15 @@ struct LaunchArgs {
   int64_t total_blocks;
   int32_t d_max, precision;
   void *ev_start, *ev_stop;        // optional hipEvent_t pair recorded around the main kernel
+  int32_t n_dim_launches, pad1;
+  DimLaunch dims[QMC_MAX_DIM];
 };
 
 struct PointsArgs {
   uint64_t n;
   double n_d, inv_n;
   uint64_t z[QMC_MAX_DIM], dz[QMC_MAX_DIM];
+  double ndz[QMC_MAX_DIM];
   double delta[QMC_MAX_DIM];
   int32_t d;
   uint32_t steps;

@@ -111,30 +111,28 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, uint64_t n) {
   return r;
 }
 
-__device__ __forceinline__ double quotient(uint64_t k, double n_d, double inv_n) {
-  double kd = (double)k;  // exact, k < 2^53
-  double q0 = kd * inv_n;
-  double r = __builtin_fma(-q0, n_d, kd);  // exact residual
+// The lattice state k_j = i z_j mod n is carried as an exact double (k < n < 2^53).
+__device__ __forceinline__ double quotient(double kd, double n_d, double inv_n) {
+  const double q0 = kd * inv_n;
+  const double r = __builtin_fma(-q0, n_d, kd);  // exact residual
   return __builtin_fma(r, inv_n, q0);
+}
+
+// k <- (k + dz) mod n as k - (n - dz), plus n if negative: every value is an integer of
+// magnitude below 2^53, so both operations are exact.
+__device__ __forceinline__ double lattice_step(double kd, double ndz, double n_d) {
+  const double t = kd - ndz;
+  return (t < 0.0) ? t + n_d : t;
+}
+
+// frac(q + Delta) for q, Delta in [0, 1): q + Delta < 2 and the fraction is exact.
+__device__ __forceinline__ double shifted(double q, double delta) {
+  return __builtin_amdgcn_fract(q + delta);
 }
 
 // ---------------------------------------------------------------- transforms
 
 // korobov_r: x = I_y(r+1, r+1) = y^(r+1) * poly_r(y), w = C_r (y (1 - y))^r.
-template <int R>
-struct Korobov;
-
-template <>
-struct Korobov<3> {
-  static __device__ __forceinline__ void apply(double y, double &x, double &w) {
-    double t = y * (1.0 - y);
-    w = 140.0 * (t * t * t);
-    double p = __builtin_fma(__builtin_fma(__builtin_fma(-20.0, y, 70.0), y, -84.0), y, 35.0);
-    double y2 = y * y;
-    x = (y2 * y2) * p;
-  }
-};
-
 // Generic korobov_r for r = 1..6, coefficients of poly_r in ascending powers.
 __device__ __forceinline__ void korobov_generic(int r, double y, double &x, double &w) {
   // poly_r(y) such that I_y(r+1, r+1) = y^(r+1) poly_r(y); C_r = (2r+1)!/(r!)^2.
@@ -201,15 +199,22 @@ __device__ __forceinline__ void korobov_generic(int r, double y, double &x, doub
 }
 
 template <int D>
-__device__ __forceinline__ double apply_transform(int kind, const double (&y)[D], double (&x)[D]) {
+__device__ __forceinline__ double apply_transform(int kind, double w_scale, const double (&y)[D],
+                                                  double (&x)[D]) {
   double W = 1.0;
   if (kind == QMC_TRANSFORM_KOROBOV3) {
+    // x_j = y^4 (35 - 84 y + 70 y^2 - 20 y^3);  W = 140^d (prod_j y_j (1 - y_j))^3
+    double T = 1.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      double w;
-      Korobov<3>::apply(y[j], x[j], w);
-      W *= w;
+      const double yj = y[j];
+      const double p =
+          __builtin_fma(__builtin_fma(__builtin_fma(-20.0, yj, 70.0), yj, -84.0), yj, 35.0);
+      const double y2 = yj * yj;
+      x[j] = (y2 * y2) * p;
+      T *= yj * (1.0 - yj);
     }
+    W = w_scale * (T * T * T);
   } else if (kind == QMC_TRANSFORM_BAKER) {
 #pragma unroll
     for (int j = 0; j < D; ++j) x[j] = 1.0 - __builtin_fabs(2.0 * y[j] - 1.0);
@@ -231,43 +236,59 @@ __device__ __forceinline__ double apply_transform(int kind, const double (&y)[D]
 // -------------------------------------------------------------- polynomials
 
 // Dense nested Horner of total degree DEG (<= 3) over the degree-3 layout, for S
-// points at once (each scalar coefficient feeds S FMAs).  The coefficient pointer of
-// every (j, k) group is laundered after the previous group's value, so at most one
-// group's coefficients (<= QMC_MAX_DIM + 2 doubles) are live in SGPRs.
+// points at once (each scalar coefficient feeds S FMAs).  The scalar loads of each
+// (j, k) group go through a pointer laundered after the result of the group two steps
+// back: a group's coefficients can arrive while the previous group computes, and at
+// most two groups' coefficients (<= 2 (QMC_MAX_DIM + 1) doubles) occupy SGPRs.
+struct LoadChain {
+  double dep1, dep2;   // results of the last two groups
+  __device__ __forceinline__ cptr<double> next(cptr<double> c) const { return launder_after(c, dep2); }
+  __device__ __forceinline__ void done(double v) {
+    dep2 = dep1;
+    dep1 = v;
+  }
+};
+
 template <int D, int DEG, int S>
-__device__ __forceinline__ void horner(cptr<double> c, const double (&x)[S][D], double (&out)[S]) {
+__device__ __forceinline__ void horner(cptr<double> c, const double (&x)[S][D], double (&out)[S],
+                                       LoadChain &ch) {
+  c = ch.next(c);
   double acc[S];
 #pragma unroll
   for (int u = 0; u < S; ++u) acc[u] = c[0];
   int p = 1;
 #pragma unroll
   for (int j = 0; j < D; ++j) {
+    c = ch.next(c);
     double g[S];
-    c = launder_after(c, acc[0]);
 #pragma unroll
     for (int u = 0; u < S; ++u) g[u] = c[p];
     ++p;
+    if (DEG >= 2) {
 #pragma unroll
-    for (int k = j; k < D; ++k) {
-      if (DEG >= 3) c = launder_after(c, g[0]);
-      double h[S];
+      for (int k = j; k < D; ++k) {
+        if (DEG >= 3) c = ch.next(c);
+        double h[S];
 #pragma unroll
-      for (int u = 0; u < S; ++u) h[u] = c[p];
-      ++p;
-      if (DEG >= 3) {
+        for (int u = 0; u < S; ++u) h[u] = c[p];
+        ++p;
+        if (DEG >= 3) {
 #pragma unroll
-        for (int l = k; l < D; ++l)
+          for (int l = k; l < D; ++l)
 #pragma unroll
-          for (int u = 0; u < S; ++u) h[u] = __builtin_fma(c[p + l - k], x[u][l], h[u]);
-      }
-      p += D - k;
-      if (DEG >= 2) {
+            for (int u = 0; u < S; ++u) h[u] = __builtin_fma(c[p + l - k], x[u][l], h[u]);
+          ch.done(h[0]);
+        }
+        p += D - k;
 #pragma unroll
         for (int u = 0; u < S; ++u) g[u] = __builtin_fma(x[u][k], h[u], g[u]);
       }
+    } else {
+      p += (D - j) * (D - j + 3) / 2;   // skip the degree-2 and degree-3 slots of this j
     }
 #pragma unroll
     for (int u = 0; u < S; ++u) acc[u] = __builtin_fma(x[u][j], g[u], acc[u]);
+    ch.done(acc[0]);
   }
 #pragma unroll
   for (int u = 0; u < S; ++u) out[u] = acc[u];
@@ -275,10 +296,49 @@ __device__ __forceinline__ void horner(cptr<double> c, const double (&x)[S][D], 
 
 template <int D, int S>
 __device__ __forceinline__ void poly(cptr<double> c, int deg, const double (&x)[S][D],
-                                     double (&out)[S]) {
-  // degree-1 tables hold zeros in the degree-2 slots, so the degree-2 body serves them
-  if (deg >= 3) horner<D, 3, S>(c, x, out);
-  else horner<D, 2, S>(c, x, out);
+                                     double (&out)[S], LoadChain &ch) {
+  if (deg >= 3) horner<D, 3, S>(c, x, out, ch);
+  else if (deg == 2) horner<D, 2, S>(c, x, out, ch);
+  else horner<D, 1, S>(c, x, out, ch);
+}
+
+// 1/v to within an ulp or two: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = __builtin_fma(__builtin_fma(-v, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-v, r, 1.0), r, r);
+  return r;
+}
+
+// Natural logarithm of log F, accurate to a few ulp.  x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.1716, by the
+// Taylor series atanh(s) = s sum_k s^(2k)/(2k+1) through s^19 (remainder below 2.4e-17
+// relative); e ln 2 with ln 2 split into a 32-bit head (e * head exact) and a tail.
+// log(0) = -inf, log(+inf) = +inf, negative or NaN input gives NaN.
+__device__ __forceinline__ double log_f64(double x) {
+  constexpr double kLn2Hi = 0x1.62e42ffp-1;
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+  double m = __builtin_amdgcn_frexp_mant(x);   // [0.5, 1) for finite non-zero x
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool low = m < 0.70710678118654752;
+  m = low ? m + m : m;
+  e = low ? e - 1 : e;
+  const double s = (m - 1.0) * recip(m + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 19.0;
+  p = __builtin_fma(p, z, 1.0 / 17.0);
+  p = __builtin_fma(p, z, 1.0 / 15.0);
+  p = __builtin_fma(p, z, 1.0 / 13.0);
+  p = __builtin_fma(p, z, 1.0 / 11.0);
+  p = __builtin_fma(p, z, 1.0 / 9.0);
+  p = __builtin_fma(p, z, 1.0 / 7.0);
+  p = __builtin_fma(p, z, 1.0 / 5.0);
+  p = __builtin_fma(p, z, 1.0 / 3.0);
+  const double logm = 2.0 * __builtin_fma(s * z, p, s);
+  const double ed = (double)e;
+  double r = __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, logm));
+  const bool ok = x > 0.0 && x < __builtin_inf();
+  return ok ? r : (x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan("")));
 }
 
 __device__ __forceinline__ double ipow_u(double v, int e) {
@@ -316,8 +376,9 @@ __device__ __forceinline__ void integrand(const SectorScalars &ss, cptr<SectorDe
                                           double (&f)[S][K]) {
   const int flags = ss.flags;
   double U[S], F[S];
-  poly<D, S>(coef + ss.u_off, ss.u_deg, x, U);
-  poly<D, S>(launder_after(coef, U[0]) + ss.f_off, ss.f_deg, x, F);
+  LoadChain ch{x[0][0], x[0][0]};
+  poly<D, S>(coef + ss.u_off, ss.u_deg, x, U, ch);
+  poly<D, S>(coef + ss.f_off, ss.f_deg, x, F, ch);
   double B[S];
   cptr<SectorDev> sx = launder_after(sd, F[0]);
 #pragma unroll
@@ -341,9 +402,9 @@ __device__ __forceinline__ void integrand(const SectorScalars &ss, cptr<SectorDe
       if (ss.f_half > 0) hn *= F[u];
       if (ss.f_half < 0) hd *= F[u];
       // sqrt(hn / hd) = sqrt(hn hd) / hd
-      B[u] = (num * sqrt(hn * hd)) / (den * hd);
+      B[u] = (num * sqrt(hn * hd)) * recip(den * hd);
     } else if (flags & SF_DEN) {
-      B[u] = num / den;
+      B[u] = num * recip(den);
     } else {
       B[u] = num;
     }
@@ -353,7 +414,7 @@ __device__ __forceinline__ void integrand(const SectorScalars &ss, cptr<SectorDe
   if (flags & SF_LOG) {
     double L[S];
 #pragma unroll
-    for (int u = 0; u < S; ++u) L[u] = log(F[u]);
+    for (int u = 0; u < S; ++u) L[u] = log_f64(F[u]);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double v[S];
@@ -375,6 +436,81 @@ __device__ __forceinline__ void integrand(const SectorScalars &ss, cptr<SectorDe
   }
 }
 
+// Integrand orders for the common sector shape (the plan sets SF_FAST): integer
+// exponents of U and F only, no powers of x_j, and log F polynomials of degree at most
+// K - 1 (the plan zero-pads them to that degree).  Straight-line code apart from the
+// uniform exponent loops, which are shared by the S samples.
+template <int D, int K, int S>
+__device__ __forceinline__ void integrand_fast(const SectorScalars &ss, cptr<SectorDev> sd,
+                                               cptr<double> coef, const double (&x)[S][D],
+                                               double (&f)[S][K]) {
+  double U[S], F[S];
+  LoadChain ch{x[0][0], x[0][0]};
+  poly<D, S>(coef + ss.u_off, ss.u_deg, x, U, ch);
+  poly<D, S>(coef + ss.f_off, ss.f_deg, x, F, ch);
+  double num[S], den[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) num[u] = den[u] = 1.0;
+  for (int t = 0; t < ss.u_num; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) num[u] *= U[u];
+  for (int t = 0; t < ss.u_den; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) den[u] *= U[u];
+  for (int t = 0; t < ss.f_num; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) num[u] *= F[u];
+  for (int t = 0; t < ss.f_den; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) den[u] *= F[u];
+  double B[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) B[u] = num[u] * recip(den[u]);
+  cptr<SectorDev> sl = launder_after(sd, B[0]);
+  if (K > 1) {
+    double L[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) L[u] = log_f64(F[u]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v[S];
+#pragma unroll
+      for (int u = 0; u < S; ++u) v[u] = sl->logc[k][K - 1];
+#pragma unroll
+      for (int m = K - 2; m >= 0; --m) {
+        const double cm = sl->logc[k][m];
+#pragma unroll
+        for (int u = 0; u < S; ++u) v[u] = __builtin_fma(v[u], L[u], cm);
+      }
+#pragma unroll
+      for (int u = 0; u < S; ++u) f[u][k] = B[u] * v[u];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < S; ++u) f[u][0] = B[u] * sl->logc[0][0];
+  }
+}
+
+// korobov3 on S samples: x = y^4 (35 - 84 y + 70 y^2 - 20 y^3), W = 140^d (prod y(1-y))^3.
+template <int D, int S>
+__device__ __forceinline__ void korobov3_fast(double w_scale, const double (&y)[S][D],
+                                              double (&x)[S][D], double (&W)[S]) {
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    double T = 1.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double yj = y[u][j];
+      const double p =
+          __builtin_fma(__builtin_fma(__builtin_fma(-20.0, yj, 70.0), yj, -84.0), yj, 35.0);
+      const double y2 = yj * yj;
+      x[u][j] = (y2 * y2) * p;
+      T *= yj * (1.0 - yj);
+    }
+    W[u] = w_scale * (T * T * T);
+  }
+}
+
 // ------------------------------------------------------------- main kernel
 
 // Workgroup -> sector by binary search over the launch's first-workgroup table.
@@ -392,12 +528,17 @@ __device__ __forceinline__ int find_sector(const int64_t *__restrict__ begin, in
 constexpr int kMaxTile = 16;
 constexpr int kMaxWaves = 4;
 
+// Lattice points a thread sums in plain FP64 before folding the partial into its
+// compensated (TwoSum) accumulator.
+constexpr int kFold = 8;
+
 // One workgroup: sector s, shifts [l_begin, l_begin + tile), lattice points of one
 // chunk.  The shifts are processed S at a time: for each point the quotient k/n is
-// formed once and reused by the S shifts of the pass, whose S*K compensated
-// accumulators stay in registers.  After each pass the accumulators are reduced over
-// the wavefront and staged in LDS.
-template <int D, int K, int S>
+// formed once and reused by the S shifts of the pass, whose S*K accumulators stay in
+// registers.  Each accumulator is a plain partial over at most kFold points folded
+// into a (sum, compensation) pair.  After each pass the pairs are reduced over the
+// wavefront and staged in LDS.
+template <int D, int K, int S, bool FAST>
 __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int l_begin, int tile,
                                                 int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
   const SectorDev *__restrict__ sd = a.sectors + s;
@@ -409,16 +550,19 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
   uint64_t i_end = i_begin + (uint64_t)chunk;
   if (i_end > n) i_end = n;
   const int kind = sd->transform;
+  const double w_scale = sd->w_scale;
   const SectorScalars ss = load_scalars(sd);
   const uint64_t B = blockDim.x;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  // every lane runs the same number of iterations; lanes past i_end contribute 0
+  const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
 
   // lattice state of this thread at its first point i0: k_j = i0 z_j mod n
-  uint64_t k0[D];
+  double k0[D];
   const uint64_t i0 = i_begin + threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < D; ++j) k0[j] = mulmod(i0 % n, lt->z[j], n);
+  for (int j = 0; j < D; ++j) k0[j] = (double)mulmod(i0 % n, lt->z[j], n);
 
 #pragma unroll 1
   for (int l0 = 0; l0 < tile; l0 += S) {
@@ -428,41 +572,57 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) acc[u][kk] = DD{0.0, 0.0};
     const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
-    uint64_t k[D];
+    double k[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) k[j] = k0[j];
 
+    uint64_t i = i0;
+    int64_t it = 0;
 #pragma unroll 1
-    for (uint64_t i = i0; i < i_end; i += B) {
-      const cptr<double> cl = launder_uniform(a.coef);
-      const cptr<LatticeDev> ltl = launder_uniform(lt);
-      const cptr<double> shl = launder_uniform(sh);
-      double q[D];
+    while (it < n_iter) {
+      double part[S][K];
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        q[j] = quotient(k[j], n_d, inv_n);
-        const uint64_t kn = k[j] + ltl->dz[j];  // dz_j = (workgroup size * z_j) mod n
-        k[j] = (kn >= n) ? kn - n : kn;
-      }
-      double x[S][D], W[S];
+      for (int u = 0; u < S; ++u)
 #pragma unroll
-      for (int u = 0; u < S; ++u) {
-        double y[D];
+        for (int kk = 0; kk < K; ++kk) part[u][kk] = 0.0;
+      const int64_t it_end = (n_iter - it < kFold) ? n_iter : it + kFold;
+#pragma unroll 1
+      for (; it < it_end; ++it, i += B) {
+        const cptr<double> cl = launder_uniform(a.coef);
+        const cptr<LatticeDev> ltl = launder_uniform(lt);
+        const cptr<double> shl = launder_uniform(sh);
+        double q[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-          const double t = q[j] + shl[u * QMC_MAX_DIM + j];
-          y[j] = (t >= 1.0) ? t - 1.0 : t;
+          q[j] = quotient(k[j], n_d, inv_n);
+          k[j] = lattice_step(k[j], ltl->ndz[j], n_d);
         }
-        W[u] = apply_transform<D>(kind, y, x[u]);
-      }
-      double f[S][K];
-      integrand<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
+        double y[S][D], x[S][D], W[S];
 #pragma unroll
-      for (int u = 0; u < S; ++u) {
-        const bool use = (W[u] != 0.0);
+        for (int u = 0; u < S; ++u)
 #pragma unroll
-        for (int kk = 0; kk < K; ++kk) dd_add(acc[u][kk], use ? W[u] * f[u][kk] : 0.0);
+          for (int j = 0; j < D; ++j) y[u][j] = shifted(q[j], shl[u * QMC_MAX_DIM + j]);
+        double f[S][K];
+        if (FAST) {
+          korobov3_fast<D, S>(w_scale, y, x, W);
+          integrand_fast<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
+        } else {
+#pragma unroll
+          for (int u = 0; u < S; ++u) W[u] = apply_transform<D>(kind, w_scale, y[u], x[u]);
+          integrand<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
+        }
+        const bool valid = i < i_end;
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+          const bool use = valid && (W[u] != 0.0);
+#pragma unroll
+          for (int kk = 0; kk < K; ++kk) part[u][kk] += use ? W[u] * f[u][kk] : 0.0;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) dd_add(acc[u][kk], part[u][kk]);
     }
 #pragma unroll
     for (int u = 0; u < S; ++u)
@@ -477,11 +637,14 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
   }
 }
 
-template <int K, int S>
-__global__ __launch_bounds__(256) void qmc_integrate_kernel(LaunchArgs a) {
+// One launch per sector dimension D: workgroup blockIdx.x + block_base of the launch's
+// global workgroup numbering (workgroups are numbered sector by sector, sectors ordered
+// by dimension, so a dimension's workgroups are contiguous).
+template <int D, int K, int S>
+__global__ __launch_bounds__(256) void qmc_integrate_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
-  const int64_t b = blockIdx.x;
-  const int s = find_sector(a.block_begin, a.n_sectors, b);
+  const int64_t b = block_base + blockIdx.x;
+  const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
   const LatticeDev *__restrict__ lt = a.lat + s;
   const int64_t local = b - lt->block_begin;
   const int nch = lt->n_chunks;
@@ -490,20 +653,8 @@ __global__ __launch_bounds__(256) void qmc_integrate_kernel(LaunchArgs a) {
   const int T = a.shift_tile;
   const int l_begin = tile_id * T;
 
-#ifdef QMC_QUICK_D
-  integrate_block<QMC_QUICK_D, K, S>(a, s, l_begin, T, chunk_id, red);
-#else
-  switch (a.sectors[s].d) {
-    case 1: integrate_block<1, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    case 2: integrate_block<2, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    case 3: integrate_block<3, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    case 4: integrate_block<4, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    case 5: integrate_block<5, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    case 6: integrate_block<6, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    case 7: integrate_block<7, K, S>(a, s, l_begin, T, chunk_id, red); break;
-    default: integrate_block<8, K, S>(a, s, l_begin, T, chunk_id, red); break;
-  }
-#endif
+  if (a.sectors[s].flags & SF_FAST) integrate_block<D, K, S, true>(a, s, l_begin, T, chunk_id, red);
+  else integrate_block<D, K, S, false>(a, s, l_begin, T, chunk_id, red);
   __syncthreads();
   // in-order combine of the waves, one thread per (shift in tile, order)
   const int nwaves = blockDim.x >> 6;
@@ -578,16 +729,14 @@ __global__ __launch_bounds__(256) void qmc_points_kernel(PointsArgs pa) {
   const uint64_t B = blockDim.x;
   const uint64_t first = pa.i0 + (uint64_t)blockIdx.x * pa.steps * B + threadIdx.x;
   const uint64_t end = pa.i0 + pa.count;
-  uint64_t k[QMC_MAX_DIM];
-  for (int j = 0; j < pa.d; ++j) k[j] = mulmod(first % pa.n, pa.z[j], pa.n);
+  double k[QMC_MAX_DIM];
+  for (int j = 0; j < pa.d; ++j) k[j] = (double)mulmod(first % pa.n, pa.z[j], pa.n);
   uint64_t i = first;
   for (uint32_t r = 0; r < pa.steps && i < end; ++r, i += B) {
     for (int j = 0; j < pa.d; ++j) {
       const double q = quotient(k[j], pa.n_d, pa.inv_n);
-      const double t = q + pa.delta[j];
-      pa.out[(i - pa.i0) * pa.d + j] = (t >= 1.0) ? t - 1.0 : t;
-      const uint64_t kn = k[j] + pa.dz[j];
-      k[j] = (kn >= pa.n) ? kn - pa.n : kn;
+      pa.out[(i - pa.i0) * pa.d + j] = shifted(q, pa.delta[j]);
+      k[j] = lattice_step(k[j], pa.ndz[j], pa.n_d);
     }
   }
 }
@@ -625,7 +774,7 @@ __global__ __launch_bounds__(256) void qmc_p2_kernel(uint64_t n, int32_t d,
   for (uint64_t k = k0; k < k_end; k += blockDim.x) {
     double prod = 1.0;
     for (int j = 0; j < d; ++j) {
-      const double x = quotient(kz[j], n_d, inv_n);
+      const double x = quotient((double)kz[j], n_d, inv_n);
       const double b2 = __builtin_fma(x, x - 1.0, 1.0 / 6.0);
       prod *= __builtin_fma(two_pi2, b2, 1.0);
       const uint64_t kn = kz[j] + dz[j];
@@ -665,20 +814,30 @@ __global__ void qmc_p2_finish_kernel(uint64_t n, int32_t n_cand, int32_t chunks,
 
 // ------------------------------------------------------------------ launchers
 
-template <int S>
-static hipError_t launch_s(const LaunchArgs &a, hipStream_t st) {
-  dim3 grid((unsigned)a.total_blocks), blk((unsigned)a.block);
-#ifdef QMC_QUICK_BUILD
-  hipLaunchKernelGGL((qmc_integrate_kernel<3, S>), grid, blk, 0, st, a);
-#else
+template <int D, int S>
+static hipError_t launch_ds(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
+  dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
   switch (a.K) {
-    case 1: hipLaunchKernelGGL((qmc_integrate_kernel<1, S>), grid, blk, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((qmc_integrate_kernel<2, S>), grid, blk, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((qmc_integrate_kernel<3, S>), grid, blk, 0, st, a); break;
-    default: hipLaunchKernelGGL((qmc_integrate_kernel<4, S>), grid, blk, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((qmc_integrate_kernel<D, 1, S>), grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL((qmc_integrate_kernel<D, 2, S>), grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL((qmc_integrate_kernel<D, 3, S>), grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL((qmc_integrate_kernel<D, 4, S>), grid, blk, 0, st, a, dl.base); break;
   }
-#endif
   return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_s(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
+  switch (dl.d) {
+    case 1: return launch_ds<1, S>(a, dl, st);
+    case 2: return launch_ds<2, S>(a, dl, st);
+    case 3: return launch_ds<3, S>(a, dl, st);
+    case 4: return launch_ds<4, S>(a, dl, st);
+    case 5: return launch_ds<5, S>(a, dl, st);
+    case 6: return launch_ds<6, S>(a, dl, st);
+    case 7: return launch_ds<7, S>(a, dl, st);
+    default: return launch_ds<8, S>(a, dl, st);
+  }
 }
 
 bool tile_supported(int shift_tile, int shifts_per_pass, int block) {
@@ -692,16 +851,16 @@ int launch_integrate(const LaunchArgs &a, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (a.ev_start && (e = hipEventRecord((hipEvent_t)a.ev_start, st)) != hipSuccess) return (int)e;
-#ifdef QMC_QUICK_BUILD
-  e = launch_s<QMC_QUICK_S>(a, st);
-#else
-  switch (a.shifts_per_pass) {
-    case 1: e = launch_s<1>(a, st); break;
-    case 4: e = launch_s<4>(a, st); break;
-    default: e = launch_s<2>(a, st); break;
+  for (int t = 0; t < a.n_dim_launches; ++t) {
+    const DimLaunch &dl = a.dims[t];
+    if (dl.blocks == 0) continue;
+    switch (a.shifts_per_pass) {
+      case 1: e = launch_s<1>(a, dl, st); break;
+      case 4: e = launch_s<4>(a, dl, st); break;
+      default: e = launch_s<2>(a, dl, st); break;
+    }
+    if (e != hipSuccess) return (int)e;
   }
-#endif
-  if (e != hipSuccess) return (int)e;
   if (a.ev_stop && (e = hipEventRecord((hipEvent_t)a.ev_stop, st)) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(qmc_reduce_kernel, dim3((unsigned)(a.n_sectors * a.m)), dim3(64), 0, st, a);
   e = hipGetLastError();
