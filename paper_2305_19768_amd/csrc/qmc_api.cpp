@@ -353,8 +353,11 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
       }
   p->order.resize(p->S);
   for (int s = 0; s < p->S; ++s) p->order[s] = s;
-  std::stable_sort(p->order.begin(), p->order.end(),
-                   [&](int32_t x, int32_t y) { return p->dims[x] < p->dims[y]; });
+  // workgroup order: by dimension, then generic before fast path, then sector index
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int32_t x, int32_t y) {
+    const int fx = (p->sec[x].flags & SF_FAST) ? 1 : 0, fy = (p->sec[y].flags & SF_FAST) ? 1 : 0;
+    return p->dims[x] != p->dims[y] ? p->dims[x] < p->dims[y] : fx < fy;
+  });
   layout(p);
   p->lat.resize(p->S);
   p->begin.resize(p->S + 1);
@@ -457,7 +460,7 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
   if (ppt < 1) ppt = 1;
   const int64_t chunk = ppt * p->block;
   int64_t b = 0;
-  DimLaunch dl[QMC_MAX_DIM];
+  DimLaunch dl[2 * QMC_MAX_DIM];
   int n_dl = 0;
   for (int t = 0; t < p->S; ++t) {
     const int s = p->order[t];
@@ -466,11 +469,12 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
     L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
     L.block_begin = b;
     p->begin[t] = b;
-    if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s]) {
+    const int fast = (p->sec[s].flags & SF_FAST) ? 1 : 0;
+    if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast) {
       dl[n_dl].d = p->dims[s];
       dl[n_dl].base = b;
       dl[n_dl].blocks = 0;
-      dl[n_dl].pad = 0;
+      dl[n_dl].fast = fast;
       ++n_dl;
     }
     const int64_t nb = (int64_t)L.n_chunks * tiles;

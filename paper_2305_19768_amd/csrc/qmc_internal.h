@@ -57,10 +57,11 @@ struct alignas(16) LatticeDev {
 // Status word: first non-finite (sector, shift, order), linearised, or INT32_MAX.
 
 // ---------------------------------------------------------------- launchers
-// Workgroups [base, base + blocks) of the launch numbering hold the sectors of dimension d.
+// Workgroups [base, base + blocks) of the launch numbering hold the sectors of dimension
+// d and path class `fast` (SF_FAST set or not).
 struct DimLaunch {
   int64_t base, blocks;
-  int32_t d, pad;
+  int32_t d, fast;
 };
 
 struct LaunchArgs {
@@ -79,7 +80,7 @@ struct LaunchArgs {
   int32_t d_max, precision;
   void *ev_start, *ev_stop;        // optional hipEvent_t pair recorded around the main kernel
   int32_t n_dim_launches, pad1;
-  DimLaunch dims[QMC_MAX_DIM];
+  DimLaunch dims[2 * QMC_MAX_DIM];
 };
 
 struct PointsArgs {

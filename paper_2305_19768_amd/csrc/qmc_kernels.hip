@@ -240,9 +240,14 @@ __device__ __forceinline__ double apply_transform(int kind, double w_scale, cons
 // (j, k) group go through a pointer laundered after the result of the group two steps
 // back: a group's coefficients can arrive while the previous group computes, and at
 // most two groups' coefficients (<= 2 (QMC_MAX_DIM + 1) doubles) occupy SGPRs.
+#ifndef QMC_CHAIN_LAG
+#define QMC_CHAIN_LAG 1
+#endif
 struct LoadChain {
   double dep1, dep2;   // results of the last two groups
-  __device__ __forceinline__ cptr<double> next(cptr<double> c) const { return launder_after(c, dep2); }
+  __device__ __forceinline__ cptr<double> next(cptr<double> c) const {
+    return launder_after(c, QMC_CHAIN_LAG == 1 ? dep1 : dep2);
+  }
   __device__ __forceinline__ void done(double v) {
     dep2 = dep1;
     dep1 = v;
@@ -640,7 +645,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
 // One launch per sector dimension D: workgroup blockIdx.x + block_base of the launch's
 // global workgroup numbering (workgroups are numbered sector by sector, sectors ordered
 // by dimension, so a dimension's workgroups are contiguous).
-template <int D, int K, int S>
+template <int D, int K, int S, bool FAST>
 __global__ __launch_bounds__(256) void qmc_integrate_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   const int64_t b = block_base + blockIdx.x;
@@ -653,8 +658,7 @@ __global__ __launch_bounds__(256) void qmc_integrate_kernel(LaunchArgs a, int64_
   const int T = a.shift_tile;
   const int l_begin = tile_id * T;
 
-  if (a.sectors[s].flags & SF_FAST) integrate_block<D, K, S, true>(a, s, l_begin, T, chunk_id, red);
-  else integrate_block<D, K, S, false>(a, s, l_begin, T, chunk_id, red);
+  integrate_block<D, K, S, FAST>(a, s, l_begin, T, chunk_id, red);
   __syncthreads();
   // in-order combine of the waves, one thread per (shift in tile, order)
   const int nwaves = blockDim.x >> 6;
@@ -814,29 +818,39 @@ __global__ void qmc_p2_finish_kernel(uint64_t n, int32_t n_cand, int32_t chunks,
 
 // ------------------------------------------------------------------ launchers
 
-template <int D, int S>
+template <int D, int S, bool FAST>
 static hipError_t launch_ds(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
   dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
   switch (a.K) {
-    case 1: hipLaunchKernelGGL((qmc_integrate_kernel<D, 1, S>), grid, blk, 0, st, a, dl.base); break;
-    case 2: hipLaunchKernelGGL((qmc_integrate_kernel<D, 2, S>), grid, blk, 0, st, a, dl.base); break;
-    case 3: hipLaunchKernelGGL((qmc_integrate_kernel<D, 3, S>), grid, blk, 0, st, a, dl.base); break;
-    default: hipLaunchKernelGGL((qmc_integrate_kernel<D, 4, S>), grid, blk, 0, st, a, dl.base); break;
+    case 1: hipLaunchKernelGGL((qmc_integrate_kernel<D, 1, S, FAST>), grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL((qmc_integrate_kernel<D, 2, S, FAST>), grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL((qmc_integrate_kernel<D, 3, S, FAST>), grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL((qmc_integrate_kernel<D, 4, S, FAST>), grid, blk, 0, st, a, dl.base); break;
   }
   return hipGetLastError();
 }
 
-template <int S>
-static hipError_t launch_s(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
+// Sectors of the generic shape run one shift per pass (they are the uncommon case).
+template <int D>
+static hipError_t launch_d(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
+  if (!dl.fast) return launch_ds<D, 1, false>(a, dl, st);
+  switch (a.shifts_per_pass) {
+    case 1: return launch_ds<D, 1, true>(a, dl, st);
+    case 4: return launch_ds<D, 4, true>(a, dl, st);
+    default: return launch_ds<D, 2, true>(a, dl, st);
+  }
+}
+
+static hipError_t launch_class(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
   switch (dl.d) {
-    case 1: return launch_ds<1, S>(a, dl, st);
-    case 2: return launch_ds<2, S>(a, dl, st);
-    case 3: return launch_ds<3, S>(a, dl, st);
-    case 4: return launch_ds<4, S>(a, dl, st);
-    case 5: return launch_ds<5, S>(a, dl, st);
-    case 6: return launch_ds<6, S>(a, dl, st);
-    case 7: return launch_ds<7, S>(a, dl, st);
-    default: return launch_ds<8, S>(a, dl, st);
+    case 1: return launch_d<1>(a, dl, st);
+    case 2: return launch_d<2>(a, dl, st);
+    case 3: return launch_d<3>(a, dl, st);
+    case 4: return launch_d<4>(a, dl, st);
+    case 5: return launch_d<5>(a, dl, st);
+    case 6: return launch_d<6>(a, dl, st);
+    case 7: return launch_d<7>(a, dl, st);
+    default: return launch_d<8>(a, dl, st);
   }
 }
 
@@ -854,12 +868,7 @@ int launch_integrate(const LaunchArgs &a, void *stream) {
   for (int t = 0; t < a.n_dim_launches; ++t) {
     const DimLaunch &dl = a.dims[t];
     if (dl.blocks == 0) continue;
-    switch (a.shifts_per_pass) {
-      case 1: e = launch_s<1>(a, dl, st); break;
-      case 4: e = launch_s<4>(a, dl, st); break;
-      default: e = launch_s<2>(a, dl, st); break;
-    }
-    if (e != hipSuccess) return (int)e;
+    if ((e = launch_class(a, dl, st)) != hipSuccess) return (int)e;
   }
   if (a.ev_stop && (e = hipEventRecord((hipEvent_t)a.ev_stop, st)) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(qmc_reduce_kernel, dim3((unsigned)(a.n_sectors * a.m)), dim3(64), 0, st, a);

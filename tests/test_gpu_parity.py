@@ -113,6 +113,21 @@ def test_dimensions_orders_logs(qmc, d, K, M):
     _parity(qmc, W.single_problem(sec, m=4, seed=d))
 
 
+@pytest.mark.parametrize("d,K,M,u_pow,f_pow2", [(1, 1, 0, 0, -2), (3, 2, 1, -1, -4), (5, 3, 2, 2, -6),
+                                                (7, 4, 3, 1, -8), (8, 4, 1, 0, 4), (6, 3, 0, 3, 0)])
+def test_fast_path_shapes(qmc, d, K, M, u_pow, f_pow2):
+    # korobov3, no x powers, integer exponents, log degree <= K - 1: the specialised path
+    rng = np.random.default_rng(7 * d + K)
+    ue, uc = W.random_polynomial(rng, d, 6, 2)
+    fe, fc = W.random_polynomial(rng, d, 15, 3)
+    sec = W.Sector(d=d, u_exp=ue, u_coef=uc, f_exp=fe, f_coef=fc,
+                   x_pow2=np.zeros(d, np.int32), u_pow=u_pow, f_pow2=f_pow2,
+                   logc=rng.uniform(-1, 1, size=(K, M + 1)), n=20011,
+                   a=int(rng.integers(2, 20009)), transform="korobov3")
+    for spp in (1, 2, 4):
+        _parity(qmc, W.single_problem(sec, m=8, seed=d), shifts_per_pass=spp)
+
+
 @pytest.mark.parametrize("block,tile,spp,m", [(256, 8, 2, 16), (64, 1, 1, 2), (128, 4, 4, 8),
                                               (192, 16, 4, 32), (256, 3, 1, 6), (64, 2, 2, 4)])
 def test_launch_shapes_agree(qmc, block, tile, spp, m):
