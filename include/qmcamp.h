@@ -210,6 +210,76 @@ qmc_status qmc_lattice_points(uint64_t n, int32_t d, uint64_t a, const double *s
                               uint64_t i0, uint64_t count, void *stream, double *dev_y);
 
 /*
+ * Weighted sums of integrals A_t = sum_i C_ti I_i (Sec. 2.1.3; coefficient rows may be
+ * sparse, Sec. 2.4): row t holds the entries row_ptr[t] .. row_ptr[t+1]-1 of col
+ * (integral index) and coef_re / coef_im.  n_sums >= 1.
+ */
+typedef struct {
+    int32_t n_sums;
+    int32_t reserved0;
+    const int64_t *row_ptr;           /* [n_sums + 1] */
+    const int32_t *col;               /* [nnz] integral indices (< the problem's n_integrals) */
+    const double *coef_re;            /* [nnz] */
+    const double *coef_im;            /* [nnz], may be NULL (real coefficients) */
+} qmc_amplitude;
+
+enum { QMC_AMP_HOST = 0, QMC_AMP_DEVICE = 1 };
+
+/*
+ * Options of the adaptive evaluation (Sec. 2.1.3): every epsilon order of every sum
+ * must reach relative error epsrel (error definition of Sec. 3.3) or absolute error
+ * epsabs.  Lattice sizes come from the ascending table lattice_n[n_lattice]; the
+ * Korobov parameter of size lattice_n[l] for a sector of dimension d is
+ * lattice_a[l * QMC_MAX_DIM + d - 1].  tau: per-sector cost of one evaluation (any
+ * unit), or NULL for the library's cost model (dense polynomial slots + transform +
+ * logarithm work).
+ */
+typedef struct {
+    double epsrel, epsabs;
+    double timeout_s;                 /* wall-clock limit, <= 0: none */
+    double alpha;                     /* variance decay exponent, var ~ w / n^alpha (2) */
+    uint64_t n_presample;             /* initial lattice size (the paper's 1e4) */
+    int32_t max_rounds;               /* allocation rounds after the presample (>= 1) */
+    int32_t mode;                     /* QMC_AMP_HOST (host loop) or QMC_AMP_DEVICE */
+    int32_t n_lattice;
+    int32_t reserved0;
+    const uint64_t *lattice_n;        /* [n_lattice], ascending, each <= the plan's n_max */
+    const uint64_t *lattice_a;        /* [n_lattice][QMC_MAX_DIM] */
+    const double *tau;                /* [n_sectors] or NULL */
+} qmc_amp_options;
+
+typedef struct {
+    int32_t rounds;                   /* integration rounds, presample included */
+    int32_t converged;                /* 1 if every target met its error bound */
+    int32_t timed_out;                /* 1 if stopped by timeout_s */
+    int32_t lattice_limited;          /* 1 if some sector wanted more than the largest size */
+    int64_t evaluations;              /* sum over rounds of n_s * m over integrated sectors */
+    double seconds;                   /* wall time of the call */
+    double max_eps_rel;               /* largest relative error over sums and orders */
+} qmc_amp_stats;
+
+/*
+ * amp_evaluate -- adaptive evaluation of weighted sums of integrals (Sec. 2.1.3):
+ * presample every sector at the smallest table size >= n_presample; then, per round,
+ * form the integrals (sums of their sectors, variances added) and the sums
+ * A_t = sum_i C_ti I_i with var(A_t) = sum_i |C_ti|^2 var(I_i) per order; stop when
+ * every target meets its bound; otherwise, for every unmet target (sum t, order k) in
+ * order, set V = max(epsrel^2 |A_tk|^2, epsabs^2), w_s = var_sk n_s^alpha and take the
+ * closed-form sizes n_s = (alpha w_s lambda |C|^2 / tau_s)^(1/(alpha+1)) with
+ * lambda = (1/alpha) [(1/V) sum_s (|C|^2 w_s tau_s^alpha)^(1/(alpha+1))]^((alpha+1)/alpha)
+ * (the Lagrange solution of Eq. adaptive-solution with one consistent index), keep the
+ * largest size any target asks for and never shrink, round up to the table and
+ * re-integrate the sectors whose lattice changed.  Synchronous on `stream`.
+ * Outputs (host, caller-owned): value and error [n_sums][n_orders][2] (re, im);
+ * n_final [n_sectors] (may be NULL); stats (may be NULL).  Returns QMC_OK (converged
+ * or not: see stats), QMC_E_TIMEOUT with valid results when the time limit stopped it,
+ * QMC_E_INVAL / QMC_E_NONFINITE / QMC_E_DEVICE on failure.
+ */
+qmc_status amp_evaluate(qmc_plan_t plan, const qmc_amplitude *amp, const qmc_amp_options *opt,
+                        void *stream, double *value, double *error, uint64_t *n_final,
+                        qmc_amp_stats *stats);
+
+/*
  * qmc_enable_timing / qmc_read_timing -- kernel timing for measurement: while enabled,
  * every qmc_integrate records a HIP event pair on its stream around its main
  * (integrand) kernel.  Enabling (or disabling) clears the record; at most 4096

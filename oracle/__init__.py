@@ -320,3 +320,97 @@ def allocate(c2, w, tau, V, alpha: float = 2.0):
     lam = (1.0 / alpha) * (s / V) ** ((alpha + 1.0) / alpha)
     n = (alpha * w * lam * c2 / tau) ** (1.0 / (alpha + 1.0))
     return n, lam
+
+
+# ------------------------------------------------------------ adaptive sums
+
+def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=0.0,
+                       alpha=2.0, n_presample=10000, max_rounds=50, threads=8):
+    """Adaptive evaluation of weighted sums of integrals, Sec. 2.1.3 (reading: the unit
+    is a sector; its coefficient is its integral's; unmet (sum, order) targets are
+    processed in order keeping each sector's largest request; sizes never shrink and
+    are rounded up to the table of available lattices).
+
+    coef: complex [n_sums, n_integrals].  lattice_n: ascending sizes; lattice_a:
+    [L, 8] Korobov parameter per size and dimension (column d-1).  tau: cost per
+    evaluation of each sector.  Returns (value [T, K] complex, error [T, K] complex
+    (err_re + 1j err_im), n_final [S], rounds, converged).
+    """
+    C = np.atleast_2d(np.asarray(coef, dtype=np.complex128))
+    T, NI = C.shape
+    S = len(problem.sectors)
+    K = problem.K
+    lad = [int(v) for v in lattice_n]
+    la = np.asarray(lattice_a, dtype=np.uint64).reshape(len(lad), 8)
+    tau = np.asarray(tau, dtype=np.float64)
+
+    def ceil_index(x):
+        for l, v in enumerate(lad):
+            if v >= x:
+                return l
+        return len(lad) - 1
+
+    lidx = [ceil_index(max(n_presample, 2))] * S
+    Q = [None] * S
+    active = [True] * S
+    rounds = 0
+    converged = False
+    while True:
+        todo = [s for s in range(S) if active[s]]
+
+        def run(s):
+            sec = problem.sectors[s]
+            n = lad[lidx[s]]
+            a = int(la[lidx[s], sec.d - 1])
+            Q[s] = sector_sums(sec, problem.shifts[s], n=n, a=a)[0]
+
+        if threads > 1:
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                list(ex.map(run, todo))
+        else:
+            for s in todo:
+                run(s)
+        rounds += 1
+        mean = np.zeros((S, K))
+        err = np.zeros((S, K))
+        for s in range(S):
+            mean[s], err[s] = estimate(Q[s])
+        ival, ierr = integral_values(problem, list(mean), list(err))
+        vals = np.zeros((T, K), dtype=np.complex128)
+        errs = np.zeros((T, K), dtype=np.complex128)
+        unmet = []
+        for t in range(T):
+            re, im, dre, dim_ = amplitude(C[t], ival, ierr)
+            vals[t] = re + 1j * im
+            errs[t] = dre + 1j * dim_
+            for k in range(K):
+                mag2 = re[k] ** 2 + im[k] ** 2
+                var = dre[k] ** 2 + dim_[k] ** 2
+                eps = math.sqrt(var / mag2) if mag2 > 0 else (math.inf if var > 0 else 0.0)
+                if not (eps <= epsrel or math.sqrt(var) <= epsabs):
+                    unmet.append((t, k, mag2))
+        if not unmet:
+            converged = True
+            break
+        if rounds > max_rounds:
+            break
+        n_cur = np.array([lad[lidx[s]] for s in range(S)], dtype=np.float64)
+        want = n_cur.copy()
+        for t, k, mag2 in unmet:
+            V = max(epsrel ** 2 * mag2, epsabs ** 2)
+            if not V > 0:
+                continue
+            c2 = np.array([abs(C[t, problem.sectors[s].integral]) ** 2 for s in range(S)])
+            w = err[:, k] ** 2 * n_cur ** alpha
+            use = c2 * w > 0
+            if not use.any():
+                continue
+            n_opt, _ = allocate(c2[use], w[use], tau[use], V, alpha)
+            want[use] = np.maximum(want[use], n_opt)
+        new = [max(lidx[s], ceil_index(want[s])) for s in range(S)]
+        active = [new[s] != lidx[s] for s in range(S)]
+        lidx = new
+        if not any(active):
+            break
+    n_final = np.array([lad[l] for l in lidx], dtype=np.uint64)
+    return vals, errs, n_final, rounds, converged

@@ -15,7 +15,11 @@ from typing import Optional, Sequence
 import numpy as np
 
 from ._abi import (QMC_MAX_DIM, QMC_MAX_LOG, QMC_MAX_ORDERS, QMC_PREC_FP32, QMC_PREC_FP64,
-                   TRANSFORMS, QmcError, lib, options_struct, problem_struct)
+                   TRANSFORMS, AmpOptions, AmpStats, Amplitude, QmcError, lib, options_struct,
+                   problem_struct)
+
+QMC_AMP_HOST = 0
+QMC_AMP_DEVICE = 1
 
 __all__ = ["Plan", "QmcError", "lib", "korobov_search", "lattice_points", "TRANSFORMS",
            "QMC_PREC_FP64", "QMC_PREC_FP32"]
@@ -155,6 +159,73 @@ class Plan:
                                         ctypes.c_int32(len(c)), _stream_ptr(stream),
                                         ctypes.byref(a), ctypes.byref(p2)), "qmc_korobov_search")
         return int(a.value), float(p2.value)
+
+
+    def lattice_table(self, sizes, candidates, dims=None):
+        """Korobov parameter per (size, dimension): the P_2-minimising candidate, chosen on
+        the device.  candidates: [L, QMC_MAX_DIM, R] (row d-1 for dimension d).  Returns
+        uint64 [L, QMC_MAX_DIM]; dimensions not in `dims` (default: the plan's) get 1."""
+        sizes = np.asarray(sizes, dtype=np.uint64)
+        cands = np.asarray(candidates, dtype=np.uint64)
+        dims = sorted({s.d for s in self.problem.sectors}) if dims is None else sorted(dims)
+        out = np.ones((len(sizes), QMC_MAX_DIM), dtype=np.uint64)
+        for l, n in enumerate(sizes):
+            for d in dims:
+                out[l, d - 1] = self.korobov_search(int(n), d, [int(c) for c in cands[l, d - 1]])[0]
+        return out
+
+    def amp_evaluate(self, coef, epsrel: float, epsabs: float = 0.0, lattice_n=None,
+                     lattice_a=None, tau=None, alpha: float = 2.0, n_presample: int = 10000,
+                     max_rounds: int = 50, timeout_s: float = 0.0, mode: int = QMC_AMP_HOST,
+                     stream=None):
+        """Adaptive evaluation of weighted sums A_t = sum_i C_ti I_i (see amp_evaluate in
+        include/qmcamp.h).  coef: complex [n_sums, n_integrals] (or [n_integrals] for one
+        sum).  Returns (value complex [n_sums, K], error complex [n_sums, K] as
+        (err_re + 1j err_im), n_final [S], stats dict)."""
+        C = np.atleast_2d(np.asarray(coef, dtype=np.complex128))
+        T, NI = C.shape
+        rows, cols, cre, cim = [0], [], [], []
+        for t in range(T):
+            nz = np.nonzero(C[t])[0]
+            cols.extend(int(i) for i in nz)
+            cre.extend(float(C[t, i].real) for i in nz)
+            cim.extend(float(C[t, i].imag) for i in nz)
+            rows.append(len(cols))
+        row_ptr = np.array(rows, dtype=np.int64)
+        col = np.array(cols, dtype=np.int32)
+        cr = np.array(cre, dtype=np.float64)
+        ci = np.array(cim, dtype=np.float64)
+        A = Amplitude()
+        A.n_sums = T
+        A.row_ptr = row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        A.col = col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        A.coef_re = cr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        A.coef_im = ci.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        ln = np.ascontiguousarray(lattice_n, dtype=np.uint64)
+        la = np.ascontiguousarray(lattice_a, dtype=np.uint64).reshape(len(ln), QMC_MAX_DIM)
+        O = AmpOptions()
+        O.epsrel, O.epsabs, O.timeout_s, O.alpha = epsrel, epsabs, timeout_s, alpha
+        O.n_presample, O.max_rounds, O.mode, O.n_lattice = n_presample, max_rounds, mode, len(ln)
+        O.lattice_n = ln.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        O.lattice_a = la.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        tau_arr = None
+        if tau is not None:
+            tau_arr = np.ascontiguousarray(tau, dtype=np.float64)
+            O.tau = tau_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        val = np.zeros((T, self.K, 2))
+        err = np.zeros((T, self.K, 2))
+        nfin = np.zeros(self.S, dtype=np.uint64)
+        st = AmpStats()
+        rc = lib().amp_evaluate(self._h, ctypes.byref(A), ctypes.byref(O), _stream_ptr(stream),
+                                val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                err.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                nfin.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                ctypes.byref(st))
+        if rc not in (0, -5):
+            _check(rc, "amp_evaluate")
+        stats = {f: getattr(st, f) for f, _ in AmpStats._fields_}
+        stats["status"] = rc
+        return (val[..., 0] + 1j * val[..., 1], err[..., 0] + 1j * err[..., 1], nfin, stats)
 
 
 def korobov_search(plan: Plan, n: int, d: int, candidates: Sequence[int]):

@@ -53,6 +53,32 @@ class Options(ctypes.Structure):
                 ("reserved0", ctypes.c_int32)]
 
 
+class Amplitude(ctypes.Structure):
+    _fields_ = [("n_sums", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("row_ptr", ctypes.POINTER(ctypes.c_int64)),
+                ("col", ctypes.POINTER(ctypes.c_int32)),
+                ("coef_re", ctypes.POINTER(ctypes.c_double)),
+                ("coef_im", ctypes.POINTER(ctypes.c_double))]
+
+
+class AmpOptions(ctypes.Structure):
+    _fields_ = [("epsrel", ctypes.c_double), ("epsabs", ctypes.c_double),
+                ("timeout_s", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("n_presample", ctypes.c_uint64), ("max_rounds", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("n_lattice", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32),
+                ("lattice_n", ctypes.POINTER(ctypes.c_uint64)),
+                ("lattice_a", ctypes.POINTER(ctypes.c_uint64)),
+                ("tau", ctypes.POINTER(ctypes.c_double))]
+
+
+class AmpStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("timed_out", ctypes.c_int32), ("lattice_limited", ctypes.c_int32),
+                ("evaluations", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("max_eps_rel", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -91,6 +117,11 @@ def lib():
                                          ctypes.POINTER(ctypes.c_double), ctypes.c_uint64,
                                          ctypes.c_uint64, vp, vp]
         L.qmc_lattice_points.restype = ctypes.c_int
+        L.amp_evaluate.argtypes = [vp, ctypes.POINTER(Amplitude), ctypes.POINTER(AmpOptions), vp,
+                                   ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double), u64p,
+                                   ctypes.POINTER(AmpStats)]
+        L.amp_evaluate.restype = ctypes.c_int
         L.qmc_enable_timing.argtypes = [vp, ctypes.c_int32]
         L.qmc_enable_timing.restype = ctypes.c_int
         L.qmc_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]

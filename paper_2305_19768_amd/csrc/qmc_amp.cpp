@@ -1,0 +1,243 @@
+// qmc_amp.cpp -- adaptive evaluation of weighted sums of integrals (amplitudes).
+//
+// Implements the allocation of Sec. 2.1.3 of arXiv:2305.19768: each sector (the unit
+// with its own lattice size n_s, cost tau_s and convergence constant w_s) is first
+// sampled on a presample lattice; then every round forms the integrals, the weighted
+// sums and their variances, and for every sum/order that misses its error bound
+// chooses the sizes that minimise sum_s tau_s n_s subject to the target variance
+// (Lagrange closed form), keeping the largest request per sector, never shrinking,
+// rounding up to the table of available lattices.  Only sectors whose lattice changed
+// are integrated again.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "qmc_plan.h"
+
+using namespace qmc;
+
+namespace {
+
+struct Target {
+  int t, k;
+};
+
+// Cost of one evaluation in the units of the dense polynomial work: the slots the
+// nested Horner visits for U and F, the transform and the logarithm.
+double cost_model(const SectorDev &sd) {
+  const int d = sd.d;
+  auto slots = [d](int deg) {
+    const double c1 = d, c2 = d * (d + 1) / 2.0, c3 = d * (d + 1) * (d + 2) / 6.0;
+    return 1.0 + c1 + (deg >= 2 ? c2 : 0.0) + (deg >= 3 ? c3 : 0.0);
+  };
+  return slots(sd.u_deg) + slots(sd.f_deg) + 10.0 * d + ((sd.flags & SF_LOG) ? 40.0 : 0.0) + 20.0;
+}
+
+size_t ladder_ceil(const std::vector<uint64_t> &lad, double want, bool *limited) {
+  for (size_t l = 0; l < lad.size(); ++l)
+    if ((double)lad[l] >= want) return l;
+  if (limited) *limited = true;
+  return lad.size() - 1;
+}
+
+}  // namespace
+
+extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
+                                   const qmc_amp_options *opt, void *stream, double *value,
+                                   double *error, uint64_t *n_final, qmc_amp_stats *stats) {
+  g_last_error.clear();
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!p || !amp || !opt || !value || !error) return fail(QMC_E_INVAL, "NULL argument");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  const int S = p->S, K = p->K, m = p->m, NI = p->n_integrals;
+  const int T = amp->n_sums;
+  // ---- validate the sums
+  if (T < 1 || !amp->row_ptr) return fail(QMC_E_INVAL, "n_sums must be >= 1 with row_ptr");
+  if (amp->row_ptr[0] != 0) return fail(QMC_E_INVAL, "row_ptr[0] must be 0");
+  for (int t = 0; t < T; ++t)
+    if (amp->row_ptr[t + 1] < amp->row_ptr[t]) return fail(QMC_E_INVAL, "row_ptr not ascending");
+  const int64_t nnz = amp->row_ptr[T];
+  if (nnz > 0 && (!amp->col || !amp->coef_re)) return fail(QMC_E_INVAL, "missing coefficients");
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (amp->col[e] < 0 || amp->col[e] >= NI)
+      return fail(QMC_E_INVAL, "coefficient %lld: integral %d outside [0, %d)", (long long)e,
+                  amp->col[e], NI);
+    const double im = amp->coef_im ? amp->coef_im[e] : 0.0;
+    if (!std::isfinite(amp->coef_re[e]) || !std::isfinite(im))
+      return fail(QMC_E_INVAL, "coefficient %lld is not finite", (long long)e);
+  }
+  // ---- validate the options
+  if (!(opt->epsrel >= 0.0) || !(opt->epsabs >= 0.0) || (opt->epsrel == 0.0 && opt->epsabs == 0.0))
+    return fail(QMC_E_INVAL, "need epsrel >= 0, epsabs >= 0, not both 0");
+  if (!(opt->alpha > 0.0) || !std::isfinite(opt->alpha)) return fail(QMC_E_INVAL, "alpha must be > 0");
+  if (opt->max_rounds < 1) return fail(QMC_E_INVAL, "max_rounds must be >= 1");
+  if (opt->mode != QMC_AMP_HOST && opt->mode != QMC_AMP_DEVICE)
+    return fail(QMC_E_INVAL, "unknown mode %d", opt->mode);
+  if (opt->mode == QMC_AMP_DEVICE)
+    return fail(QMC_E_INVAL, "the device-side allocation mode is not available in this build");
+  if (opt->n_lattice < 1 || !opt->lattice_n || !opt->lattice_a)
+    return fail(QMC_E_INVAL, "a lattice table is required");
+  std::vector<uint64_t> lad(opt->lattice_n, opt->lattice_n + opt->n_lattice);
+  for (size_t l = 0; l < lad.size(); ++l) {
+    if (lad[l] < 2 || lad[l] > p->n_max)
+      return fail(QMC_E_INVAL, "lattice size %llu outside [2, n_max = %llu]",
+                  (unsigned long long)lad[l], (unsigned long long)p->n_max);
+    if (l && lad[l] <= lad[l - 1]) return fail(QMC_E_INVAL, "lattice sizes must ascend");
+    for (int d = 1; d <= QMC_MAX_DIM; ++d) {
+      bool used = false;
+      for (int s = 0; s < S && !used; ++s) used = p->dims[s] == d;
+      if (!used) continue;
+      const uint64_t n = lad[l], a = opt->lattice_a[l * QMC_MAX_DIM + d - 1] % n;
+      uint64_t z = 1 % n;
+      for (int j = 0; j < d; ++j, z = mulmod_host(z, a, n))
+        if (gcd_u64(z, n) != 1)
+          return fail(QMC_E_INVAL, "lattice %llu, d = %d: a = %llu gives z_%d sharing a factor with n",
+                      (unsigned long long)n, d, (unsigned long long)a, j + 1);
+    }
+  }
+  std::vector<double> tau(S);
+  for (int s = 0; s < S; ++s) {
+    tau[s] = opt->tau ? opt->tau[s] : cost_model(p->sec[s]);
+    if (!(tau[s] > 0.0) || !std::isfinite(tau[s])) return fail(QMC_E_INVAL, "tau[%d] must be > 0", s);
+  }
+  // coefficient |C|^2 of each sector's integral in each sum
+  std::vector<double> c2((size_t)T * NI, 0.0), cre((size_t)T * NI, 0.0), cim((size_t)T * NI, 0.0);
+  for (int t = 0; t < T; ++t)
+    for (int64_t e = amp->row_ptr[t]; e < amp->row_ptr[t + 1]; ++e) {
+      const double re = amp->coef_re[e], im = amp->coef_im ? amp->coef_im[e] : 0.0;
+      cre[(size_t)t * NI + amp->col[e]] += re;
+      cim[(size_t)t * NI + amp->col[e]] += im;
+    }
+  for (size_t i = 0; i < c2.size(); ++i) c2[i] = cre[i] * cre[i] + cim[i] * cim[i];
+
+  // ---- presample
+  bool limited = false;
+  std::vector<size_t> lidx(S, ladder_ceil(lad, (double)std::max<uint64_t>(opt->n_presample, 2), &limited));
+  std::vector<uint64_t> n(S), a(S);
+  std::vector<uint8_t> active(S, 1);
+  std::vector<double> mean((size_t)S * K), err((size_t)S * K);
+  double *dev_mean = (double *)(p->ws + p->off_mean), *dev_err = (double *)(p->ws + p->off_err);
+  hipStream_t st = (hipStream_t)stream;
+  int64_t evals = 0;
+  int rounds = 0;
+  bool converged = false, timed_out = false;
+  double max_eps = 0.0;
+  std::vector<double> Are((size_t)T * K), Aim((size_t)T * K), Vre((size_t)T * K), Vim((size_t)T * K);
+  qmc_status status = QMC_OK;
+  for (;;) {
+    for (int s = 0; s < S; ++s) {
+      n[s] = lad[lidx[s]];
+      a[s] = opt->lattice_a[lidx[s] * QMC_MAX_DIM + p->dims[s] - 1];
+      if (active[s]) evals += (int64_t)n[s] * m;
+    }
+    qmc_status r = integrate_sectors(p, n.data(), a.data(), active.data(), stream, nullptr,
+                                     dev_mean, dev_err);
+    if (r != QMC_OK) return r;
+    ++rounds;
+    int e;
+    if ((e = hipMemcpyAsync(mean.data(), dev_mean, sizeof(double) * mean.size(),
+                            hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(e, "read sector means");
+    if ((e = hipMemcpyAsync(err.data(), dev_err, sizeof(double) * err.size(),
+                            hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(e, "read sector errors");
+    if ((r = qmc_query_status(p, stream, nullptr, nullptr, nullptr)) != QMC_OK) return r;
+    // ---- integrals and sums
+    std::vector<double> I((size_t)NI * K, 0.0), VI((size_t)NI * K, 0.0);
+    for (int s = 0; s < S; ++s)
+      for (int k = 0; k < K; ++k) {
+        I[(size_t)p->sec[s].integral * K + k] += mean[(size_t)s * K + k];
+        VI[(size_t)p->sec[s].integral * K + k] += err[(size_t)s * K + k] * err[(size_t)s * K + k];
+      }
+    std::vector<Target> unmet;
+    max_eps = 0.0;
+    for (int t = 0; t < T; ++t)
+      for (int k = 0; k < K; ++k) {
+        double re = 0.0, im = 0.0, vre = 0.0, vim = 0.0;
+        for (int i = 0; i < NI; ++i) {
+          const double cr = cre[(size_t)t * NI + i], ci = cim[(size_t)t * NI + i];
+          const double v = I[(size_t)i * K + k], vv = VI[(size_t)i * K + k];
+          re += cr * v;
+          im += ci * v;
+          vre += cr * cr * vv;
+          vim += ci * ci * vv;
+        }
+        const size_t at = (size_t)t * K + k;
+        Are[at] = re;
+        Aim[at] = im;
+        Vre[at] = vre;
+        Vim[at] = vim;
+        const double mag2 = re * re + im * im, var = vre + vim;
+        const double eps = mag2 > 0.0 ? std::sqrt(var / mag2) : (var > 0.0 ? INFINITY : 0.0);
+        max_eps = std::max(max_eps, eps);
+        const bool ok = eps <= opt->epsrel || std::sqrt(var) <= opt->epsabs;
+        if (!ok) unmet.push_back({t, k});
+      }
+    if (unmet.empty()) {
+      converged = true;
+      break;
+    }
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (opt->timeout_s > 0.0 && secs >= opt->timeout_s) {
+      timed_out = true;
+      status = fail(QMC_E_TIMEOUT, "stopped after %.3f s with max relative error %.3g", secs,
+                    max_eps);
+      break;
+    }
+    if (rounds > opt->max_rounds) break;
+    // ---- allocation (sequential over the unmet targets, largest request kept)
+    const double al = opt->alpha;
+    std::vector<double> want(S);
+    for (int s = 0; s < S; ++s) want[s] = (double)n[s];
+    for (const Target &tg : unmet) {
+      const size_t at = (size_t)tg.t * K + tg.k;
+      const double mag2 = Are[at] * Are[at] + Aim[at] * Aim[at];
+      const double V = std::max(opt->epsrel * opt->epsrel * mag2, opt->epsabs * opt->epsabs);
+      if (!(V > 0.0)) continue;
+      double sum = 0.0;
+      std::vector<double> w(S, 0.0), cc(S, 0.0);
+      for (int s = 0; s < S; ++s) {
+        cc[s] = c2[(size_t)tg.t * NI + p->sec[s].integral];
+        const double var = err[(size_t)s * K + tg.k] * err[(size_t)s * K + tg.k];
+        w[s] = var * std::pow((double)n[s], al);
+        if (cc[s] * w[s] > 0.0) sum += std::pow(cc[s] * w[s] * std::pow(tau[s], al), 1.0 / (al + 1.0));
+      }
+      if (!(sum > 0.0)) continue;
+      const double lam = (1.0 / al) * std::pow(sum / V, (al + 1.0) / al);
+      for (int s = 0; s < S; ++s)
+        if (cc[s] * w[s] > 0.0)
+          want[s] = std::max(want[s], std::pow(al * w[s] * lam * cc[s] / tau[s], 1.0 / (al + 1.0)));
+    }
+    bool any = false;
+    for (int s = 0; s < S; ++s) {
+      const size_t l = std::max(lidx[s], ladder_ceil(lad, want[s], &limited));
+      active[s] = l != lidx[s];
+      any = any || active[s];
+      lidx[s] = l;
+    }
+    if (!any) break;   // every sector that matters already sits on the largest lattice
+  }
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < K; ++k) {
+      const size_t at = (size_t)t * K + k;
+      value[at * 2] = Are[at];
+      value[at * 2 + 1] = Aim[at];
+      error[at * 2] = std::sqrt(Vre[at]);
+      error[at * 2 + 1] = std::sqrt(Vim[at]);
+    }
+  if (n_final)
+    for (int s = 0; s < S; ++s) n_final[s] = lad[lidx[s]];
+  if (stats) {
+    stats->rounds = rounds;
+    stats->converged = converged ? 1 : 0;
+    stats->timed_out = timed_out ? 1 : 0;
+    stats->lattice_limited = limited ? 1 : 0;
+    stats->evaluations = evals;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    stats->max_eps_rel = max_eps;
+  }
+  return status;
+}

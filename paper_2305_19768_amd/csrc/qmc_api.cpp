@@ -17,11 +17,11 @@
 #include <string>
 #include <vector>
 
-#include "qmc_internal.h"
+#include "qmc_plan.h"
 
 using namespace qmc;
 
-namespace {
+namespace qmc {
 
 thread_local std::string g_last_error;
 
@@ -63,44 +63,7 @@ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-constexpr int64_t kTargetBlocks = 16384;   // workgroups per launch the chunking aims at
-constexpr int32_t kP2MaxCand = 65536;
-constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
-
-}  // namespace
-
-struct qmc_plan_s {
-  // problem
-  int32_t S = 0, K = 0, M = 0, n_integrals = 0, d_max = 0;
-  std::vector<SectorDev> sec;
-  std::vector<double> coef;
-  std::vector<double> shifts;          // [S][m][QMC_MAX_DIM]
-  std::vector<uint64_t> n_default, a_default;
-  std::vector<int32_t> dims;
-  std::vector<int32_t> order;          // sectors in workgroup order: by dimension, then index
-  // options
-  int32_t m = 0, precision = 0, block = 256, tile = 8, spp = 2;
-  uint64_t n_max = 0;
-  // workspace layout (byte offsets)
-  size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
-         off_status = 0, off_partial = 0, off_order = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
-         total = 0;
-  int64_t max_blocks = 0;
-  char *ws = nullptr;
-  size_t ws_bytes = 0;
-  // per-call staging
-  std::vector<LatticeDev> lat;
-  std::vector<int64_t> begin;
-  std::vector<LatticeDev> lat_uploaded;
-  bool lat_valid = false;
-  // kernel timing (HIP events around the main kernel of each qmc_integrate)
-  bool timing = false;
-  std::vector<hipEvent_t> ev;   // pairs: start, stop
-  size_t ev_used = 0;
-  ~qmc_plan_s() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-  }
-};
+}  // namespace qmc
 
 static void layout(qmc_plan_s *p) {
   size_t o = 0;
@@ -118,6 +81,8 @@ static void layout(qmc_plan_s *p) {
   p->off_begin = take(sizeof(int64_t) * (p->S + 1));
   p->off_order = take(sizeof(int32_t) * p->S);
   p->off_q = take(sizeof(double) * (size_t)p->S * p->m * p->K);
+  p->off_mean = take(sizeof(double) * (size_t)p->S * p->K);
+  p->off_err = take(sizeof(double) * (size_t)p->S * p->K);
   p->off_status = take(256);
   p->off_partial = take(sizeof(double) * 2 * (size_t)p->max_blocks * p->tile * p->K);
   p->off_p2cand = take(sizeof(uint64_t) * kP2MaxCand);
@@ -420,9 +385,13 @@ qmc_status qmc_set_shifts(qmc_plan_t p, const double *shifts, void *stream) {
   return QMC_OK;
 }
 
-qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_in, void *stream,
-                         double *dev_q, double *dev_mean, double *dev_err) {
-  g_last_error.clear();
+}  // extern "C"
+
+namespace qmc {
+
+qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t *a_in,
+                             const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
+                             double *dev_err) {
   if (!p) return fail(QMC_E_INVAL, "NULL plan");
   if (!dev_mean || !dev_err) return fail(QMC_E_INVAL, "dev_mean and dev_err are required");
   if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
@@ -430,13 +399,18 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
   // lattice table
   __int128 total = 0;
   for (int s = 0; s < p->S; ++s) {
+    LatticeDev &L = p->lat[s];
+    if (active && !active[s]) {   // keeps its previous Q; no workgroups
+      std::memset(&L, 0, sizeof L);
+      continue;
+    }
     const uint64_t n = n_in ? n_in[s] : p->n_default[s];
     if (n < 2 || n > p->n_max || n >= (1ull << 53))
       return fail(QMC_E_INVAL, "sector %d: n = %llu outside [2, n_max = %llu]", s,
                   (unsigned long long)n, (unsigned long long)p->n_max);
     const uint64_t a = (a_in ? a_in[s] : p->a_default[s]) % n;
-    LatticeDev &L = p->lat[s];
     std::memset(&L, 0, sizeof L);
+    L.active = 1;
     L.n = n;
     L.n_d = (double)n;
     L.inv_n = 1.0 / (double)n;
@@ -466,7 +440,7 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
     const int s = p->order[t];
     LatticeDev &L = p->lat[s];
     L.chunk = chunk;
-    L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
+    L.n_chunks = L.active ? (int32_t)((L.n + chunk - 1) / chunk) : 0;
     L.block_begin = b;
     p->begin[t] = b;
     const int fast = (p->sec[s].flags & SF_FAST) ? 1 : 0;
@@ -540,6 +514,16 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
   if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
   if ((e = launch_integrate(la, stream)) != hipSuccess) return hip_fail(e, "integrate launch");
   return QMC_OK;
+}
+
+}  // namespace qmc
+
+extern "C" {
+
+qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_in, void *stream,
+                         double *dev_q, double *dev_mean, double *dev_err) {
+  g_last_error.clear();
+  return integrate_sectors(p, n_in, a_in, nullptr, stream, dev_q, dev_mean, dev_err);
 }
 
 qmc_status qmc_query_status(qmc_plan_t p, void *stream, int32_t *sector, int32_t *shift,

@@ -49,8 +49,8 @@ struct alignas(16) LatticeDev {
   uint64_t dz[QMC_MAX_DIM];        // (workgroup size * z_j) mod n: lattice stride of a thread
   double ndz[QMC_MAX_DIM];         // n - dz_j as an exact double (the stride step subtracts it)
   int64_t chunk;                   // lattice points per workgroup
-  int32_t n_chunks;                // workgroups per shift tile
-  int32_t pad;
+  int32_t n_chunks;                // workgroups per shift tile (0 when inactive)
+  int32_t active;                  // 0: sector skipped by this launch, its Q is kept
 };
 
 // Workgroup partials: per (shift in tile, order): (sum, compensation).

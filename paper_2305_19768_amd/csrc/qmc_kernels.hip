@@ -680,6 +680,7 @@ __global__ __launch_bounds__(64) void qmc_reduce_kernel(LaunchArgs a) {
   const int K = a.K;
   const int tile = l / T, lt_ = l - tile * T;
   const LatticeDev *__restrict__ lat = a.lat + s;
+  if (!lat->active) return;   // sector not integrated by this launch: keep its Q
   const int nch = lat->n_chunks;
   const int64_t first = lat->block_begin + (int64_t)tile * nch;
   for (int kk = 0; kk < K; ++kk) {

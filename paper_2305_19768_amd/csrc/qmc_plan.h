@@ -1,0 +1,69 @@
+// qmc_plan.h -- host-side plan object shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "qmc_internal.h"
+
+namespace qmc {
+
+extern thread_local std::string g_last_error;
+qmc_status fail(qmc_status st, const char *fmt, ...);
+qmc_status hip_fail(int e, const char *what);
+uint64_t mulmod_host(uint64_t a, uint64_t b, uint64_t n);
+uint64_t gcd_u64(uint64_t a, uint64_t b);
+uint64_t splitmix64(uint64_t seed, uint64_t counter);
+size_t align256(size_t v);
+
+constexpr int64_t kTargetBlocks = 16384;   // workgroups per launch the chunking aims at
+constexpr int32_t kP2MaxCand = 65536;
+constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
+
+}  // namespace qmc
+
+struct qmc_plan_s {
+  // the plan's host state and the layout of its device workspace
+  // problem
+  int32_t S = 0, K = 0, M = 0, n_integrals = 0, d_max = 0;
+  std::vector<qmc::SectorDev> sec;
+  std::vector<double> coef;
+  std::vector<double> shifts;          // [S][m][QMC_MAX_DIM]
+  std::vector<uint64_t> n_default, a_default;
+  std::vector<int32_t> dims;
+  std::vector<int32_t> order;          // sectors in workgroup order: by dimension, then index
+  // options
+  int32_t m = 0, precision = 0, block = 256, tile = 8, spp = 2;
+  uint64_t n_max = 0;
+  // workspace layout (byte offsets)
+  size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
+         off_status = 0, off_partial = 0, off_order = 0, off_mean = 0, off_err = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
+         total = 0;
+  int64_t max_blocks = 0;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  // per-call staging
+  std::vector<qmc::LatticeDev> lat;
+  std::vector<int64_t> begin;
+  std::vector<qmc::LatticeDev> lat_uploaded;
+  bool lat_valid = false;
+  // kernel timing (HIP events around the main kernel of each qmc_integrate)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // pairs: start, stop
+  size_t ev_used = 0;
+  ~qmc_plan_s() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+
+namespace qmc {
+// Integrate the sectors with active[s] != 0 (all if active is NULL) on lattices n, a;
+// inactive sectors keep their previous Q.  Writes Q to dev_q (or the workspace) and
+// the statistics of every sector to dev_mean / dev_err.
+qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n, const uint64_t *a,
+                             const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
+                             double *dev_err);
+}  // namespace qmc

@@ -1,0 +1,80 @@
+"""GPU parity of amp_evaluate (adaptive weighted sums, Sec. 2.1.3) with the oracle's
+adaptive loop: same lattice table, costs and shifts give the same rounds and final
+lattice sizes, and sums within 1e-12 of the oracle's on their scale."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from test_oracle_adaptive import closed_form_problem, ladder
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qmc():
+    import __graft_entry__ as g
+    g._ensure_built()
+    import torch
+    import paper_2305_19768_amd as q
+    torch.cuda.set_device(0)
+    return q
+
+
+def _compare(qmc, prob, coef, sizes, a_tab, tau, epsrel, n_presample, **kw):
+    plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+    val, err, nfin, st = plan.amp_evaluate(coef, epsrel=epsrel, lattice_n=sizes, lattice_a=a_tab,
+                                           tau=tau, n_presample=n_presample, **kw)
+    ov, oe, on, orounds, oconv = oracle.adaptive_amplitude(prob, coef, sizes, a_tab, tau,
+                                                           epsrel=epsrel, n_presample=n_presample)
+    print("rounds", st["rounds"], orounds, "n", nfin, on, flush=True)
+    assert st["rounds"] == orounds
+    assert bool(st["converged"]) == oconv
+    assert np.array_equal(nfin, on)
+    scale = np.abs(ov) + np.abs(oe)
+    assert np.all(np.abs(val - ov) <= 1e-12 * scale)
+    assert np.allclose(err.real, oe.real, rtol=1e-8, atol=1e-12 * np.max(scale))
+    assert np.allclose(err.imag, oe.imag, rtol=1e-8, atol=1e-12 * np.max(scale))
+    return val, err, nfin, st
+
+
+def test_closed_form_amplitude_parity(qmc):
+    prob, exact = closed_form_problem()
+    coef = np.array([[2.0, -0.5 + 0.25j, 1.5j]])
+    sizes, a_tab = ladder()
+    tau = np.array([1.0, 1.0, 1.0, 1.0, 2.0, 2.0])
+    val, err, nfin, st = _compare(qmc, prob, coef, sizes, a_tab, tau, 1e-9, 1009)
+    assert st["converged"] and st["evaluations"] > 0
+    assert np.all(np.abs(val[0] - coef[0] @ exact) <= 6 * np.abs(err[0]) + 1e-14)
+
+
+def test_synthetic_amplitude_parity(qmc):
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    coef = np.array([prob.amp_coef, prob.amp_coef * (0.5 - 1j)])   # two sums, in order
+    _compare(qmc, prob, coef, sizes, a_tab, tau, 2e-6, 1009)
+
+
+def test_timeout_returns_valid_partial_results(qmc):
+    prob, _ = closed_form_problem()
+    sizes, a_tab = ladder()
+    plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+    val, err, nfin, st = plan.amp_evaluate([[1.0, 1.0, 1.0]], epsrel=1e-15, lattice_n=sizes,
+                                           lattice_a=a_tab, n_presample=1009, timeout_s=1e-9)
+    assert st["status"] == -5 and st["timed_out"] == 1 and st["rounds"] == 1
+    assert np.all(np.isfinite(val)) and np.all(np.abs(err) > 0)
+
+
+def test_invalid_amplitude_arguments(qmc):
+    prob, _ = closed_form_problem()
+    sizes, a_tab = ladder()
+    plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+    with pytest.raises(qmc.QmcError, match="ascend"):
+        plan.amp_evaluate([[1.0, 1.0, 1.0]], 1e-6, lattice_n=sizes[::-1].copy(),
+                          lattice_a=a_tab[::-1].copy())
+    with pytest.raises(qmc.QmcError, match="epsrel"):
+        plan.amp_evaluate([[1.0, 1.0, 1.0]], 0.0, lattice_n=sizes, lattice_a=a_tab)
+    with pytest.raises(qmc.QmcError, match="n_max"):
+        plan.amp_evaluate([[1.0, 1.0, 1.0]], 1e-6, lattice_n=np.array([2**40 + 15], np.uint64),
+                          lattice_a=np.ones((1, 8), np.uint64))

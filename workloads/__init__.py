@@ -297,3 +297,24 @@ def single_problem(sector: Sector, m: int = 8, seed: int = 0, order_lo: int = 0)
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 9])))
     return Problem(sectors=[sector], order_lo=order_lo, m=m,
                    shifts=[uniform_shifts(rng, m, sector.d)], seed=seed)
+
+
+def lattice_ladder(n_min: int = 10007, n_max: int = 2 ** 31 - 1, ratio: float = 1.5,
+                   n_cand: int = 8, seed: int = 0):
+    """Table of available lattice sizes (primes near n_min * ratio^l, up to n_max) with
+    n_cand random Korobov-parameter candidates per size and dimension (the role of a
+    precomputed generating-vector table).  Returns (sizes uint64 [L],
+    candidates uint64 [L, QMC_MAX_DIM = 8, n_cand])."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    sizes = []
+    v = float(n_min)
+    while True:
+        p = next_prime(int(math.ceil(v)))
+        if p > n_max:
+            break
+        if not sizes or p > sizes[-1]:
+            sizes.append(p)
+        v *= ratio
+    cands = np.stack([np.stack([_korobov_candidates(rng, n, n_cand) for _ in range(8)])
+                      for n in sizes])
+    return np.array(sizes, dtype=np.uint64), cands
