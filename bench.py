@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = library default)")
     ap.add_argument("--tile", type=int, default=0, help="shifts per workgroup (0 = default)")
     ap.add_argument("--spp", type=int, default=0, help="shifts per pass (0 = default)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-integrand measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -161,6 +162,24 @@ def main():
     plan.enable_timing(False)
     plan.check_status()
 
+    fp32 = None
+    if not args.no_fp32:
+        plan32 = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32, block=args.block,
+                          shift_tile=args.tile, shifts_per_pass=args.spp)
+        for _ in range(args.warmup):
+            plan32.integrate(out=out, check=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            plan32.integrate(out=out, check=False)
+        torch.cuda.synchronize()
+        e32 = time.perf_counter() - t1
+        plan32.check_status()
+        fp32 = {"value": prob.evals() * args.steps / e32, "unit": "evals/s",
+                "ms_per_step": e32 / args.steps * 1e3,
+                "note": "FP32 integrand, FP64 lattice points and accumulation"}
+        del plan32
+
     if args.copy_probe:
         a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -191,6 +210,7 @@ def main():
                      "kernel_ms": kernel_ms / max(launches, 1),
                      "algorithmic_flops_per_launch": flops_launch,
                      "flops_per_eval": flops_launch / evals},
+        "fp32": fp32,
         "plan_seconds": plan_s,
         "launch": {"block": args.block or 256, "shift_tile": args.tile or 16,
                    "shifts_per_pass": args.spp or 0},

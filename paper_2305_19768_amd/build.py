@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmcamp.so")
-SOURCES = ["qmc_kernels.hip", "qmc_api.cpp", "qmc_amp.cpp"]
+SOURCES = ["qmc_kernels.hip", "qmc_amp_kernels.hip", "qmc_api.cpp", "qmc_amp.cpp"]
 ARCH = os.environ.get("QMC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -27,11 +27,28 @@ def flags():
 
 
 def build(verbose: bool = False, extra=None) -> str:
-    cmd = [hipcc(), *flags(), *(extra or []), "-shared", "-o", LIB + ".tmp",
-           *[os.path.join(CSRC, s) for s in SOURCES]]
+    """Compiles every source to an object (in parallel), then links the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        jobs.append(([hipcc(), *flags(), *(extra or []), "-c", "-o", obj,
+                      os.path.join(CSRC, src)], obj))
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        for cmd, _ in jobs:
+            print(" ".join(cmd), flush=True)
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        for r in ex.map(lambda j: subprocess.run(j[0], capture_output=True, text=True), jobs):
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise subprocess.CalledProcessError(r.returncode, r.args)
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-o", LIB + ".tmp",
+            *[o for _, o in jobs]]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -42,6 +42,190 @@ size_t ladder_ceil(const std::vector<uint64_t> &lad, double want, bool *limited)
   return lad.size() - 1;
 }
 
+// Batched form: the rounds run on the device (round kernel, persistent integrand
+// kernel, reduction, statistics); the host queues a few rounds at a time and only reads
+// the state word between them.
+qmc_status amp_device(qmc_plan_s *p, int T, int NI, const std::vector<double> &cre,
+                      const std::vector<double> &cim, const std::vector<double> &c2,
+                      const std::vector<uint64_t> &lad, const qmc_amp_options *opt,
+                      const std::vector<double> &tau, void *stream, double *value, double *error,
+                      uint64_t *n_final, qmc_amp_stats *stats,
+                      std::chrono::steady_clock::time_point t_start) {
+  const int S = p->S, K = p->K;
+  for (int s = 0; s < S; ++s)
+    if (!(p->sec[s].flags & SF_FAST))
+      return fail(QMC_E_INVAL, "device mode evaluates sectors of the common shape only "
+                               "(korobov3, integer powers of U and F); sector %d is not", s);
+  if (T > kAmpMaxSums) return fail(QMC_E_INVAL, "device mode: at most %d sums", kAmpMaxSums);
+  if ((int)lad.size() > kAmpMaxLattice)
+    return fail(QMC_E_INVAL, "device mode: at most %d lattice sizes", kAmpMaxLattice);
+  const bool f32 = p->precision == QMC_PREC_FP32;
+  int &grid = p->persistent_grid[f32 ? 1 : 0];
+  int e;
+  if (!grid && (e = persistent_grid(p->d_max, f32, p->block, &grid)) != hipSuccess)
+    return hip_fail(e, "occupancy query");
+  // ---- device tables in the workspace
+  char *base = p->ws + p->off_amp;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    char *at = base + o;
+    o += align256(bytes);
+    return at;
+  };
+  AmpState *dst = (AmpState *)take(sizeof(AmpState));
+  int32_t *d_integral = (int32_t *)take(4 * S), *d_dims = (int32_t *)take(4 * S);
+  int32_t *d_lidx = (int32_t *)take(4 * S), *d_active = (int32_t *)take(4 * S);
+  double *d_want = (double *)take(8 * S), *d_tau = (double *)take(8 * S);
+  double *d_c2 = (double *)take(8 * kAmpMaxSums * NI), *d_cre = (double *)take(8 * kAmpMaxSums * NI);
+  double *d_cim = (double *)take(8 * kAmpMaxSums * NI);
+  double *d_I = (double *)take(8 * NI * K), *d_VI = (double *)take(8 * NI * K);
+  double *d_Are = (double *)take(8 * kAmpMaxSums * K), *d_Aim = (double *)take(8 * kAmpMaxSums * K);
+  double *d_Vre = (double *)take(8 * kAmpMaxSums * K), *d_Vim = (double *)take(8 * kAmpMaxSums * K);
+  int32_t *d_unmet = (int32_t *)take(4 * kAmpMaxSums * K);
+  uint64_t *d_ln = (uint64_t *)take(8 * kAmpMaxLattice);
+  uint64_t *d_la = (uint64_t *)take(8 * kAmpMaxLattice * QMC_MAX_DIM);
+  if (o > p->amp_bytes) return fail(QMC_E_NOMEM, "amplitude region too small");
+  std::vector<int32_t> integral(S), lidx(S);
+  size_t l0 = lad.size() - 1;
+  for (size_t l = 0; l < lad.size(); ++l)
+    if ((double)lad[l] >= (double)std::max<uint64_t>(opt->n_presample, 2)) {
+      l0 = l;
+      break;
+    }
+  for (int s = 0; s < S; ++s) {
+    integral[s] = p->sec[s].integral;
+    lidx[s] = (int32_t)l0;
+  }
+  AmpState init;
+  std::memset(&init, 0, sizeof init);
+  hipStream_t st = (hipStream_t)stream;
+  auto up = [&](void *dst_, const void *src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst_, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  if ((e = up(dst, &init, sizeof init)) || (e = up(d_integral, integral.data(), 4 * S)) ||
+      (e = up(d_dims, p->dims.data(), 4 * S)) || (e = up(d_lidx, lidx.data(), 4 * S)) ||
+      (e = up(d_tau, tau.data(), 8 * S)) || (e = up(d_c2, c2.data(), 8 * c2.size())) ||
+      (e = up(d_cre, cre.data(), 8 * cre.size())) || (e = up(d_cim, cim.data(), 8 * cim.size())) ||
+      (e = up(d_ln, lad.data(), 8 * lad.size())) ||
+      (e = up(d_la, opt->lattice_a, 8 * lad.size() * QMC_MAX_DIM)))
+    return hip_fail(e, "upload amplitude tables");
+  AmpArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.state = dst;
+  g.S = S;
+  g.K = K;
+  g.T = T;
+  g.NI = NI;
+  g.m = p->m;
+  g.tile = p->tile;
+  g.block = p->block;
+  g.n_lattice = (int32_t)lad.size();
+  g.max_rounds = opt->max_rounds;
+  g.epsrel = opt->epsrel;
+  g.epsabs = opt->epsabs;
+  g.alpha = opt->alpha;
+  g.integral = d_integral;
+  g.dims = d_dims;
+  g.order = (const int32_t *)(p->ws + p->off_order);
+  g.lidx = d_lidx;
+  g.active = d_active;
+  g.unmet = d_unmet;
+  g.want = d_want;
+  g.tau = d_tau;
+  g.c2 = d_c2;
+  g.cre = d_cre;
+  g.cim = d_cim;
+  g.I = d_I;
+  g.VI = d_VI;
+  g.Are = d_Are;
+  g.Aim = d_Aim;
+  g.Vre = d_Vre;
+  g.Vim = d_Vim;
+  g.mean = (const double *)(p->ws + p->off_mean);
+  g.err = (const double *)(p->ws + p->off_err);
+  g.lattice_n = d_ln;
+  g.lattice_a = d_la;
+  g.lat = (LatticeDev *)(p->ws + p->off_lat);
+  g.block_begin = (int64_t *)(p->ws + p->off_begin);
+  LaunchArgs la;
+  std::memset(&la, 0, sizeof la);
+  la.sectors = (const SectorDev *)(p->ws + p->off_sec);
+  la.coef = (const double *)(p->ws + p->off_coef);
+  la.coef32 = (const float *)(p->ws + p->off_coef32);
+  la.shifts = (const double *)(p->ws + p->off_shift);
+  la.lat = (const LatticeDev *)(p->ws + p->off_lat);
+  la.block_begin = (const int64_t *)(p->ws + p->off_begin);
+  la.order = (const int32_t *)(p->ws + p->off_order);
+  la.partial = (double *)(p->ws + p->off_partial);
+  la.q = (double *)(p->ws + p->off_q);
+  la.mean = (double *)(p->ws + p->off_mean);
+  la.err = (double *)(p->ws + p->off_err);
+  la.status = (int32_t *)(p->ws + p->off_status);
+  la.n_sectors = S;
+  la.m = p->m;
+  la.K = K;
+  la.shift_tile = p->tile;
+  la.shifts_per_pass = 2;
+  la.block = p->block;
+  la.d_max = p->d_max;
+  la.precision = p->precision;
+  la.done = &dst->done;
+  p->lat_valid = false;   // the device rewrites the lattice records
+  if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
+  AmpState hs;
+  bool timed_out = false;
+  for (;;) {
+    for (int r = 0; r < 4; ++r) {   // queue a few rounds; finished rounds return at once
+      if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");
+      if ((e = launch_persistent(la, dst, p->d_max, f32, (unsigned)grid, stream)) != hipSuccess)
+        return hip_fail(e, "persistent kernel");
+      if ((e = launch_reduce_stats(la, stream)) != hipSuccess) return hip_fail(e, "reduction");
+    }
+    if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");
+    if ((e = hipMemcpyAsync(&hs, dst, sizeof hs, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return hip_fail(e, "read state");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
+    qmc_status r = qmc_query_status(p, stream, nullptr, nullptr, nullptr);
+    if (r != QMC_OK) return r;
+    if (hs.done) break;
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (opt->timeout_s > 0.0 && secs >= opt->timeout_s) {
+      timed_out = true;
+      break;
+    }
+  }
+  std::vector<double> Are(T * K), Aim(T * K), Vre(T * K), Vim(T * K);
+  if ((e = hipMemcpyAsync(Are.data(), d_Are, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
+      (e = hipMemcpyAsync(Aim.data(), d_Aim, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
+      (e = hipMemcpyAsync(Vre.data(), d_Vre, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
+      (e = hipMemcpyAsync(Vim.data(), d_Vim, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
+      (e = hipMemcpyAsync(lidx.data(), d_lidx, 4 * S, hipMemcpyDeviceToHost, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "read results");
+  for (int i = 0; i < T * K; ++i) {
+    value[2 * i] = Are[i];
+    value[2 * i + 1] = Aim[i];
+    error[2 * i] = std::sqrt(Vre[i]);
+    error[2 * i + 1] = std::sqrt(Vim[i]);
+  }
+  if (n_final)
+    for (int s = 0; s < S; ++s) n_final[s] = lad[lidx[s]];
+  if (stats) {
+    stats->rounds = hs.rounds;
+    stats->converged = hs.done == 1;
+    stats->timed_out = timed_out;
+    stats->lattice_limited = hs.limited;
+    stats->evaluations = hs.evaluations;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    stats->max_eps_rel = hs.max_eps;
+  }
+  if (timed_out)
+    return fail(QMC_E_TIMEOUT, "stopped after the time limit with max relative error %.3g",
+                hs.max_eps);
+  return QMC_OK;
+}
+
 }  // namespace
 
 extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
@@ -75,8 +259,6 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
   if (opt->max_rounds < 1) return fail(QMC_E_INVAL, "max_rounds must be >= 1");
   if (opt->mode != QMC_AMP_HOST && opt->mode != QMC_AMP_DEVICE)
     return fail(QMC_E_INVAL, "unknown mode %d", opt->mode);
-  if (opt->mode == QMC_AMP_DEVICE)
-    return fail(QMC_E_INVAL, "the device-side allocation mode is not available in this build");
   if (opt->n_lattice < 1 || !opt->lattice_n || !opt->lattice_a)
     return fail(QMC_E_INVAL, "a lattice table is required");
   std::vector<uint64_t> lad(opt->lattice_n, opt->lattice_n + opt->n_lattice);
@@ -112,6 +294,9 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
     }
   for (size_t i = 0; i < c2.size(); ++i) c2[i] = cre[i] * cre[i] + cim[i] * cim[i];
 
+  if (opt->mode == QMC_AMP_DEVICE)
+    return amp_device(p, T, NI, cre, cim, c2, lad, opt, tau, stream, value, error, n_final, stats,
+                      t_start);
   // ---- presample
   bool limited = false;
   std::vector<size_t> lidx(S, ladder_ceil(lad, (double)std::max<uint64_t>(opt->n_presample, 2), &limited));

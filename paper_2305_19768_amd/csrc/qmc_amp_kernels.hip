@@ -1,0 +1,336 @@
+// qmc_amp_kernels.hip -- device-resident adaptive evaluation of weighted sums of
+// integrals (the batched form of amp_evaluate): a single-workgroup round kernel that
+// forms integrals, sums and errors, decides convergence and computes the next lattice
+// sizes with the closed form of Sec. 2.1.3 of arXiv:2305.19768 (same reading as the
+// host loop), and a persistent integrand kernel that drains the round's work items
+// (sector, chunk, shift tile) of every dimension from one atomic counter.  Every kernel
+// of a round returns at once when the state says the evaluation is finished, so the
+// host can queue several rounds and synchronise once.
+#include "qmc_device.h"
+
+namespace qmc {
+
+// ------------------------------------------------------------ round kernel
+
+constexpr int kRoundThreads = 256;
+
+__device__ __forceinline__ double block_sum_ordered(double v, double *sh) {
+  // deterministic: fixed thread -> slot assignment, fixed pairwise tree
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = kRoundThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] = sh[t] + sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int block_or(int v, int *sh) {
+  if (threadIdx.x == 0) *sh = 0;
+  __syncthreads();
+  if (v) atomicOr(sh, 1);
+  __syncthreads();
+  const int r = *sh;
+  __syncthreads();
+  return r;
+}
+
+// Lattice record of sector s on table entry l (validity was checked on the host).
+__device__ void set_lattice(const AmpArgs &g, int s, int l) {
+  LatticeDev &L = g.lat[s];
+  const uint64_t n = g.lattice_n[l];
+  const uint64_t a = g.lattice_a[l * QMC_MAX_DIM + g.dims[s] - 1] % n;
+  L.n = n;
+  L.n_d = (double)n;
+  L.inv_n = 1.0 / (double)n;
+  uint64_t z = 1 % n;
+  for (int j = 0; j < QMC_MAX_DIM; ++j) {
+    if (j < g.dims[s]) {
+      L.z[j] = z;
+      L.dz[j] = mulmod((uint64_t)g.block % n, z, n);
+      L.ndz[j] = (double)(n - L.dz[j]);
+    } else {
+      L.z[j] = 0;
+      L.dz[j] = 0;
+      L.ndz[j] = 0.0;
+    }
+    z = mulmod(z, a, n);
+  }
+  L.active = 1;
+}
+
+__global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g) {
+  AmpState *st = g.state;
+  if (st->done) return;
+  __shared__ double shd[kRoundThreads];
+  __shared__ int shi;
+  const int t = threadIdx.x;
+  const int S = g.S, K = g.K, T = g.T, NI = g.NI;
+
+  if (st->rounds > 0) {
+    // ---- integrals (sum of sectors, variances added) and sums, in a fixed order
+    for (int idx = t; idx < NI * K; idx += kRoundThreads) {
+      const int c = idx / K, k = idx - c * K;
+      double v = 0.0, var = 0.0;
+      for (int s = 0; s < S; ++s)
+        if (g.integral[s] == c) {
+          v += g.mean[s * K + k];
+          var += g.err[s * K + k] * g.err[s * K + k];
+        }
+      g.I[idx] = v;
+      g.VI[idx] = var;
+    }
+    __syncthreads();
+    int unmet_any = 0;
+    double eps_max = 0.0;
+    for (int idx = t; idx < T * K; idx += kRoundThreads) {
+      const int tt = idx / K, k = idx - tt * K;
+      double re = 0.0, im = 0.0, vre = 0.0, vim = 0.0;
+      for (int i = 0; i < NI; ++i) {
+        const double cr = g.cre[tt * NI + i], ci = g.cim[tt * NI + i];
+        const double v = g.I[i * K + k], vv = g.VI[i * K + k];
+        re += cr * v;
+        im += ci * v;
+        vre += cr * cr * vv;
+        vim += ci * ci * vv;
+      }
+      g.Are[idx] = re;
+      g.Aim[idx] = im;
+      g.Vre[idx] = vre;
+      g.Vim[idx] = vim;
+      const double mag2 = re * re + im * im, var = vre + vim;
+      const double eps = mag2 > 0.0 ? sqrt(var / mag2) : (var > 0.0 ? __builtin_inf() : 0.0);
+      eps_max = fmax(eps_max, eps);
+      const int ok = (eps <= g.epsrel) || (sqrt(var) <= g.epsabs);
+      g.unmet[idx] = !ok;
+      unmet_any |= !ok;
+    }
+    const int any = block_or(unmet_any, &shi);
+    // max eps over threads (order-independent)
+    shd[t] = eps_max;
+    __syncthreads();
+    for (int w = kRoundThreads / 2; w > 0; w >>= 1) {
+      if (t < w) shd[t] = fmax(shd[t], shd[t + w]);
+      __syncthreads();
+    }
+    if (t == 0) st->max_eps = shd[0];
+    __syncthreads();
+    if (!any) {
+      if (t == 0) st->done = 1;
+      return;
+    }
+    if (st->rounds > g.max_rounds) {
+      if (t == 0) st->done = 2;
+      return;
+    }
+    // ---- allocation: unmet targets in order, largest request per sector kept
+    const double al = g.alpha;
+    for (int s = t; s < S; s += kRoundThreads) g.want[s] = (double)g.lattice_n[g.lidx[s]];
+    __syncthreads();
+    for (int idx = 0; idx < T * K; ++idx) {
+      if (!g.unmet[idx]) continue;   // uniform
+      const int tt = idx / K, k = idx - tt * K;
+      const double mag2 = g.Are[idx] * g.Are[idx] + g.Aim[idx] * g.Aim[idx];
+      const double V = fmax(g.epsrel * g.epsrel * mag2, g.epsabs * g.epsabs);
+      if (!(V > 0.0)) continue;
+      double part = 0.0;
+      for (int s = t; s < S; s += kRoundThreads) {
+        const double cc = g.c2[tt * NI + g.integral[s]];
+        const double e = g.err[s * K + k];
+        const double w = e * e * pow((double)g.lattice_n[g.lidx[s]], al);
+        if (cc * w > 0.0) part += pow(cc * w * pow(g.tau[s], al), 1.0 / (al + 1.0));
+      }
+      const double sum = block_sum_ordered(part, shd);
+      if (!(sum > 0.0)) continue;
+      const double lam = (1.0 / al) * pow(sum / V, (al + 1.0) / al);
+      for (int s = t; s < S; s += kRoundThreads) {
+        const double cc = g.c2[tt * NI + g.integral[s]];
+        const double e = g.err[s * K + k];
+        const double w = e * e * pow((double)g.lattice_n[g.lidx[s]], al);
+        if (cc * w > 0.0)
+          g.want[s] = fmax(g.want[s], pow(al * w * lam * cc / g.tau[s], 1.0 / (al + 1.0)));
+      }
+      __syncthreads();
+    }
+    // ---- round up to the table, never shrink
+    int act_any = 0, lim_any = 0;
+    for (int s = t; s < S; s += kRoundThreads) {
+      int l = g.n_lattice - 1;
+      bool found = false;
+      for (int q = 0; q < g.n_lattice; ++q)
+        if ((double)g.lattice_n[q] >= g.want[s]) {
+          l = q;
+          found = true;
+          break;
+        }
+      if (!found) lim_any = 1;
+      if (l < g.lidx[s]) l = g.lidx[s];
+      const int act = l != g.lidx[s];
+      g.active[s] = act;
+      g.lidx[s] = l;
+      act_any |= act;
+    }
+    const int any_act = block_or(act_any, &shi);
+    const int lim = block_or(lim_any, &shi);
+    if (t == 0 && lim) st->limited = 1;
+    if (!any_act) {
+      if (t == 0) st->done = 3;
+      return;
+    }
+  } else {
+    for (int s = t; s < S; s += kRoundThreads) g.active[s] = 1;   // presample: every sector
+    __syncthreads();
+  }
+  // ---- lattice records of the active sectors, chunking and workgroup table
+  double pts = 0.0;
+  for (int s = t; s < S; s += kRoundThreads) {
+    if (g.active[s]) {
+      set_lattice(g, s, g.lidx[s]);
+      pts += (double)g.lattice_n[g.lidx[s]];
+    } else {
+      g.lat[s].active = 0;
+      g.lat[s].n_chunks = 0;
+    }
+  }
+  const double total_pts = block_sum_ordered(pts, shd);
+  if (t == 0) {
+    const int tiles = g.m / g.tile;
+    const double per_block = (double)kTargetBlocksDevice * g.block;
+    int64_t ppt = (int64_t)ceil(total_pts * tiles / per_block);
+    if (ppt < 1) ppt = 1;
+    const int64_t chunk = ppt * g.block;
+    int64_t b = 0, evals = 0;
+    for (int q = 0; q < S; ++q) {
+      const int s = g.order[q];
+      LatticeDev &L = g.lat[s];
+      L.chunk = chunk;
+      if (g.active[s]) {
+        L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
+        evals += (int64_t)L.n * g.m;
+      } else {
+        L.n_chunks = 0;
+      }
+      L.block_begin = b;
+      g.block_begin[q] = b;
+      b += (int64_t)L.n_chunks * tiles;
+    }
+    g.block_begin[S] = b;
+    st->total_blocks = b;
+    st->work_counter = 0;
+    st->evaluations += evals;
+    st->rounds += 1;
+  }
+}
+
+// -------------------------------------------------------- persistent kernel
+
+// Every sector of the fast path, all dimensions up to DMAX, in one launch: each
+// workgroup takes the next work item (sector, chunk, shift tile) from the round's
+// atomic counter until none is left, and writes its compensated partial exactly where
+// the per-dimension launch would, so the reduction and its order are unchanged.
+template <int D, int K, int S, bool F32>
+__device__ __forceinline__ void run_item(const LaunchArgs &a, int s, int l_begin, int T,
+                                         int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
+  if (F32 && (a.sectors[s].flags & SF_F32OK))
+    integrate_block<D, K, S, true, true>(a, s, l_begin, T, chunk_id, red);
+  else
+    integrate_block<D, K, S, true, false>(a, s, l_begin, T, chunk_id, red);
+}
+
+// The work item is the same for every lane; make that explicit so that the sector's
+// tables stay in scalar registers.
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int DMAX, int K, int S, bool F32>
+__global__ __launch_bounds__(256) void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
+  __shared__ double red[kMaxWaves][kMaxTile * 4][2];
+  __shared__ int64_t item;
+  if (st->done) return;
+  const int64_t total = st->total_blocks;
+  const int T = a.shift_tile;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(&st->work_counter, 1u);
+    __syncthreads();
+    const int64_t b = wave_uniform(item);
+    if (b >= total) break;
+    const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
+    const LatticeDev *__restrict__ lt = a.lat + s;
+    const int64_t local = b - lt->block_begin;
+    const int nch = lt->n_chunks;
+    const int tile_id = (int)(local / nch);
+    const int64_t chunk_id = local - (int64_t)tile_id * nch;
+    const int l_begin = tile_id * T;
+    switch (a.sectors[s].d) {
+      case 1: run_item<1, K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 2: if (DMAX >= 2) run_item<(DMAX >= 2 ? 2 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 3: if (DMAX >= 3) run_item<(DMAX >= 3 ? 3 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 4: if (DMAX >= 4) run_item<(DMAX >= 4 ? 4 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 5: if (DMAX >= 5) run_item<(DMAX >= 5 ? 5 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 6: if (DMAX >= 6) run_item<(DMAX >= 6 ? 6 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 7: if (DMAX >= 7) run_item<(DMAX >= 7 ? 7 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      default: if (DMAX >= 8) run_item<(DMAX >= 8 ? 8 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+    }
+    __syncthreads();
+    const int nwaves = blockDim.x >> 6;
+    if ((int)threadIdx.x < T * K) {
+      DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
+      for (int w = 1; w < nwaves; ++w) r = dd_combine(r, DD{red[w][threadIdx.x][0], red[w][threadIdx.x][1]});
+      double *out = a.partial + (b * (T * K) + threadIdx.x) * 2;
+      out[0] = r.s;
+      out[1] = r.c;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+int launch_amp_round(const AmpArgs &g, void *stream) {
+  hipLaunchKernelGGL(qmc_amp_round_kernel, dim3(1), dim3(kRoundThreads), 0, (hipStream_t)stream, g);
+  return (int)hipGetLastError();
+}
+
+template <int DMAX, bool F32>
+static hipError_t launch_pk(const LaunchArgs &a, AmpState *st, unsigned grid, hipStream_t s) {
+  switch (a.K) {
+    case 1: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 1, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
+    case 2: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 2, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
+    case 3: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 3, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
+    default: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 4, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
+  }
+  return hipGetLastError();
+}
+
+int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, bool f32, unsigned grid,
+                      void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (d_max <= 4) e = f32 ? launch_pk<4, true>(a, st, grid, s) : launch_pk<4, false>(a, st, grid, s);
+  else if (d_max <= 6) e = f32 ? launch_pk<6, true>(a, st, grid, s) : launch_pk<6, false>(a, st, grid, s);
+  else e = f32 ? launch_pk<8, true>(a, st, grid, s) : launch_pk<8, false>(a, st, grid, s);
+  return (int)e;
+}
+
+int persistent_grid(int d_max, bool f32, int block, int *grid) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return (int)e;
+  const void *fn;
+  if (d_max <= 4) fn = f32 ? (const void *)qmc_persistent_kernel<4, 3, 2, true> : (const void *)qmc_persistent_kernel<4, 3, 2, false>;
+  else if (d_max <= 6) fn = f32 ? (const void *)qmc_persistent_kernel<6, 3, 2, true> : (const void *)qmc_persistent_kernel<6, 3, 2, false>;
+  else fn = f32 ? (const void *)qmc_persistent_kernel<8, 3, 2, true> : (const void *)qmc_persistent_kernel<8, 3, 2, false>;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, block, 0);
+  if (e != hipSuccess) return (int)e;
+  *grid = cus * (per > 0 ? per : 1);
+  return 0;
+}
+
+}  // namespace qmc

@@ -76,6 +76,16 @@ static void layout(qmc_plan_s *p) {
   p->max_blocks = kTargetBlocks + (int64_t)p->S * tiles + 64;
   p->off_sec = take(sizeof(SectorDev) * p->S);
   p->off_coef = take(sizeof(double) * p->coef.size());
+  p->off_coef32 = take(sizeof(float) * p->coef.size());
+  {  // batched amplitude evaluation: state and tables, bounded by kAmpMaxSums sums and
+     // kAmpMaxLattice table entries
+    const size_t S = p->S, NI = p->n_integrals, K = p->K;
+    p->amp_bytes = align256(sizeof(AmpState)) + 4 * align256(4 * S) + 2 * align256(8 * S) +
+                   3 * align256(8 * kAmpMaxSums * NI) + 2 * align256(8 * NI * K) +
+                   4 * align256(8 * kAmpMaxSums * K) + align256(4 * kAmpMaxSums * K) +
+                   align256(8 * kAmpMaxLattice) + align256(8 * kAmpMaxLattice * QMC_MAX_DIM);
+    p->off_amp = take(p->amp_bytes);
+  }
   p->off_shift = take(sizeof(double) * p->shifts.size());
   p->off_lat = take(sizeof(LatticeDev) * p->S);
   p->off_begin = take(sizeof(int64_t) * (p->S + 1));
@@ -149,6 +159,13 @@ static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t
   return QMC_OK;
 }
 
+// 0: generic path, 1: fast path in FP64, 2: fast path in FP32.
+static int path_class(const qmc_plan_s *p, int s) {
+  const int f = p->sec[s].flags;
+  if (!(f & SF_FAST)) return 0;
+  return (p->precision == QMC_PREC_FP32 && (f & SF_F32OK)) ? 2 : 1;
+}
+
 static void split_pow2(int32_t e2, int32_t *num, int32_t *den, int32_t *half) {
   const int32_t mag = e2 < 0 ? -e2 : e2;
   *num = e2 > 0 ? mag / 2 : 0;
@@ -179,8 +196,6 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
     return fail(QMC_E_INVAL, "m must be in [2, %d]", QMC_MAX_SHIFTS);
   if (opt->precision != QMC_PREC_FP64 && opt->precision != QMC_PREC_FP32)
     return fail(QMC_E_INVAL, "unknown precision %d", opt->precision);
-  if (opt->precision == QMC_PREC_FP32)
-    return fail(QMC_E_INVAL, "FP32 integrand form is not available in this build");
   const int block = opt->block ? opt->block : 256;
   int tile = opt->shift_tile;
   if (!tile)  // largest power of two <= 16 dividing m
@@ -288,7 +303,17 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
     if (in.transform == QMC_TRANSFORM_KOROBOV3 && !(flags & (SF_XPOW | SF_HALF)) &&
         p->M <= p->K - 1)
       flags |= SF_FAST;
+    // FP32 eligibility: no cancellation in U or F on the cube and no vanishing divisor
+    if (flags & SF_FAST) {
+      bool ok = p->coef[sd.f_off] >= 1e-30;   // F >= its constant term > 0
+      for (int i = 0; i < dense_len(D) && ok; ++i)
+        ok = p->coef[sd.f_off + i] >= 0.0 && p->coef[sd.u_off + i] >= 0.0;
+      if (ok && sd.u_den > 0) ok = p->coef[sd.u_off] >= 1e-30;
+      if (ok) flags |= SF_F32OK;
+    }
     sd.flags = flags;
+    sd.u_off32 = sd.u_off;
+    sd.f_off32 = sd.f_off;
     for (int k = 0; k < QMC_MAX_ORDERS; ++k)
       for (int mm = 0; mm <= QMC_MAX_LOG; ++mm) {
         const double c = (k < p->K && mm <= p->M) ? in.logc[k][mm] : 0.0;
@@ -297,6 +322,7 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
           return fail(QMC_E_INVAL, "sector %d: non-finite logc[%d][%d]", s, k, mm);
         }
         sd.logc[k][mm] = c;
+        sd.logc32[k][mm] = (float)c;
       }
     p->n_default[s] = in.n;
     p->a_default[s] = in.a;
@@ -316,11 +342,12 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
         p->shifts[((size_t)s * p->m + l) * QMC_MAX_DIM + j] =
             (double)(splitmix64(opt->seed, c) >> 11) * 0x1.0p-53;
       }
+  p->coef32.assign(p->coef.begin(), p->coef.end());
   p->order.resize(p->S);
   for (int s = 0; s < p->S; ++s) p->order[s] = s;
-  // workgroup order: by dimension, then generic before fast path, then sector index
+  // workgroup order: by dimension, then path class (generic, fast FP64, fast FP32), then index
   std::stable_sort(p->order.begin(), p->order.end(), [&](int32_t x, int32_t y) {
-    const int fx = (p->sec[x].flags & SF_FAST) ? 1 : 0, fy = (p->sec[y].flags & SF_FAST) ? 1 : 0;
+    const int fx = path_class(p, x), fy = path_class(p, y);
     return p->dims[x] != p->dims[y] ? p->dims[x] < p->dims[y] : fx < fy;
   });
   layout(p);
@@ -350,6 +377,10 @@ qmc_status qmc_bind_workspace(qmc_plan_t p, void *dev, size_t bytes, void *strea
       (e = hipMemcpyAsync(p->ws + p->off_coef, p->coef.data(), sizeof(double) * p->coef.size(),
                           hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "upload coefficients");
+  if (!p->coef32.empty() &&
+      (e = hipMemcpyAsync(p->ws + p->off_coef32, p->coef32.data(), sizeof(float) * p->coef32.size(),
+                          hipMemcpyHostToDevice, st)) != hipSuccess)
+    return hip_fail(e, "upload FP32 coefficients");
   if ((e = hipMemcpyAsync(p->ws + p->off_shift, p->shifts.data(),
                           sizeof(double) * p->shifts.size(), hipMemcpyHostToDevice, st)) !=
       hipSuccess)
@@ -434,7 +465,7 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   if (ppt < 1) ppt = 1;
   const int64_t chunk = ppt * p->block;
   int64_t b = 0;
-  DimLaunch dl[2 * QMC_MAX_DIM];
+  DimLaunch dl[3 * QMC_MAX_DIM];
   int n_dl = 0;
   for (int t = 0; t < p->S; ++t) {
     const int s = p->order[t];
@@ -443,12 +474,16 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     L.n_chunks = L.active ? (int32_t)((L.n + chunk - 1) / chunk) : 0;
     L.block_begin = b;
     p->begin[t] = b;
-    const int fast = (p->sec[s].flags & SF_FAST) ? 1 : 0;
-    if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast) {
+    const int cls = path_class(p, s);
+    const int fast = cls >= 1 ? 1 : 0, f32 = cls == 2 ? 1 : 0;
+    if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
+        dl[n_dl - 1].f32 != f32) {
       dl[n_dl].d = p->dims[s];
       dl[n_dl].base = b;
       dl[n_dl].blocks = 0;
       dl[n_dl].fast = fast;
+      dl[n_dl].f32 = f32;
+      dl[n_dl].pad = 0;
       ++n_dl;
     }
     const int64_t nb = (int64_t)L.n_chunks * tiles;
@@ -478,6 +513,7 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   std::memset(&la, 0, sizeof la);
   la.sectors = (const SectorDev *)(p->ws + p->off_sec);
   la.coef = (const double *)(p->ws + p->off_coef);
+  la.coef32 = (const float *)(p->ws + p->off_coef32);
   la.shifts = (const double *)(p->ws + p->off_shift);
   la.lat = (const LatticeDev *)(p->ws + p->off_lat);
   la.block_begin = (const int64_t *)(p->ws + p->off_begin);

@@ -1,0 +1,798 @@
+// qmc_device.h -- device functions of the lattice QMC kernels (gfx950): compensated
+// sums, exact lattice points, periodizing transforms, dense nested-Horner polynomials,
+// the integrand orders in FP64 and FP32, and the body of one integration workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "qmc_internal.h"
+
+namespace qmc {
+
+// ----------------------------------------------------------- compensated sums
+
+struct DD {
+  double s, c;
+};
+
+// Knuth's TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void dd_add(DD &acc, double v) {
+  double s, e;
+  two_sum(acc.s, v, s, e);
+  acc.s = s;
+  acc.c += e;
+}
+
+__device__ __forceinline__ DD dd_combine(DD a, DD b) {
+  DD r;
+  double e;
+  two_sum(a.s, b.s, r.s, e);
+  r.c = (a.c + b.c) + e;
+  return r;
+}
+
+__device__ __forceinline__ DD wave_reduce(DD v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    DD o;
+    o.s = __shfl_xor(v.s, off, 64);
+    o.c = __shfl_xor(v.c, off, 64);
+    v = dd_combine(v, o);
+  }
+  return v;
+}
+
+// Opaque copy of a wave-uniform pointer: loads through the result cannot be hoisted
+// out of the loop iteration that launders it, so the per-sector tables are re-read
+// from the scalar cache each iteration instead of pinning hundreds of SGPRs.
+// The tables are read through the constant address space, where wave-uniform loads
+// are always scalar (s_load) loads.
+template <typename T>
+using cptr = const T __attribute__((address_space(4))) *;
+
+// A wave-uniform 64-bit value moved into scalar registers (a copy when it already is).
+__device__ __forceinline__ uint64_t to_sgpr64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T>
+__device__ __forceinline__ cptr<T> launder_uniform(const T *p) {
+  cptr<T> c = (cptr<T>)to_sgpr64((uint64_t)(uintptr_t)p);
+  asm volatile("" : "+s"(c));
+  return c;
+}
+
+// Launder that also waits for a per-lane value: the loads through the result cannot
+// start before `after` is computed.  Chaining each group of table reads to the
+// previous group's result bounds the number of table values held in SGPRs.
+template <typename T>
+__device__ __forceinline__ cptr<T> launder_after(cptr<T> c, double after) {
+  c = (cptr<T>)to_sgpr64((uint64_t)c);
+  asm volatile("" : "+s"(c) : "v"(after));
+  return c;
+}
+
+// ------------------------------------------------------------- lattice points
+
+// (a * b) mod n for a, b < n < 2^53 (double-and-add; used once per thread).
+__device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, uint64_t n) {
+  if ((a | b) < (1ull << 32)) return (a * b) % n;
+  uint64_t r = 0;
+  a %= n;
+  while (b) {
+    if (b & 1) {
+      r += a;
+      if (r >= n) r -= n;
+    }
+    a += a;
+    if (a >= n) a -= n;
+    b >>= 1;
+  }
+  return r;
+}
+
+// The lattice state k_j = i z_j mod n is carried as an exact double (k < n < 2^53).
+__device__ __forceinline__ double quotient(double kd, double n_d, double inv_n) {
+  const double q0 = kd * inv_n;
+  const double r = __builtin_fma(-q0, n_d, kd);  // exact residual
+  return __builtin_fma(r, inv_n, q0);
+}
+
+// k <- (k + dz) mod n as k - (n - dz), plus n if negative: every value is an integer of
+// magnitude below 2^53, so both operations are exact.
+__device__ __forceinline__ double lattice_step(double kd, double ndz, double n_d) {
+  const double t = kd - ndz;
+  return (t < 0.0) ? t + n_d : t;
+}
+
+// frac(q + Delta) for q, Delta in [0, 1): q + Delta < 2 and the fraction is exact.
+__device__ __forceinline__ double shifted(double q, double delta) {
+  return __builtin_amdgcn_fract(q + delta);
+}
+
+// ---------------------------------------------------------------- transforms
+
+// korobov_r: x = I_y(r+1, r+1) = y^(r+1) * poly_r(y), w = C_r (y (1 - y))^r.
+// Generic korobov_r for r = 1..6, coefficients of poly_r in ascending powers.
+__device__ __forceinline__ void korobov_generic(int r, double y, double &x, double &w) {
+  // poly_r(y) such that I_y(r+1, r+1) = y^(r+1) poly_r(y); C_r = (2r+1)!/(r!)^2.
+  // r = 1: 3 - 2y;  r = 2: 10 - 15y + 6y^2;  r = 3: 35 - 84y + 70y^2 - 20y^3;
+  // r = 4: 126 - 420y + 540y^2 - 315y^3 + 70y^4;
+  // r = 5: 462 - 1980y + 3465y^2 - 3080y^3 + 1386y^4 - 252y^5;
+  // r = 6: 1716 - 9009y + 20020y^2 - 24024y^3 + 16380y^4 - 6006y^5 + 924y^6.
+  double t = y * (1.0 - y);
+  double p, c, tr, yr;
+  switch (r) {
+    case 1:
+      p = __builtin_fma(-2.0, y, 3.0);
+      c = 6.0;
+      tr = t;
+      yr = y * y;
+      break;
+    case 2:
+      p = __builtin_fma(__builtin_fma(6.0, y, -15.0), y, 10.0);
+      c = 30.0;
+      tr = t * t;
+      yr = y * y * y;
+      break;
+    case 4:
+      p = __builtin_fma(
+          __builtin_fma(__builtin_fma(__builtin_fma(70.0, y, -315.0), y, 540.0), y, -420.0), y,
+          126.0);
+      c = 630.0;
+      tr = (t * t) * (t * t);
+      yr = (y * y) * (y * y) * y;
+      break;
+    case 5:
+      p = __builtin_fma(
+          __builtin_fma(
+              __builtin_fma(__builtin_fma(__builtin_fma(-252.0, y, 1386.0), y, -3080.0), y,
+                            3465.0),
+              y, -1980.0),
+          y, 462.0);
+      c = 2772.0;
+      tr = (t * t) * (t * t) * t;
+      yr = (y * y) * (y * y) * (y * y);
+      break;
+    case 6:
+      p = __builtin_fma(
+          __builtin_fma(
+              __builtin_fma(
+                  __builtin_fma(__builtin_fma(__builtin_fma(924.0, y, -6006.0), y, 16380.0), y,
+                                -24024.0),
+                  y, 20020.0),
+              y, -9009.0),
+          y, 1716.0);
+      c = 12012.0;
+      tr = (t * t) * (t * t) * (t * t);
+      yr = (y * y) * (y * y) * (y * y) * y;
+      break;
+    default:  // r = 3
+      p = __builtin_fma(__builtin_fma(__builtin_fma(-20.0, y, 70.0), y, -84.0), y, 35.0);
+      c = 140.0;
+      tr = t * t * t;
+      yr = (y * y) * (y * y);
+      break;
+  }
+  w = c * tr;
+  x = yr * p;
+}
+
+template <int D>
+__device__ __forceinline__ double apply_transform(int kind, double w_scale, const double (&y)[D],
+                                                  double (&x)[D]) {
+  double W = 1.0;
+  if (kind == QMC_TRANSFORM_KOROBOV3) {
+    // x_j = y^4 (35 - 84 y + 70 y^2 - 20 y^3);  W = 140^d (prod_j y_j (1 - y_j))^3
+    double T = 1.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double yj = y[j];
+      const double p =
+          __builtin_fma(__builtin_fma(__builtin_fma(-20.0, yj, 70.0), yj, -84.0), yj, 35.0);
+      const double y2 = yj * yj;
+      x[j] = (y2 * y2) * p;
+      T *= yj * (1.0 - yj);
+    }
+    W = w_scale * (T * T * T);
+  } else if (kind == QMC_TRANSFORM_BAKER) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = 1.0 - __builtin_fabs(2.0 * y[j] - 1.0);
+  } else if (kind == QMC_TRANSFORM_NONE) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) x[j] = y[j];
+  } else {
+    const int r = kind - QMC_TRANSFORM_KOROBOV1 + 1;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double w;
+      korobov_generic(r, y[j], x[j], w);
+      W *= w;
+    }
+  }
+  return W;
+}
+
+// -------------------------------------------------------------- polynomials
+
+// Dense nested Horner of total degree DEG (<= 3) over the degree-3 layout, for S
+// points at once (each scalar coefficient feeds S FMAs).  The scalar loads of each
+// (j, k) group go through a pointer laundered after the result of the group two steps
+// back: a group's coefficients can arrive while the previous group computes, and at
+// most two groups' coefficients (<= 2 (QMC_MAX_DIM + 1) doubles) occupy SGPRs.
+#ifndef QMC_CHAIN_LAG
+#define QMC_CHAIN_LAG 1
+#endif
+struct LoadChain {
+  double dep1, dep2;   // results of the last two groups
+  __device__ __forceinline__ cptr<double> next(cptr<double> c) const {
+    return launder_after(c, QMC_CHAIN_LAG == 1 ? dep1 : dep2);
+  }
+  __device__ __forceinline__ void done(double v) {
+    dep2 = dep1;
+    dep1 = v;
+  }
+};
+
+template <int D, int DEG, int S>
+__device__ __forceinline__ void horner(cptr<double> c, const double (&x)[S][D], double (&out)[S],
+                                       LoadChain &ch) {
+  c = ch.next(c);
+  double acc[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) acc[u] = c[0];
+  int p = 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    c = ch.next(c);
+    double g[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) g[u] = c[p];
+    ++p;
+    if (DEG >= 2) {
+#pragma unroll
+      for (int k = j; k < D; ++k) {
+        if (DEG >= 3) c = ch.next(c);
+        double h[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u) h[u] = c[p];
+        ++p;
+        if (DEG >= 3) {
+#pragma unroll
+          for (int l = k; l < D; ++l)
+#pragma unroll
+            for (int u = 0; u < S; ++u) h[u] = __builtin_fma(c[p + l - k], x[u][l], h[u]);
+          ch.done(h[0]);
+        }
+        p += D - k;
+#pragma unroll
+        for (int u = 0; u < S; ++u) g[u] = __builtin_fma(x[u][k], h[u], g[u]);
+      }
+    } else {
+      p += (D - j) * (D - j + 3) / 2;   // skip the degree-2 and degree-3 slots of this j
+    }
+#pragma unroll
+    for (int u = 0; u < S; ++u) acc[u] = __builtin_fma(x[u][j], g[u], acc[u]);
+    ch.done(acc[0]);
+  }
+#pragma unroll
+  for (int u = 0; u < S; ++u) out[u] = acc[u];
+}
+
+template <int D, int S>
+__device__ __forceinline__ void poly(cptr<double> c, int deg, const double (&x)[S][D],
+                                     double (&out)[S], LoadChain &ch) {
+  if (deg >= 3) horner<D, 3, S>(c, x, out, ch);
+  else if (deg == 2) horner<D, 2, S>(c, x, out, ch);
+  else horner<D, 1, S>(c, x, out, ch);
+}
+
+// 1/v to within an ulp or two: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = __builtin_fma(__builtin_fma(-v, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-v, r, 1.0), r, r);
+  return r;
+}
+
+// Natural logarithm of log F, accurate to a few ulp.  x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.1716, by the
+// Taylor series atanh(s) = s sum_k s^(2k)/(2k+1) through s^19 (remainder below 2.4e-17
+// relative); e ln 2 with ln 2 split into a 32-bit head (e * head exact) and a tail.
+// log(0) = -inf, log(+inf) = +inf, negative or NaN input gives NaN.
+__device__ __forceinline__ double log_f64(double x) {
+  constexpr double kLn2Hi = 0x1.62e42ffp-1;
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+  double m = __builtin_amdgcn_frexp_mant(x);   // [0.5, 1) for finite non-zero x
+  int e = __builtin_amdgcn_frexp_exp(x);
+  const bool low = m < 0.70710678118654752;
+  m = low ? m + m : m;
+  e = low ? e - 1 : e;
+  const double s = (m - 1.0) * recip(m + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 19.0;
+  p = __builtin_fma(p, z, 1.0 / 17.0);
+  p = __builtin_fma(p, z, 1.0 / 15.0);
+  p = __builtin_fma(p, z, 1.0 / 13.0);
+  p = __builtin_fma(p, z, 1.0 / 11.0);
+  p = __builtin_fma(p, z, 1.0 / 9.0);
+  p = __builtin_fma(p, z, 1.0 / 7.0);
+  p = __builtin_fma(p, z, 1.0 / 5.0);
+  p = __builtin_fma(p, z, 1.0 / 3.0);
+  const double logm = 2.0 * __builtin_fma(s * z, p, s);
+  const double ed = (double)e;
+  double r = __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, logm));
+  const bool ok = x > 0.0 && x < __builtin_inf();
+  return ok ? r : (x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan("")));
+}
+
+__device__ __forceinline__ double ipow_u(double v, int e) {
+  double r = 1.0;
+  for (int t = 0; t < e; ++t) r *= v;
+  return r;
+}
+
+// Per-sector scalars read once per workgroup (they stay in SGPRs).
+struct SectorScalars {
+  int flags, u_deg, f_deg, u_num, u_den, f_num, f_den, f_half, max_log;
+  int u_off, f_off, u_off32, f_off32;
+};
+
+__device__ __forceinline__ SectorScalars load_scalars(const SectorDev *sd) {
+  SectorScalars r;
+  r.flags = sd->flags;
+  r.u_deg = sd->u_deg;
+  r.f_deg = sd->f_deg;
+  r.u_num = sd->u_num;
+  r.u_den = sd->u_den;
+  r.f_num = sd->f_num;
+  r.f_den = sd->f_den;
+  r.f_half = sd->f_half;
+  r.max_log = sd->max_log;
+  r.u_off = sd->u_off;
+  r.f_off = sd->f_off;
+  r.u_off32 = sd->u_off32;
+  r.f_off32 = sd->f_off32;
+  return r;
+}
+
+// Integrand orders f_k(x) (without the transform weight) for S samples.
+template <int D, int K, int S>
+__device__ __forceinline__ void integrand(const SectorScalars &ss, cptr<SectorDev> sd,
+                                          cptr<double> coef, const double (&x)[S][D],
+                                          double (&f)[S][K]) {
+  const int flags = ss.flags;
+  double U[S], F[S];
+  LoadChain ch{x[0][0], x[0][0]};
+  poly<D, S>(coef + ss.u_off, ss.u_deg, x, U, ch);
+  poly<D, S>(coef + ss.f_off, ss.f_deg, x, F, ch);
+  double B[S];
+  cptr<SectorDev> sx = launder_after(sd, F[0]);
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    double num = 1.0, den = 1.0, hn = 1.0, hd = 1.0;
+    if (flags & SF_XPOW) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        num *= ipow_u(x[u][j], sx->x_num[j]);
+        den *= ipow_u(x[u][j], sx->x_den[j]);
+        const int h = sx->x_half[j];
+        if (h > 0) hn *= x[u][j];
+        if (h < 0) hd *= x[u][j];
+      }
+    }
+    num *= ipow_u(U[u], ss.u_num);
+    den *= ipow_u(U[u], ss.u_den);
+    num *= ipow_u(F[u], ss.f_num);
+    den *= ipow_u(F[u], ss.f_den);
+    if (flags & SF_HALF) {
+      if (ss.f_half > 0) hn *= F[u];
+      if (ss.f_half < 0) hd *= F[u];
+      // sqrt(hn / hd) = sqrt(hn hd) / hd
+      B[u] = (num * sqrt(hn * hd)) * recip(den * hd);
+    } else if (flags & SF_DEN) {
+      B[u] = num * recip(den);
+    } else {
+      B[u] = num;
+    }
+  }
+  const int M = ss.max_log;
+  cptr<SectorDev> sl = launder_after(sd, B[0]);
+  if (flags & SF_LOG) {
+    double L[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) L[u] = log_f64(F[u]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v[S];
+#pragma unroll
+      for (int u = 0; u < S; ++u) v[u] = sl->logc[k][M];
+      for (int m = M - 1; m >= 0; --m) {
+        const double cm = sl->logc[k][m];
+#pragma unroll
+        for (int u = 0; u < S; ++u) v[u] = __builtin_fma(v[u], L[u], cm);
+      }
+#pragma unroll
+      for (int u = 0; u < S; ++u) f[u][k] = B[u] * v[u];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int u = 0; u < S; ++u) f[u][k] = B[u] * sl->logc[k][0];
+  }
+}
+
+// Integrand orders for the common sector shape (the plan sets SF_FAST): integer
+// exponents of U and F only, no powers of x_j, and log F polynomials of degree at most
+// K - 1 (the plan zero-pads them to that degree).  Straight-line code apart from the
+// uniform exponent loops, which are shared by the S samples.
+template <int D, int K, int S>
+__device__ __forceinline__ void integrand_fast(const SectorScalars &ss, cptr<SectorDev> sd,
+                                               cptr<double> coef, const double (&x)[S][D],
+                                               double (&f)[S][K]) {
+  double U[S], F[S];
+  LoadChain ch{x[0][0], x[0][0]};
+  poly<D, S>(coef + ss.u_off, ss.u_deg, x, U, ch);
+  poly<D, S>(coef + ss.f_off, ss.f_deg, x, F, ch);
+  double num[S], den[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) num[u] = den[u] = 1.0;
+  for (int t = 0; t < ss.u_num; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) num[u] *= U[u];
+  for (int t = 0; t < ss.u_den; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) den[u] *= U[u];
+  for (int t = 0; t < ss.f_num; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) num[u] *= F[u];
+  for (int t = 0; t < ss.f_den; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) den[u] *= F[u];
+  double B[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) B[u] = num[u] * recip(den[u]);
+  cptr<SectorDev> sl = launder_after(sd, B[0]);
+  if (K > 1) {
+    double L[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) L[u] = log_f64(F[u]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v[S];
+#pragma unroll
+      for (int u = 0; u < S; ++u) v[u] = sl->logc[k][K - 1];
+#pragma unroll
+      for (int m = K - 2; m >= 0; --m) {
+        const double cm = sl->logc[k][m];
+#pragma unroll
+        for (int u = 0; u < S; ++u) v[u] = __builtin_fma(v[u], L[u], cm);
+      }
+#pragma unroll
+      for (int u = 0; u < S; ++u) f[u][k] = B[u] * v[u];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < S; ++u) f[u][0] = B[u] * sl->logc[0][0];
+  }
+}
+
+// korobov3 on S samples: x = y^4 (35 - 84 y + 70 y^2 - 20 y^3), W = 140^d (prod y(1-y))^3.
+template <int D, int S>
+__device__ __forceinline__ void korobov3_fast(double w_scale, const double (&y)[S][D],
+                                              double (&x)[S][D], double (&W)[S]) {
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    double T = 1.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double yj = y[u][j];
+      const double p =
+          __builtin_fma(__builtin_fma(__builtin_fma(-20.0, yj, 70.0), yj, -84.0), yj, 35.0);
+      const double y2 = yj * yj;
+      x[u][j] = (y2 * y2) * p;
+      T *= yj * (1.0 - yj);
+    }
+    W[u] = w_scale * (T * T * T);
+  }
+}
+
+// --------------------------------------------------------- FP32 integrand form
+// The same fast-path integrand with the transform, polynomials, powers, logarithm and
+// orders in FP32 (coefficients from the FP32 copy of the tables); the lattice point
+// stays FP64 and every contribution is accumulated in FP64.  Used for sectors whose F
+// has no cancellation and a positive constant term (SF_F32OK), where FP32 keeps a
+// relative accuracy of a few ulp in every factor.
+__device__ __forceinline__ cptr<float> launder_after_f(cptr<float> c, float after) {
+  c = (cptr<float>)to_sgpr64((uint64_t)c);
+  asm volatile("" : "+s"(c) : "v"(after));
+  return c;
+}
+
+struct LoadChainF {
+  float dep1;
+  __device__ __forceinline__ cptr<float> next(cptr<float> c) const { return launder_after_f(c, dep1); }
+  __device__ __forceinline__ void done(float v) { dep1 = v; }
+};
+
+template <int D, int DEG, int S>
+__device__ __forceinline__ void horner_f32(cptr<float> c, const float (&x)[S][D], float (&out)[S],
+                                           LoadChainF &ch) {
+  c = ch.next(c);
+  float acc[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) acc[u] = c[0];
+  int p = 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    c = ch.next(c);
+    float g[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) g[u] = c[p];
+    ++p;
+    if (DEG >= 2) {
+#pragma unroll
+      for (int k = j; k < D; ++k) {
+        if (DEG >= 3) c = ch.next(c);
+        float h[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u) h[u] = c[p];
+        ++p;
+        if (DEG >= 3) {
+#pragma unroll
+          for (int l = k; l < D; ++l)
+#pragma unroll
+            for (int u = 0; u < S; ++u) h[u] = __builtin_fmaf(c[p + l - k], x[u][l], h[u]);
+          ch.done(h[0]);
+        }
+        p += D - k;
+#pragma unroll
+        for (int u = 0; u < S; ++u) g[u] = __builtin_fmaf(x[u][k], h[u], g[u]);
+      }
+    } else {
+      p += (D - j) * (D - j + 3) / 2;
+    }
+#pragma unroll
+    for (int u = 0; u < S; ++u) acc[u] = __builtin_fmaf(x[u][j], g[u], acc[u]);
+    ch.done(acc[0]);
+  }
+#pragma unroll
+  for (int u = 0; u < S; ++u) out[u] = acc[u];
+}
+
+template <int D, int S>
+__device__ __forceinline__ void poly_f32(cptr<float> c, int deg, const float (&x)[S][D],
+                                         float (&out)[S], LoadChainF &ch) {
+  if (deg >= 3) horner_f32<D, 3, S>(c, x, out, ch);
+  else if (deg == 2) horner_f32<D, 2, S>(c, x, out, ch);
+  else horner_f32<D, 1, S>(c, x, out, ch);
+}
+
+template <int D, int K, int S>
+__device__ __forceinline__ void integrand_fast_f32(const SectorScalars &ss, cptr<SectorDev> sd,
+                                                   cptr<float> coef, const float (&x)[S][D],
+                                                   float (&f)[S][K]) {
+  float U[S], F[S];
+  LoadChainF ch{x[0][0]};
+  poly_f32<D, S>(coef + ss.u_off32, ss.u_deg, x, U, ch);
+  poly_f32<D, S>(coef + ss.f_off32, ss.f_deg, x, F, ch);
+  float num[S], den[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) num[u] = den[u] = 1.0f;
+  for (int t = 0; t < ss.u_num; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) num[u] *= U[u];
+  for (int t = 0; t < ss.u_den; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) den[u] *= U[u];
+  for (int t = 0; t < ss.f_num; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) num[u] *= F[u];
+  for (int t = 0; t < ss.f_den; ++t)
+#pragma unroll
+    for (int u = 0; u < S; ++u) den[u] *= F[u];
+  float B[S];
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    float r = __builtin_amdgcn_rcpf(den[u]);
+    r = __builtin_fmaf(__builtin_fmaf(-den[u], r, 1.0f), r, r);   // one Newton step
+    B[u] = num[u] * r;
+  }
+  cptr<SectorDev> sl = launder_after(sd, (double)B[0]);
+  if (K > 1) {
+    float L[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) L[u] = __builtin_amdgcn_logf(F[u]) * 0.693147180559945309f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      float v[S];
+#pragma unroll
+      for (int u = 0; u < S; ++u) v[u] = sl->logc32[k][K - 1];
+#pragma unroll
+      for (int m = K - 2; m >= 0; --m) {
+        const float cm = sl->logc32[k][m];
+#pragma unroll
+        for (int u = 0; u < S; ++u) v[u] = __builtin_fmaf(v[u], L[u], cm);
+      }
+#pragma unroll
+      for (int u = 0; u < S; ++u) f[u][k] = B[u] * v[u];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < S; ++u) f[u][0] = B[u] * sl->logc32[0][0];
+  }
+}
+
+template <int D, int S>
+__device__ __forceinline__ void korobov3_f32(float w_scale, const float (&y)[S][D],
+                                             float (&x)[S][D], float (&W)[S]) {
+#pragma unroll
+  for (int u = 0; u < S; ++u) {
+    float T = 1.0f;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const float yj = y[u][j];
+      const float p =
+          __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(-20.0f, yj, 70.0f), yj, -84.0f), yj, 35.0f);
+      const float y2 = yj * yj;
+      x[u][j] = (y2 * y2) * p;
+      T *= yj * (1.0f - yj);
+    }
+    W[u] = w_scale * (T * T * T);
+  }
+}
+
+// ------------------------------------------------------------- main kernel
+
+// Workgroup -> sector by binary search over the launch's first-workgroup table.
+__device__ __forceinline__ int find_sector(const int64_t *__restrict__ begin, int S, int64_t b) {
+  int lo = 0, hi = S;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (begin[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Maximum shifts per workgroup and waves per workgroup (LDS staging of the partials).
+constexpr int kMaxTile = 16;
+constexpr int kMaxWaves = 4;
+
+// Lattice points a thread sums in plain FP64 before folding the partial into its
+// compensated (TwoSum) accumulator.
+constexpr int kFold = 8;
+
+// One workgroup: sector s, shifts [l_begin, l_begin + tile), lattice points of one
+// chunk.  The shifts are processed S at a time: for each point the quotient k/n is
+// formed once and reused by the S shifts of the pass, whose S*K accumulators stay in
+// registers.  Each accumulator is a plain partial over at most kFold points folded
+// into a (sum, compensation) pair.  After each pass the pairs are reduced over the
+// wavefront and staged in LDS.
+template <int D, int K, int S, bool FAST, bool F32>
+__device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int l_begin, int tile,
+                                                int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
+  const SectorDev *__restrict__ sd = a.sectors + s;
+  const LatticeDev *__restrict__ lt = a.lat + s;
+  const uint64_t n = lt->n;
+  const double n_d = lt->n_d, inv_n = lt->inv_n;
+  const int64_t chunk = lt->chunk;
+  const uint64_t i_begin = (uint64_t)(chunk_id * chunk);
+  uint64_t i_end = i_begin + (uint64_t)chunk;
+  if (i_end > n) i_end = n;
+  const int kind = sd->transform;
+  const double w_scale = sd->w_scale;
+  const SectorScalars ss = load_scalars(sd);
+  const uint64_t B = blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  // every lane runs the same number of iterations; lanes past i_end contribute 0
+  const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
+
+  // lattice state of this thread at its first point i0: k_j = i0 z_j mod n
+  double k0[D];
+  const uint64_t i0 = i_begin + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < D; ++j) k0[j] = (double)mulmod(i0 % n, lt->z[j], n);
+
+#pragma unroll 1
+  for (int l0 = 0; l0 < tile; l0 += S) {
+    DD acc[S][K];
+#pragma unroll
+    for (int u = 0; u < S; ++u)
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) acc[u][kk] = DD{0.0, 0.0};
+    const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
+    double k[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) k[j] = k0[j];
+
+    uint64_t i = i0;
+    int64_t it = 0;
+#pragma unroll 1
+    while (it < n_iter) {
+      double part[S][K];
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) part[u][kk] = 0.0;
+      const int64_t it_end = (n_iter - it < kFold) ? n_iter : it + kFold;
+#pragma unroll 1
+      for (; it < it_end; ++it, i += B) {
+        const cptr<double> cl = launder_uniform(a.coef);
+        const cptr<float> cl32 = launder_uniform(a.coef32);
+        const cptr<LatticeDev> ltl = launder_uniform(lt);
+        const cptr<double> shl = launder_uniform(sh);
+        double q[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          q[j] = quotient(k[j], n_d, inv_n);
+          k[j] = lattice_step(k[j], ltl->ndz[j], n_d);
+        }
+        double y[S][D], x[S][D], W[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+          for (int j = 0; j < D; ++j) y[u][j] = shifted(q[j], shl[u * QMC_MAX_DIM + j]);
+        double f[S][K];
+        if (F32) {
+          float yf[S][D], xf[S][D], Wf[S], ff[S][K];
+#pragma unroll
+          for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int j = 0; j < D; ++j) yf[u][j] = (float)y[u][j];
+          korobov3_f32<D, S>((float)w_scale, yf, xf, Wf);
+          integrand_fast_f32<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after_f(cl32, Wf[0]), xf, ff);
+#pragma unroll
+          for (int u = 0; u < S; ++u) {
+            W[u] = (double)Wf[u];
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) f[u][kk] = (double)(Wf[u] * ff[u][kk]);
+          }
+        } else if (FAST) {
+          korobov3_fast<D, S>(w_scale, y, x, W);
+          integrand_fast<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
+        } else {
+#pragma unroll
+          for (int u = 0; u < S; ++u) W[u] = apply_transform<D>(kind, w_scale, y[u], x[u]);
+          integrand<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
+        }
+        const bool valid = i < i_end;
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+          const bool use = valid && (W[u] != 0.0);
+#pragma unroll
+          for (int kk = 0; kk < K; ++kk)
+            part[u][kk] += use ? (F32 ? f[u][kk] : W[u] * f[u][kk]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) dd_add(acc[u][kk], part[u][kk]);
+    }
+#pragma unroll
+    for (int u = 0; u < S; ++u)
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) {
+        const DD r = wave_reduce(acc[u][kk]);
+        if (lane == 0) {
+          red[wave][(l0 + u) * K + kk][0] = r.s;
+          red[wave][(l0 + u) * K + kk][1] = r.c;
+        }
+      }
+  }
+}
+
+}  // namespace qmc

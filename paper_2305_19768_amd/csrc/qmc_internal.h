@@ -22,6 +22,8 @@ enum : int32_t {
   SF_LOG = 8,       // max_log > 0: log F is needed
   SF_FAST = 16,     // korobov3, no x powers, integer exponents of U and F,
                     // max_log <= n_orders - 1 (log polynomials zero-padded to that degree)
+  SF_F32OK = 32,    // SF_FAST and F has non-negative coefficients with a positive constant
+                    // term (F >= c0 > 0 on the cube): the FP32 form may evaluate it
 };
 
 // Static per-sector record (plan time).  Read with uniform (scalar) loads.
@@ -37,6 +39,9 @@ struct alignas(16) SectorDev {
   double f_abs;                    // sum of |coefficients| of F (bound of sum |c m(x)| on the cube)
   double w_scale;                  // korobov3: 140^d, the constant of W = 140^d prod (y(1-y))^3
   double logc[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
+  float logc32[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
+  int32_t u_off32, f_off32;        // offsets of the FP32 copies of the dense tables
+  int32_t pad2[2];
 };
 
 // Per-call lattice record of a sector.
@@ -61,12 +66,13 @@ struct alignas(16) LatticeDev {
 // d and path class `fast` (SF_FAST set or not).
 struct DimLaunch {
   int64_t base, blocks;
-  int32_t d, fast;
+  int32_t d, fast, f32, pad;
 };
 
 struct LaunchArgs {
   const SectorDev *sectors;
   const double *coef;
+  const float *coef32;             // FP32 copy of coef (FP32 integrand form)
   const double *shifts;            // [S][m][QMC_MAX_DIM]
   const LatticeDev *lat;
   const int64_t *block_begin;      // [S+1], in workgroup order (sectors ordered by dimension)
@@ -79,8 +85,9 @@ struct LaunchArgs {
   int64_t total_blocks;
   int32_t d_max, precision;
   void *ev_start, *ev_stop;        // optional hipEvent_t pair recorded around the main kernel
+  const int32_t *done;             // batched form: nonzero once the evaluation finished
   int32_t n_dim_launches, pad1;
-  DimLaunch dims[2 * QMC_MAX_DIM];
+  DimLaunch dims[3 * QMC_MAX_DIM];
 };
 
 struct PointsArgs {
@@ -95,10 +102,47 @@ struct PointsArgs {
   double *out;
 };
 
+// ------------------------------------------------ batched amplitude evaluation
+constexpr int64_t kTargetBlocksDevice = 16384;
+constexpr int kAmpMaxSums = 16;
+constexpr int kAmpMaxLattice = 256;
+
+struct AmpState {
+  int32_t done;          // 0 running, 1 converged, 2 round limit, 3 no lattice can grow
+  int32_t rounds;        // integration rounds set up so far (presample included)
+  int32_t limited;       // a sector asked for more than the largest lattice
+  uint32_t work_counter; // persistent kernel's next work item
+  int64_t evaluations;
+  int64_t total_blocks;  // work items of the current round
+  double max_eps;
+  double pad;
+};
+
+struct AmpArgs {
+  AmpState *state;
+  int32_t S, K, T, NI, m, tile, block, n_lattice, max_rounds, pad;
+  double epsrel, epsabs, alpha;
+  const int32_t *integral, *dims, *order;
+  int32_t *lidx, *active, *unmet;
+  double *want;
+  const double *tau, *c2, *cre, *cim;
+  double *I, *VI, *Are, *Aim, *Vre, *Vim;
+  const double *mean, *err;
+  const uint64_t *lattice_n, *lattice_a;
+  LatticeDev *lat;
+  int64_t *block_begin;
+};
+
+int launch_amp_round(const AmpArgs &g, void *stream);
+int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, bool f32, unsigned grid,
+                      void *stream);
+int persistent_grid(int d_max, bool f32, int block, int *grid);
+
 // Returns a hipError_t value (0 = success).
 int launch_points(const PointsArgs &pa, unsigned grid, void *stream);
 int launch_integrate(const LaunchArgs &a, void *stream);
 int launch_status_reset(int32_t *status, void *stream);
+int launch_reduce_stats(const LaunchArgs &a, void *stream);
 int launch_korobov_p2(uint64_t n, int32_t d, const uint64_t *dev_cand, int32_t n_cand,
                       int32_t chunks, double *dev_partial, double *dev_p2, void *stream);
 

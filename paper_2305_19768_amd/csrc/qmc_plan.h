@@ -30,16 +30,18 @@ struct qmc_plan_s {
   int32_t S = 0, K = 0, M = 0, n_integrals = 0, d_max = 0;
   std::vector<qmc::SectorDev> sec;
   std::vector<double> coef;
+  std::vector<float> coef32;           // FP32 copy of coef (same offsets)
   std::vector<double> shifts;          // [S][m][QMC_MAX_DIM]
   std::vector<uint64_t> n_default, a_default;
   std::vector<int32_t> dims;
   std::vector<int32_t> order;          // sectors in workgroup order: by dimension, then index
+  int32_t persistent_grid[2] = {0, 0};  // resident workgroups of the persistent kernel (FP64, FP32)
   // options
   int32_t m = 0, precision = 0, block = 256, tile = 8, spp = 2;
   uint64_t n_max = 0;
   // workspace layout (byte offsets)
   size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
-         off_status = 0, off_partial = 0, off_order = 0, off_mean = 0, off_err = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
+         off_status = 0, off_partial = 0, off_order = 0, off_mean = 0, off_err = 0, off_coef32 = 0, off_amp = 0, amp_bytes = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
          total = 0;
   int64_t max_blocks = 0;
   char *ws = nullptr;

@@ -184,6 +184,52 @@ def test_invalid_lattice_rejected_before_launch(qmc):
         plan.integrate(n=[2003], a=[5])
 
 
+# ----------------------------------------------------------- FP32 integrand form
+
+FP32_TOL = 1e-5
+
+
+def test_fp32_form_two_loop_parity(qmc):
+    """FP32 integrand with FP64 lattice and accumulation: every per-shift sum within
+    1e-5 (on its scale) of the FP64 oracle; the largest deviation is reported."""
+    prob = W.two_loop_integral(seed=0, n_sectors=12, n_scale=0.01)
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
+    q, mean, err = plan.integrate()
+    q = q.cpu().numpy()
+    worst = 0.0
+    for s, sec in enumerate(prob.sectors):
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], threads=8)
+        scale = np.maximum(np.abs(Qo), So)
+        rel = np.abs(q[s] - Qo) / scale
+        worst = max(worst, float(rel.max()))
+        print(f"sector {s}: d={sec.d} n={sec.n} max rel dev FP32 vs FP64 oracle {rel.max():.2e}",
+              flush=True)
+        assert rel.max() <= FP32_TOL
+    assert worst > 1e-12   # the FP32 form really ran (not the FP64 path)
+
+
+def test_fp32_form_keeps_fp64_for_cancelling_F(qmc):
+    # F with a negative coefficient: not eligible, so it is evaluated in FP64 (1e-12 bar)
+    sec = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
+                          [(1.0, (0, 0, 0)), (-0.3, (1, 1, 0)), (0.2, (0, 0, 2))], u_pow=1,
+                          f_pow2=-6, logc=[[1, 0, 0], [0, -2, 0], [0, 0, 2]], n=20011, a=5467,
+                          transform="korobov3")
+    good = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
+                           [(1.0, (0, 0, 0)), (0.3, (1, 1, 0)), (0.2, (0, 0, 2))], u_pow=1,
+                           f_pow2=-6, logc=[[1, 0, 0], [0, -2, 0], [0, 0, 2]], n=20011, a=5467,
+                           transform="korobov3")
+    rng = np.random.default_rng(3)
+    prob = W.Problem(sectors=[sec, good], order_lo=-2, m=8,
+                     shifts=[W.uniform_shifts(rng, 8, 3) for _ in range(2)])
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
+    q = plan.integrate()[0].cpu().numpy()
+    Qo, So = oracle.sector_sums(sec, prob.shifts[0], threads=4)
+    _check_sums(q[0], Qo, So, what="cancelling F in FP32 plan")
+    Qg, Sg = oracle.sector_sums(good, prob.shifts[1], threads=4)
+    rel = np.abs(q[1] - Qg) / np.maximum(np.abs(Qg), Sg)
+    assert 1e-12 < rel.max() <= FP32_TOL
+
+
 # ------------------------------------------------------------------- P_2
 
 def test_p2_values_match_oracle(qmc):
