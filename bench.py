@@ -110,6 +110,56 @@ def cpu_baseline(problem, threads: int):
                       f"({evals} evaluations, FP64 scalar C, {dt:.1f} s)"}
 
 
+def amplitude_leg(qmc, torch, repeats: int):
+    """Wall time to a relative error of 1e-4 on every epsilon order of the synthetic
+    amplitude (20 integrals, 500 sectors, d 3..7, 32 shifts, FP64 oracle-pinned method),
+    for the plain FP64 host loop and the batched on-device forms in FP64 and FP32.  The
+    lattice table (prime sizes, P_2-chosen Korobov parameters) is built once beforehand,
+    as a precomputed table would be; each timed call starts from the presampling round."""
+    import numpy as np
+    import workloads
+    prob = workloads.amplitude(seed=0)
+    sizes, cands = workloads.lattice_ladder(n_min=10007, n_max=1 << 26, ratio=1.5, n_cand=8)
+    t0 = time.perf_counter()
+    table = qmc.Plan(prob).lattice_table(sizes, cands)
+    setup_s = time.perf_counter() - t0
+    forms = {"fp64_host": (qmc.QMC_PREC_FP64, qmc.QMC_AMP_HOST),
+             "fp64_device": (qmc.QMC_PREC_FP64, qmc.QMC_AMP_DEVICE),
+             "fp32_device": (qmc.QMC_PREC_FP32, qmc.QMC_AMP_DEVICE)}
+    out = {"workload": "amplitude: 20 integrals, 500 sectors, d 3..7, 32 shifts, orders "
+                       "eps^-2..eps^0, korobov3, target epsrel 1e-4 per order",
+           "lattice_sizes": [int(sizes[0]), int(sizes[-1]), len(sizes)],
+           "table_setup_s": setup_s}
+    vals = {}
+    for name, (prec, mode) in forms.items():
+        plan = qmc.Plan(prob, precision=prec)
+        times = []
+        for _ in range(repeats + 1):              # first call warms up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            val, err, nfin, st = plan.amp_evaluate(prob.amp_coef, epsrel=1e-4, lattice_n=sizes,
+                                                   lattice_a=table, n_presample=10007,
+                                                   mode=mode)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+        rel = np.abs(err[0]) / np.abs(val[0])
+        vals[name] = (val[0], err[0])
+        out[name] = {"wall_s": float(np.median(times[1:])), "rounds": st["rounds"],
+                     "converged": st["converged"], "evaluations": st["evaluations"],
+                     "max_rel_err": float(np.max(rel)), "max_n": int(np.max(nfin))}
+        print(f"# amplitude {name}: {out[name]}", file=sys.stderr, flush=True)
+        del plan
+    v64, e64 = vals["fp64_host"]
+    for name in ("fp64_device", "fp32_device"):
+        v, e = vals[name]
+        # distance from the FP64 host-loop result in units of the combined error estimates
+        out[name]["dev_vs_fp64_in_sigma"] = float(np.max(np.abs(v - v64) /
+                                                         (np.abs(e) + np.abs(e64))))
+    out["speedup_fp32_device_vs_fp64_host"] = (out["fp64_host"]["wall_s"] /
+                                              out["fp32_device"]["wall_s"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +171,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="shifts per workgroup (0 = default)")
     ap.add_argument("--spp", type=int, default=0, help="shifts per pass (0 = default)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-integrand measurement")
+    ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
+    ap.add_argument("--amp-repeats", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -215,6 +267,8 @@ def main():
         "launch": {"block": args.block or 256, "shift_tile": args.tile or 16,
                    "shifts_per_pass": args.spp or 0},
     }
+    if not args.no_amp:
+        result["amplitude_time_to_1e-4"] = amplitude_leg(qmc, torch, args.amp_repeats)
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(prob, threads)

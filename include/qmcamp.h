@@ -42,7 +42,7 @@ typedef enum {
     QMC_E_STATE = -7       /* call out of order (e.g. no workspace bound) */
 } qmc_status;
 
-/* Periodizing transforms (the paper's "korobov3" default and "baker", Sec. 3.3). */
+/* Periodizing transforms (the paper's "korobov3" default and "baker", Sec. 3.2 timing notes). */
 enum {
     QMC_TRANSFORM_NONE = 0,     /* x = y, w = 1 (tests only) */
     QMC_TRANSFORM_BAKER = 1,    /* tent map x = 1 - |2y - 1|, w = 1 */
@@ -227,7 +227,7 @@ enum { QMC_AMP_HOST = 0, QMC_AMP_DEVICE = 1 };
 
 /*
  * Options of the adaptive evaluation (Sec. 2.1.3): every epsilon order of every sum
- * must reach relative error epsrel (error definition of Sec. 3.3) or absolute error
+ * must reach relative error epsrel (error definition of the Sec. 3.2 timing notes) or absolute error
  * epsabs.  Lattice sizes come from the ascending table lattice_n[n_lattice]; the
  * Korobov parameter of size lattice_n[l] for a sector of dimension d is
  * lattice_a[l * QMC_MAX_DIM + d - 1].  tau: per-sector cost of one evaluation (any

@@ -73,6 +73,19 @@ def lib():
         L.or_p2.restype = ctypes.c_double
         L.or_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.or_splitmix64.restype = ctypes.c_uint64
+        L.or_deform_point.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
+                                      _dp, _dp, _dp, _dp]
+        L.or_deform_point.restype = None
+        L.or_sums_deformed.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_int,
+                                       _u8p, _dp, _i32p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
+                                       ctypes.c_int, ctypes.c_uint64, _u64p, _dp, ctypes.c_int,
+                                       ctypes.c_int, _dp, _dp, _i64p, _i64p]
+        L.or_sums_deformed.restype = ctypes.c_int
+        L.or_sign_violations.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_uint64, _u64p, _dp, ctypes.c_int,
+                                         ctypes.c_int]
+        L.or_sign_violations.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -148,13 +161,25 @@ class OracleNonFinite(RuntimeError):
     pass
 
 
+class OracleSignCheck(RuntimeError):
+    pass
+
+
 def sector_sums(sec, shifts, n: Optional[int] = None, a: Optional[int] = None,
                 z: Optional[Sequence[int]] = None, shift_range=None, threads: int = 1):
     """Per-shift lattice estimates of one sector.
 
     Returns (Q, S) with Q[l, k] = (1/n) sum_i W f_k and S[l, k] = (1/n) sum_i |W f_k|,
-    summed with Neumaier compensation (the per-shift sums of Sec. 2.1).
+    summed with Neumaier compensation (the per-shift sums of Sec. 2.1).  A sector with
+    deform_lambda > 0 is integrated on the deformed contour: Q is complex and a failed
+    sign check raises OracleSignCheck (use sector_sums_deformed for the counts).
     """
+    if getattr(sec, "deform_lambda", 0.0) > 0.0:
+        Q, S, viol, first = sector_sums_deformed(sec, shifts, n=n, a=a, z=z,
+                                                 shift_range=shift_range, threads=threads)
+        if viol:
+            raise OracleSignCheck(f"Im F(z) > 0 at {viol} samples, first (shift, index) {first}")
+        return Q, S
     A = _SectorArrays(sec)
     n = int(sec.n if n is None else n)
     if z is None:
@@ -186,6 +211,98 @@ def sector_sums(sec, shifts, n: Optional[int] = None, a: Optional[int] = None,
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(lambda l: run(l, l + 1), range(l0, l1)))
     return Q, S
+
+
+def deform_point(sec, x, lam: Optional[float] = None):
+    """z(x), J(x) = det dz/dx and F(z) of the deformed contour at real points x [count, d]
+    (z_j = x_j - i lambda x_j (1 - x_j) dF/dx_j)."""
+    A = _SectorArrays(sec)
+    lam = float(sec.deform_lambda if lam is None else lam)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, A.d)
+    z = np.empty((x.shape[0], A.d, 2))
+    J = np.empty((x.shape[0], 2))
+    F = np.empty((x.shape[0], 2))
+    for t in range(x.shape[0]):
+        xt = np.ascontiguousarray(x[t])
+        zt, Jt, Ft = np.empty((A.d, 2)), np.empty(2), np.empty(2)
+        lib().or_deform_point(A.d, A.n_f, _p(A.f_exp, _u8p), _p(A.f_coef, _dp), lam,
+                              _p(xt, _dp), _p(zt, _dp), _p(Jt, _dp), _p(Ft, _dp))
+        z[t], J[t], F[t] = zt, Jt, Ft
+    return (z[..., 0] + 1j * z[..., 1], J[:, 0] + 1j * J[:, 1], F[:, 0] + 1j * F[:, 1])
+
+
+def sector_sums_deformed(sec, shifts, n: Optional[int] = None, a: Optional[int] = None,
+                         z: Optional[Sequence[int]] = None, shift_range=None, threads: int = 1,
+                         lam: Optional[float] = None):
+    """Per-shift estimates of one sector on the deformed contour.
+
+    Returns (Q complex [l, k], S [l, k] = (1/n) sum |W J f_k|, number of samples with
+    Im F(z) > 0, (shift, index) of the first such sample or None)."""
+    A = _SectorArrays(sec)
+    lam = float(sec.deform_lambda if lam is None else lam)
+    n = int(sec.n if n is None else n)
+    if z is None:
+        z = korobov_vector(n, sec.a if a is None else a, A.d)
+    z = np.ascontiguousarray(z, dtype=np.uint64)
+    shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+    m = shifts.shape[0]
+    l0, l1 = (0, m) if shift_range is None else shift_range
+    Q = np.empty((l1 - l0, A.K), dtype=np.complex128)
+    S = np.empty((l1 - l0, A.K))
+    sign = np.zeros((l1 - l0, 3), dtype=np.int64)
+    L = lib()
+
+    def run(l):
+        bad = np.zeros(2, dtype=np.int64)
+        sg = np.zeros(3, dtype=np.int64)
+        q = np.empty((1, A.K, 2))
+        s = np.empty((1, A.K))
+        rc = L.or_sums_deformed(*A.head(), lam, A.transform, n, _p(z, _u64p), _p(shifts, _dp),
+                                l, l + 1, _p(q, _dp), _p(s, _dp), _p(bad, _i64p),
+                                _p(sg, _i64p))
+        if rc == 1:
+            raise OracleNonFinite(f"non-finite sample at shift {bad[0]}, index {bad[1]}")
+        if rc != 0:
+            raise ValueError("invalid sector")
+        Q[l - l0] = q[0, :, 0] + 1j * q[0, :, 1]
+        S[l - l0] = s[0]
+        sign[l - l0] = sg
+
+    if threads <= 1 or l1 - l0 == 1:
+        for l in range(l0, l1):
+            run(l)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(run, range(l0, l1)))
+    viol = int(sign[:, 0].sum())
+    first = None
+    for row in sign:
+        if row[0] > 0:
+            first = (int(row[1]), int(row[2]))
+            break
+    return Q, S, viol, first
+
+
+def sign_violations(sec, shifts, lam: float, n: int, a: int) -> int:
+    """Samples of the lattice (n, Korobov a) and the given shifts with Im F(z) > 0."""
+    A = _SectorArrays(sec)
+    z = korobov_vector(n, a, A.d)
+    shifts = np.ascontiguousarray(shifts, dtype=np.float64)
+    return int(lib().or_sign_violations(A.d, A.n_f, _p(A.f_exp, _u8p), _p(A.f_coef, _dp),
+                                        float(lam), A.transform, int(n), _p(z, _u64p),
+                                        _p(shifts, _dp), 0, shifts.shape[0]))
+
+
+def choose_lambda(sec, shifts, lam0: float, n: int, a: int, max_halvings: int = 16):
+    """Deformation parameter from presamples (the library-call parameter
+    number_of_presamples of Sec. 3.1.3): start at lam0 and halve until no presample
+    point has Im F(z) > 0.  Returns (lambda, halvings) or raises OracleSignCheck."""
+    lam = float(lam0)
+    for h in range(max_halvings + 1):
+        if sign_violations(sec, shifts, lam, n, a) == 0:
+            return lam, h
+        lam *= 0.5
+    raise OracleSignCheck(f"no valid deformation parameter down to {lam * 2:g}")
 
 
 def problem_sums(problem, threads: int = 1, sectors=None):
@@ -297,7 +414,7 @@ def amplitude(coef, ival, ierr, ival_im=None, ierr_im=None):
 
 
 def eps_rel(re, im, dre, dim):
-    """epsilon_rel = sqrt((dR^2 + dI^2) / (R^2 + I^2)) (Sec. 3.3, timing notes)."""
+    """epsilon_rel = sqrt((dR^2 + dI^2) / (R^2 + I^2)) (Sec. 3.2, timing notes)."""
     return np.sqrt((np.asarray(dre) ** 2 + np.asarray(dim) ** 2) /
                    (np.asarray(re) ** 2 + np.asarray(im) ** 2))
 

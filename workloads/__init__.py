@@ -55,6 +55,7 @@ class Sector:
     transform: str = "korobov3"
     integral: int = 0      # parent integral index (a sum of sectors)
     a_candidates: Optional[np.ndarray] = None  # uint64, random candidates for a
+    deform_lambda: float = 0.0  # > 0: integrate on the deformed contour (F - i0), complex
 
     @property
     def K(self) -> int:
@@ -277,7 +278,7 @@ def amplitude(seed: int = 0, n_integrals: int = 20, n_sectors: int = 500, d_lo: 
 
 
 def custom_sector(d, u_terms, f_terms, x_pow2=None, u_pow=0, f_pow2=0, logc=((1.0,),),
-                  n=1009, a=1, transform="none", integral=0) -> Sector:
+                  n=1009, a=1, transform="none", integral=0, deform_lambda=0.0) -> Sector:
     """A hand-specified sector: u_terms / f_terms are lists of (coef, exponent tuple)."""
     def poly(terms):
         if not terms:
@@ -290,7 +291,8 @@ def custom_sector(d, u_terms, f_terms, x_pow2=None, u_pow=0, f_pow2=0, logc=((1.
     return Sector(d=d, u_exp=ue, u_coef=uc, f_exp=fe, f_coef=fc,
                   x_pow2=np.zeros(d, np.int32) if x_pow2 is None else np.asarray(x_pow2, np.int32),
                   u_pow=u_pow, f_pow2=f_pow2, logc=np.asarray(logc, dtype=np.float64),
-                  n=n, a=a, transform=transform, integral=integral)
+                  n=n, a=a, transform=transform, integral=integral,
+                  deform_lambda=float(deform_lambda))
 
 
 def single_problem(sector: Sector, m: int = 8, seed: int = 0, order_lo: int = 0) -> Problem:
