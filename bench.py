@@ -121,7 +121,7 @@ def amplitude_leg(qmc, torch, repeats: int):
     prob = workloads.amplitude(seed=0)
     sizes, cands = workloads.lattice_ladder(n_min=10007, n_max=1 << 26, ratio=1.5, n_cand=8)
     t0 = time.perf_counter()
-    table = qmc.Plan(prob).lattice_table(sizes, cands)
+    table = qmc.Plan(prob, n_max=int(sizes[-1])).lattice_table(sizes, cands)
     setup_s = time.perf_counter() - t0
     forms = {"fp64_host": (qmc.QMC_PREC_FP64, qmc.QMC_AMP_HOST),
              "fp64_device": (qmc.QMC_PREC_FP64, qmc.QMC_AMP_DEVICE),
@@ -132,7 +132,7 @@ def amplitude_leg(qmc, torch, repeats: int):
            "table_setup_s": setup_s}
     vals = {}
     for name, (prec, mode) in forms.items():
-        plan = qmc.Plan(prob, precision=prec)
+        plan = qmc.Plan(prob, precision=prec, n_max=int(sizes[-1]))
         times = []
         for _ in range(repeats + 1):              # first call warms up
             torch.cuda.synchronize()
@@ -160,6 +160,45 @@ def amplitude_leg(qmc, torch, repeats: int):
     return out
 
 
+def scan_leg(qmc, torch, n_points: int, steps: int):
+    """Physical-region scan on the deformed contour (complex FP64): n_points kinematic
+    points x 200 base sectors (d 3..8), n = 65521, 16 shifts, lambda chosen from
+    presamples (n = 4099) by halving from 0.5.  Reports complex evaluations per second
+    of the integration step and how many sectors needed a smaller lambda."""
+    import numpy as np
+    import workloads
+    prob = workloads.physical_scan(seed=0, n_points=n_points)
+    plan = qmc.Plan(prob)
+    t0 = time.perf_counter()
+    lam, halv, rc = plan.choose_deformation(4099)
+    torch.cuda.synchronize()
+    choose_s = time.perf_counter() - t0
+    S, m, K = plan.S, plan.m, plan.K
+    out = (torch.empty((S, m, K, 2), dtype=torch.float64, device="cuda"),
+           torch.empty((S, K, 2), dtype=torch.float64, device="cuda"),
+           torch.empty((S, K, 2), dtype=torch.float64, device="cuda"))
+    plan.integrate(out=out, check=False)
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.integrate(out=out, check=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kernel_ms, launches = plan.read_timing()
+    plan.enable_timing(False)
+    viol = plan.sign_violations()
+    evals = prob.evals()
+    return {"workload": f"physical_scan: {n_points} kinematic points x 200 sectors, d 3..8, "
+                        "n 65521, 16 shifts, orders eps^-2..eps^0, deformed contour, FP64 complex",
+            "value": evals * steps / el, "unit": "complex evals/s",
+            "ms_per_step": el / steps * 1e3, "kernel_ms": kernel_ms / max(launches, 1),
+            "evals_per_step": evals, "lambda_choice_s": choose_s,
+            "sectors_lambda_halved": int(np.count_nonzero(halv)),
+            "sectors_unfixed": int(rc != 0),
+            "sectors_violating_at_full_n": int(np.count_nonzero(viol))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +211,8 @@ def main():
     ap.add_argument("--spp", type=int, default=0, help="shifts per pass (0 = default)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-integrand measurement")
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
+    ap.add_argument("--scan-points", type=int, default=10,
+                    help="kinematic points of the deformed-contour scan leg (0 = skip)")
     ap.add_argument("--amp-repeats", type=int, default=3)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
@@ -269,6 +310,8 @@ def main():
     }
     if not args.no_amp:
         result["amplitude_time_to_1e-4"] = amplitude_leg(qmc, torch, args.amp_repeats)
+    if args.scan_points > 0:
+        result["physical_scan"] = scan_leg(qmc, torch, args.scan_points, max(1, args.steps // 4))
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(prob, threads)

@@ -39,6 +39,7 @@ typedef enum {
     QMC_E_DEVICE = -3,     /* a HIP runtime call failed */
     QMC_E_NONFINITE = -4,  /* a per-shift sum is not finite; see qmc_query_status */
     QMC_E_TIMEOUT = -5,    /* amp_evaluate stopped at its time limit (results valid, flagged) */
+    QMC_E_SIGNCHECK = -6,  /* deformed contour left the F - i0 half plane; see qmc_sign_violations */
     QMC_E_STATE = -7       /* call out of order (e.g. no workspace bound) */
 } qmc_status;
 
@@ -69,6 +70,18 @@ enum { QMC_PREC_FP64 = 0, QMC_PREC_FP32 = 1 };
  * U and F are sums of monomials c * prod_j x_j^e_j with total degree <= QMC_MAX_DEG;
  * their monomials are rows u_off .. u_off+n_u-1 (f_off .. f_off+n_f-1) of the
  * problem's mono_exp / mono_coef arrays.  Repeated exponent rows are summed.
+ *
+ * Contour deformation (physical kinematics, F may change sign; the deformation
+ * parameter is chosen from presamples in the paper's library call, Sec. 3.1.3): with
+ * deform_lambda = lambda > 0 the sector is integrated over
+ *   z_j(x) = x_j - i lambda x_j (1 - x_j) dF/dx_j(x),
+ *   I_k = int dx det(dz/dx) f_k(z(x)),
+ * f_k continued analytically (x^p, U, F, log F all at z); log F and half-integer powers
+ * of F take the F - i0 branch (argument of F in [-pi, pi)).  The contour is valid where
+ * Im F(z) <= 0; a sample with Im F(z) > 2^-40 |F(z)| is a sign-check violation.  A
+ * problem with any deformed sector makes a complex plan: every sector's integrand is
+ * complex (lambda = 0 sectors are integrated on the real contour with the F - i0
+ * branch) and every per-order output carries (re, im) pairs.
  */
 typedef struct {
     int32_t d;                        /* 1 .. QMC_MAX_DIM */
@@ -83,6 +96,7 @@ typedef struct {
     double logc[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
     uint64_t n;                       /* default lattice size (prime or any n >= 2) */
     uint64_t a;                       /* default Korobov parameter, z = (1, a, a^2, ...) mod n */
+    double deform_lambda;             /* >= 0; > 0: contour deformation (see above) */
 } qmc_sector_desc;
 
 typedef struct {
@@ -161,7 +175,11 @@ qmc_status qmc_set_shifts(qmc_plan_t plan, const double *shifts, void *stream);
  * the sectors' defaults.  Requires 2 <= n_s <= n_max, n_s < 2^53, gcd(a_s^j, n_s) = 1
  * for j < d_s (checked on the host before launch: QMC_E_INVAL).
  * Outputs (device, caller-owned, float64): dev_q [n_sectors][m][K] (may be NULL),
- * dev_mean and dev_err [n_sectors][K].  Sums are compensated (TwoSum) within each
+ * dev_mean and dev_err [n_sectors][K]; in a complex plan (qmc_plan_complex) the
+ * shapes are [n_sectors][m][K][2], [n_sectors][K][2] with (re, im) pairs and err holds
+ * the standard errors of the real and imaginary parts.  Complex plans also count
+ * sign-check violations per sector (qmc_sign_violations); the sums are formed
+ * regardless.  Sums are compensated (TwoSum) within each
  * thread, across the wavefront and across workgroups, in a fixed order, so results
  * are bitwise reproducible.  Non-finite sums are reported by qmc_query_status, not
  * here (the call does not synchronize).
@@ -172,10 +190,43 @@ qmc_status qmc_integrate(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, 
 /*
  * qmc_query_status -- synchronize `stream` and report the device status word of the
  * last qmc_integrate: QMC_OK, or QMC_E_NONFINITE with *sector, *shift, *order set to
- * the first non-finite sum in (sector, shift, order) order.
+ * the first non-finite sum in (sector, shift, order) order; else, in a complex plan,
+ * QMC_E_SIGNCHECK with *sector the first sector with a sign-check violation (*shift
+ * and *order set to -1).
  */
 qmc_status qmc_query_status(qmc_plan_t plan, void *stream, int32_t *sector, int32_t *shift,
                             int32_t *order);
+
+/* 1 if the plan is complex (some sector deformed), 0 if real, -1 for NULL. */
+int32_t qmc_plan_complex(qmc_plan_t plan);
+
+/*
+ * qmc_sign_violations -- synchronize `stream` and copy the per-sector counts of
+ * sign-check violations (samples with Im F(z) > 2^-40 |F(z)|) of the last
+ * qmc_integrate into the host array counts[n_sectors].  Real plans: all zero.
+ */
+qmc_status qmc_sign_violations(qmc_plan_t plan, void *stream, uint64_t *counts);
+
+/*
+ * qmc_set_deformation -- replace the deformation parameters of a complex plan with the
+ * host array lambda[n_sectors] (each >= 0, finite); uploaded on `stream`.
+ * Errors: QMC_E_INVAL (bad value), QMC_E_STATE (real plan or no workspace).
+ */
+qmc_status qmc_set_deformation(qmc_plan_t plan, const double *lambda, void *stream);
+
+/*
+ * qmc_choose_deformation -- the presample selection of the deformation parameter: for
+ * every sector with lambda > 0, integrate at lattice size n_pre (Korobov parameters
+ * a_pre[n_sectors], or NULL for the sectors' defaults) with the plan's shifts, and halve
+ * lambda while any sample violates the sign check, at most max_halvings times.
+ * Synchronous.  Writes the chosen parameters to lambda_out[n_sectors] and the number of
+ * halvings to halvings_out[n_sectors] (either may be NULL) and leaves them set in the
+ * plan.  Returns QMC_E_SIGNCHECK (parameters of the other sectors still chosen and set)
+ * if some sector still violates after max_halvings.
+ */
+qmc_status qmc_choose_deformation(qmc_plan_t plan, uint64_t n_pre, const uint64_t *a_pre,
+                                  int32_t max_halvings, void *stream, double *lambda_out,
+                                  int32_t *halvings_out);
 
 /*
  * qmc_korobov_p2 -- figure of merit of Korobov lattices on the device:
@@ -273,7 +324,8 @@ typedef struct {
  * Outputs (host, caller-owned): value and error [n_sums][n_orders][2] (re, im);
  * n_final [n_sectors] (may be NULL); stats (may be NULL).  Returns QMC_OK (converged
  * or not: see stats), QMC_E_TIMEOUT with valid results when the time limit stopped it,
- * QMC_E_INVAL / QMC_E_NONFINITE / QMC_E_DEVICE on failure.
+ * QMC_E_INVAL / QMC_E_NONFINITE / QMC_E_DEVICE on failure.  Complex (deformed) plans
+ * are not accepted (QMC_E_INVAL).
  */
 qmc_status amp_evaluate(qmc_plan_t plan, const qmc_amplitude *amp, const qmc_amp_options *opt,
                         void *stream, double *value, double *error, uint64_t *n_final,

@@ -64,6 +64,7 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().qmc_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)), "qmc_plan")
         self._h = h
+        self.complex = bool(lib().qmc_plan_complex(h))
         nbytes = int(lib().qmc_workspace_bytes(h))
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -98,13 +99,16 @@ class Plan:
     def integrate(self, n: Optional[Sequence[int]] = None, a: Optional[Sequence[int]] = None,
                   out=None, stream=None, check: bool = True):
         """Runs the lattice rule on every sector.  Returns (q [S, m, K], mean [S, K],
-        err [S, K]) as float64 device tensors.  With check=True the stream is
-        synchronised and a non-finite sum raises QmcError."""
+        err [S, K]) as float64 device tensors; a complex plan appends a (re, im) axis of
+        length 2 to each.  With check=True the stream is synchronised and a non-finite sum
+        (or, in a complex plan, a sign-check violation) raises QmcError."""
         torch = _torch()
+        tail = (2,) if self.complex else ()
         if out is None:
-            q = torch.empty((self.S, self.m, self.K), dtype=torch.float64, device=self.device)
-            mean = torch.empty((self.S, self.K), dtype=torch.float64, device=self.device)
-            err = torch.empty((self.S, self.K), dtype=torch.float64, device=self.device)
+            q = torch.empty((self.S, self.m, self.K) + tail, dtype=torch.float64,
+                            device=self.device)
+            mean = torch.empty((self.S, self.K) + tail, dtype=torch.float64, device=self.device)
+            err = torch.empty((self.S, self.K) + tail, dtype=torch.float64, device=self.device)
         else:
             q, mean, err = out
         n_arr = None if n is None else np.ascontiguousarray(n, dtype=np.uint64)
@@ -119,6 +123,38 @@ class Plan:
         if check:
             self.check_status(stream)
         return q, mean, err
+
+    def sign_violations(self, stream=None) -> np.ndarray:
+        """Per-sector sign-check violation counts of the last integrate() (complex plans)."""
+        out = np.zeros(self.S, dtype=np.uint64)
+        _check(lib().qmc_sign_violations(self._h, _stream_ptr(stream),
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+               "qmc_sign_violations")
+        return out
+
+    def set_deformation(self, lam, stream=None):
+        arr = np.ascontiguousarray(lam, dtype=np.float64)
+        _check(lib().qmc_set_deformation(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         _stream_ptr(stream)), "qmc_set_deformation")
+        torch = _torch()
+        torch.cuda.current_stream().synchronize()
+
+    def choose_deformation(self, n_pre: int, a_pre=None, max_halvings: int = 16, stream=None):
+        """Presample choice of the deformation parameters (halve lambda while a sample
+        violates the sign check).  Returns (lambda [S], halvings [S], status) with status
+        0 or QMC_E_SIGNCHECK (-6) if some sector could not be fixed."""
+        lam = np.zeros(self.S, dtype=np.float64)
+        halv = np.zeros(self.S, dtype=np.int32)
+        a_arr = None if a_pre is None else np.ascontiguousarray(a_pre, dtype=np.uint64)
+        rc = lib().qmc_choose_deformation(
+            self._h, ctypes.c_uint64(int(n_pre)),
+            None if a_arr is None else a_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+            ctypes.c_int32(max_halvings), _stream_ptr(stream),
+            lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            halv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if rc not in (0, -6):
+            _check(rc, "qmc_choose_deformation")
+        return lam, halv, rc
 
     def check_status(self, stream=None):
         sec, sh, order = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

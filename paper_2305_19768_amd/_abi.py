@@ -18,7 +18,8 @@ TRANSFORMS = {"none": 0, "baker": 1, "korobov1": 2, "korobov2": 3, "korobov3": 4
               "korobov4": 5, "korobov5": 6, "korobov6": 7}
 
 STATUS_NAMES = {0: "QMC_OK", -1: "QMC_E_INVAL", -2: "QMC_E_NOMEM", -3: "QMC_E_DEVICE",
-                -4: "QMC_E_NONFINITE", -5: "QMC_E_TIMEOUT", -7: "QMC_E_STATE"}
+                -4: "QMC_E_NONFINITE", -5: "QMC_E_TIMEOUT", -6: "QMC_E_SIGNCHECK",
+                -7: "QMC_E_STATE"}
 
 
 class QmcError(RuntimeError):
@@ -34,7 +35,8 @@ class SectorDesc(ctypes.Structure):
                 ("f_pow2", ctypes.c_int32), ("transform", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32),
                 ("logc", (ctypes.c_double * (QMC_MAX_LOG + 1)) * QMC_MAX_ORDERS),
-                ("n", ctypes.c_uint64), ("a", ctypes.c_uint64)]
+                ("n", ctypes.c_uint64), ("a", ctypes.c_uint64),
+                ("deform_lambda", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -106,6 +108,15 @@ def lib():
         L.qmc_integrate.restype = ctypes.c_int
         L.qmc_query_status.argtypes = [vp, vp, i32p, i32p, i32p]
         L.qmc_query_status.restype = ctypes.c_int
+        L.qmc_plan_complex.argtypes = [vp]
+        L.qmc_plan_complex.restype = ctypes.c_int32
+        L.qmc_sign_violations.argtypes = [vp, vp, u64p]
+        L.qmc_sign_violations.restype = ctypes.c_int
+        L.qmc_set_deformation.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp]
+        L.qmc_set_deformation.restype = ctypes.c_int
+        L.qmc_choose_deformation.argtypes = [vp, ctypes.c_uint64, u64p, ctypes.c_int32, vp,
+                                             ctypes.POINTER(ctypes.c_double), i32p]
+        L.qmc_choose_deformation.restype = ctypes.c_int
         L.qmc_korobov_p2.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, u64p, ctypes.c_int32,
                                      vp, vp]
         L.qmc_korobov_p2.restype = ctypes.c_int
@@ -174,6 +185,7 @@ def problem_struct(problem):
                 D.logc[k][m] = float(lc[k, m])
         D.n = int(sec.n)
         D.a = int(sec.a)
+        D.deform_lambda = float(getattr(sec, "deform_lambda", 0.0))
     exps = np.ascontiguousarray(np.concatenate(rows_e, axis=0) if rows_e else
                                 np.zeros((0, QMC_MAX_DIM), np.uint8))
     coef = np.ascontiguousarray(np.concatenate(rows_c) if rows_c else np.zeros(0))

@@ -235,6 +235,7 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
   const auto t_start = std::chrono::steady_clock::now();
   if (!p || !amp || !opt || !value || !error) return fail(QMC_E_INVAL, "NULL argument");
   if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (p->cplx) return fail(QMC_E_INVAL, "amp_evaluate does not take complex (deformed) plans");
   const int S = p->S, K = p->K, m = p->m, NI = p->n_integrals;
   const int T = amp->n_sums;
   // ---- validate the sums

@@ -90,11 +90,12 @@ static void layout(qmc_plan_s *p) {
   p->off_lat = take(sizeof(LatticeDev) * p->S);
   p->off_begin = take(sizeof(int64_t) * (p->S + 1));
   p->off_order = take(sizeof(int32_t) * p->S);
-  p->off_q = take(sizeof(double) * (size_t)p->S * p->m * p->K);
-  p->off_mean = take(sizeof(double) * (size_t)p->S * p->K);
-  p->off_err = take(sizeof(double) * (size_t)p->S * p->K);
+  p->off_q = take(sizeof(double) * (size_t)p->S * p->m * p->KC);
+  p->off_mean = take(sizeof(double) * (size_t)p->S * p->KC);
+  p->off_err = take(sizeof(double) * (size_t)p->S * p->KC);
   p->off_status = take(256);
-  p->off_partial = take(sizeof(double) * 2 * (size_t)p->max_blocks * p->tile * p->K);
+  p->off_sign = take(sizeof(unsigned long long) * (size_t)p->S);
+  p->off_partial = take(sizeof(double) * 2 * (size_t)p->max_blocks * p->tile * p->KC);
   p->off_p2cand = take(sizeof(uint64_t) * kP2MaxCand);
   p->off_p2part = take(sizeof(double) * kP2PartialDoubles);
   p->off_p2vals = take(sizeof(double) * kP2MaxCand);
@@ -125,6 +126,67 @@ static int dense_pos(int D, const uint8_t *e, int *deg_out) {
     }
   }
   return -1;
+}
+
+// Position of a monomial of total degree <= 2 in the compact degree-2 layout
+// (c0; per j: c_j, then c_jk for k >= j), or -1.
+static int dense_pos2(int D, const int *e) {
+  int var[2], g = 0;
+  for (int j = 0; j < D; ++j)
+    for (int t = 0; t < e[j]; ++t) {
+      if (g >= 2) return -1;
+      var[g++] = j;
+    }
+  if (g == 0) return 0;
+  int p = 1;
+  for (int j = 0; j < D; ++j) {
+    if (g == 1 && var[0] == j) return p;
+    for (int k = j; k < D; ++k)
+      if (g == 2 && var[0] == j && var[1] == k) return p + 1 + (k - j);
+    p += 1 + D - j;
+  }
+  return -1;
+}
+
+// Complex plans: dense tables of dF/dx_a (degree 2, D tables) and d2F/dx_a dx_b for
+// b >= a (degree 1, D(D+1)/2 tables), differentiated monomial by monomial.
+static void pack_derivatives(int D, const qmc_problem *prob, int64_t off, int32_t count,
+                             std::vector<double> &coef, int32_t *grad_off, int32_t *hess_off) {
+  const size_t gbase = coef.size();
+  const size_t hbase = gbase + (size_t)D * dense_len2(D);
+  coef.resize(hbase + (size_t)(D * (D + 1) / 2) * dense_len1(D), 0.0);
+  *grad_off = (int32_t)gbase;
+  *hess_off = (int32_t)hbase;
+  for (int32_t r = 0; r < count; ++r) {
+    const uint8_t *er = prob->mono_exp + (size_t)(off + r) * QMC_MAX_DIM;
+    const double c = prob->mono_coef[off + r];
+    int e[QMC_MAX_DIM];
+    for (int j = 0; j < D; ++j) e[j] = er[j];
+    // first derivatives: c e_a x^(e - 1_a)
+    for (int a = 0; a < D; ++a) {
+      if (e[a] == 0) continue;
+      int ea[QMC_MAX_DIM];
+      for (int j = 0; j < D; ++j) ea[j] = e[j] - (j == a);
+      const int pos = dense_pos2(D, ea);   // degree <= 2 since F has degree <= 3
+      coef[gbase + (size_t)a * dense_len2(D) + pos] += c * e[a];
+    }
+    // second derivatives d2/dx_i dx_k, k >= i: c e_i (e_k - [i == k]) x^(e - 1_i - 1_k)
+    int t = 0;
+    for (int i = 0; i < D; ++i)
+      for (int k = i; k < D; ++k, ++t) {
+        int eik[QMC_MAX_DIM];
+        for (int j = 0; j < D; ++j) eik[j] = e[j];
+        const double fi = (double)eik[i];
+        eik[i] -= 1;
+        const double fk = (double)eik[k];
+        eik[k] -= 1;
+        if (fi <= 0.0 || fk <= 0.0) continue;
+        int var = -1;
+        for (int j = 0; j < D; ++j)
+          if (eik[j] > 0) var = j;   // remaining degree <= 1
+        coef[hbase + (size_t)t * dense_len1(D) + (var < 0 ? 0 : 1 + var)] += c * fi * fk;
+      }
+  }
 }
 
 static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t count,
@@ -159,8 +221,9 @@ static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t
   return QMC_OK;
 }
 
-// 0: generic path, 1: fast path in FP64, 2: fast path in FP32.
+// 0: generic path, 1: fast path in FP64, 2: fast path in FP32, 3: deformed (complex plan).
 static int path_class(const qmc_plan_s *p, int s) {
+  if (p->cplx) return 3;
   const int f = p->sec[s].flags;
   if (!(f & SF_FAST)) return 0;
   return (p->precision == QMC_PREC_FP32 && (f & SF_F32OK)) ? 2 : 1;
@@ -196,13 +259,25 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
     return fail(QMC_E_INVAL, "m must be in [2, %d]", QMC_MAX_SHIFTS);
   if (opt->precision != QMC_PREC_FP64 && opt->precision != QMC_PREC_FP32)
     return fail(QMC_E_INVAL, "unknown precision %d", opt->precision);
+  // complex plan: some sector integrated on a deformed contour
+  int cplx = 0;
+  for (int s = 0; s < prob->n_sectors; ++s) {
+    const double lam = prob->sectors[s].deform_lambda;
+    if (!(lam >= 0.0) || !std::isfinite(lam))
+      return fail(QMC_E_INVAL, "sector %d: deform_lambda must be finite and >= 0", s);
+    if (lam > 0.0) cplx = 1;
+  }
+  const int KC = cplx ? 2 * prob->n_orders : prob->n_orders;
   const int block = opt->block ? opt->block : 256;
   int tile = opt->shift_tile;
-  if (!tile)  // largest power of two <= 16 dividing m
-    for (tile = 16; tile > 1 && opt->m % tile != 0; tile >>= 1) {
+  if (!tile)  // largest power of two <= 16 dividing m (and fitting 64 columns per workgroup)
+    for (tile = 16; tile > 1 && (opt->m % tile != 0 || tile * KC > 64); tile >>= 1) {
     }
-  const int spp = opt->shifts_per_pass ? opt->shifts_per_pass : (tile % 2 == 0 ? 2 : 1);
-  if (!tile_supported(tile, spp, block))
+  const int spp = cplx ? 1
+                       : (opt->shifts_per_pass ? opt->shifts_per_pass : (tile % 2 == 0 ? 2 : 1));
+  if (cplx && opt->shifts_per_pass > 1)
+    return fail(QMC_E_INVAL, "unsupported launch shape: deformed sectors run one shift per pass");
+  if (!tile_supported(tile, spp, block) || tile * KC > 64)
     return fail(QMC_E_INVAL, "unsupported launch shape: shift_tile %d, shifts_per_pass %d, block %d",
                 tile, spp, block);
   if (opt->m % tile != 0)
@@ -212,6 +287,8 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
   if (!p) return fail(QMC_E_NOMEM, "out of host memory");
   p->S = prob->n_sectors;
   p->K = prob->n_orders;
+  p->cplx = cplx;
+  p->KC = KC;
   p->M = prob->max_log;
   p->n_integrals = prob->n_integrals;
   p->m = opt->m;
@@ -275,6 +352,10 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
                         "F")) != QMC_OK) {
       delete p;
       return st;
+    }
+    if (cplx) {
+      pack_derivatives(D, prob, in.f_off, in.n_f, p->coef, &sd.grad_off, &sd.hess_off);
+      sd.lambda = in.deform_lambda;
     }
     int flags = 0;
     for (int j = 0; j < QMC_MAX_DIM; ++j) {
@@ -475,15 +556,16 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     L.block_begin = b;
     p->begin[t] = b;
     const int cls = path_class(p, s);
-    const int fast = cls >= 1 ? 1 : 0, f32 = cls == 2 ? 1 : 0;
+    const int fast = (cls == 1 || cls == 2) ? 1 : 0, f32 = cls == 2 ? 1 : 0;
+    const int deform = cls == 3 ? 1 : 0;
     if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
-        dl[n_dl - 1].f32 != f32) {
+        dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].deform != deform) {
       dl[n_dl].d = p->dims[s];
       dl[n_dl].base = b;
       dl[n_dl].blocks = 0;
       dl[n_dl].fast = fast;
       dl[n_dl].f32 = f32;
-      dl[n_dl].pad = 0;
+      dl[n_dl].deform = deform;
       ++n_dl;
     }
     const int64_t nb = (int64_t)L.n_chunks * tiles;
@@ -527,7 +609,9 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   la.status = (int32_t *)(p->ws + p->off_status);
   la.n_sectors = p->S;
   la.m = p->m;
-  la.K = p->K;
+  la.K = p->KC;
+  la.cplx = p->cplx;
+  la.sign_count = (unsigned long long *)(p->ws + p->off_sign);
   la.shift_tile = p->tile;
   la.shifts_per_pass = p->spp;
   la.block = p->block;
@@ -548,6 +632,8 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     p->ev_used += 2;
   }
   if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
+  if (p->cplx && (e = launch_clear_u64(la.sign_count, p->S, stream)) != hipSuccess)
+    return hip_fail(e, "sign-check counter reset");
   if ((e = launch_integrate(la, stream)) != hipSuccess) return hip_fail(e, "integrate launch");
   return QMC_OK;
 }
@@ -572,7 +658,21 @@ qmc_status qmc_query_status(qmc_plan_t p, void *stream, int32_t *sector, int32_t
   int e = hipMemcpyAsync(&code, p->ws + p->off_status, sizeof code, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "read status");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
-  if (code == INT32_MAX) return QMC_OK;
+  if (code == INT32_MAX) {
+    if (!p->cplx) return QMC_OK;
+    std::vector<uint64_t> cnt(p->S);
+    qmc_status sc = qmc_sign_violations(p, stream, cnt.data());
+    if (sc != QMC_OK) return sc;
+    for (int s = 0; s < p->S; ++s)
+      if (cnt[s]) {
+        if (sector) *sector = s;
+        if (shift) *shift = -1;
+        if (order) *order = -1;
+        return fail(QMC_E_SIGNCHECK, "sign check failed: sector %d, %llu samples with Im F(z) > 0",
+                    s, (unsigned long long)cnt[s]);
+      }
+    return QMC_OK;
+  }
   const int ko = code % QMC_MAX_ORDERS;
   const int sl = code / QMC_MAX_ORDERS;
   if (sector) *sector = sl / p->m;
@@ -580,6 +680,96 @@ qmc_status qmc_query_status(qmc_plan_t p, void *stream, int32_t *sector, int32_t
   if (order) *order = ko;
   return fail(QMC_E_NONFINITE, "non-finite sum: sector %d, shift %d, order %d", sl / p->m,
               sl % p->m, ko);
+}
+
+int32_t qmc_plan_complex(qmc_plan_t p) { return p ? p->cplx : -1; }
+
+qmc_status qmc_sign_violations(qmc_plan_t p, void *stream, uint64_t *counts) {
+  if (!p || !counts) return fail(QMC_E_INVAL, "NULL argument");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (!p->cplx) {
+    for (int s = 0; s < p->S; ++s) counts[s] = 0;
+    return QMC_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int e = hipMemcpyAsync(counts, p->ws + p->off_sign, sizeof(uint64_t) * p->S,
+                         hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "read sign-check counters");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
+  return QMC_OK;
+}
+
+qmc_status qmc_set_deformation(qmc_plan_t p, const double *lambda, void *stream) {
+  g_last_error.clear();
+  if (!p || !lambda) return fail(QMC_E_INVAL, "NULL argument");
+  if (!p->cplx) return fail(QMC_E_STATE, "the plan is real (no deformed sector)");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  for (int s = 0; s < p->S; ++s)
+    if (!(lambda[s] >= 0.0) || !std::isfinite(lambda[s]))
+      return fail(QMC_E_INVAL, "lambda[%d] must be finite and >= 0", s);
+  for (int s = 0; s < p->S; ++s) p->sec[s].lambda = lambda[s];
+  int e = hipMemcpyAsync(p->ws + p->off_sec, p->sec.data(), sizeof(SectorDev) * p->S,
+                         hipMemcpyHostToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "upload sectors");
+  return QMC_OK;
+}
+
+qmc_status qmc_choose_deformation(qmc_plan_t p, uint64_t n_pre, const uint64_t *a_pre,
+                                  int32_t max_halvings, void *stream, double *lambda_out,
+                                  int32_t *halvings_out) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  if (!p->cplx) return fail(QMC_E_STATE, "the plan is real (no deformed sector)");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (max_halvings < 0 || max_halvings > 60)
+    return fail(QMC_E_INVAL, "max_halvings = %d outside [0, 60]", max_halvings);
+  const int S = p->S;
+  std::vector<uint64_t> n(S, n_pre), a(S), cnt(S);
+  std::vector<uint8_t> active(S);
+  std::vector<int32_t> halv(S, 0);
+  std::vector<double> lam(S);
+  for (int s = 0; s < S; ++s) {
+    a[s] = a_pre ? a_pre[s] : p->a_default[s];
+    lam[s] = p->sec[s].lambda;
+    active[s] = lam[s] > 0.0;
+  }
+  double *mean = (double *)(p->ws + p->off_mean), *err = (double *)(p->ws + p->off_err);
+  bool failed = false;
+  int first_failed = -1;
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < S; ++s) any = any || active[s];
+    if (!any) break;
+    qmc_status st = qmc_set_deformation(p, lam.data(), stream);
+    if (st != QMC_OK) return st;
+    st = integrate_sectors(p, n.data(), a.data(), active.data(), stream, nullptr, mean, err);
+    if (st != QMC_OK) return st;
+    if ((st = qmc_sign_violations(p, stream, cnt.data())) != QMC_OK) return st;
+    for (int s = 0; s < S; ++s) {
+      if (!active[s] || cnt[s] == 0) {
+        active[s] = 0;
+        continue;
+      }
+      if (halv[s] < max_halvings) {
+        lam[s] *= 0.5;
+        ++halv[s];
+      } else {
+        active[s] = 0;
+        if (!failed) first_failed = s;
+        failed = true;
+      }
+    }
+  }
+  qmc_status st = qmc_set_deformation(p, lam.data(), stream);
+  if (st != QMC_OK) return st;
+  for (int s = 0; s < S; ++s) {
+    if (lambda_out) lambda_out[s] = lam[s];
+    if (halvings_out) halvings_out[s] = halv[s];
+  }
+  if (failed)
+    return fail(QMC_E_SIGNCHECK, "sector %d: sign check still fails after %d halvings",
+                first_failed, max_halvings);
+  return QMC_OK;
 }
 
 qmc_status qmc_korobov_p2(qmc_plan_t p, uint64_t n, int32_t d, const uint64_t *cand,

@@ -1,0 +1,400 @@
+// qmc_deform_kernels.hip -- complex integrand on a deformed integration contour.
+//
+// For kinematics where F changes sign on the unit cube the integral is taken with the
+// F - i0 prescription on the contour
+//   z_j(x) = x_j - i lambda x_j (1 - x_j) g_j(x),   g = grad F at real x,
+// with Jacobian det(dz/dx) and the integrand continued analytically to z.  The
+// deformation parameter is chosen from presamples (the paper's library call,
+// Sec. 3.1.3).  Per sample, in FP64:
+//   lattice point and transform   as on the real contour (shared device helpers)
+//   g_j, H_jk                     dense Horner over per-sector derivative tables of F
+//   det(dz/dx)                    dz/dx = I - i lambda (D1 + D2 H), D1 = diag((1-2x) g),
+//                                 D2 = diag(x(1-x)); with S = D2^(1/2) it is similar to
+//                                 the complex symmetric I - i lambda (D1 + S H S), whose
+//                                 Hermitian part is I, so Gaussian elimination needs no
+//                                 pivoting: a symmetric LDL^T on the lower triangle
+//   U(z), F(z)                    nested Horner with complex variables, real coefficients
+//   x^p U^a F^b (log F)^m         complex powers; log F = log|F| + i arg F with
+//                                 arg F in [-pi, pi) (F - i0); half-integer powers of F
+//                                 on the same branch
+//   sign check                    Im F(z) > 2^-40 |F(z)| counts as a violation
+// The (re, im) parts of every order are accumulated as two real columns, so the
+// workgroup partials, the per-sector reduction and the statistics are those of the
+// real contour with 2 K columns.
+#include "qmc_device.h"
+
+namespace qmc {
+
+struct C2 {
+  double r, i;
+};
+
+__device__ __forceinline__ C2 cmul(C2 a, C2 b) {
+  return C2{__builtin_fma(a.r, b.r, -(a.i * b.i)), __builtin_fma(a.r, b.i, a.i * b.r)};
+}
+
+// a * b + c
+__device__ __forceinline__ C2 cfma(C2 a, C2 b, C2 c) {
+  return C2{__builtin_fma(a.r, b.r, __builtin_fma(-a.i, b.i, c.r)),
+            __builtin_fma(a.r, b.i, __builtin_fma(a.i, b.r, c.i))};
+}
+
+__device__ __forceinline__ C2 crecip(C2 a) {
+  const double inv = recip(__builtin_fma(a.r, a.r, a.i * a.i));
+  return C2{a.r * inv, -a.i * inv};
+}
+
+__device__ __forceinline__ C2 cipow(C2 z, int e) {
+  C2 r{1.0, 0.0};
+  for (int t = 0; t < e; ++t) r = cmul(r, z);
+  return r;
+}
+
+// Square root with the branch cut on the negative real axis taken from below
+// (argument of a in [-pi, pi), so sqrt(-|a|) = -i sqrt|a|); for Re a >= 0 it is the
+// principal root.
+__device__ __forceinline__ C2 csqrt_minus_i0(C2 a) {
+  const double r = sqrt(__builtin_fma(a.r, a.r, a.i * a.i));
+  if (r == 0.0) return C2{0.0, 0.0};
+  if (a.r >= 0.0) {
+    const double t = sqrt(0.5 * (r + a.r));
+    return C2{t, a.i * (0.5 * recip(t))};
+  }
+  const double t = sqrt(0.5 * (r - a.r));
+  const double sgn = a.i > 0.0 ? 1.0 : -1.0;   // Im a = +-0: below the cut
+  return C2{__builtin_fabs(a.i) * (0.5 * recip(t)), sgn * t};
+}
+
+// log(F - i0)
+__device__ __forceinline__ C2 clog_minus_i0(C2 a) {
+  const double lr = 0.5 * log_f64(__builtin_fma(a.r, a.r, a.i * a.i));
+  const double arg = (a.i == 0.0 && a.r < 0.0) ? -3.141592653589793 : atan2(a.i, a.r);
+  return C2{lr, arg};
+}
+
+// Dense nested Horner with complex variables over the degree-3 layout (coefficients
+// real and wave-uniform), total degree DEG.
+template <int D, int DEG>
+__device__ __forceinline__ C2 horner_c(cptr<double> c, const C2 (&z)[D], LoadChain &ch) {
+  c = ch.next(c);
+  C2 acc{c[0], 0.0};
+  int p = 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    c = ch.next(c);
+    C2 g{c[p], 0.0};
+    ++p;
+    if (DEG >= 2) {
+#pragma unroll
+      for (int k = j; k < D; ++k) {
+        if (DEG >= 3) c = ch.next(c);
+        C2 h{c[p], 0.0};
+        ++p;
+        if (DEG >= 3) {
+#pragma unroll
+          for (int l = k; l < D; ++l) {
+            h.r = __builtin_fma(c[p + l - k], z[l].r, h.r);
+            h.i = __builtin_fma(c[p + l - k], z[l].i, h.i);
+          }
+          ch.done(h.r);
+        }
+        p += D - k;
+        g = cfma(z[k], h, g);
+      }
+    } else {
+      p += (D - j) * (D - j + 3) / 2;
+    }
+    acc = cfma(z[j], g, acc);
+    ch.done(acc.r);
+  }
+  return acc;
+}
+
+template <int D>
+__device__ __forceinline__ C2 poly_c(cptr<double> c, int deg, const C2 (&z)[D], LoadChain &ch) {
+  if (deg >= 3) return horner_c<D, 3>(c, z, ch);
+  if (deg == 2) return horner_c<D, 2>(c, z, ch);
+  return horner_c<D, 1>(c, z, ch);
+}
+
+// Real Horner over the compact degree-2 layout (c0, then per j: c_j, c_jk for k >= j).
+template <int D>
+__device__ __forceinline__ double horner2(cptr<double> c, const double (&x)[D], LoadChain &ch) {
+  c = ch.next(c);
+  double acc = c[0];
+  int p = 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    double g = c[p];
+#pragma unroll
+    for (int k = j; k < D; ++k) g = __builtin_fma(x[k], c[p + 1 + k - j], g);
+    p += 1 + D - j;
+    acc = __builtin_fma(x[j], g, acc);
+  }
+  ch.done(acc);
+  return acc;
+}
+
+// Real linear polynomial c0 + sum_j c_{j+1} x_j.
+template <int D>
+__device__ __forceinline__ double horner1(cptr<double> c, const double (&x)[D], LoadChain &ch) {
+  c = ch.next(c);
+  double acc = c[0];
+#pragma unroll
+  for (int j = 0; j < D; ++j) acc = __builtin_fma(c[1 + j], x[j], acc);
+  ch.done(acc);
+  return acc;
+}
+
+constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // lower triangle, j <= i
+
+// J f_k(z(x)) for every order; returns whether the sample violates the sign check.
+template <int D>
+__device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<SectorDev> sd,
+                                                 cptr<double> coef, int grad_off, int hess_off,
+                                                 double lam, const double (&x)[D],
+                                                 C2 (&f)[QMC_MAX_ORDERS]) {
+  LoadChain ch{x[0], x[0]};
+  double g[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) g[j] = horner2<D>(coef + grad_off + j * dense_len2(D), x, ch);
+  double sq[D];
+  C2 z[D];
+  C2 A[D * (D + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double s = x[j] * (1.0 - x[j]);
+    // korobov3 evaluated with fused multiply-adds can round x a few ulp above 1 near
+    // y = 1, making s a tiny negative number; the symmetric scaling takes its root
+    sq[j] = sqrt(__builtin_fmax(s, 0.0));
+    z[j] = C2{x[j], -lam * s * g[j]};
+    A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
+  }
+  {
+    int t = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int k = j; k < D; ++k, ++t) {
+        const double h = horner1<D>(coef + hess_off + t * dense_len1(D), x, ch);
+        const double v = -lam * sq[j] * sq[k] * h;
+        if (k == j) A[tri(j, j)].i += v;
+        else A[tri(k, j)] = C2{0.0, v};
+      }
+  }
+  // det by symmetric elimination without pivoting
+  C2 det{1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const C2 piv = A[tri(k, k)];
+    det = cmul(det, piv);
+    if (k + 1 < D) {
+      const C2 r = crecip(piv);
+#pragma unroll
+      for (int i = k + 1; i < D; ++i) {
+        const C2 t = cmul(A[tri(i, k)], r);
+#pragma unroll
+        for (int j = k + 1; j <= i; ++j) {
+          const C2 u = cmul(t, A[tri(j, k)]);
+          A[tri(i, j)] = C2{A[tri(i, j)].r - u.r, A[tri(i, j)].i - u.i};
+        }
+      }
+    }
+  }
+  const C2 U = poly_c<D>(coef + ss.u_off, ss.u_deg, z, ch);
+  const C2 F = poly_c<D>(coef + ss.f_off, ss.f_deg, z, ch);
+  const bool viol = F.i > 0.0 && F.i * F.i > 0x1p-80 * __builtin_fma(F.r, F.r, F.i * F.i);
+
+  const int flags = ss.flags;
+  cptr<SectorDev> sx = launder_after(sd, F.r);
+  C2 num = det, den{1.0, 0.0};
+  if (flags & SF_XPOW) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      num = cmul(num, cipow(z[j], sx->x_num[j]));
+      den = cmul(den, cipow(z[j], sx->x_den[j]));
+      const int h = sx->x_half[j];
+      if (h != 0) {
+        const C2 r = csqrt_minus_i0(z[j]);   // Re z_j = x_j >= 0: principal root
+        if (h > 0) num = cmul(num, r);
+        else den = cmul(den, r);
+      }
+    }
+  }
+  num = cmul(num, cipow(U, ss.u_num));
+  den = cmul(den, cipow(U, ss.u_den));
+  num = cmul(num, cipow(F, ss.f_num));
+  den = cmul(den, cipow(F, ss.f_den));
+  if (ss.f_half != 0) {
+    const C2 r = csqrt_minus_i0(F);
+    if (ss.f_half > 0) num = cmul(num, r);
+    else den = cmul(den, r);
+  }
+  const C2 B = (flags & SF_DEN) ? cmul(num, crecip(den)) : num;
+  const int M = ss.max_log;
+  cptr<SectorDev> sl = launder_after(sd, B.r);
+  const int K = sl->n_orders;
+  if (flags & SF_LOG) {
+    const C2 L = clog_minus_i0(F);
+#pragma unroll
+    for (int k = 0; k < QMC_MAX_ORDERS; ++k) {
+      if (k >= K) break;
+      C2 v{sl->logc[k][M], 0.0};
+      for (int m = M - 1; m >= 0; --m) v = cfma(v, L, C2{sl->logc[k][m], 0.0});
+      f[k] = cmul(B, v);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < QMC_MAX_ORDERS; ++k) {
+      if (k >= K) break;
+      const double c0 = sl->logc[k][0];
+      f[k] = C2{B.r * c0, B.i * c0};
+    }
+  }
+  return viol;
+}
+
+// One workgroup's share of a sector on the deformed contour: the loop structure of
+// the real-contour block (one shift per pass), with 2 K accumulator columns.
+template <int D>
+__device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_begin, int tile,
+                                             int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
+  const SectorDev *__restrict__ sd = a.sectors + s;
+  const LatticeDev *__restrict__ lt = a.lat + s;
+  const uint64_t n = lt->n;
+  const double n_d = lt->n_d, inv_n = lt->inv_n;
+  const int64_t chunk = lt->chunk;
+  const uint64_t i_begin = (uint64_t)(chunk_id * chunk);
+  uint64_t i_end = i_begin + (uint64_t)chunk;
+  if (i_end > n) i_end = n;
+  const int kind = sd->transform;
+  const double w_scale = sd->w_scale;
+  const double lam = sd->lambda;
+  const int grad_off = sd->grad_off, hess_off = sd->hess_off;
+  const SectorScalars ss = load_scalars(sd);
+  const int KC = a.K;   // 2 K columns
+  const uint64_t B = blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
+  double k0[D];
+  const uint64_t i0 = i_begin + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < D; ++j) k0[j] = (double)mulmod(i0 % n, lt->z[j], n);
+  uint32_t viol = 0;
+
+#pragma unroll 1
+  for (int l0 = 0; l0 < tile; ++l0) {
+    DD acc[2 * QMC_MAX_ORDERS];
+#pragma unroll
+    for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) acc[c] = DD{0.0, 0.0};
+    const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
+    double k[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) k[j] = k0[j];
+    uint64_t i = i0;
+    int64_t it = 0;
+#pragma unroll 1
+    while (it < n_iter) {
+      double part[2 * QMC_MAX_ORDERS];
+#pragma unroll
+      for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) part[c] = 0.0;
+      const int64_t it_end = (n_iter - it < kFold) ? n_iter : it + kFold;
+#pragma unroll 1
+      for (; it < it_end; ++it, i += B) {
+        const cptr<double> cl = launder_uniform(a.coef);
+        const cptr<LatticeDev> ltl = launder_uniform(lt);
+        const cptr<double> shl = launder_uniform(sh);
+        double y[D], x[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const double q = quotient(k[j], n_d, inv_n);
+          k[j] = lattice_step(k[j], ltl->ndz[j], n_d);
+          y[j] = shifted(q, shl[j]);
+        }
+        const double W = apply_transform<D>(kind, w_scale, y, x);
+        C2 f[QMC_MAX_ORDERS];
+#pragma unroll
+        for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) f[kk] = C2{0.0, 0.0};
+        const bool bad = integrand_deform<D>(ss, (cptr<SectorDev>)sd, launder_after(cl, W),
+                                             grad_off, hess_off, lam, x, f);
+        const bool use = (i < i_end) && (W != 0.0);
+        viol += (use && bad) ? 1u : 0u;
+#pragma unroll
+        for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) {
+          part[2 * kk] += use ? W * f[kk].r : 0.0;
+          part[2 * kk + 1] += use ? W * f[kk].i : 0.0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) dd_add(acc[c], part[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) {
+      if (c >= KC) break;
+      const DD r = wave_reduce(acc[c]);
+      if (lane == 0) {
+        red[wave][l0 * KC + c][0] = r.s;
+        red[wave][l0 * KC + c][1] = r.c;
+      }
+    }
+  }
+  // sign-check violations of this workgroup's samples: one vector atomic per wave
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) viol += (uint32_t)__shfl_xor((int)viol, o, 64);
+  if (lane == 0 && viol != 0) atomicAdd(a.sign_count + s, (unsigned long long)viol);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void qmc_deform_kernel(LaunchArgs a, int64_t block_base) {
+  __shared__ double red[kMaxWaves][kMaxTile * 4][2];
+  const int64_t b = block_base + blockIdx.x;
+  const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
+  const LatticeDev *__restrict__ lt = a.lat + s;
+  const int64_t local = b - lt->block_begin;
+  const int nch = lt->n_chunks;
+  const int tile_id = (int)(local / nch);
+  const int64_t chunk_id = local - (int64_t)tile_id * nch;
+  const int T = a.shift_tile;
+  deform_block<D>(a, s, tile_id * T, T, chunk_id, red);
+  __syncthreads();
+  const int nwaves = blockDim.x >> 6;
+  const int cols = T * a.K;
+  if ((int)threadIdx.x < cols) {
+    DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
+    for (int w = 1; w < nwaves; ++w) r = dd_combine(r, DD{red[w][threadIdx.x][0], red[w][threadIdx.x][1]});
+    double *out = a.partial + (b * cols + threadIdx.x) * 2;
+    out[0] = r.s;
+    out[1] = r.c;
+  }
+}
+
+__global__ void qmc_clear_u64_kernel(unsigned long long *p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+int launch_deform(const LaunchArgs &a, const DimLaunch &dl, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
+  switch (dl.d) {
+    case 1: hipLaunchKernelGGL(qmc_deform_kernel<1>, grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL(qmc_deform_kernel<2>, grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL(qmc_deform_kernel<3>, grid, blk, 0, st, a, dl.base); break;
+    case 4: hipLaunchKernelGGL(qmc_deform_kernel<4>, grid, blk, 0, st, a, dl.base); break;
+    case 5: hipLaunchKernelGGL(qmc_deform_kernel<5>, grid, blk, 0, st, a, dl.base); break;
+    case 6: hipLaunchKernelGGL(qmc_deform_kernel<6>, grid, blk, 0, st, a, dl.base); break;
+    case 7: hipLaunchKernelGGL(qmc_deform_kernel<7>, grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL(qmc_deform_kernel<8>, grid, blk, 0, st, a, dl.base); break;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_clear_u64(unsigned long long *p, int64_t count, void *stream) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(qmc_clear_u64_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, p, count);
+  return (int)hipGetLastError();
+}
+
+}  // namespace qmc

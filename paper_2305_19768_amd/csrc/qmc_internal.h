@@ -14,6 +14,11 @@ namespace qmc {
 // stored as c0, then for each j: c_j, then for each k >= j: c_jk followed by the
 // c_jkl for l = k .. D-1.  Length C(D+3, 3).
 constexpr int dense_len(int D) { return (D + 1) * (D + 2) * (D + 3) / 6; }
+// The same layout truncated to total degree 2 (c0, then per j: c_j and the c_jk, k >= j;
+// length C(D+2, 2)) and to degree 1 (c0, c_0 .. c_{D-1}; length D + 1): the gradient
+// and Hessian tables of F in complex plans.
+constexpr int dense_len2(int D) { return (D + 1) * (D + 2) / 2; }
+constexpr int dense_len1(int D) { return D + 1; }
 
 enum : int32_t {
   SF_XPOW = 1,      // some x_j has a non-zero exponent
@@ -41,7 +46,10 @@ struct alignas(16) SectorDev {
   double logc[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
   float logc32[QMC_MAX_ORDERS][QMC_MAX_LOG + 1];
   int32_t u_off32, f_off32;        // offsets of the FP32 copies of the dense tables
-  int32_t pad2[2];
+  int32_t grad_off, hess_off;      // complex plans: D tables dF/dx_j (degree-2 layout), then
+                                   // D(D+1)/2 tables d2F/dx_j dx_k, k >= j (degree-1 layout)
+  double lambda;                   // complex plans: contour deformation parameter (>= 0)
+  double pad3;
 };
 
 // Per-call lattice record of a sector.
@@ -66,7 +74,7 @@ struct alignas(16) LatticeDev {
 // d and path class `fast` (SF_FAST set or not).
 struct DimLaunch {
   int64_t base, blocks;
-  int32_t d, fast, f32, pad;
+  int32_t d, fast, f32, deform;   // deform: complex plan (every sector on the deformed path)
 };
 
 struct LaunchArgs {
@@ -86,7 +94,9 @@ struct LaunchArgs {
   int32_t d_max, precision;
   void *ev_start, *ev_stop;        // optional hipEvent_t pair recorded around the main kernel
   const int32_t *done;             // batched form: nonzero once the evaluation finished
-  int32_t n_dim_launches, pad1;
+  int32_t n_dim_launches;
+  int32_t cplx;                    // complex plan: K counts (re, im) columns, K = 2 n_orders
+  unsigned long long *sign_count;  // complex plans: [S] sign-check violations
   DimLaunch dims[3 * QMC_MAX_DIM];
 };
 
@@ -141,6 +151,10 @@ int persistent_grid(int d_max, bool f32, int block, int *grid);
 // Returns a hipError_t value (0 = success).
 int launch_points(const PointsArgs &pa, unsigned grid, void *stream);
 int launch_integrate(const LaunchArgs &a, void *stream);
+// complex plans: the deformed-contour integrand kernel for one dimension class, and
+// the clearing of the per-sector sign-check counters
+int launch_deform(const LaunchArgs &a, const DimLaunch &dl, void *stream);
+int launch_clear_u64(unsigned long long *p, int64_t count, void *stream);
 int launch_status_reset(int32_t *status, void *stream);
 int launch_reduce_stats(const LaunchArgs &a, void *stream);
 int launch_korobov_p2(uint64_t n, int32_t d, const uint64_t *dev_cand, int32_t n_cand,

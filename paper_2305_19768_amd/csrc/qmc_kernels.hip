@@ -78,7 +78,7 @@ __global__ __launch_bounds__(64) void qmc_reduce_kernel(LaunchArgs a) {
       const double q = (r.s + r.c) / lat->n_d;
       a.q[((int64_t)s * a.m + l) * K + kk] = q;
       if (!isfinite(q)) {
-        const int code = (s * a.m + l) * QMC_MAX_ORDERS + kk;
+        const int code = (s * a.m + l) * QMC_MAX_ORDERS + (a.cplx ? kk >> 1 : kk);
         atomicMin(a.status, code);
       }
     }
@@ -258,7 +258,8 @@ int launch_integrate(const LaunchArgs &a, void *stream) {
   for (int t = 0; t < a.n_dim_launches; ++t) {
     const DimLaunch &dl = a.dims[t];
     if (dl.blocks == 0) continue;
-    if ((e = launch_class(a, dl, st)) != hipSuccess) return (int)e;
+    e = dl.deform ? (hipError_t)launch_deform(a, dl, st) : launch_class(a, dl, st);
+    if (e != hipSuccess) return (int)e;
   }
   if (a.ev_stop && (e = hipEventRecord((hipEvent_t)a.ev_stop, st)) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(qmc_reduce_kernel, dim3((unsigned)(a.n_sectors * a.m)), dim3(64), 0, st, a);

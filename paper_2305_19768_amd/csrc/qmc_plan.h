@@ -28,6 +28,8 @@ struct qmc_plan_s {
   // the plan's host state and the layout of its device workspace
   // problem
   int32_t S = 0, K = 0, M = 0, n_integrals = 0, d_max = 0;
+  int32_t cplx = 0;                    // some sector deformed: complex integrands
+  int32_t KC = 0;                      // columns per (sector, shift): K, or 2 K if complex
   std::vector<qmc::SectorDev> sec;
   std::vector<double> coef;
   std::vector<float> coef32;           // FP32 copy of coef (same offsets)
@@ -42,7 +44,7 @@ struct qmc_plan_s {
   // workspace layout (byte offsets)
   size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
          off_status = 0, off_partial = 0, off_order = 0, off_mean = 0, off_err = 0, off_coef32 = 0, off_amp = 0, amp_bytes = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
-         total = 0;
+         off_sign = 0, total = 0;
   int64_t max_blocks = 0;
   char *ws = nullptr;
   size_t ws_bytes = 0;

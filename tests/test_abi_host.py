@@ -111,3 +111,34 @@ def test_lattice_points_validates_before_launch(L):
     assert L.qmc_lattice_points(101, 3, 5, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                 0, 5, None, out) == -1
     assert L.qmc_lattice_points(101, 3, 5, p, 0, 0, None, out) == 0   # empty: nothing to do
+
+
+def test_complex_plan_validation_and_shape(L):
+    prob = W.physical_scan(seed=0, n_points=1, n_sectors=2, d_lo=3, d_hi=4, n=1009, m=16)
+    rc, h, _ = _plan(prob)
+    assert rc == 0, _err()
+    assert L.qmc_plan_complex(h) == 1
+    # 2 K = 6 columns: the default tile shrinks so that tile * 6 <= 64 (8 of the 16 shifts)
+    nb_c = L.qmc_workspace_bytes(h)
+    L.qmc_plan_free(h)
+    for s in prob.sectors:
+        s.deform_lambda = 0.0
+    rc, h, _ = _plan(prob)
+    assert rc == 0 and L.qmc_plan_complex(h) == 0
+    assert L.qmc_workspace_bytes(h) < nb_c
+    # real plans refuse deformation calls; no device is touched
+    lam = np.array([0.5, 0.5])
+    assert L.qmc_set_deformation(h, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 None) == -7
+    assert "real" in _err()
+    assert L.qmc_choose_deformation(h, 1009, None, 4, None, None, None) == -7
+    L.qmc_plan_free(h)
+    assert L.qmc_plan_complex(None) == -1
+    prob.sectors[1].deform_lambda = -0.5
+    assert _plan(prob)[0] == -1 and "deform_lambda" in _err()
+    prob.sectors[1].deform_lambda = float("inf")
+    assert _plan(prob)[0] == -1
+    prob.sectors[1].deform_lambda = 0.5
+    assert _plan(prob, shifts_per_pass=2)[0] == -1 and "one shift per pass" in _err()
+    assert _plan(prob, shift_tile=16)[0] == -1 and "launch shape" in _err()
+    assert _plan(prob, shift_tile=8)[0] == 0

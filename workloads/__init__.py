@@ -233,6 +233,54 @@ def two_loop_integral(seed: int = 0, n_sectors: int = 40, d_lo: int = 4, d_hi: i
                    seed=seed)
 
 
+def _physical_sector(rng, d, n, integral, s1, s2, lam, shapes=None):
+    """Sector of a physical-region scan point: U as the two-loop sectors; F has the
+    two-loop monomial structure with coefficients alpha_t - beta_t s1 - gamma_t s2,
+    alpha, beta, gamma ~ U(0.1, 1), so F changes sign on the cube.  `shapes` reuses
+    (u_exp, u_coef, f_exp, alpha, beta, gamma, a) of a base sector across points."""
+    if shapes is None:
+        nu = int(rng.integers(4, 9))
+        nf = int(rng.integers(10, 31))
+        u_exp, u_coef = random_polynomial(rng, d, nu, 2)
+        f_exp, _ = random_polynomial(rng, d, nf, 3)
+        al, be, ga = (rng.uniform(0.1, 1.0, size=len(f_exp)) for _ in range(3))
+        a = int(_korobov_candidates(rng, n, 1)[0])
+        shapes = (u_exp, u_coef, f_exp, al, be, ga, a)
+    u_exp, u_coef, f_exp, al, be, ga, a = shapes
+    f_coef = al - be * s1 - ga * s2
+    sec = Sector(d=d, u_exp=u_exp, u_coef=u_coef, f_exp=f_exp, f_coef=f_coef,
+                 x_pow2=np.zeros(d, dtype=np.int32), u_pow=1, f_pow2=-6,
+                 logc=TWO_LOOP_LOGC.copy(), n=n, a=a, transform="korobov3",
+                 integral=integral, deform_lambda=lam)
+    return sec, shapes
+
+
+def physical_scan(seed: int = 0, n_points: int = 1000, n_sectors: int = 200, d_lo: int = 3,
+                  d_hi: int = 8, n: int = 65521, m: int = 16, lam: float = 0.5) -> Problem:
+    """Physical-region scan: n_points kinematic points (s1, s2 ~ U(1, 10)) times the same
+    n_sectors base sectors (d uniform in [d_lo, d_hi]); sector (p, b) belongs to integral
+    p.  Integrand eps^-2 U F^(-3-2 eps) to orders -2..0 as the two-loop sectors, on the
+    deformed contour with initial parameter lam; lattice size n, m shifts."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 5])))
+    base = []
+    for _ in range(n_sectors):
+        d = int(rng.integers(d_lo, d_hi + 1))
+        base.append((d, None))
+    kin = rng.uniform(1.0, 10.0, size=(n_points, 2))
+    secs, shifts = [], []
+    for p in range(n_points):
+        for b in range(n_sectors):
+            d, shapes = base[b]
+            sec, shapes = _physical_sector(rng, d, n, p, kin[p, 0], kin[p, 1], lam, shapes)
+            base[b] = (d, shapes)
+            secs.append(sec)
+            shifts.append(uniform_shifts(rng, m, d))
+    prob = Problem(sectors=secs, order_lo=-2, m=m, shifts=shifts, n_integrals=n_points,
+                   name="physical_scan", seed=seed)
+    prob.kinematics = kin
+    return prob
+
+
 def _rational_in(rng, nvars=3, lo=-9, hi=9, nonneg=False):
     mons = _monomials(nvars, 0, 2)
     if nonneg:
