@@ -59,6 +59,8 @@ enum { QMC_PREC_FP64 = 0, QMC_PREC_FP32 = 1 };
 #define QMC_MAX_LOG 4      /* highest power of log F per order */
 #define QMC_MAX_DEG 3      /* total degree of U and F (one- and two-loop graphs) */
 #define QMC_MAX_SHIFTS 64
+#define QMC_FLOW_LAYERS 4  /* affine coupling layers of a learned flow transform */
+#define QMC_FLOW_HIDDEN 64 /* hidden width of each coupling layer's network */
 
 /*
  * One sector integrand, expanded in epsilon (Sec. 2.3 and 3: sector-decomposed
@@ -330,6 +332,114 @@ typedef struct {
 qmc_status amp_evaluate(qmc_plan_t plan, const qmc_amplitude *amp, const qmc_amp_options *opt,
                         void *stream, double *value, double *error, uint64_t *n_final,
                         qmc_amp_stats *stats);
+
+/*
+ * Launch shape of the integrand kernels: threads per workgroup, shifts per workgroup,
+ * shifts evaluated per lattice point in one pass, and the number of workgroups a launch
+ * aims at (lattice points per thread follow from it).  All shapes give the same sums up
+ * to rounding order.
+ */
+typedef struct {
+    int32_t block;                    /* 64, 128 or 256 */
+    int32_t shift_tile;               /* 1..16, divides m, shift_tile * columns <= 64 */
+    int32_t shifts_per_pass;          /* 1, 2, 4 (divides shift_tile); 1 for complex plans */
+    int32_t target_blocks;            /* 256 .. 32768 */
+    double ms;                        /* qmc_autotune: measured time of the shape, ms */
+} qmc_launch_shape;
+
+qmc_status qmc_set_launch_shape(qmc_plan_t plan, const qmc_launch_shape *shape);
+qmc_status qmc_get_launch_shape(qmc_plan_t plan, qmc_launch_shape *shape);
+
+/*
+ * qmc_autotune -- grid search over launch shapes (block 64/128/256, power-of-two shift
+ * tiles dividing m, 1/2/4 shifts per pass where compiled, 8192/16384/32768 target
+ * workgroups): each shape is timed with HIP events around `reps` qmc_integrate calls on
+ * lattices n, a (NULL: the sectors' defaults), after one warm-up; the fastest (minimum
+ * over the repetitions) is set on the plan and cached for the process under a key of
+ * the plan's shape (sectors, dimensions, orders, precision, shifts, degrees, flows).
+ * With use_cache != 0 a cached shape for the same key is applied without timing.
+ * Synchronous; overwrites the plan's internal Q and statistics buffers.
+ */
+qmc_status qmc_autotune(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, int32_t reps,
+                        int32_t use_cache, void *stream, qmc_launch_shape *best);
+
+/*
+ * Learned coupling-flow transform (an alternative variable transform beside the
+ * periodizing ones; not in the paper).  A flow for dimension d is a stack of
+ * QMC_FLOW_LAYERS affine coupling layers in logit space of the unit cube: layer l keeps
+ * the coordinates j with j % 2 == l % 2 and maps the others by z -> z exp(s) + t, where
+ * (o_s, o_t) = W3 tanh(W2 tanh(W1 (m_l z) + b1) + b2) + b3 (widths d, 64, 64, 2d) and
+ * s = 0.25 tanh(o_s), t = o_t, restricted to the moved coordinates.  The density
+ * direction G: x -> u has log q(x) = log|det du/dx|; the sampling direction T = G^-1 is
+ * what integration uses: x = T(u) after the sector's periodizing transform, weight
+ * J_T(u) = 1/q(x).  The networks run on the matrix cores in bfloat16 with float32
+ * accumulation; the coupling updates, logit and sigmoid are float64.
+ *
+ * Parameters (host float32, qmc_flow_param_count(d) values) are laid out per layer as
+ * W1 [64][d], b1 [64], W2 [64][64], b2 [64], W3 [2d][64] (rows s then t), b3 [2d].  A flow's
+ * device state (parameters, Adam moments, gradient, packed operands) is a caller-owned,
+ * 256-byte aligned device buffer of qmc_flow_bytes(d) bytes.
+ */
+enum { QMC_FLOW_SAMPLE = 0, QMC_FLOW_DENSITY = 1 };
+
+typedef struct {
+    float lr, beta1, beta2, eps;      /* Adam (Kingma and Ba 2015) */
+    int32_t step;                     /* 1-based step number of this update (bias correction) */
+    int32_t reserved0;
+} qmc_flow_adam;
+
+int64_t qmc_flow_param_count(int32_t d);          /* -1 if d is outside [1, QMC_MAX_DIM] */
+size_t qmc_flow_bytes(int32_t d);                  /* 0 if d is out of range */
+
+/* Upload parameters, zero the Adam moments and gradient, pack the matrix-core operands.
+ * Synchronous.  Errors: QMC_E_INVAL (NULL, misaligned, non-finite parameter). */
+qmc_status qmc_flow_load(void *dev_flow, int32_t d, const float *params, void *stream);
+
+/* Copy parameters and/or the last gradient (either may be NULL) to the host.  Synchronous. */
+qmc_status qmc_flow_read(const void *dev_flow, int32_t d, float *params, float *grad, void *stream);
+
+/* dev_out[i][j], dev_logdet[i] for dev_in [count][d] (device float64, coordinates in
+ * (0, 1)): QMC_FLOW_SAMPLE gives x = T(u) and log J_T(u); QMC_FLOW_DENSITY gives u = G(x)
+ * and log q(x).  Asynchronous. */
+qmc_status qmc_flow_transform(const void *dev_flow, int32_t d, int32_t direction,
+                              const double *dev_in, int64_t count, void *stream, double *dev_out,
+                              double *dev_logdet);
+
+/* Device scratch bytes of qmc_flow_gradient over `count` points. */
+size_t qmc_flow_scratch_bytes(int32_t d, int64_t count);
+
+/* Gradient of L = -(1/w_sum) sum_i w_i log q(x_i) (weighted maximum likelihood of samples
+ * x [count][d] with weights w [count], device float64) into the flow's gradient buffer;
+ * *dev_loss (device, may be NULL) receives L.  Asynchronous; deterministic. */
+qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, const double *dev_x, const double *dev_w,
+                             int64_t count, double w_sum, void *dev_scratch, size_t scratch_bytes,
+                             void *stream, double *dev_loss);
+
+/* One Adam update of the parameters from the gradient buffer; repacks the operands. */
+qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, const qmc_flow_adam *opt, void *stream);
+
+/* Training: `epochs` passes over `batches` strided minibatches (batch b: samples
+ * b, b + batches, ...), one gradient and one Adam step each (steps numbered from
+ * opt->step).  w_sum: sum of all weights.  dev_loss_history (device, may be NULL) gets
+ * each step's loss.  Scratch: qmc_flow_scratch_bytes(d, count / batches).  Asynchronous. */
+qmc_status qmc_flow_train(void *dev_flow, int32_t d, const double *dev_x, const double *dev_w,
+                          int64_t count, double w_sum, const qmc_flow_adam *opt, int32_t batches,
+                          int32_t epochs, void *dev_scratch, size_t scratch_bytes, void *stream,
+                          double *dev_loss_history);
+
+/* Training samples of a sector of a real plan: for the points i < n of the Korobov
+ * lattice (n, a) with the plan's shift `shift`, dev_x[i][j] = phi(y_i)_j (the sector's
+ * periodizing transform) and dev_w[i] = W(y_i) ||(f_k(x_i))_k||_2, the weight for which
+ * the optimal model density is proportional to the root of the summed squares of the
+ * orders (0 where W = 0 or f is not finite).  Asynchronous. */
+qmc_status qmc_flow_samples(qmc_plan_t plan, int32_t sector, uint64_t n, uint64_t a, int32_t shift,
+                            void *stream, double *dev_x, double *dev_w);
+
+/* Integrate `sector` of a real plan through the flow: per lattice sample y,
+ * u = phi(y) with weight W, x = T(u), contribution W J_T(u) f(x) (0 when a coordinate of
+ * u or x is not inside (0, 1)).  dev_flow NULL detaches.  The flow buffer must stay
+ * valid while attached.  Synchronous. */
+qmc_status qmc_flow_attach(qmc_plan_t plan, int32_t sector, const void *dev_flow, void *stream);
 
 /*
  * qmc_enable_timing / qmc_read_timing -- kernel timing for measurement: while enabled,

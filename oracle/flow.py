@@ -177,3 +177,56 @@ def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 def adam_init(params):
     z = [[np.zeros_like(a) for a in p] for p in params]
     return (0, z, [[np.zeros_like(a) for a in p] for p in params])
+
+
+def sector_sums(sec, shifts, params, n=None, a=None, bf=True):
+    """Per-shift estimates of a sector integrated through the flow:
+        Q[l, k] = (1/n) sum_i W(y_i) J_T(u_i) f_k(T(u_i)),   u_i = phi(y_i)
+    with the sector's periodizing transform phi (weight W) and the flow's sampling
+    direction T; a sample with a coordinate of u or x outside (0, 1) contributes 0.
+    Lattice points, phi and f come from the C oracle; sums are exact (math.fsum).
+    Returns (Q, S) with S[l, k] = (1/n) sum_i |W J f_k| (tolerance scale)."""
+    import math
+    from . import integrand, korobov_vector, points, transform
+    n = int(sec.n if n is None else n)
+    z = korobov_vector(n, sec.a if a is None else a, sec.d)
+    out = np.empty((len(shifts), sec.K))
+    scale = np.empty((len(shifts), sec.K))
+    for l, sh in enumerate(np.asarray(shifts, dtype=np.float64)):
+        y = points(n, z, sh)
+        u, w = transform(sec.transform, y)
+        W = np.prod(w, axis=1)
+        in_u = np.all((u > 0.0) & (u < 1.0), axis=1)
+        uu = np.where(in_u[:, None], u, 0.5)
+        with np.errstate(divide="ignore"):      # x rounded onto a face: excluded below
+            x, logJ = sampling_direction(params, uu, bf)
+        in_x = np.all((x > 0.0) & (x < 1.0), axis=1)
+        xx = np.where(in_x[:, None], x, 0.5)
+        f = integrand(sec, xx)
+        Wt = W * np.exp(logJ)
+        use = in_u & in_x & (Wt != 0.0)
+        for k in range(sec.K):
+            c = np.where(use, Wt * f[:, k], 0.0)
+            out[l, k] = math.fsum(c) / n
+            scale[l, k] = math.fsum(np.abs(c)) / n
+    return out, scale
+
+
+def flatten(params) -> np.ndarray:
+    """Parameters in the library's layout: per layer W1, b1, W2, b2, W3, b3 (float32)."""
+    return np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for p in params
+                           for a in p]).astype(np.float32)
+
+
+def unflatten(v, d):
+    v = np.asarray(v, dtype=np.float64)
+    shapes = [(HIDDEN, d), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (2 * d, HIDDEN), (2 * d,)]
+    out, o = [], 0
+    for _ in range(LAYERS):
+        layer = []
+        for sh in shapes:
+            size = int(np.prod(sh))
+            layer.append(v[o:o + size].reshape(sh))
+            o += size
+        out.append(layer)
+    return out

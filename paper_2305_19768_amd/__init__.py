@@ -14,8 +14,10 @@ from typing import Optional, Sequence
 
 import numpy as np
 
+from . import flow  # noqa: F401  (learned flow transform)
 from ._abi import (QMC_MAX_DIM, QMC_MAX_LOG, QMC_MAX_ORDERS, QMC_PREC_FP32, QMC_PREC_FP64,
-                   TRANSFORMS, AmpOptions, AmpStats, Amplitude, QmcError, lib, options_struct,
+                   TRANSFORMS, AmpOptions, AmpStats, Amplitude, LaunchShape, QmcError, lib,
+                   options_struct,
                    problem_struct)
 
 QMC_AMP_HOST = 0
@@ -123,6 +125,55 @@ class Plan:
         if check:
             self.check_status(stream)
         return q, mean, err
+
+    def flow_samples(self, sector: int, n: int, a: int, shift: int = 0, stream=None):
+        """Training samples of a sector for a flow transform: (x [n, d], w [n]) device
+        float64 tensors (see qmc_flow_samples)."""
+        torch = _torch()
+        d = int(self.problem.sectors[sector].d)
+        x = torch.empty((int(n), d), dtype=torch.float64, device=self.device)
+        w = torch.empty(int(n), dtype=torch.float64, device=self.device)
+        _check(lib().qmc_flow_samples(self._h, int(sector), ctypes.c_uint64(int(n)),
+                                      ctypes.c_uint64(int(a)), int(shift), _stream_ptr(stream),
+                                      ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(w.data_ptr())),
+               "qmc_flow_samples")
+        return x, w
+
+    def attach_flow(self, sector: int, flow, stream=None):
+        """Integrate `sector` through `flow` (a paper_2305_19768_amd.flow.Flow), or detach
+        with None.  The plan keeps a reference to the flow while attached."""
+        if not hasattr(self, "_flows"):
+            self._flows = {}
+        ptr = None if flow is None else ctypes.c_void_p(flow.ptr)
+        _check(lib().qmc_flow_attach(self._h, int(sector), ptr, _stream_ptr(stream)),
+               "qmc_flow_attach")
+        if flow is None:
+            self._flows.pop(int(sector), None)
+        else:
+            self._flows[int(sector)] = flow
+
+    def launch_shape(self) -> dict:
+        sh = LaunchShape()
+        _check(lib().qmc_get_launch_shape(self._h, ctypes.byref(sh)), "qmc_get_launch_shape")
+        return {f: getattr(sh, f) for f, _ in LaunchShape._fields_}
+
+    def set_launch_shape(self, block: int, shift_tile: int, shifts_per_pass: int,
+                         target_blocks: int = 16384):
+        sh = LaunchShape(block, shift_tile, shifts_per_pass, target_blocks, 0.0)
+        _check(lib().qmc_set_launch_shape(self._h, ctypes.byref(sh)), "qmc_set_launch_shape")
+
+    def autotune(self, n=None, a=None, reps: int = 3, use_cache: bool = True, stream=None) -> dict:
+        """Times the launch shapes of the integrand kernels on lattices n, a and keeps the
+        fastest (see qmc_autotune); returns it with its time in ms."""
+        n_arr = None if n is None else np.ascontiguousarray(n, dtype=np.uint64)
+        a_arr = None if a is None else np.ascontiguousarray(a, dtype=np.uint64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        sh = LaunchShape()
+        _check(lib().qmc_autotune(self._h, None if n_arr is None else n_arr.ctypes.data_as(u64p),
+                                  None if a_arr is None else a_arr.ctypes.data_as(u64p),
+                                  int(reps), 1 if use_cache else 0, _stream_ptr(stream),
+                                  ctypes.byref(sh)), "qmc_autotune")
+        return {f: getattr(sh, f) for f, _ in LaunchShape._fields_}
 
     def sign_violations(self, stream=None) -> np.ndarray:
         """Per-sector sign-check violation counts of the last integrate() (complex plans)."""

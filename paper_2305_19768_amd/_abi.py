@@ -39,6 +39,12 @@ class SectorDesc(ctypes.Structure):
                 ("deform_lambda", ctypes.c_double)]
 
 
+class LaunchShape(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("shift_tile", ctypes.c_int32),
+                ("shifts_per_pass", ctypes.c_int32), ("target_blocks", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("n_sectors", ctypes.c_int32), ("n_orders", ctypes.c_int32),
                 ("order_lo", ctypes.c_int32), ("max_log", ctypes.c_int32),
@@ -117,6 +123,15 @@ def lib():
         L.qmc_choose_deformation.argtypes = [vp, ctypes.c_uint64, u64p, ctypes.c_int32, vp,
                                              ctypes.POINTER(ctypes.c_double), i32p]
         L.qmc_choose_deformation.restype = ctypes.c_int
+        L.qmc_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
+        L.qmc_set_launch_shape.restype = ctypes.c_int
+        L.qmc_get_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
+        L.qmc_get_launch_shape.restype = ctypes.c_int
+        L.qmc_autotune.argtypes = [vp, u64p, u64p, ctypes.c_int32, ctypes.c_int32, vp,
+                                   ctypes.POINTER(LaunchShape)]
+        L.qmc_autotune.restype = ctypes.c_int
+        from . import flow as _flow
+        _flow.bind(L)
         L.qmc_korobov_p2.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, u64p, ctypes.c_int32,
                                      vp, vp]
         L.qmc_korobov_p2.restype = ctypes.c_int

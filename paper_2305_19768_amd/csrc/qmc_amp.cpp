@@ -53,6 +53,10 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, const std::vector<double> &c
                       std::chrono::steady_clock::time_point t_start) {
   const int S = p->S, K = p->K;
   for (int s = 0; s < S; ++s)
+    if (p->sec[s].flow)
+      return fail(QMC_E_INVAL, "device mode does not integrate flow-transformed sectors "
+                               "(sector %d has a flow attached); use the host mode", s);
+  for (int s = 0; s < S; ++s)
     if (!(p->sec[s].flags & SF_FAST))
       return fail(QMC_E_INVAL, "device mode evaluates sectors of the common shape only "
                                "(korobov3, integer powers of U and F); sector %d is not", s);

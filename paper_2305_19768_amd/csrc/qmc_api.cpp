@@ -10,7 +10,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -72,8 +75,12 @@ static void layout(qmc_plan_s *p) {
     o = align256(o + bytes);
     return at;
   };
+  // the partial buffer holds any tunable launch shape: at most target + S (m / tile) + 64
+  // workgroups (one rounding workgroup per sector and tile), tile * KC pairs each
   const int tiles = (p->m + p->tile - 1) / p->tile;
   p->max_blocks = kTargetBlocks + (int64_t)p->S * tiles + 64;
+  p->partial_doubles = 2 * (size_t)p->KC *
+                       ((size_t)kTargetBlocksMax * kMaxTile + (size_t)p->S * p->m + 64 * kMaxTile);
   p->off_sec = take(sizeof(SectorDev) * p->S);
   p->off_coef = take(sizeof(double) * p->coef.size());
   p->off_coef32 = take(sizeof(float) * p->coef.size());
@@ -95,7 +102,7 @@ static void layout(qmc_plan_s *p) {
   p->off_err = take(sizeof(double) * (size_t)p->S * p->KC);
   p->off_status = take(256);
   p->off_sign = take(sizeof(unsigned long long) * (size_t)p->S);
-  p->off_partial = take(sizeof(double) * 2 * (size_t)p->max_blocks * p->tile * p->KC);
+  p->off_partial = take(sizeof(double) * p->partial_doubles);
   p->off_p2cand = take(sizeof(uint64_t) * kP2MaxCand);
   p->off_p2part = take(sizeof(double) * kP2PartialDoubles);
   p->off_p2vals = take(sizeof(double) * kP2MaxCand);
@@ -221,13 +228,27 @@ static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t
   return QMC_OK;
 }
 
-// 0: generic path, 1: fast path in FP64, 2: fast path in FP32, 3: deformed (complex plan).
+// 0: generic path, 1: fast path in FP64, 2: fast path in FP32, 3: deformed (complex plan),
+// 4: attached flow transform.
 static int path_class(const qmc_plan_s *p, int s) {
   if (p->cplx) return 3;
+  if (p->sec[s].flow) return 4;
   const int f = p->sec[s].flags;
   if (!(f & SF_FAST)) return 0;
   return (p->precision == QMC_PREC_FP32 && (f & SF_F32OK)) ? 2 : 1;
 }
+
+namespace qmc {
+// Workgroup order: by dimension, then path class, then sector index.
+void plan_reorder(qmc_plan_s *p) {
+  p->order.resize(p->S);
+  for (int s = 0; s < p->S; ++s) p->order[s] = s;
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int32_t x, int32_t y) {
+    const int fx = path_class(p, x), fy = path_class(p, y);
+    return p->dims[x] != p->dims[y] ? p->dims[x] < p->dims[y] : fx < fy;
+  });
+}
+}  // namespace qmc
 
 static void split_pow2(int32_t e2, int32_t *num, int32_t *den, int32_t *half) {
   const int32_t mag = e2 < 0 ? -e2 : e2;
@@ -424,13 +445,7 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
             (double)(splitmix64(opt->seed, c) >> 11) * 0x1.0p-53;
       }
   p->coef32.assign(p->coef.begin(), p->coef.end());
-  p->order.resize(p->S);
-  for (int s = 0; s < p->S; ++s) p->order[s] = s;
-  // workgroup order: by dimension, then path class (generic, fast FP64, fast FP32), then index
-  std::stable_sort(p->order.begin(), p->order.end(), [&](int32_t x, int32_t y) {
-    const int fx = path_class(p, x), fy = path_class(p, y);
-    return p->dims[x] != p->dims[y] ? p->dims[x] < p->dims[y] : fx < fy;
-  });
+  plan_reorder(p);
   layout(p);
   p->lat.resize(p->S);
   p->begin.resize(p->S + 1);
@@ -540,13 +555,13 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     }
     total += (__int128)n * tiles;
   }
-  // points per thread: enough that the launch has about kTargetBlocks workgroups
-  const __int128 per_block = (__int128)kTargetBlocks * p->block;
+  // points per thread: enough that the launch has about target_blocks workgroups
+  const __int128 per_block = (__int128)p->target_blocks * p->block;
   int64_t ppt = (int64_t)((total + per_block - 1) / per_block);
   if (ppt < 1) ppt = 1;
   const int64_t chunk = ppt * p->block;
   int64_t b = 0;
-  DimLaunch dl[3 * QMC_MAX_DIM];
+  DimLaunch dl[4 * QMC_MAX_DIM];
   int n_dl = 0;
   for (int t = 0; t < p->S; ++t) {
     const int s = p->order[t];
@@ -557,15 +572,18 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     p->begin[t] = b;
     const int cls = path_class(p, s);
     const int fast = (cls == 1 || cls == 2) ? 1 : 0, f32 = cls == 2 ? 1 : 0;
-    const int deform = cls == 3 ? 1 : 0;
+    const int deform = cls == 3 ? 1 : 0, flow = cls == 4 ? 1 : 0;
     if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
-        dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].deform != deform) {
+        dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].deform != deform || dl[n_dl - 1].flow != flow) {
+      if (n_dl == 4 * QMC_MAX_DIM) return fail(QMC_E_STATE, "too many launch classes");
       dl[n_dl].d = p->dims[s];
       dl[n_dl].base = b;
       dl[n_dl].blocks = 0;
       dl[n_dl].fast = fast;
       dl[n_dl].f32 = f32;
       dl[n_dl].deform = deform;
+      dl[n_dl].flow = flow;
+      dl[n_dl].pad = 0;
       ++n_dl;
     }
     const int64_t nb = (int64_t)L.n_chunks * tiles;
@@ -573,9 +591,9 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     b += nb;
   }
   p->begin[p->S] = b;
-  if (b > p->max_blocks)
+  if ((size_t)b * p->tile * p->KC * 2 > p->partial_doubles)
     return fail(QMC_E_NOMEM, "launch needs %lld workgroups, workspace holds %lld", (long long)b,
-                (long long)p->max_blocks);
+                (long long)(p->partial_doubles / (2 * (size_t)p->tile * p->KC)));
   hipStream_t st = (hipStream_t)stream;
   int e;
   const bool same = p->lat_valid && p->lat_uploaded.size() == p->lat.size() &&
@@ -769,6 +787,131 @@ qmc_status qmc_choose_deformation(qmc_plan_t p, uint64_t n_pre, const uint64_t *
   if (failed)
     return fail(QMC_E_SIGNCHECK, "sector %d: sign check still fails after %d halvings",
                 first_failed, max_halvings);
+  return QMC_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+static std::mutex g_tune_mu;
+static std::map<std::string, qmc_launch_shape> g_tune_cache;
+
+// Cache key: what decides the best launch shape of the integrand kernels.
+static std::string tune_key(const qmc_plan_s *p) {
+  long long mono = 0, flows = 0;
+  for (const SectorDev &sd : p->sec) {
+    mono += sd.u_deg * 1000 + sd.f_deg;
+    flows += sd.flow != 0;
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "S%d d%d K%d M%d p%d m%d c%d f%lld u%lld", p->S, p->d_max, p->K,
+                p->M, p->precision, p->m, p->cplx, flows, mono);
+  return buf;
+}
+
+qmc_status qmc_set_launch_shape(qmc_plan_t p, const qmc_launch_shape *sh) {
+  g_last_error.clear();
+  if (!p || !sh) return fail(QMC_E_INVAL, "NULL argument");
+  const int spp = p->cplx ? 1 : sh->shifts_per_pass;
+  if (!tile_supported(sh->shift_tile, spp, sh->block) || sh->shift_tile * p->KC > 64 ||
+      p->m % sh->shift_tile != 0 || (p->cplx && sh->shifts_per_pass != 1))
+    return fail(QMC_E_INVAL, "unsupported launch shape: block %d, shift_tile %d, shifts_per_pass %d",
+                sh->block, sh->shift_tile, sh->shifts_per_pass);
+  if (sh->target_blocks < 256 || sh->target_blocks > kTargetBlocksMax)
+    return fail(QMC_E_INVAL, "target_blocks = %d outside [256, %lld]", sh->target_blocks,
+                (long long)kTargetBlocksMax);
+  p->block = sh->block;
+  p->tile = sh->shift_tile;
+  p->spp = spp;
+  p->target_blocks = sh->target_blocks;
+  p->persistent_grid[0] = p->persistent_grid[1] = 0;   // occupancy depends on the block size
+  p->lat_valid = false;
+  return QMC_OK;
+}
+
+qmc_status qmc_get_launch_shape(qmc_plan_t p, qmc_launch_shape *sh) {
+  if (!p || !sh) return fail(QMC_E_INVAL, "NULL argument");
+  sh->block = p->block;
+  sh->shift_tile = p->tile;
+  sh->shifts_per_pass = p->spp;
+  sh->target_blocks = (int32_t)p->target_blocks;
+  sh->ms = 0.0;
+  return QMC_OK;
+}
+
+qmc_status qmc_autotune(qmc_plan_t p, const uint64_t *n, const uint64_t *a, int32_t reps,
+                        int32_t use_cache, void *stream, qmc_launch_shape *best) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (reps < 1 || reps > 100) return fail(QMC_E_INVAL, "reps = %d outside [1, 100]", reps);
+  const std::string key = tune_key(p);
+  if (use_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      qmc_status st = qmc_set_launch_shape(p, &it->second);
+      if (st == QMC_OK && best) *best = it->second;
+      return st;
+    }
+  }
+  qmc_launch_shape keep;
+  qmc_get_launch_shape(p, &keep);
+  hipStream_t hs = (hipStream_t)stream;
+  double *mean = (double *)(p->ws + p->off_mean), *err = (double *)(p->ws + p->off_err);
+  hipEvent_t e0, e1;
+  int e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "create event");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "create event");
+  }
+  qmc_launch_shape top = keep;
+  top.ms = 1e300;
+  qmc_status res = QMC_OK;
+  const int blocks[] = {64, 128, 256};
+  const int spps[] = {1, 2, 4};
+  const int targets[] = {8192, 16384, 32768};
+  for (int bl : blocks)
+    for (int tile = 1; tile <= kMaxTile && res == QMC_OK; tile *= 2)
+      for (int spp : spps)
+        for (int tg : targets) {
+          qmc_launch_shape c{bl, tile, spp, tg, 0.0};
+          if (p->cplx && spp != 1) continue;
+          if (p->precision == QMC_PREC_FP32 && spp == 4) continue;   // FP32 kernels: 1 or 2
+          if (qmc_set_launch_shape(p, &c) != QMC_OK) continue;
+          // warm-up (uploads the lattice table), then the timed repetitions
+          if ((res = integrate_sectors(p, n, a, nullptr, stream, nullptr, mean, err)) != QMC_OK)
+            break;
+          float best_ms = 1e30f;
+          for (int r = 0; r < reps && res == QMC_OK; ++r) {
+            if ((e = hipEventRecord(e0, hs)) != hipSuccess) res = hip_fail(e, "record event");
+            else if ((res = integrate_sectors(p, n, a, nullptr, stream, nullptr, mean, err)) != QMC_OK) {
+            } else if ((e = hipEventRecord(e1, hs)) != hipSuccess) res = hip_fail(e, "record event");
+            else if ((e = hipEventSynchronize(e1)) != hipSuccess) res = hip_fail(e, "synchronize");
+            else {
+              float ms = 0.0f;
+              if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) res = hip_fail(e, "elapsed time");
+              best_ms = std::min(best_ms, ms);
+            }
+          }
+          if (res == QMC_OK && best_ms < top.ms) {
+            top = c;
+            top.ms = best_ms;
+          }
+        }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (res != QMC_OK) {
+    qmc_set_launch_shape(p, &keep);
+    return res;
+  }
+  res = qmc_set_launch_shape(p, &top);
+  if (res != QMC_OK) return res;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = top;
+  }
+  if (best) *best = top;
   return QMC_OK;
 }
 

@@ -667,8 +667,6 @@ __device__ __forceinline__ int find_sector(const int64_t *__restrict__ begin, in
 }
 
 // Maximum shifts per workgroup and waves per workgroup (LDS staging of the partials).
-constexpr int kMaxTile = 16;
-constexpr int kMaxWaves = 4;
 
 // Lattice points a thread sums in plain FP64 before folding the partial into its
 // compensated (TwoSum) accumulator.

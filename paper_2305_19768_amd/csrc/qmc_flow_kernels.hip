@@ -1,0 +1,868 @@
+// qmc_flow_kernels.hip -- learned coupling-flow variable transform on the matrix cores.
+//
+// A flow is a stack of kFlowLayers affine coupling layers in logit space of the unit
+// cube; layer l conditions on the coordinates j with j % 2 == l % 2 and moves the
+// others by z <- z exp(s) + t (density direction x -> u) or z <- (z - t) exp(-s)
+// (sampling direction u -> x), with (s, t) from a d-64-64-2d network with tanh
+// activations and s = 0.25 tanh(o_s).  The sampling direction replaces x = u after the
+// periodizing transform, x = T(u), with weight J_T(u) = 1 / q(x).  Training maximises
+// the weighted log-likelihood of QMC samples of the integrand (weights |W f|), which
+// needs no derivative of the integrand.
+//
+// Matrix-core mapping: the points of a wavefront are the N dimension of every product,
+// in four groups of 16 (bfloat16 16x16x16 and 16x16x32 products, float32 accumulation).
+// A 16x16 result tile leaves lane (p, g) = (lane % 16, lane / 16) holding rows 4g..4g+3
+// of column p; with the weight columns permuted at packing time (flow_perm), those
+// registers are exactly the B operand of the next product, so the network runs from
+// registers.  Only the network input and output pass through LDS, where each lane
+// hands its point's coordinates to the lanes that feed them to the matrix core.
+#include "qmc_device.h"
+#include "qmc_flow.h"
+
+namespace qmc {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf_bits(float f) {
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
+}
+
+// tanh in float32 to a few 1e-7 relative: the odd Taylor series through x^15 for
+// |x| < 0.55 (truncation below 5e-8 relative), else 1 - 2 / (exp(2x) + 1) from the
+// hardware exponential and reciprocal (no cancellation there; saturates at both ends).
+// The results are rounded to bfloat16 before use.
+__device__ __forceinline__ float tanh_f(float x) {
+  const float u = x * x;
+  float p = -929569.0f / 638512875.0f;
+  p = __builtin_fmaf(p, u, 21844.0f / 6081075.0f);
+  p = __builtin_fmaf(p, u, -1382.0f / 155925.0f);
+  p = __builtin_fmaf(p, u, 62.0f / 2835.0f);
+  p = __builtin_fmaf(p, u, -17.0f / 315.0f);
+  p = __builtin_fmaf(p, u, 2.0f / 15.0f);
+  p = __builtin_fmaf(p, u, -1.0f / 3.0f);
+  const float small = __builtin_fmaf(x * u, p, x);
+  const float e = __expf(2.0f * x);
+  const float large = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+  return __builtin_fabsf(x) < 0.55f ? small : large;
+}
+
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma32(v8b a, v8b b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Biases of one layer staged as float: b1 [64], b2 [64], b3 [16] (zero beyond 2d).
+struct FlowBias {
+  float b1[kFlowHidden], b2[kFlowHidden], b3[kFlowOut];
+};
+
+__device__ __forceinline__ void stage_bias(const char *flow, int d, FlowBias *sb, int tid, int nt) {
+  const float *P = (const float *)(flow + flow_off_params(d));
+  for (int e = tid; e < kFlowLayers * (2 * kFlowHidden + kFlowOut); e += nt) {
+    const int l = e / (2 * kFlowHidden + kFlowOut), r = e % (2 * kFlowHidden + kFlowOut);
+    const FlowParamOffsets o = flow_offsets(d, l);
+    float v;
+    if (r < kFlowHidden) v = P[o.b1 + r];
+    else if (r < 2 * kFlowHidden) v = P[o.b2 + r - kFlowHidden];
+    else v = (r - 2 * kFlowHidden) < 2 * d ? P[o.b3 + r - 2 * kFlowHidden] : 0.0f;
+    float *dst = &sb[l].b1[0];
+    dst[r] = v;
+  }
+}
+
+// The network of one layer for the 64 points of a wavefront.  zin: [64][16] bfloat16
+// inputs (point-major, masked); pk: the layer's packed operands.  Returns the outputs
+// o[q] (rows 4g..4g+3 of the 16 output rows, column p of point group q), and with KEEP
+// the hidden activations h1, h2 [q][rb] (rows 16 rb + 4g + i).
+template <bool KEEP>
+__device__ __forceinline__ void flow_mlp(const unsigned short *pk, const FlowBias &bs,
+                                         const unsigned short *zin, int lane, v4f (&o)[4],
+                                         v4f (*h1)[4], v4f (*h2)[4]) {
+  const int p = lane & 15, g = lane >> 4;
+  const v4f zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  v4s B1[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) B1[q] = *(const v4s *)(zin + (16 * q + p) * kFlowIn + 4 * g);
+  v4f C[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const v4s A = *(const v4s *)(pk + kPackF1 + (rb * 64 + lane) * 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) C[q][rb] = mfma16(A, B1[q], zero);
+  }
+  v8b H[4][2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = tanh_f(C[q][rb][i] + bs.b1[16 * rb + 4 * g + i]);
+        if (KEEP) h1[q][rb][i] = v;
+        H[q][rb >> 1][(rb & 1) * 4 + i] = (__bf16)v;
+      }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) C[q][rb] = zero;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const v8b A = *(const v8b *)(pk + kPackF2 + ((rb * 2 + ks) * 64 + lane) * 8);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) C[q][rb] = mfma32(A, H[q][ks], C[q][rb]);
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = tanh_f(C[q][rb][i] + bs.b2[16 * rb + 4 * g + i]);
+        if (KEEP) h2[q][rb][i] = v;
+        H[q][rb >> 1][(rb & 1) * 4 + i] = (__bf16)v;
+      }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) o[q] = zero;
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const v8b A = *(const v8b *)(pk + kPackF3 + (ks * 64 + lane) * 8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q] = mfma32(A, H[q][ks], o[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[q][i] += bs.b3[4 * g + i];
+}
+
+// Per-wave LDS exchange areas: network input (bfloat16) and output (float).
+struct FlowXchg {
+  unsigned short zin[64 * kFlowIn];
+  float out[64 * kFlowOut];
+};
+
+// Per-wave LDS of the backward pass: output gradients (bfloat16, point-major) and two
+// transposed tiles [feature][16 points] for the parameter products.
+struct FlowBack {
+  unsigned short gout[64 * kFlowOut];
+  unsigned short ta[kFlowHidden * 16], tb[kFlowHidden * 16];
+};
+
+__device__ __forceinline__ bool conditioning(int j, int l) { return (j & 1) == (l & 1); }
+
+// One coupling layer applied to the lane's point (z in logit space, d coordinates),
+// all lanes of the workgroup together.  dir 0: sampling (inverse affine), 1: density.
+template <int DMAX>
+__device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBias &bs,
+                                         FlowXchg &xc, int d, int l, int dir, int lane,
+                                         double (&z)[DMAX], double &ssum) {
+#pragma unroll
+  for (int j = 0; j < kFlowIn; ++j) {
+    const bool use = j < d && j < DMAX && conditioning(j, l);
+    xc.zin[lane * kFlowIn + j] = use ? bf_bits((float)z[j < DMAX ? j : 0]) : (unsigned short)0;
+  }
+  __syncthreads();
+  v4f o[4];
+  flow_mlp<false>(pk, bs, xc.zin, lane, o, nullptr, nullptr);
+  const int p = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xc.out[(16 * q + p) * kFlowOut + 4 * g + i] = o[q][i];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < DMAX; ++j) {
+    if (j >= d || conditioning(j, l)) continue;
+    const double s = 0.25 * tanh((double)xc.out[lane * kFlowOut + j]);
+    const double t = (double)xc.out[lane * kFlowOut + d + j];
+    z[j] = dir == 0 ? (z[j] - t) * exp(-s) : __builtin_fma(z[j], exp(s), t);
+    ssum += s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------- packing
+
+__global__ void flow_pack_kernel(char *flow, int d) {
+  const int l = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kPackLayer) return;
+  const float *P = (const float *)(flow + flow_off_params(d));
+  const FlowParamOffsets o = flow_offsets(d, l);
+  float v = 0.0f;
+  if (e < kPackF2) {                      // W1: rows hidden, k = inputs
+    const int rb = e / 256, lane = (e / 4) % 64, el = e % 4;
+    const int row = 16 * rb + lane % 16, k = 4 * (lane / 16) + el;
+    v = k < d ? P[o.W1 + row * d + k] : 0.0f;
+  } else if (e < kPackF3) {               // W2: rows hidden, k = hidden (permuted)
+    const int t = e - kPackF2, rb = t / 1024, ks = (t / 512) % 2, lane = (t / 8) % 64, j = t % 8;
+    const int row = 16 * rb + lane % 16, slot = 8 * (lane / 16) + j;
+    v = P[o.W2 + row * kFlowHidden + flow_perm(ks, slot)];
+  } else if (e < kPackB3) {               // W3: rows outputs, k = hidden (permuted)
+    const int t = e - kPackF3, ks = t / 512, lane = (t / 8) % 64, j = t % 8;
+    const int row = lane % 16, slot = 8 * (lane / 16) + j;
+    v = row < 2 * d ? P[o.W3 + row * kFlowHidden + flow_perm(ks, slot)] : 0.0f;
+  } else if (e < kPackB2) {               // W3^T: rows hidden, k = outputs
+    const int t = e - kPackB3, rb = t / 256, lane = (t / 4) % 64, el = t % 4;
+    const int row = 16 * rb + lane % 16, k = 4 * (lane / 16) + el;
+    v = k < 2 * d ? P[o.W3 + k * kFlowHidden + row] : 0.0f;
+  } else if (e < kPackB1) {               // W2^T: rows hidden in, k = hidden out (permuted)
+    const int t = e - kPackB2, rb = t / 1024, ks = (t / 512) % 2, lane = (t / 8) % 64, j = t % 8;
+    const int row = 16 * rb + lane % 16, slot = 8 * (lane / 16) + j;
+    v = P[o.W2 + flow_perm(ks, slot) * kFlowHidden + row];
+  } else {                                // W1^T: rows inputs, k = hidden (permuted)
+    const int t = e - kPackB1, ks = t / 512, lane = (t / 8) % 64, j = t % 8;
+    const int row = lane % 16, slot = 8 * (lane / 16) + j;
+    v = row < d ? P[o.W1 + flow_perm(ks, slot) * d + row] : 0.0f;
+  }
+  ((unsigned short *)(flow + flow_off_pack(d)))[(int64_t)l * kPackLayer + e] = bf_bits(v);
+}
+
+// ----------------------------------------------------------- transform alone
+
+// dir 0: u -> x = T(u) and log J_T(u); dir 1: x -> u = G(x) and log q(x).  Points with a
+// coordinate outside (0, 1) give NaN outputs.
+__global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, int d,
+                                                             const double *in, int64_t count,
+                                                             double *out, double *logdet,
+                                                             int dir) {
+  __shared__ FlowBias sb[kFlowLayers];
+  __shared__ FlowXchg xc[4];
+  stage_bias(flow, d, sb, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const unsigned short *pk = (const unsigned short *)(flow + flow_off_pack(d));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < count;
+  double z[8], a[8];
+  double lsum = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    a[j] = (valid && j < d) ? in[i * d + j] : 0.5;
+    z[j] = log(a[j]) - log1p(-a[j]);
+    if (j < d) lsum += log(a[j] * (1.0 - a[j]));
+  }
+  double ssum = 0.0;
+  for (int step = 0; step < kFlowLayers; ++step) {
+    const int l = dir == 0 ? kFlowLayers - 1 - step : step;
+    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], xc[wave], d, l, dir, lane, z, ssum);
+  }
+  double rsum = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double r = 1.0 / (1.0 + exp(-z[j]));
+    if (valid && j < d) out[i * d + j] = r;
+    if (j < d) rsum += log(r * (1.0 - r));
+  }
+  if (valid) logdet[i] = dir == 0 ? rsum - lsum - ssum : rsum - lsum + ssum;
+}
+
+// ------------------------------------------------------------------- training
+
+// Loss L = -sum_i w_i log q(x_i) * inv_wsum and its gradient for the points of this
+// launch.  Every wavefront handles 64 points: the density direction forward (layer
+// inputs kept in scratch), then the layers backwards with the network recomputed.
+// Input gradients run through the packed transposed weights; parameter gradients are
+// products over the points (K = 16 points of a group, bfloat16 tiles transposed through
+// LDS).  Each wavefront writes its complete parameter gradient to its own slice of
+// scratch, summed over wavefronts in a fixed order by flow_reduce_kernel.
+struct FlowTrainArgs {
+  char *flow;
+  int d;
+  const double *x, *w;
+  int64_t count;     // points of this batch: sample index offset + i * stride
+  int64_t offset, stride;
+  double inv_wsum;
+  double *zs;        // [L][count][8] layer inputs
+  float *gpart;      // [waves][P] per-wavefront parameter gradients
+  double *lpart;     // [waves] per-wavefront loss
+};
+
+// Sum over the 16 lanes of a lane group (same g, all p).
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Transposed tile of a result held in the 16x16 layout (rows 16 rb + 4g + i, point p).
+__device__ __forceinline__ void put_tile(unsigned short *t, const v4f (&v)[4], int p, int g) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[(16 * rb + 4 * g + i) * 16 + p] = bf_bits(v[rb][i]);
+}
+
+__global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
+  __shared__ FlowBias sb[kFlowLayers];
+  __shared__ FlowXchg xc[4];
+  __shared__ FlowBack bk[4];
+  const int d = a.d;
+  stage_bias(a.flow, d, sb, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const unsigned short *pk = (const unsigned short *)(a.flow + flow_off_pack(d));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, g = lane >> 4;
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in_range = i < a.count;
+  const int64_t gi = a.offset + i * a.stride;   // sample index
+  const int64_t P = flow_params(d);
+  FlowXchg &X = xc[wave];
+  FlowBack &Bk = bk[wave];
+  // a sample on (or rounded beyond) a face of the cube carries no weight
+  double xs[8];
+  bool inside = in_range;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    xs[j] = (in_range && j < d) ? a.x[gi * d + j] : 0.5;
+    if (j < d) inside = inside && xs[j] > 0.0 && xs[j] < 1.0;
+  }
+  const bool valid = inside;
+  const double wi = valid ? a.w[gi] * a.inv_wsum : 0.0;
+
+  // forward, density direction
+  double z[8];
+  double lx = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double xj = valid ? xs[j] : 0.5;
+    z[j] = log(xj) - log1p(-xj);
+    if (j < d) lx += log(xj * (1.0 - xj));
+  }
+  double ssum = 0.0;
+  for (int l = 0; l < kFlowLayers; ++l) {
+    if (valid)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a.zs[((int64_t)l * a.count + i) * 8 + j] = z[j];
+    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], X, d, l, 1, lane, z, ssum);
+  }
+  double dz[8], lu = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double u = 1.0 / (1.0 + exp(-z[j]));
+    if (j < d) lu += log(u * (1.0 - u));
+    dz[j] = j < d ? -wi * (1.0 - 2.0 * u) : 0.0;   // d/dz of -w log(u (1 - u))
+  }
+  double lq = valid ? -wi * (lu - lx + ssum) : 0.0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) lq += __shfl_xor(lq, o, 64);
+  if (lane == 0) a.lpart[gw] = lq;
+
+  float *G = a.gpart + gw * P;
+  const v4f zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int l = kFlowLayers - 1; l >= 0; --l) {
+    const unsigned short *pl = pk + (int64_t)l * kPackLayer;
+    const FlowParamOffsets po = flow_offsets(d, l);
+    double zl[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) zl[j] = valid ? a.zs[((int64_t)l * a.count + i) * 8 + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kFlowIn; ++j) {
+      const bool use = j < d && conditioning(j, l);
+      X.zin[lane * kFlowIn + j] = use ? bf_bits((float)zl[j < 8 ? j : 0]) : (unsigned short)0;
+    }
+    __syncthreads();
+    v4f o[4], h1[4][4], h2[4][4];
+    flow_mlp<true>(pl, sb[l], X.zin, lane, o, h1, h2);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) X.out[(16 * q + p) * kFlowOut + 4 * g + ii] = o[q][ii];
+    __syncthreads();
+    // coupling backward on the lane's own point: gradient of the 2d network outputs
+    float dof[kFlowOut];
+#pragma unroll
+    for (int r = 0; r < kFlowOut; ++r) dof[r] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= d || conditioning(j, l)) continue;
+      const double th = tanh((double)X.out[lane * kFlowOut + j]);
+      const double es = exp(0.25 * th);
+      const double ds = dz[j] * zl[j] * es - wi;       // log q carries + s
+      dof[j] = (float)(ds * 0.25 * (1.0 - th * th));
+      dof[d + j] = (float)dz[j];
+      dz[j] *= es;
+    }
+#pragma unroll
+    for (int r = 0; r < kFlowOut; ++r) Bk.gout[lane * kFlowOut + r] = bf_bits(dof[r]);
+    // bias of the last product: sum over the wavefront's points
+#pragma unroll
+    for (int r = 0; r < kFlowOut; ++r) {
+      float v = dof[r];
+#pragma unroll
+      for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft, 64);
+      if (lane == 0 && r < 2 * d) G[po.b3 + r] = v;
+    }
+    __syncthreads();
+
+    // dh2 = (W3^T do) (1 - h2^2)
+    v4f dh[4][4];
+    {
+      v4s Bo[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Bo[q] = *(const v4s *)(Bk.gout + (16 * q + p) * kFlowOut + 4 * g);
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        const v4s A = *(const v4s *)(pl + kPackB3 + (rb * 64 + lane) * 4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dh[q][rb] = mfma16(A, Bo[q], zero);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) dh[q][rb][ii] *= 1.0f - h2[q][rb][ii] * h2[q][rb][ii];
+    // gW3 = sum_points do h2^T (rows: outputs, columns: hidden), then gb2
+    {
+      v4f acc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = zero;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        put_tile(Bk.ta, h2[q], p, g);
+        if (g == q)
+#pragma unroll
+          for (int r = 0; r < kFlowOut; ++r) Bk.tb[r * 16 + p] = Bk.gout[lane * kFlowOut + r];
+        __syncthreads();
+        const v4s Ao = *(const v4s *)(Bk.tb + p * 16 + 4 * g);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[c] = mfma16(Ao, *(const v4s *)(Bk.ta + (16 * c + p) * 16 + 4 * g), acc[c]);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+          if (4 * g + ii < 2 * d) G[po.W3 + (4 * g + ii) * kFlowHidden + 16 * c + p] = acc[c][ii];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          float v = 0.0f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v += dh[q][rb][ii];
+          v = group_sum(v);
+          if (p == 0) G[po.b2 + 16 * rb + 4 * g + ii] = v;
+        }
+    }
+    // dh1 = (W2^T dh2) (1 - h1^2)
+    v4f dg[4][4];
+    {
+      v8b Hb[4][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) Hb[q][rb >> 1][(rb & 1) * 4 + ii] = (__bf16)dh[q][rb][ii];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) dg[q][rb] = zero;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+          const v8b A = *(const v8b *)(pl + kPackB2 + ((rb * 2 + ks) * 64 + lane) * 8);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dg[q][rb] = mfma32(A, Hb[q][ks], dg[q][rb]);
+        }
+    }
+    // gW2 = sum_points dh2 h1^T (rows: hidden out, columns: hidden in)
+    {
+      v4f acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = zero;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        put_tile(Bk.ta, h1[q], p, g);
+        put_tile(Bk.tb, dh[q], p, g);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const v4s Bh = *(const v4s *)(Bk.ta + (16 * c + p) * 16 + 4 * g);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[r][c] = mfma16(*(const v4s *)(Bk.tb + (16 * r + p) * 16 + 4 * g), Bh, acc[r][c]);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii)
+            G[po.W2 + (16 * r + 4 * g + ii) * kFlowHidden + 16 * c + p] = acc[r][c][ii];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) dg[q][rb][ii] *= 1.0f - h1[q][rb][ii] * h1[q][rb][ii];
+    // gb1, gW1 = sum_points dh1 v^T (columns: network inputs), dv = W1^T dh1
+    {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          float v = 0.0f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v += dg[q][rb][ii];
+          v = group_sum(v);
+          if (p == 0) G[po.b1 + 16 * rb + 4 * g + ii] = v;
+        }
+      v4f acc[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = zero;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        put_tile(Bk.ta, dg[q], p, g);
+        if (g == q)
+#pragma unroll
+          for (int r = 0; r < kFlowIn; ++r) Bk.tb[r * 16 + p] = X.zin[lane * kFlowIn + r];
+        __syncthreads();
+        const v4s Bv = *(const v4s *)(Bk.tb + p * 16 + 4 * g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[r] = mfma16(*(const v4s *)(Bk.ta + (16 * r + p) * 16 + 4 * g), Bv, acc[r]);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+          if (p < d) G[po.W1 + (16 * r + 4 * g + ii) * d + p] = acc[r][ii];
+      v8b Hb[4][2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) Hb[q][rb >> 1][(rb & 1) * 4 + ii] = (__bf16)dg[q][rb][ii];
+      v4f dv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dv[q] = zero;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const v8b A = *(const v8b *)(pl + kPackB1 + (ks * 64 + lane) * 8);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dv[q] = mfma32(A, Hb[q][ks], dv[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) X.out[(16 * q + p) * kFlowOut + 4 * g + ii] = dv[q][ii];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j < d && conditioning(j, l)) dz[j] += (double)X.out[lane * kFlowOut + j];
+      __syncthreads();
+    }
+  }
+}
+
+// grad[k] = sum over wavefronts of gpart[w][k] (fixed order); loss likewise.
+__global__ void flow_reduce_kernel(char *flow, int d, const float *gpart, const double *lpart,
+                                   int64_t waves, double *loss) {
+  const int64_t P = flow_params(d);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float *grad = (float *)(flow + flow_off_grad(d));
+  if (k < P) {
+    double s = 0.0;
+    for (int64_t w = 0; w < waves; ++w) s += (double)gpart[w * P + k];
+    grad[k] = (float)s;
+  }
+  if (k == 0 && loss) {
+    double s = 0.0;
+    for (int64_t w = 0; w < waves; ++w) s += lpart[w];
+    *loss = s;
+  }
+}
+
+// Adam (Kingma and Ba 2015) on the float32 master parameters; c1, c2 are the bias
+// corrections 1 - beta^t of this step.
+__global__ void flow_adam_kernel(char *flow, int d, float lr, float b1, float b2, float eps,
+                                 float c1, float c2) {
+  const int64_t P = flow_params(d);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  float *prm = (float *)(flow + flow_off_params(d));
+  float *m = (float *)(flow + flow_off_m(d));
+  float *v = (float *)(flow + flow_off_v(d));
+  const float gk = ((const float *)(flow + flow_off_grad(d)))[k];
+  const float mk = b1 * m[k] + (1.0f - b1) * gk;
+  const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  prm[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+__global__ void flow_clear_kernel(float *p, int64_t count) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count) p[k] = 0.0f;
+}
+
+// ------------------------------------------------------- integration with a flow
+
+// LDS of one workgroup of the flow-transformed integration: the forward operands of all
+// layers (F1, F2, F3: the first kPackF3 + 1024 elements of each layer's pack), biases
+// and the per-wave exchange areas.
+constexpr int kPackFwd = kPackB3;   // forward part of a layer's pack
+struct FlowIntegrateLds {
+  unsigned short pack[kFlowLayers][kPackFwd];
+  FlowBias bias[kFlowLayers];
+  FlowXchg xc[4];
+};
+
+// A workgroup's share of a sector with an attached flow: per sample y, u = phi(y) with
+// weight W (the sector's periodizing transform), x = T(u) and J_T(u) by the flow, then
+// the integrand at x; W J_T f accumulated as on the real contour.  A sample with a
+// coordinate of u or x outside (0, 1) contributes 0.
+template <int D>
+__device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_begin, int tile,
+                                           int64_t chunk_id, double (*red)[kMaxTile * 4][2],
+                                           FlowIntegrateLds &L) {
+  const SectorDev *__restrict__ sd = a.sectors + s;
+  const LatticeDev *__restrict__ lt = a.lat + s;
+  const uint64_t n = lt->n;
+  const double n_d = lt->n_d, inv_n = lt->inv_n;
+  const int64_t chunk = lt->chunk;
+  const uint64_t i_begin = (uint64_t)(chunk_id * chunk);
+  uint64_t i_end = i_begin + (uint64_t)chunk;
+  if (i_end > n) i_end = n;
+  const int kind = sd->transform;
+  const double w_scale = sd->w_scale;
+  const SectorScalars ss = load_scalars(sd);
+  const int K = a.K;
+  const uint64_t B = blockDim.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
+  double k0[D];
+  const uint64_t i0 = i_begin + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < D; ++j) k0[j] = (double)mulmod(i0 % n, lt->z[j], n);
+
+#pragma unroll 1
+  for (int l0 = 0; l0 < tile; ++l0) {
+    DD acc[QMC_MAX_ORDERS];
+#pragma unroll
+    for (int c = 0; c < QMC_MAX_ORDERS; ++c) acc[c] = DD{0.0, 0.0};
+    const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
+    double k[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) k[j] = k0[j];
+    uint64_t i = i0;
+#pragma unroll 1
+    for (int64_t it = 0; it < n_iter; ++it, i += B) {
+      const cptr<double> cl = launder_uniform(a.coef);
+      const cptr<LatticeDev> ltl = launder_uniform(lt);
+      const cptr<double> shl = launder_uniform(sh);
+      double y[D], u[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double q = quotient(k[j], n_d, inv_n);
+        k[j] = lattice_step(k[j], ltl->ndz[j], n_d);
+        y[j] = shifted(q, shl[j]);
+      }
+      const double Wk = apply_transform<D>(kind, w_scale, y, u);
+      bool inside = true;
+      double z[D], lsum = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        inside = inside && u[j] > 0.0 && u[j] < 1.0;
+        const double uj = (u[j] > 0.0 && u[j] < 1.0) ? u[j] : 0.5;
+        z[j] = log(uj) - log1p(-uj);
+        lsum += log(uj * (1.0 - uj));
+      }
+      double ssum = 0.0;
+      for (int step = 0; step < kFlowLayers; ++step) {
+        const int l = kFlowLayers - 1 - step;
+        coupling<D>(L.pack[l], L.bias[l], L.xc[wave], D, l, 0, lane, z, ssum);
+      }
+      double x[1][D], rsum = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double r = 1.0 / (1.0 + exp(-z[j]));
+        inside = inside && r > 0.0 && r < 1.0;
+        x[0][j] = (r > 0.0 && r < 1.0) ? r : 0.5;
+        rsum += log(x[0][j] * (1.0 - x[0][j]));
+      }
+      const double W = Wk * exp(rsum - lsum - ssum);
+      double f[1][QMC_MAX_ORDERS];
+      integrand<D, QMC_MAX_ORDERS, 1>(ss, (cptr<SectorDev>)sd, launder_after(cl, W), x, f);
+      const bool use = (i < i_end) && inside && (W != 0.0);
+#pragma unroll
+      for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) dd_add(acc[kk], use ? W * f[0][kk] : 0.0);
+    }
+#pragma unroll
+    for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) {
+      if (kk >= K) break;
+      const DD r = wave_reduce(acc[kk]);
+      if (lane == 0) {
+        red[wave][l0 * K + kk][0] = r.s;
+        red[wave][l0 * K + kk][1] = r.c;
+      }
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
+  __shared__ double red[kMaxWaves][kMaxTile * 4][2];
+  __shared__ FlowIntegrateLds L;
+  const int64_t b = block_base + blockIdx.x;
+  const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
+  const LatticeDev *__restrict__ lt = a.lat + s;
+  const char *flow = (const char *)a.sectors[s].flow;
+  {   // stage the flow's forward operands and biases
+    const int d = a.sectors[s].d;
+    const uint4 *src = (const uint4 *)(flow + flow_off_pack(d));
+    for (int l = 0; l < kFlowLayers; ++l) {
+      const uint4 *sl = src + (int64_t)l * kPackLayer / 8;
+      uint4 *dl = (uint4 *)L.pack[l];
+      for (int e = threadIdx.x; e < kPackFwd / 8; e += blockDim.x) dl[e] = sl[e];
+    }
+    stage_bias(flow, d, L.bias, threadIdx.x, blockDim.x);
+  }
+  __syncthreads();
+  const int64_t local = b - lt->block_begin;
+  const int nch = lt->n_chunks;
+  const int tile_id = (int)(local / nch);
+  const int64_t chunk_id = local - (int64_t)tile_id * nch;
+  const int T = a.shift_tile;
+  flow_block<D>(a, s, tile_id * T, T, chunk_id, red, L);
+  __syncthreads();
+  const int nwaves = blockDim.x >> 6;
+  const int cols = T * a.K;
+  if ((int)threadIdx.x < cols) {
+    DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
+    for (int w = 1; w < nwaves; ++w) r = dd_combine(r, DD{red[w][threadIdx.x][0], red[w][threadIdx.x][1]});
+    double *out = a.partial + (b * cols + threadIdx.x) * 2;
+    out[0] = r.s;
+    out[1] = r.c;
+  }
+}
+
+// Training samples of one sector: x_i = phi(y_i) for the points of lattice (n, z) with
+// one shift, and weights w_i = W(y_i) ||f(x_i)||_2 over the orders (0 where W = 0).
+template <int D>
+__global__ __launch_bounds__(256) void qmc_flow_samples_kernel(FlowSampleArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const SectorScalars ss = load_scalars(a.sd);
+  double y[D], x[1][D];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    y[j] = shifted(quotient((double)mulmod(i, a.z[j], a.n), a.n_d, a.inv_n), a.shift[j]);
+  const double W = apply_transform<D>(a.sd->transform, a.sd->w_scale, y, x[0]);
+  double f[1][QMC_MAX_ORDERS];
+  integrand<D, QMC_MAX_ORDERS, 1>(ss, (cptr<SectorDev>)a.sd, launder_after(launder_uniform(a.coef), W), x, f);
+  double nrm = 0.0;
+#pragma unroll
+  for (int k = 0; k < QMC_MAX_ORDERS; ++k)
+    if (k < a.K) nrm = __builtin_fma(f[0][k], f[0][k], nrm);
+  const double wi = W != 0.0 ? W * sqrt(nrm) : 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) a.x[i * D + j] = x[0][j];
+  a.w[i] = isfinite(wi) ? wi : 0.0;
+}
+
+int launch_flow_integrate(const LaunchArgs &a, const DimLaunch &dl, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
+  switch (dl.d) {
+    case 1: hipLaunchKernelGGL(qmc_flow_integrate_kernel<1>, grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL(qmc_flow_integrate_kernel<2>, grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL(qmc_flow_integrate_kernel<3>, grid, blk, 0, st, a, dl.base); break;
+    case 4: hipLaunchKernelGGL(qmc_flow_integrate_kernel<4>, grid, blk, 0, st, a, dl.base); break;
+    case 5: hipLaunchKernelGGL(qmc_flow_integrate_kernel<5>, grid, blk, 0, st, a, dl.base); break;
+    case 6: hipLaunchKernelGGL(qmc_flow_integrate_kernel<6>, grid, blk, 0, st, a, dl.base); break;
+    case 7: hipLaunchKernelGGL(qmc_flow_integrate_kernel<7>, grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL(qmc_flow_integrate_kernel<8>, grid, blk, 0, st, a, dl.base); break;
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_flow_samples(const FlowSampleArgs &fa, int d, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  dim3 grid((unsigned)((fa.n + 255) / 256)), blk(256);
+  switch (d) {
+    case 1: hipLaunchKernelGGL(qmc_flow_samples_kernel<1>, grid, blk, 0, st, fa); break;
+    case 2: hipLaunchKernelGGL(qmc_flow_samples_kernel<2>, grid, blk, 0, st, fa); break;
+    case 3: hipLaunchKernelGGL(qmc_flow_samples_kernel<3>, grid, blk, 0, st, fa); break;
+    case 4: hipLaunchKernelGGL(qmc_flow_samples_kernel<4>, grid, blk, 0, st, fa); break;
+    case 5: hipLaunchKernelGGL(qmc_flow_samples_kernel<5>, grid, blk, 0, st, fa); break;
+    case 6: hipLaunchKernelGGL(qmc_flow_samples_kernel<6>, grid, blk, 0, st, fa); break;
+    case 7: hipLaunchKernelGGL(qmc_flow_samples_kernel<7>, grid, blk, 0, st, fa); break;
+    default: hipLaunchKernelGGL(qmc_flow_samples_kernel<8>, grid, blk, 0, st, fa); break;
+  }
+  return (int)hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launchers
+
+int launch_flow_pack(void *flow, int d, void *stream) {
+  hipLaunchKernelGGL(flow_pack_kernel, dim3((kPackLayer + 255) / 256, kFlowLayers), dim3(256), 0,
+                     (hipStream_t)stream, (char *)flow, d);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_transform(const void *flow, int d, const double *u, int64_t count, double *x,
+                          double *logJ, int dir, void *stream) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(flow_transform_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, (const char *)flow, d, u, count, x, logJ, dir);
+  return (int)hipGetLastError();
+}
+
+int flow_grad_waves(int64_t count) { return (int)((count + 255) / 256) * 4; }
+
+int launch_flow_grad(void *flow, int d, const double *x, const double *w, int64_t count,
+                     int64_t offset, int64_t stride, double inv_wsum, double *zs, float *gpart,
+                     double *lpart, double *loss, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  FlowTrainArgs a{(char *)flow, d, x, w, count, offset, stride, inv_wsum, zs, gpart, lpart};
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(flow_grad_kernel, dim3(blocks), dim3(256), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  const int64_t P = flow_params(d);
+  hipLaunchKernelGGL(flow_reduce_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st,
+                     (char *)flow, d, (const float *)gpart, (const double *)lpart,
+                     (int64_t)blocks * 4, loss);
+  return (int)hipGetLastError();
+}
+
+int launch_flow_adam(void *flow, int d, float lr, float b1, float b2, float eps, float c1,
+                     float c2, void *stream) {
+  const int64_t P = flow_params(d);
+  hipLaunchKernelGGL(flow_adam_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, (char *)flow, d, lr, b1, b2, eps, c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  return launch_flow_pack(flow, d, stream);
+}
+
+int launch_flow_clear(float *p, int64_t count, void *stream) {
+  if (count <= 0) return 0;
+  hipLaunchKernelGGL(flow_clear_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, p, count);
+  return (int)hipGetLastError();
+}
+
+}  // namespace qmc

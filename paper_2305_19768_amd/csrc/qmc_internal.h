@@ -14,6 +14,9 @@ namespace qmc {
 // stored as c0, then for each j: c_j, then for each k >= j: c_jk followed by the
 // c_jkl for l = k .. D-1.  Length C(D+3, 3).
 constexpr int dense_len(int D) { return (D + 1) * (D + 2) * (D + 3) / 6; }
+
+constexpr int kMaxTile = 16;    // shifts per workgroup
+constexpr int kMaxWaves = 4;    // wavefronts per workgroup
 // The same layout truncated to total degree 2 (c0, then per j: c_j and the c_jk, k >= j;
 // length C(D+2, 2)) and to degree 1 (c0, c_0 .. c_{D-1}; length D + 1): the gradient
 // and Hessian tables of F in complex plans.
@@ -49,7 +52,7 @@ struct alignas(16) SectorDev {
   int32_t grad_off, hess_off;      // complex plans: D tables dF/dx_j (degree-2 layout), then
                                    // D(D+1)/2 tables d2F/dx_j dx_k, k >= j (degree-1 layout)
   double lambda;                   // complex plans: contour deformation parameter (>= 0)
-  double pad3;
+  uint64_t flow;                   // device address of an attached flow transform, or 0
 };
 
 // Per-call lattice record of a sector.
@@ -75,6 +78,7 @@ struct alignas(16) LatticeDev {
 struct DimLaunch {
   int64_t base, blocks;
   int32_t d, fast, f32, deform;   // deform: complex plan (every sector on the deformed path)
+  int32_t flow, pad;              // flow: sectors with an attached learned transform
 };
 
 struct LaunchArgs {
@@ -97,7 +101,7 @@ struct LaunchArgs {
   int32_t n_dim_launches;
   int32_t cplx;                    // complex plan: K counts (re, im) columns, K = 2 n_orders
   unsigned long long *sign_count;  // complex plans: [S] sign-check violations
-  DimLaunch dims[3 * QMC_MAX_DIM];
+  DimLaunch dims[4 * QMC_MAX_DIM];
 };
 
 struct PointsArgs {
@@ -154,6 +158,8 @@ int launch_integrate(const LaunchArgs &a, void *stream);
 // complex plans: the deformed-contour integrand kernel for one dimension class, and
 // the clearing of the per-sector sign-check counters
 int launch_deform(const LaunchArgs &a, const DimLaunch &dl, void *stream);
+// sectors with an attached flow transform: x = T(periodizing transform(y))
+int launch_flow_integrate(const LaunchArgs &a, const DimLaunch &dl, void *stream);
 int launch_clear_u64(unsigned long long *p, int64_t count, void *stream);
 int launch_status_reset(int32_t *status, void *stream);
 int launch_reduce_stats(const LaunchArgs &a, void *stream);

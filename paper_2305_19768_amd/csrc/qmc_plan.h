@@ -18,7 +18,8 @@ uint64_t gcd_u64(uint64_t a, uint64_t b);
 uint64_t splitmix64(uint64_t seed, uint64_t counter);
 size_t align256(size_t v);
 
-constexpr int64_t kTargetBlocks = 16384;   // workgroups per launch the chunking aims at
+constexpr int64_t kTargetBlocks = 16384;   // default workgroups per launch the chunking aims at
+constexpr int64_t kTargetBlocksMax = 32768;   // largest target a launch shape may choose
 constexpr int32_t kP2MaxCand = 65536;
 constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
 
@@ -46,6 +47,8 @@ struct qmc_plan_s {
          off_status = 0, off_partial = 0, off_order = 0, off_mean = 0, off_err = 0, off_coef32 = 0, off_amp = 0, amp_bytes = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
          off_sign = 0, total = 0;
   int64_t max_blocks = 0;
+  int64_t target_blocks = 16384;      // workgroups per launch the chunking aims at
+  size_t partial_doubles = 0;         // capacity of the workgroup partial buffer
   char *ws = nullptr;
   size_t ws_bytes = 0;
   // per-call staging

@@ -142,3 +142,22 @@ def test_complex_plan_validation_and_shape(L):
     assert _plan(prob, shifts_per_pass=2)[0] == -1 and "one shift per pass" in _err()
     assert _plan(prob, shift_tile=16)[0] == -1 and "launch shape" in _err()
     assert _plan(prob, shift_tile=8)[0] == 0
+
+
+def test_launch_shape_validation(L):
+    prob = W.two_loop_integral(n_sectors=2, n_scale=0.01, m=16)
+    rc, h, _ = _plan(prob)
+    assert rc == 0
+    S = _abi.LaunchShape
+    assert L.qmc_set_launch_shape(h, ctypes.byref(S(96, 8, 2, 16384, 0))) == -1
+    assert L.qmc_set_launch_shape(h, ctypes.byref(S(256, 3, 1, 16384, 0))) == -1
+    assert L.qmc_set_launch_shape(h, ctypes.byref(S(256, 8, 3, 16384, 0))) == -1
+    assert L.qmc_set_launch_shape(h, ctypes.byref(S(256, 8, 2, 100, 0))) == -1
+    assert L.qmc_set_launch_shape(h, ctypes.byref(S(256, 8, 2, 40000, 0))) == -1
+    assert L.qmc_set_launch_shape(h, ctypes.byref(S(128, 4, 4, 8192, 0))) == 0
+    got = S()
+    assert L.qmc_get_launch_shape(h, ctypes.byref(got)) == 0
+    assert (got.block, got.shift_tile, got.shifts_per_pass, got.target_blocks) == (128, 4, 4, 8192)
+    # timing needs a bound workspace: refused before any device call
+    assert L.qmc_autotune(h, None, None, 1, 0, None, None) == -7
+    L.qmc_plan_free(h)
