@@ -204,6 +204,63 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
             "sectors_violating_at_full_n": int(np.count_nonzero(viol))}
 
 
+def flow_leg(qmc, torch, batches: int = 64, epochs: int = 3):
+    """Learned transform against korobov3 on the d = 6 sectors of the two-loop integral:
+    per sector a flow trained on 1e6 QMC samples (one shift, n = nextprime(1e6)), then the
+    shift variance at each sector's own n with and without the flow (32 shifts), the
+    training wall time, the flow-integrated throughput and its matrix-core rate."""
+    import numpy as np
+    import workloads
+    full = workloads.two_loop_integral(seed=0)
+    idx = [s for s, sec in enumerate(full.sectors) if sec.d == 6]
+    prob = workloads.Problem(sectors=[full.sectors[s] for s in idx], order_lo=full.order_lo,
+                             m=full.m, shifts=[full.shifts[s] for s in idx])
+    n_train = workloads.next_prime(1000000)
+    plan = qmc.Plan(prob, n_max=max(n_train, max(s.n for s in prob.sectors)))
+    _, m0, e0 = plan.integrate()
+    plan.enable_timing(True)
+    plan.integrate()
+    k_plain, _ = plan.read_timing()
+    plan.enable_timing(False)
+    cands = np.arange(2, 2 + 64, dtype=np.uint64) * 15485863 % np.uint64(n_train)
+    a_train, _ = plan.korobov_search(n_train, 6, [int(c) for c in cands if c > 1])
+    flows = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(len(idx)):
+        x, w = plan.flow_samples(s, n_train, a_train, shift=0)
+        fl = qmc.flow.Flow(6, seed=s)
+        fl.train(x, w, batches=batches, epochs=epochs, lr=2e-3)
+        flows.append(fl)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    for s, fl in enumerate(flows):
+        plan.attach_flow(s, fl)
+    _, m1, e1 = plan.integrate()
+    plan.enable_timing(True)
+    plan.integrate()
+    k_flow, _ = plan.read_timing()
+    plan.enable_timing(False)
+    v0 = (e0.cpu().numpy() ** 2).sum(axis=1)
+    v1 = (e1.cpu().numpy() ** 2).sum(axis=1)
+    ratio = v0 / v1                      # > 1: the flow lowers the shift variance
+    evals = prob.evals()
+    cost = k_flow / k_plain
+    flops_eval = 4 * 2 * (6 * 64 + 64 * 64 + 64 * 12)
+    return {"workload": f"{len(idx)} d=6 sectors of two_loop_integral, flows trained on "
+                        f"{n_train} samples each ({batches} batches x {epochs} epochs)",
+            "variance_ratio_plain_over_flow": {"median": float(np.median(ratio)),
+                                               "min": float(ratio.min()),
+                                               "max": float(ratio.max())},
+            "sectors_flow_wins": int(np.count_nonzero(ratio > 1.0)),
+            "cost_ratio_flow_over_plain": float(cost),
+            "cost_adjusted_ratio_median": float(np.median(ratio / cost)),
+            "training_wall_s": train_s,
+            "flow_evals_per_s": evals / (k_flow / 1e3), "plain_evals_per_s": evals / (k_plain / 1e3),
+            "flow_network_tflops": evals * flops_eval / (k_flow / 1e3) / 1e12,
+            "flow_network_frac_of_bf16_peak": evals * flops_eval / (k_flow / 1e3) / 2.5e15}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +273,7 @@ def main():
     ap.add_argument("--spp", type=int, default=0, help="shifts per pass (0 = default)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-integrand measurement")
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
+    ap.add_argument("--no-flow", action="store_true", help="skip the learned-transform leg")
     ap.add_argument("--scan-points", type=int, default=10,
                     help="kinematic points of the deformed-contour scan leg (0 = skip)")
     ap.add_argument("--amp-repeats", type=int, default=3)
@@ -315,6 +373,8 @@ def main():
     }
     if not args.no_amp:
         result["amplitude_time_to_1e-4"] = amplitude_leg(qmc, torch, args.amp_repeats)
+    if not args.no_flow:
+        result["learned_transform"] = flow_leg(qmc, torch)
     if args.scan_points > 0:
         result["physical_scan"] = scan_leg(qmc, torch, args.scan_points, max(1, args.steps // 4))
     if not args.no_cpu:
