@@ -271,7 +271,12 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0 = library default)")
     ap.add_argument("--tile", type=int, default=0, help="shifts per workgroup (0 = default)")
     ap.add_argument("--spp", type=int, default=0, help="shifts per pass (0 = default)")
+    ap.add_argument("--target", type=int, default=0,
+                    help="workgroups a launch aims at (0 = default); with --block/--tile/--spp "
+                         "it fixes the launch shape and skips the autotuner")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-integrand measurement")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shape (no autotuner search)")
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
     ap.add_argument("--no-flow", action="store_true", help="skip the learned-transform leg")
     ap.add_argument("--scan-points", type=int, default=10,
@@ -295,8 +300,18 @@ def main():
     prob = workloads.two_loop_integral(seed=0)
     t0 = time.perf_counter()
     plan = qmc.Plan(prob, block=args.block, shift_tile=args.tile, shifts_per_pass=args.spp)
+    explicit = bool(args.block or args.tile or args.spp or args.target)
+    if explicit:
+        plan.set_launch_shape(args.block or 256, args.tile or 16, args.spp or 2,
+                              args.target or 16384)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
+    tune = None
+    if not (args.no_tune or explicit):
+        t0 = time.perf_counter()
+        tune = plan.autotune(reps=2)        # launch-shape search, outside the timed region
+        tune["seconds"] = time.perf_counter() - t0
+        print(f"# autotuned launch shape {tune}", file=sys.stderr, flush=True)
     S, m, K = plan.S, plan.m, plan.K
     out = (torch.empty((S, m, K), dtype=torch.float64, device="cuda"),
            torch.empty((S, K), dtype=torch.float64, device="cuda"),
@@ -322,6 +337,12 @@ def main():
     if not args.no_fp32:
         plan32 = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32, block=args.block,
                           shift_tile=args.tile, shifts_per_pass=args.spp)
+        tune32 = None
+        if explicit:
+            plan32.set_launch_shape(args.block or 256, args.tile or 16, min(args.spp or 2, 2),
+                                    args.target or 16384)
+        elif tune is not None:
+            tune32 = plan32.autotune(reps=2)
         for _ in range(args.warmup):
             plan32.integrate(out=out, check=False)
         torch.cuda.synchronize()
@@ -333,7 +354,8 @@ def main():
         plan32.check_status()
         fp32 = {"value": prob.evals() * args.steps / e32, "unit": "evals/s",
                 "ms_per_step": e32 / args.steps * 1e3,
-                "note": "FP32 integrand, FP64 lattice points and accumulation"}
+                "note": "FP32 integrand, FP64 lattice points and accumulation",
+                "launch": tune32}
         del plan32
 
     if args.copy_probe:
@@ -368,8 +390,8 @@ def main():
                      "flops_per_eval": flops_launch / evals},
         "fp32": fp32,
         "plan_seconds": plan_s,
-        "launch": {"block": args.block or 256, "shift_tile": args.tile or 16,
-                   "shifts_per_pass": args.spp or 0},
+        "launch": plan.launch_shape(),
+        "autotune": tune,
     }
     if not args.no_amp:
         result["amplitude_time_to_1e-4"] = amplitude_leg(qmc, torch, args.amp_repeats)
