@@ -305,6 +305,22 @@ def choose_lambda(sec, shifts, lam0: float, n: int, a: int, max_halvings: int = 
     raise OracleSignCheck(f"no valid deformation parameter down to {lam * 2:g}")
 
 
+def median_rule(sec, n: int, candidates, order: int = -1):
+    """Median QMC rule (Sec. 2.2, Eq. median): the unshifted rank-1 lattice estimates
+    Q_{n,z_c} of candidates z_c [r, d] (components in U_n), and the candidate whose
+    estimate of epsilon order `order` is the median (r odd: the middle one; r even: the
+    lower middle; equal estimates ordered by candidate index).
+    Returns (chosen index, Q [r, K])."""
+    cands = np.ascontiguousarray(candidates, dtype=np.uint64).reshape(-1, sec.d)
+    zero = np.zeros((1, sec.d))
+    Q = np.empty((cands.shape[0], sec.K))
+    for c, z in enumerate(cands):
+        Q[c] = sector_sums(sec, zero, n=n, z=z)[0][0]
+    key = Q[:, order]
+    idx = sorted(range(len(key)), key=lambda c: (key[c], c))
+    return idx[(len(idx) - 1) // 2], Q
+
+
 def problem_sums(problem, threads: int = 1, sectors=None):
     """Q[s] (m x K) and S[s] for every sector of a workloads.Problem."""
     idx = range(len(problem.sectors)) if sectors is None else sectors

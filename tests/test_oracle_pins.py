@@ -399,3 +399,27 @@ def test_splitmix64_reference_values():
     assert oracle.splitmix64(0, 0) == 0xE220A8397B1DCDAF
     assert oracle.splitmix64(0, 1) == 0x6E789E6AA1B965F4
     assert oracle.splitmix64(0, 2) == 0x06C45D188009454F
+
+
+def test_median_rule_picks_the_middle_estimate():
+    # Sec. 2.2, Eq. median: the median of r unshifted lattice estimates, each the plain
+    # rank-1 rule with its candidate vector; r = 1 is the candidate itself
+    sec = W.custom_sector(2, [(1.0, (0, 0))], [(1.0, (0, 0)), (1.0, (1, 1))], f_pow2=-2,
+                          logc=[[1.0]], transform="korobov3", n=1009)
+    exact = math.pi ** 2 / 12
+    rng = np.random.default_rng(0)
+    cands = W.median_candidates(rng, 1009, 2, 15)
+    assert np.all(np.gcd(cands.astype(np.int64), 1009) == 1) and cands.min() >= 1
+    c, Q = oracle.median_rule(sec, 1009, cands)
+    vals = Q[:, 0]
+    assert vals[c] == np.sort(vals)[7]                     # the middle of 15
+    assert np.all(np.abs(vals - exact) < 1e-2)             # every candidate is a lattice rule
+    # each candidate's estimate is the unshifted lattice rule with that vector
+    z = cands[3]
+    direct = oracle.sector_sums(sec, np.zeros((1, 2)), n=1009, z=z)[0][0, 0]
+    assert Q[3, 0] == direct
+    c1, Q1 = oracle.median_rule(sec, 1009, cands[:1])
+    assert c1 == 0 and Q1[0, 0] == Q[0, 0]
+    # even r: the lower middle
+    c4, Q4 = oracle.median_rule(sec, 1009, cands[:4])
+    assert Q4[c4, 0] == np.sort(Q4[:, 0])[1]

@@ -349,6 +349,20 @@ def single_problem(sector: Sector, m: int = 8, seed: int = 0, order_lo: int = 0)
                    shifts=[uniform_shifts(rng, m, sector.d)], seed=seed)
 
 
+def median_candidates(rng, n: int, d: int, r: int) -> np.ndarray:
+    """r random generating vectors [r, d] with every component uniform in
+    U_n = {1 <= z <= n - 1 : gcd(z, n) = 1} (rejection sampling)."""
+    out = np.empty((r, d), dtype=np.uint64)
+    for c in range(r):
+        for j in range(d):
+            while True:
+                z = int(rng.integers(1, n))
+                if math.gcd(z, n) == 1:
+                    out[c, j] = z
+                    break
+    return out
+
+
 def lattice_ladder(n_min: int = 10007, n_max: int = 2 ** 31 - 1, ratio: float = 1.5,
                    n_cand: int = 8, seed: int = 0):
     """Table of available lattice sizes (primes near n_min * ratio^l, up to n_max) with
