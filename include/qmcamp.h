@@ -190,6 +190,33 @@ qmc_status qmc_integrate(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, 
                          double *dev_q, double *dev_mean, double *dev_err);
 
 /*
+ * qmc_integrate_vec -- qmc_integrate with general generating vectors instead of Korobov
+ * parameters: z [n_sectors][QMC_MAX_DIM] host array, z[s][j] in [1, n_s) with
+ * gcd(z[s][j], n_s) = 1 for j < d_s (entries beyond d_s ignored).  Otherwise identical.
+ */
+qmc_status qmc_integrate_vec(qmc_plan_t plan, const uint64_t *n, const uint64_t *z, void *stream,
+                             double *dev_q, double *dev_mean, double *dev_err);
+
+/*
+ * Median QMC rule (Sec. 2.2, Eq. median): for every sector, the unshifted rank-1
+ * estimates Q_{n,z_c} of r candidate generating vectors with components in
+ * U_n = {1 <= z <= n-1 : gcd(z, n) = 1}, and the candidate whose estimate of epsilon
+ * order `order` (negative: counted from the last) is the median (r odd: the middle; r
+ * even: the lower middle; equal estimates keep candidate order).  The chosen vector is
+ * then used with the m random shifts (qmc_integrate_vec).
+ *   n: [n_sectors] lattice sizes or NULL (defaults); candidates: host
+ *   [n_sectors][r][QMC_MAX_DIM] (the random draws are the caller's); dev_scratch: device
+ *   buffer of qmc_median_workspace_bytes(plan, r) bytes, 256-byte aligned.
+ * Outputs (host): z_out [n_sectors][QMC_MAX_DIM] chosen vectors; q_out [n_sectors][r]
+ * (may be NULL) the candidates' estimates of the deciding order.  All candidates of all
+ * sectors are integrated in one launch.  Synchronous.  Real plans only.
+ */
+size_t qmc_median_workspace_bytes(qmc_plan_t plan, int32_t r);
+qmc_status qmc_median_lattice(qmc_plan_t plan, const uint64_t *n, int32_t r,
+                              const uint64_t *candidates, int32_t order, void *dev_scratch,
+                              size_t scratch_bytes, void *stream, uint64_t *z_out, double *q_out);
+
+/*
  * qmc_query_status -- synchronize `stream` and report the device status word of the
  * last qmc_integrate: QMC_OK, or QMC_E_NONFINITE with *sector, *shift, *order set to
  * the first non-finite sum in (sector, shift, order) order; else, in a complex plan,

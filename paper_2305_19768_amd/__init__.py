@@ -99,7 +99,7 @@ class Plan:
         self._shift_host = arr   # keep alive until the copy is issued
 
     def integrate(self, n: Optional[Sequence[int]] = None, a: Optional[Sequence[int]] = None,
-                  out=None, stream=None, check: bool = True):
+                  out=None, stream=None, check: bool = True, z=None):
         """Runs the lattice rule on every sector.  Returns (q [S, m, K], mean [S, K],
         err [S, K]) as float64 device tensors; a complex plan appends a (re, im) axis of
         length 2 to each.  With check=True the stream is synchronised and a non-finite sum
@@ -118,10 +118,20 @@ class Plan:
         u64p = ctypes.POINTER(ctypes.c_uint64)
         dp = ctypes.c_void_p
         st = _stream_ptr(stream)
-        _check(lib().qmc_integrate(self._h, None if n_arr is None else n_arr.ctypes.data_as(u64p),
-                                   None if a_arr is None else a_arr.ctypes.data_as(u64p), st,
-                                   dp(q.data_ptr()) if q is not None else None,
-                                   dp(mean.data_ptr()), dp(err.data_ptr())), "qmc_integrate")
+        if z is not None:   # general generating vectors [S][QMC_MAX_DIM]
+            z_arr = np.ascontiguousarray(z, dtype=np.uint64).reshape(self.S, QMC_MAX_DIM)
+            _check(lib().qmc_integrate_vec(self._h,
+                                           None if n_arr is None else n_arr.ctypes.data_as(u64p),
+                                           z_arr.ctypes.data_as(u64p), st,
+                                           dp(q.data_ptr()) if q is not None else None,
+                                           dp(mean.data_ptr()), dp(err.data_ptr())),
+                   "qmc_integrate_vec")
+        else:
+            _check(lib().qmc_integrate(self._h,
+                                       None if n_arr is None else n_arr.ctypes.data_as(u64p),
+                                       None if a_arr is None else a_arr.ctypes.data_as(u64p), st,
+                                       dp(q.data_ptr()) if q is not None else None,
+                                       dp(mean.data_ptr()), dp(err.data_ptr())), "qmc_integrate")
         if check:
             self.check_status(stream)
         return q, mean, err
@@ -151,6 +161,43 @@ class Plan:
             self._flows.pop(int(sector), None)
         else:
             self._flows[int(sector)] = flow
+
+    def median_lattice(self, r: int = 11, n=None, candidates=None, seed: int = 0,
+                       order: int = -1, stream=None):
+        """Median QMC rule per sector (see qmc_median_lattice).  candidates: [S][r][d or 8]
+        generating vectors; None draws them (seeded) uniformly from U_n.  Returns
+        (z [S][QMC_MAX_DIM], estimates [S][r], candidates [S][r][QMC_MAX_DIM])."""
+        import math
+        torch = _torch()
+        ns = [int(x) for x in (n if n is not None else [s.n for s in self.problem.sectors])]
+        c = np.zeros((self.S, r, QMC_MAX_DIM), dtype=np.uint64)
+        if candidates is None:
+            rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 23])))
+            for s, sec in enumerate(self.problem.sectors):
+                for k in range(r):
+                    for j in range(sec.d):
+                        while True:
+                            v = int(rng.integers(1, ns[s]))
+                            if math.gcd(v, ns[s]) == 1:
+                                c[s, k, j] = v
+                                break
+        else:
+            cc = np.asarray(candidates, dtype=np.uint64)
+            c[:, :, :cc.shape[2]] = cc
+        nb = int(lib().qmc_median_workspace_bytes(self._h, r))
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        ptr = scratch.data_ptr() + (-scratch.data_ptr()) % 256
+        n_arr = np.ascontiguousarray(ns, dtype=np.uint64)
+        z = np.zeros((self.S, QMC_MAX_DIM), dtype=np.uint64)
+        q = np.zeros((self.S, r))
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        _check(lib().qmc_median_lattice(self._h, n_arr.ctypes.data_as(u64p), int(r),
+                                        c.ctypes.data_as(u64p), int(order), ctypes.c_void_p(ptr),
+                                        ctypes.c_size_t(nb), _stream_ptr(stream),
+                                        z.ctypes.data_as(u64p),
+                                        q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "qmc_median_lattice")
+        return z, q, c
 
     def launch_shape(self) -> dict:
         sh = LaunchShape()

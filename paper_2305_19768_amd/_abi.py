@@ -123,6 +123,13 @@ def lib():
         L.qmc_choose_deformation.argtypes = [vp, ctypes.c_uint64, u64p, ctypes.c_int32, vp,
                                              ctypes.POINTER(ctypes.c_double), i32p]
         L.qmc_choose_deformation.restype = ctypes.c_int
+        L.qmc_integrate_vec.argtypes = [vp, u64p, u64p, vp, vp, vp, vp]
+        L.qmc_integrate_vec.restype = ctypes.c_int
+        L.qmc_median_workspace_bytes.argtypes = [vp, ctypes.c_int32]
+        L.qmc_median_workspace_bytes.restype = ctypes.c_size_t
+        L.qmc_median_lattice.argtypes = [vp, u64p, ctypes.c_int32, u64p, ctypes.c_int32, vp,
+                                         ctypes.c_size_t, vp, u64p, ctypes.POINTER(ctypes.c_double)]
+        L.qmc_median_lattice.restype = ctypes.c_int
         L.qmc_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
         L.qmc_set_launch_shape.restype = ctypes.c_int
         L.qmc_get_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]

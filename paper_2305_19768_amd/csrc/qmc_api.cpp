@@ -518,7 +518,7 @@ namespace qmc {
 
 qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t *a_in,
                              const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
-                             double *dev_err) {
+                             double *dev_err, const uint64_t *zvec) {
   if (!p) return fail(QMC_E_INVAL, "NULL plan");
   if (!dev_mean || !dev_err) return fail(QMC_E_INVAL, "dev_mean and dev_err are required");
   if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
@@ -544,14 +544,20 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     uint64_t z = 1 % n;
     for (int j = 0; j < QMC_MAX_DIM; ++j) {
       if (j < p->dims[s]) {
+        if (zvec) {   // general generating vector
+          z = zvec[(size_t)s * QMC_MAX_DIM + j];
+          if (z < 1 || z >= n)
+            return fail(QMC_E_INVAL, "sector %d: z_%d = %llu outside [1, n)", s, j + 1,
+                        (unsigned long long)z);
+        }
         if (gcd_u64(z, n) != 1)
-          return fail(QMC_E_INVAL, "sector %d: z_%d = a^%d mod n = %llu shares a factor with n = %llu",
-                      s, j + 1, j, (unsigned long long)z, (unsigned long long)n);
+          return fail(QMC_E_INVAL, "sector %d: z_%d = %llu shares a factor with n = %llu", s,
+                      j + 1, (unsigned long long)z, (unsigned long long)n);
         L.z[j] = z;
         L.dz[j] = mulmod_host((uint64_t)p->block % n, z, n);
         L.ndz[j] = (double)(n - L.dz[j]);
       }
-      z = mulmod_host(z, a, n);
+      if (!zvec) z = mulmod_host(z, a, n);
     }
     total += (__int128)n * tiles;
   }
@@ -664,6 +670,191 @@ qmc_status qmc_integrate(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_i
                          double *dev_q, double *dev_mean, double *dev_err) {
   g_last_error.clear();
   return integrate_sectors(p, n_in, a_in, nullptr, stream, dev_q, dev_mean, dev_err);
+}
+
+qmc_status qmc_integrate_vec(qmc_plan_t p, const uint64_t *n_in, const uint64_t *z, void *stream,
+                             double *dev_q, double *dev_mean, double *dev_err) {
+  g_last_error.clear();
+  if (!z) return fail(QMC_E_INVAL, "NULL generating vectors");
+  return integrate_sectors(p, n_in, nullptr, nullptr, stream, dev_q, dev_mean, dev_err, z);
+}
+
+// ------------------------------------------------------------ median QMC rules
+
+static constexpr int64_t kMedianTarget = 16384;
+
+struct MedianLayout {
+  size_t sec, lat, shift, begin, order, q, mean, err, status, partial, total;
+};
+
+static MedianLayout median_layout(const qmc_plan_s *p, int32_t r) {
+  const size_t V = (size_t)p->S * r;
+  MedianLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t at = o;
+    o = align256(o + b);
+    return at;
+  };
+  L.sec = take(sizeof(SectorDev) * V);
+  L.lat = take(sizeof(LatticeDev) * V);
+  L.shift = take(sizeof(double) * V * QMC_MAX_DIM);
+  L.begin = take(sizeof(int64_t) * (V + 1));
+  L.order = take(sizeof(int32_t) * V);
+  L.q = take(sizeof(double) * V * p->KC);
+  L.mean = take(sizeof(double) * V * p->KC);
+  L.err = take(sizeof(double) * V * p->KC);
+  L.status = take(256);
+  L.partial = take(sizeof(double) * 2 * (size_t)p->KC * (kMedianTarget + V + 64));
+  L.total = o;
+  return L;
+}
+
+size_t qmc_median_workspace_bytes(qmc_plan_t p, int32_t r) {
+  if (!p || r < 1) return 0;
+  return median_layout(p, r).total;
+}
+
+qmc_status qmc_median_lattice(qmc_plan_t p, const uint64_t *n_in, int32_t r,
+                              const uint64_t *cand, int32_t order, void *dev_scratch,
+                              size_t scratch_bytes, void *stream, uint64_t *z_out, double *q_out) {
+  g_last_error.clear();
+  if (!p || !cand || !z_out || !dev_scratch) return fail(QMC_E_INVAL, "NULL argument");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (p->cplx) return fail(QMC_E_INVAL, "median rules take real plans");
+  if (r < 1 || r > 1024) return fail(QMC_E_INVAL, "r = %d outside [1, 1024]", r);
+  if (order < -p->K || order >= p->K)
+    return fail(QMC_E_INVAL, "order %d outside [-%d, %d)", order, p->K, p->K);
+  const int k_sel = order < 0 ? p->K + order : order;
+  const MedianLayout ML = median_layout(p, r);
+  if (scratch_bytes < ML.total)
+    return fail(QMC_E_NOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes, ML.total);
+  if (((uintptr_t)dev_scratch & 255) != 0) return fail(QMC_E_INVAL, "scratch not 256-byte aligned");
+  const int S = p->S, V = S * r, K = p->KC;
+  std::vector<SectorDev> sec(V);
+  std::vector<LatticeDev> lat(V);
+  std::vector<int32_t> ord(V);
+  std::vector<int64_t> begin(V + 1);
+  __int128 total = 0;
+  for (int s = 0; s < S; ++s) {
+    const uint64_t n = n_in ? n_in[s] : p->n_default[s];
+    if (n < 2 || n > p->n_max || n >= (1ull << 53))
+      return fail(QMC_E_INVAL, "sector %d: n = %llu outside [2, n_max]", s, (unsigned long long)n);
+    for (int c = 0; c < r; ++c) {
+      const int v = s * r + c;
+      sec[v] = p->sec[s];
+      LatticeDev &L = lat[v];
+      std::memset(&L, 0, sizeof L);
+      L.active = 1;
+      L.n = n;
+      L.n_d = (double)n;
+      L.inv_n = 1.0 / (double)n;
+      for (int j = 0; j < p->dims[s]; ++j) {
+        const uint64_t z = cand[((size_t)s * r + c) * QMC_MAX_DIM + j];
+        if (z < 1 || z >= n || gcd_u64(z, n) != 1)
+          return fail(QMC_E_INVAL, "sector %d, candidate %d: z_%d = %llu not in U_n", s, c, j + 1,
+                      (unsigned long long)z);
+        L.z[j] = z;
+        L.dz[j] = mulmod_host((uint64_t)p->block % n, z, n);
+        L.ndz[j] = (double)(n - L.dz[j]);
+      }
+      total += (__int128)n;
+    }
+  }
+  for (int v = 0; v < V; ++v) ord[v] = v;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+    const int sx = x / r, sy = y / r;
+    const int fx = path_class(p, sx), fy = path_class(p, sy);
+    return p->dims[sx] != p->dims[sy] ? p->dims[sx] < p->dims[sy] : fx < fy;
+  });
+  const __int128 per_block = (__int128)kMedianTarget * p->block;
+  int64_t ppt = (int64_t)((total + per_block - 1) / per_block);
+  if (ppt < 1) ppt = 1;
+  const int64_t chunk = ppt * p->block;
+  int64_t b = 0;
+  DimLaunch dl[4 * QMC_MAX_DIM];
+  int n_dl = 0;
+  for (int t = 0; t < V; ++t) {
+    const int v = ord[t], s = v / r;
+    LatticeDev &L = lat[v];
+    L.chunk = chunk;
+    L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
+    L.block_begin = b;
+    begin[t] = b;
+    const int cls = path_class(p, s);
+    const int fast = (cls == 1 || cls == 2) ? 1 : 0, f32 = cls == 2 ? 1 : 0, flow = cls == 4 ? 1 : 0;
+    if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
+        dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].flow != flow) {
+      if (n_dl == 4 * QMC_MAX_DIM) return fail(QMC_E_STATE, "too many launch classes");
+      dl[n_dl] = DimLaunch{b, 0, p->dims[s], fast, f32, 0, flow, 0};
+      ++n_dl;
+    }
+    dl[n_dl - 1].blocks += L.n_chunks;
+    b += L.n_chunks;
+  }
+  begin[V] = b;
+  if ((size_t)(b + 0) > (size_t)(kMedianTarget + V + 64))
+    return fail(QMC_E_STATE, "median launch needs %lld workgroups", (long long)b);
+  char *w = (char *)dev_scratch;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> zero((size_t)V * QMC_MAX_DIM, 0.0);
+  int e;
+  if ((e = hipMemcpyAsync(w + ML.sec, sec.data(), sizeof(SectorDev) * V, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(w + ML.lat, lat.data(), sizeof(LatticeDev) * V, hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(w + ML.shift, zero.data(), sizeof(double) * zero.size(), hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(w + ML.begin, begin.data(), sizeof(int64_t) * (V + 1), hipMemcpyHostToDevice, st)) ||
+      (e = hipMemcpyAsync(w + ML.order, ord.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st)))
+    return hip_fail(e, "upload median tables");
+  LaunchArgs la;
+  std::memset(&la, 0, sizeof la);
+  la.sectors = (const SectorDev *)(w + ML.sec);
+  la.coef = (const double *)(p->ws + p->off_coef);
+  la.coef32 = (const float *)(p->ws + p->off_coef32);
+  la.shifts = (const double *)(w + ML.shift);
+  la.lat = (const LatticeDev *)(w + ML.lat);
+  la.block_begin = (const int64_t *)(w + ML.begin);
+  la.order = (const int32_t *)(w + ML.order);
+  la.n_dim_launches = n_dl;
+  for (int t = 0; t < n_dl; ++t) la.dims[t] = dl[t];
+  la.partial = (double *)(w + ML.partial);
+  la.q = (double *)(w + ML.q);
+  la.mean = (double *)(w + ML.mean);
+  la.err = (double *)(w + ML.err);
+  la.status = (int32_t *)(w + ML.status);
+  la.n_sectors = V;
+  la.m = 1;
+  la.K = K;
+  la.shift_tile = 1;
+  la.shifts_per_pass = 1;
+  la.block = p->block;
+  la.total_blocks = b;
+  la.d_max = p->d_max;
+  la.precision = p->precision;
+  if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
+  if ((e = launch_integrate(la, stream)) != hipSuccess) return hip_fail(e, "median launch");
+  std::vector<double> q((size_t)V * K);
+  int32_t code = 0;
+  if ((e = hipMemcpyAsync(q.data(), w + ML.q, sizeof(double) * q.size(), hipMemcpyDeviceToHost, st)) ||
+      (e = hipMemcpyAsync(&code, w + ML.status, sizeof code, hipMemcpyDeviceToHost, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "read median estimates");
+  if (code != INT32_MAX) {
+    const int v = code / QMC_MAX_ORDERS;
+    return fail(QMC_E_NONFINITE, "non-finite estimate: sector %d, candidate %d", v / r, v % r);
+  }
+  std::vector<int> idx(r);
+  for (int s = 0; s < S; ++s) {
+    for (int c = 0; c < r; ++c) idx[c] = c;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+      return q[((size_t)s * r + x) * K + k_sel] < q[((size_t)s * r + y) * K + k_sel];
+    });
+    const int c = idx[(r - 1) / 2];
+    for (int j = 0; j < QMC_MAX_DIM; ++j)
+      z_out[(size_t)s * QMC_MAX_DIM + j] = j < p->dims[s] ? cand[((size_t)s * r + c) * QMC_MAX_DIM + j] : 0;
+    if (q_out)
+      for (int cc = 0; cc < r; ++cc) q_out[(size_t)s * r + cc] = q[((size_t)s * r + cc) * K + k_sel];
+  }
+  return QMC_OK;
 }
 
 qmc_status qmc_query_status(qmc_plan_t p, void *stream, int32_t *sector, int32_t *shift,

@@ -101,7 +101,7 @@ __global__ void qmc_stats_kernel(LaunchArgs a) {
     const double dlt = q[(int64_t)l * a.K] - mean;
     dd_add(ss, dlt * dlt);
   }
-  const double var = (ss.s + ss.c) / (double)(m - 1);
+  const double var = m > 1 ? (ss.s + ss.c) / (double)(m - 1) : 0.0;
   a.mean[idx] = mean;
   a.err[idx] = sqrt(var / (double)m);
 }

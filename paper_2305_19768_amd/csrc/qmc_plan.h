@@ -72,5 +72,5 @@ namespace qmc {
 // the statistics of every sector to dev_mean / dev_err.
 qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n, const uint64_t *a,
                              const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
-                             double *dev_err);
+                             double *dev_err, const uint64_t *zvec = nullptr);
 }  // namespace qmc
