@@ -489,9 +489,25 @@ __device__ __forceinline__ void integrand_fast(const SectorScalars &ss, cptr<Sec
 }
 
 // korobov3 on S samples: x = y^4 (35 - 84 y + 70 y^2 - 20 y^3), W = 140^d (prod y(1-y))^3.
+// Coefficients of the korobov_3 polynomial held in registers for a whole loop.  A
+// float64 operation takes at most one literal, so with literal operands every point
+// would rebuild one of them with two moves; the opaque copies below are made once.
+struct KorobovConsts {
+  double c0, c1, c2, c3;
+};
+__device__ __forceinline__ double opaque_vgpr(double v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ KorobovConsts korobov3_consts() {
+  return KorobovConsts{opaque_vgpr(35.0), opaque_vgpr(-84.0), opaque_vgpr(70.0),
+                       opaque_vgpr(-20.0)};
+}
+
 template <int D, int S>
-__device__ __forceinline__ void korobov3_fast(double w_scale, const double (&y)[S][D],
-                                              double (&x)[S][D], double (&W)[S]) {
+__device__ __forceinline__ void korobov3_fast(double w_scale, const KorobovConsts &c,
+                                              const double (&y)[S][D], double (&x)[S][D],
+                                              double (&W)[S]) {
 #pragma unroll
   for (int u = 0; u < S; ++u) {
     double T = 1.0;
@@ -499,10 +515,11 @@ __device__ __forceinline__ void korobov3_fast(double w_scale, const double (&y)[
     for (int j = 0; j < D; ++j) {
       const double yj = y[u][j];
       const double p =
-          __builtin_fma(__builtin_fma(__builtin_fma(-20.0, yj, 70.0), yj, -84.0), yj, 35.0);
+          __builtin_fma(__builtin_fma(__builtin_fma(c.c3, yj, c.c2), yj, c.c1), yj, c.c0);
       const double y2 = yj * yj;
       x[u][j] = (y2 * y2) * p;
-      T *= yj * (1.0 - yj);
+      // y (1 - y) = y - y^2 in one rounding (the exact value, correctly rounded)
+      T *= __builtin_fma(-yj, yj, yj);
     }
     W[u] = w_scale * (T * T * T);
   }
@@ -647,7 +664,7 @@ __device__ __forceinline__ void korobov3_f32(float w_scale, const float (&y)[S][
           __builtin_fmaf(__builtin_fmaf(__builtin_fmaf(-20.0f, yj, 70.0f), yj, -84.0f), yj, 35.0f);
       const float y2 = yj * yj;
       x[u][j] = (y2 * y2) * p;
-      T *= yj * (1.0f - yj);
+      T *= __builtin_fmaf(-yj, yj, yj);
     }
     W[u] = w_scale * (T * T * T);
   }
@@ -698,6 +715,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
   // every lane runs the same number of iterations; lanes past i_end contribute 0
   const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
 
+  const KorobovConsts kc = korobov3_consts();
   // lattice state of this thread at its first point i0: k_j = i0 z_j mod n
   double k0[D];
   const uint64_t i0 = i_begin + threadIdx.x;
@@ -759,7 +777,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
             for (int kk = 0; kk < K; ++kk) f[u][kk] = (double)(Wf[u] * ff[u][kk]);
           }
         } else if (FAST) {
-          korobov3_fast<D, S>(w_scale, y, x, W);
+          korobov3_fast<D, S>(w_scale, kc, y, x, W);
           integrand_fast<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
         } else {
 #pragma unroll
