@@ -261,6 +261,47 @@ def flow_leg(qmc, torch, batches: int = 64, epochs: int = 3):
             "flow_network_frac_of_bf16_peak": evals * flops_eval / (k_flow / 1e3) / 2.5e15}
 
 
+def median_leg(qmc, torch, r: int = 11, seed: int = 0):
+    """Median QMC rule (Sec. 2.2): per sector r generating vectors drawn from U_n and the
+    median of their unshifted estimates, all candidates of all sectors in one launch,
+    against the P_2-searched Korobov vectors on the two-loop integral, both at each
+    sector's own n with the same 32 shifts.  Reports the selection time, its cost in
+    units of one 32-shift integration, the selection throughput and the per-sector ratio
+    of shift errors (all epsilon orders, summed in quadrature)."""
+    import numpy as np
+    import workloads
+    prob = workloads.two_loop_integral(seed=0)
+    plan = qmc.Plan(prob)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 29])))
+    cands = np.zeros((plan.S, r, qmc.QMC_MAX_DIM), dtype=np.uint64)
+    for s, sec in enumerate(prob.sectors):
+        cands[s, :, :sec.d] = workloads.median_candidates(rng, sec.n, sec.d, r)
+    _, _, e0 = plan.integrate()
+    plan.median_lattice(r=r, candidates=cands)             # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.integrate()
+    torch.cuda.synchronize()
+    t_int = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    z, _, _ = plan.median_lattice(r=r, candidates=cands)   # synchronous
+    t_sel = time.perf_counter() - t0
+    _, _, e1 = plan.integrate(z=z)
+    v0 = np.sqrt((e0.cpu().numpy() ** 2).sum(axis=1))
+    v1 = np.sqrt((e1.cpu().numpy() ** 2).sum(axis=1))
+    ratio = v1 / v0                       # < 1: the median rule's lattice is better
+    points = sum(sec.n for sec in prob.sectors)
+    return {"workload": f"two_loop_integral ({plan.S} sectors), r = {r} candidates per sector "
+                        f"from U_n, each sector's own n, 32 shifts after selection",
+            "selection_wall_s": t_sel, "integration_wall_s": t_int,
+            "selection_cost_in_integrations": t_sel / t_int,
+            "selection_evals_per_s": r * points / t_sel,
+            "error_ratio_median_over_korobov": {"median": float(np.median(ratio)),
+                                                "min": float(ratio.min()),
+                                                "max": float(ratio.max())},
+            "sectors_median_rule_better": int(np.count_nonzero(ratio < 1.0))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +320,7 @@ def main():
                     help="keep the default launch shape (no autotuner search)")
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
     ap.add_argument("--no-flow", action="store_true", help="skip the learned-transform leg")
+    ap.add_argument("--no-median", action="store_true", help="skip the median-rule leg")
     ap.add_argument("--scan-points", type=int, default=10,
                     help="kinematic points of the deformed-contour scan leg (0 = skip)")
     ap.add_argument("--amp-repeats", type=int, default=3)
@@ -397,6 +439,8 @@ def main():
         result["amplitude_time_to_1e-4"] = amplitude_leg(qmc, torch, args.amp_repeats)
     if not args.no_flow:
         result["learned_transform"] = flow_leg(qmc, torch)
+    if not args.no_median:
+        result["median_rule"] = median_leg(qmc, torch)
     if args.scan_points > 0:
         result["physical_scan"] = scan_leg(qmc, torch, args.scan_points, max(1, args.steps // 4))
     if not args.no_cpu:

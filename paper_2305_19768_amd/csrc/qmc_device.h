@@ -755,6 +755,9 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
         for (int j = 0; j < D; ++j) {
           q[j] = quotient(k[j], n_d, inv_n);
           k[j] = lattice_step(k[j], ltl->ndz[j], n_d);
+          // step now, while the table value is in a register: sunk to the end of the
+          // iteration, the loaded values would be spilled across the integrand
+          asm volatile("" : "+v"(k[j]));
         }
         double y[S][D], x[S][D], W[S];
 #pragma unroll
