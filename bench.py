@@ -193,6 +193,30 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
     plan.enable_timing(False)
     viol = plan.sign_violations()
     evals = prob.evals()
+    m64 = out[1].cpu().numpy().copy()
+    e64 = out[2].cpu().numpy().copy()
+    # FP32 bulk (gradient, Hessian, U(z), F(z) in FP32; Jacobian, log, powers and sums in
+    # FP64) with the same deformation parameters
+    plan32 = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
+    plan32.set_deformation(lam2)
+    plan32.integrate(out=out, check=False)
+    torch.cuda.synchronize()
+    plan32.enable_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan32.integrate(out=out, check=False)
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t0
+    k32, l32 = plan32.read_timing()
+    plan32.enable_timing(False)
+    viol32 = plan32.sign_violations()
+    m32 = out[1].cpu().numpy()
+    c64 = m64[..., 0] + 1j * m64[..., 1]
+    c32 = m32[..., 0] + 1j * m32[..., 1]
+    err = np.hypot(e64[..., 0], e64[..., 1])
+    dev = np.abs(c32 - c64)
+    rel = dev / np.maximum(np.abs(c64), 1e-300)
+    del plan32
     return {"workload": f"physical_scan: {n_points} kinematic points x 200 sectors, d 3..8, "
                         "n 65521, 16 shifts, orders eps^-2..eps^0, deformed contour, FP64 complex",
             "value": evals * steps / el, "unit": "complex evals/s",
@@ -201,7 +225,15 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
             "sectors_lambda_halved_presample": int(np.count_nonzero(halv)),
             "sectors_lambda_halved_full_n": int(np.count_nonzero(halv2)),
             "sectors_unfixed": int(rc2 != 0),
-            "sectors_violating_at_full_n": int(np.count_nonzero(viol))}
+            "sectors_violating_at_full_n": int(np.count_nonzero(viol)),
+            "fp32_bulk": {"value": evals * steps / el32, "unit": "complex evals/s",
+                          "ms_per_step": el32 / steps * 1e3, "kernel_ms": k32 / max(l32, 1),
+                          "speedup_vs_fp64": el / el32,
+                          "rel_dev_vs_fp64": {"median": float(np.median(rel)),
+                                              "p99": float(np.quantile(rel, 0.99)),
+                                              "max": float(rel.max())},
+                          "dev_over_fp64_shift_error_max": float(np.max(dev / np.maximum(err, 1e-300))),
+                          "sectors_violating_at_full_n": int(np.count_nonzero(viol32))}}
 
 
 def flow_leg(qmc, torch, batches: int = 64, epochs: int = 3):

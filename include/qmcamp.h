@@ -116,7 +116,17 @@ typedef struct {
 
 typedef struct {
     int32_t m;                        /* random shifts per sector, 2 .. QMC_MAX_SHIFTS */
-    int32_t precision;                /* QMC_PREC_FP64 (default) or QMC_PREC_FP32 */
+    int32_t precision;                /* QMC_PREC_FP64 (default) or QMC_PREC_FP32.
+                                         FP32, real plans: korobov3 sectors whose U and F
+                                         have no cancellation on the cube evaluate the
+                                         transform and the integrand in FP32; the rest
+                                         stay FP64.  FP32, complex plans: sectors with
+                                         deform_lambda > 0 at plan time, or without
+                                         cancellation, evaluate grad F, the Hessian of F,
+                                         U(z) and F(z) in FP32 and the Jacobian, powers,
+                                         logarithm and sign check from those in FP64
+                                         (sign check margin 2^-20 |F| instead of 2^-40).
+                                         Lattice points and sums are FP64 throughout. */
     uint64_t seed;                    /* seed of the built-in shift generator */
     uint64_t n_max;                   /* largest lattice size any call will use (sizes the
                                          workspace); 0 = max of the sectors' n */

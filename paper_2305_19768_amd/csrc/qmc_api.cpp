@@ -229,9 +229,9 @@ static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t
 }
 
 // 0: generic path, 1: fast path in FP64, 2: fast path in FP32, 3: deformed (complex plan),
-// 4: attached flow transform.
+// 4: attached flow transform, 5: deformed with the FP32 polynomial bulk.
 static int path_class(const qmc_plan_s *p, int s) {
-  if (p->cplx) return 3;
+  if (p->cplx) return (p->sec[s].flags & SF_CF32) ? 5 : 3;
   if (p->sec[s].flow) return 4;
   const int f = p->sec[s].flags;
   if (!(f & SF_FAST)) return 0;
@@ -413,6 +413,19 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
       if (ok && sd.u_den > 0) ok = p->coef[sd.u_off] >= 1e-30;
       if (ok) flags |= SF_F32OK;
     }
+    // FP32 bulk on the deformed contour: where the contour moves off the real cube F(z)
+    // keeps a non-zero imaginary part inside it; on the real contour only without
+    // cancellation (as for SF_F32OK)
+    if (p->cplx && p->precision == QMC_PREC_FP32) {
+      bool ok = in.deform_lambda > 0.0;
+      if (!ok) {
+        ok = p->coef[sd.f_off] >= 1e-30;
+        for (int i = 0; i < dense_len(D) && ok; ++i)
+          ok = p->coef[sd.f_off + i] >= 0.0 && p->coef[sd.u_off + i] >= 0.0;
+        if (ok && sd.u_den > 0) ok = p->coef[sd.u_off] >= 1e-30;
+      }
+      if (ok) flags |= SF_CF32;
+    }
     sd.flags = flags;
     sd.u_off32 = sd.u_off;
     sd.f_off32 = sd.f_off;
@@ -577,8 +590,8 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     L.block_begin = b;
     p->begin[t] = b;
     const int cls = path_class(p, s);
-    const int fast = (cls == 1 || cls == 2) ? 1 : 0, f32 = cls == 2 ? 1 : 0;
-    const int deform = cls == 3 ? 1 : 0, flow = cls == 4 ? 1 : 0;
+    const int fast = (cls == 1 || cls == 2) ? 1 : 0, f32 = (cls == 2 || cls == 5) ? 1 : 0;
+    const int deform = (cls == 3 || cls == 5) ? 1 : 0, flow = cls == 4 ? 1 : 0;
     if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
         dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].deform != deform || dl[n_dl - 1].flow != flow) {
       if (n_dl == 4 * QMC_MAX_DIM) return fail(QMC_E_STATE, "too many launch classes");

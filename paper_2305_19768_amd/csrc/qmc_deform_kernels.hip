@@ -148,41 +148,11 @@ __device__ __forceinline__ double horner1(cptr<double> c, const double (&x)[D], 
 
 constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // lower triangle, j <= i
 
-// J f_k(z(x)) for every order; returns whether the sample violates the sign check.
+// Elimination determinant of the complex symmetric matrix A (lower triangle, packed by
+// tri), without pivoting: the Hermitian part of A is the identity, so every pivot has
+// real part >= 1.  A is overwritten.
 template <int D>
-__device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<SectorDev> sd,
-                                                 cptr<double> coef, int grad_off, int hess_off,
-                                                 double lam, const double (&x)[D],
-                                                 C2 (&f)[QMC_MAX_ORDERS]) {
-  LoadChain ch{x[0], x[0]};
-  double g[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) g[j] = horner2<D>(coef + grad_off + j * dense_len2(D), x, ch);
-  double sq[D];
-  C2 z[D];
-  C2 A[D * (D + 1) / 2];
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    const double s = x[j] * (1.0 - x[j]);
-    // korobov3 evaluated with fused multiply-adds can round x a few ulp above 1 near
-    // y = 1, making s a tiny negative number; the symmetric scaling takes its root
-    sq[j] = sqrt(__builtin_fmax(s, 0.0));
-    z[j] = C2{x[j], -lam * s * g[j]};
-    A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
-  }
-  {
-    int t = 0;
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-#pragma unroll
-      for (int k = j; k < D; ++k, ++t) {
-        const double h = horner1<D>(coef + hess_off + t * dense_len1(D), x, ch);
-        const double v = -lam * sq[j] * sq[k] * h;
-        if (k == j) A[tri(j, j)].i += v;
-        else A[tri(k, j)] = C2{0.0, v};
-      }
-  }
-  // det by symmetric elimination without pivoting
+__device__ __forceinline__ C2 det_sym(C2 (&A)[D * (D + 1) / 2]) {
   C2 det{1.0, 0.0};
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -201,10 +171,15 @@ __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<S
       }
     }
   }
-  const C2 U = poly_c<D>(coef + ss.u_off, ss.u_deg, z, ch);
-  const C2 F = poly_c<D>(coef + ss.f_off, ss.f_deg, z, ch);
-  const bool viol = F.i > 0.0 && F.i * F.i > 0x1p-80 * __builtin_fma(F.r, F.r, F.i * F.i);
+  return det;
+}
 
+// The orders f_k = det x^p U^a F^b sum_m c_km (log F)^m on the contour point z, given
+// U(z) and F(z): powers, roots, the division and the logarithm in FP64.
+template <int D>
+__device__ __forceinline__ void deform_finish(const SectorScalars &ss, cptr<SectorDev> sd, C2 det,
+                                              const C2 (&z)[D], C2 U, C2 F,
+                                              C2 (&f)[QMC_MAX_ORDERS]) {
   const int flags = ss.flags;
   cptr<SectorDev> sx = launder_after(sd, F.r);
   C2 num = det, den{1.0, 0.0};
@@ -251,12 +226,187 @@ __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<S
       f[k] = C2{B.r * c0, B.i * c0};
     }
   }
+}
+
+// J f_k(z(x)) for every order; returns whether the sample violates the sign check.
+template <int D>
+__device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<SectorDev> sd,
+                                                 cptr<double> coef, int grad_off, int hess_off,
+                                                 double lam, const double (&x)[D],
+                                                 C2 (&f)[QMC_MAX_ORDERS]) {
+  LoadChain ch{x[0], x[0]};
+  double g[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) g[j] = horner2<D>(coef + grad_off + j * dense_len2(D), x, ch);
+  double sq[D];
+  C2 z[D];
+  C2 A[D * (D + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double s = x[j] * (1.0 - x[j]);
+    // korobov3 evaluated with fused multiply-adds can round x a few ulp above 1 near
+    // y = 1, making s a tiny negative number; the symmetric scaling takes its root
+    sq[j] = sqrt(__builtin_fmax(s, 0.0));
+    z[j] = C2{x[j], -lam * s * g[j]};
+    A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
+  }
+  {
+    int t = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int k = j; k < D; ++k, ++t) {
+        const double h = horner1<D>(coef + hess_off + t * dense_len1(D), x, ch);
+        const double v = -lam * sq[j] * sq[k] * h;
+        if (k == j) A[tri(j, j)].i += v;
+        else A[tri(k, j)] = C2{0.0, v};
+      }
+  }
+  const C2 det = det_sym<D>(A);
+  const C2 U = poly_c<D>(coef + ss.u_off, ss.u_deg, z, ch);
+  const C2 F = poly_c<D>(coef + ss.f_off, ss.f_deg, z, ch);
+  const bool viol = F.i > 0.0 && F.i * F.i > 0x1p-80 * __builtin_fma(F.r, F.r, F.i * F.i);
+  deform_finish<D>(ss, sd, det, z, U, F, f);
+  return viol;
+}
+
+// ------------------------------------------------------------- FP32 bulk form
+// The polynomial work of a sample -- the gradient and Hessian of F at x, U(z) and F(z)
+// -- in FP32 from the FP32 copy of the tables; the lattice point, the transform, the
+// Jacobian matrix and its determinant, the powers, the division, the logarithm and
+// every accumulation stay FP64.
+
+struct C2f {
+  float r, i;
+};
+
+// a * b + c with real-coefficient Horner operands of the FP32 polynomials
+__device__ __forceinline__ C2f cfmaf(C2f a, C2f b, C2f c) {
+  return C2f{__builtin_fmaf(a.r, b.r, __builtin_fmaf(-a.i, b.i, c.r)),
+             __builtin_fmaf(a.r, b.i, __builtin_fmaf(a.i, b.r, c.i))};
+}
+
+template <int D, int DEG>
+__device__ __forceinline__ C2f horner_cf(cptr<float> c, const C2f (&z)[D], LoadChainF &ch) {
+  c = ch.next(c);
+  C2f acc{c[0], 0.0f};
+  int p = 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    c = ch.next(c);
+    C2f g{c[p], 0.0f};
+    ++p;
+    if (DEG >= 2) {
+#pragma unroll
+      for (int k = j; k < D; ++k) {
+        if (DEG >= 3) c = ch.next(c);
+        C2f h{c[p], 0.0f};
+        ++p;
+        if (DEG >= 3) {
+#pragma unroll
+          for (int l = k; l < D; ++l) {
+            h.r = __builtin_fmaf(c[p + l - k], z[l].r, h.r);
+            h.i = __builtin_fmaf(c[p + l - k], z[l].i, h.i);
+          }
+          ch.done(h.r);
+        }
+        p += D - k;
+        g = cfmaf(z[k], h, g);
+      }
+    } else {
+      p += (D - j) * (D - j + 3) / 2;
+    }
+    acc = cfmaf(z[j], g, acc);
+    ch.done(acc.r);
+  }
+  return acc;
+}
+
+template <int D>
+__device__ __forceinline__ C2f poly_cf(cptr<float> c, int deg, const C2f (&z)[D], LoadChainF &ch) {
+  if (deg >= 3) return horner_cf<D, 3>(c, z, ch);
+  if (deg == 2) return horner_cf<D, 2>(c, z, ch);
+  return horner_cf<D, 1>(c, z, ch);
+}
+
+template <int D>
+__device__ __forceinline__ float horner2f(cptr<float> c, const float (&x)[D], LoadChainF &ch) {
+  c = ch.next(c);
+  float acc = c[0];
+  int p = 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    float g = c[p];
+#pragma unroll
+    for (int k = j; k < D; ++k) g = __builtin_fmaf(x[k], c[p + 1 + k - j], g);
+    p += 1 + D - j;
+    acc = __builtin_fmaf(x[j], g, acc);
+  }
+  ch.done(acc);
+  return acc;
+}
+
+template <int D>
+__device__ __forceinline__ float horner1f(cptr<float> c, const float (&x)[D], LoadChainF &ch) {
+  c = ch.next(c);
+  float acc = c[0];
+#pragma unroll
+  for (int j = 0; j < D; ++j) acc = __builtin_fmaf(c[1 + j], x[j], acc);
+  ch.done(acc);
+  return acc;
+}
+
+// integrand_deform with the polynomial bulk in FP32.  The sign check uses the FP32
+// value of F(z) with a margin above FP32 rounding: Im F(z) > 2^-20 |F(z)|.
+template <int D>
+__device__ __forceinline__ bool integrand_deform_f32(const SectorScalars &ss, cptr<SectorDev> sd,
+                                                     cptr<float> coef, int grad_off, int hess_off,
+                                                     double lam, const double (&x)[D],
+                                                     C2 (&f)[QMC_MAX_ORDERS]) {
+  float xf[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) xf[j] = (float)x[j];
+  LoadChainF ch{xf[0]};
+  double g[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    g[j] = (double)horner2f<D>(coef + grad_off + j * dense_len2(D), xf, ch);
+  double sq[D];
+  C2 z[D];
+  C2f zf[D];
+  C2 A[D * (D + 1) / 2];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double s = x[j] * (1.0 - x[j]);
+    sq[j] = sqrt(__builtin_fmax(s, 0.0));
+    z[j] = C2{x[j], -lam * s * g[j]};
+    zf[j] = C2f{xf[j], (float)z[j].i};
+    A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
+  }
+  {
+    int t = 0;
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+      for (int k = j; k < D; ++k, ++t) {
+        const double h = (double)horner1f<D>(coef + hess_off + t * dense_len1(D), xf, ch);
+        const double v = -lam * sq[j] * sq[k] * h;
+        if (k == j) A[tri(j, j)].i += v;
+        else A[tri(k, j)] = C2{0.0, v};
+      }
+  }
+  const C2 det = det_sym<D>(A);
+  const C2f Uf = poly_cf<D>(coef + ss.u_off32, ss.u_deg, zf, ch);
+  const C2f Ff = poly_cf<D>(coef + ss.f_off32, ss.f_deg, zf, ch);
+  const C2 U{(double)Uf.r, (double)Uf.i}, F{(double)Ff.r, (double)Ff.i};
+  const bool viol = F.i > 0.0 && F.i * F.i > 0x1p-40 * __builtin_fma(F.r, F.r, F.i * F.i);
+  deform_finish<D>(ss, sd, det, z, U, F, f);
   return viol;
 }
 
 // One workgroup's share of a sector on the deformed contour: the loop structure of
 // the real-contour block (one shift per pass), with 2 K accumulator columns.
-template <int D>
+template <int D, bool F32>
 __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_begin, int tile,
                                              int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
   const SectorDev *__restrict__ sd = a.sectors + s;
@@ -302,7 +452,6 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
       const int64_t it_end = (n_iter - it < kFold) ? n_iter : it + kFold;
 #pragma unroll 1
       for (; it < it_end; ++it, i += B) {
-        const cptr<double> cl = launder_uniform(a.coef);
         const cptr<LatticeDev> ltl = launder_uniform(lt);
         const cptr<double> shl = launder_uniform(sh);
         double y[D], x[D];
@@ -310,14 +459,23 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
         for (int j = 0; j < D; ++j) {
           const double q = quotient(k[j], n_d, inv_n);
           k[j] = lattice_step(k[j], ltl->ndz[j], n_d);
+          asm volatile("" : "+v"(k[j]));
           y[j] = shifted(q, shl[j]);
         }
         const double W = apply_transform<D>(kind, w_scale, y, x);
         C2 f[QMC_MAX_ORDERS];
 #pragma unroll
         for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) f[kk] = C2{0.0, 0.0};
-        const bool bad = integrand_deform<D>(ss, (cptr<SectorDev>)sd, launder_after(cl, W),
-                                             grad_off, hess_off, lam, x, f);
+        bool bad;
+        if (F32) {
+          const cptr<float> cl32 = launder_uniform(a.coef32);
+          bad = integrand_deform_f32<D>(ss, (cptr<SectorDev>)sd, launder_after_f(cl32, (float)W),
+                                        grad_off, hess_off, lam, x, f);
+        } else {
+          const cptr<double> cl = launder_uniform(a.coef);
+          bad = integrand_deform<D>(ss, (cptr<SectorDev>)sd, launder_after(cl, W), grad_off,
+                                    hess_off, lam, x, f);
+        }
         const bool use = (i < i_end) && (W != 0.0);
         viol += (use && bad) ? 1u : 0u;
 #pragma unroll
@@ -345,7 +503,7 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
   if (lane == 0 && viol != 0) atomicAdd(a.sign_count + s, (unsigned long long)viol);
 }
 
-template <int D>
+template <int D, bool F32>
 __global__ __launch_bounds__(256) void qmc_deform_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   const int64_t b = block_base + blockIdx.x;
@@ -356,7 +514,7 @@ __global__ __launch_bounds__(256) void qmc_deform_kernel(LaunchArgs a, int64_t b
   const int tile_id = (int)(local / nch);
   const int64_t chunk_id = local - (int64_t)tile_id * nch;
   const int T = a.shift_tile;
-  deform_block<D>(a, s, tile_id * T, T, chunk_id, red);
+  deform_block<D, F32>(a, s, tile_id * T, T, chunk_id, red);
   __syncthreads();
   const int nwaves = blockDim.x >> 6;
   const int cols = T * a.K;
@@ -374,19 +532,25 @@ __global__ void qmc_clear_u64_kernel(unsigned long long *p, int64_t count) {
   if (i < count) p[i] = 0ull;
 }
 
-int launch_deform(const LaunchArgs &a, const DimLaunch &dl, void *stream) {
-  hipStream_t st = (hipStream_t)stream;
+template <bool F32>
+static void launch_deform_p(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
   dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
   switch (dl.d) {
-    case 1: hipLaunchKernelGGL(qmc_deform_kernel<1>, grid, blk, 0, st, a, dl.base); break;
-    case 2: hipLaunchKernelGGL(qmc_deform_kernel<2>, grid, blk, 0, st, a, dl.base); break;
-    case 3: hipLaunchKernelGGL(qmc_deform_kernel<3>, grid, blk, 0, st, a, dl.base); break;
-    case 4: hipLaunchKernelGGL(qmc_deform_kernel<4>, grid, blk, 0, st, a, dl.base); break;
-    case 5: hipLaunchKernelGGL(qmc_deform_kernel<5>, grid, blk, 0, st, a, dl.base); break;
-    case 6: hipLaunchKernelGGL(qmc_deform_kernel<6>, grid, blk, 0, st, a, dl.base); break;
-    case 7: hipLaunchKernelGGL(qmc_deform_kernel<7>, grid, blk, 0, st, a, dl.base); break;
-    default: hipLaunchKernelGGL(qmc_deform_kernel<8>, grid, blk, 0, st, a, dl.base); break;
+    case 1: hipLaunchKernelGGL((qmc_deform_kernel<1, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL((qmc_deform_kernel<2, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL((qmc_deform_kernel<3, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 4: hipLaunchKernelGGL((qmc_deform_kernel<4, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 5: hipLaunchKernelGGL((qmc_deform_kernel<5, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 6: hipLaunchKernelGGL((qmc_deform_kernel<6, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 7: hipLaunchKernelGGL((qmc_deform_kernel<7, F32>), grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL((qmc_deform_kernel<8, F32>), grid, blk, 0, st, a, dl.base); break;
   }
+}
+
+int launch_deform(const LaunchArgs &a, const DimLaunch &dl, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (dl.f32) launch_deform_p<true>(a, dl, st);
+  else launch_deform_p<false>(a, dl, st);
   return (int)hipGetLastError();
 }
 

@@ -32,6 +32,8 @@ enum : int32_t {
                     // max_log <= n_orders - 1 (log polynomials zero-padded to that degree)
   SF_F32OK = 32,    // SF_FAST and F has non-negative coefficients with a positive constant
                     // term (F >= c0 > 0 on the cube): the FP32 form may evaluate it
+  SF_CF32 = 64,     // complex plan in FP32 precision: the polynomial bulk of the deformed
+                    // integrand runs in FP32 (deformed at plan time, or no cancellation)
 };
 
 // Static per-sector record (plan time).  Read with uniform (scalar) loads.

@@ -194,3 +194,91 @@ def test_complex_plan_rejected_by_amp_evaluate(qmc):
     with pytest.raises(qmc.QmcError, match="complex"):
         plan.amp_evaluate([[1.0]], 1e-3, lattice_n=np.array([1009], np.uint64),
                           lattice_a=np.ones((1, 8), np.uint64))
+
+
+# ---------------------------------------------------------------- FP32 bulk form
+# The gradient, Hessian, U(z) and F(z) in FP32; Jacobian, powers, logarithm and
+# accumulation in FP64.  Sums against the FP64 oracle within TOL32 of the same scale;
+# the worst relative deviation is printed per case.
+TOL32 = 1e-5
+
+
+def _compare32(qmc, prob, fp64_sectors=()):
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
+    assert plan.complex
+    q, mean, err = plan.integrate(check=False)
+    q = q.cpu().numpy()
+    viol = plan.sign_violations()
+    worst = 0.0
+    for s, sec in enumerate(prob.sectors):
+        Q, S, ov, _ = oracle.sector_sums_deformed(sec, prob.shifts[s], threads=8)
+        g = q[s, :, :, 0] + 1j * q[s, :, :, 1]
+        dev = np.abs(g - Q) / np.maximum(np.abs(Q), S)
+        tol = TOL if s in fp64_sectors else TOL32
+        assert np.all(dev <= tol), (s, float(dev.max()))
+        if s not in fp64_sectors:
+            worst = max(worst, float(dev.max()))
+        # FP32 sign check: violations above FP32 rounding (2^-20 |F|) only, so counts
+        # near the margin may differ from the FP64 oracle's
+        assert abs(int(viol[s]) - ov) <= max(2, ov // 100), (s, int(viol[s]), ov)
+    return plan, worst
+
+
+@pytest.mark.parametrize("d", [1, 3, 5, 6, 8])
+def test_deformed_fp32_bulk_parity_by_dimension(qmc, d):
+    rng = np.random.default_rng(100 + d)
+    secs, shifts = [], []
+    for t in range(2):
+        n = W.next_prime(1500 + 700 * t)
+        sec = _mixed_sector(rng, d, n, lam=0.0)
+        sh = W.uniform_shifts(rng, 8, d)
+        sec.deform_lambda, _ = oracle.choose_lambda(sec, sh, 0.5, 509,
+                                                    int(W._korobov_candidates(rng, 509, 1)[0]))
+        assert sec.deform_lambda > 0
+        secs.append(sec)
+        shifts.append(sh)
+    prob = W.Problem(sectors=secs, order_lo=-2, m=8, shifts=shifts)
+    _, worst = _compare32(qmc, prob)
+    print("d", d, "FP32 bulk worst rel. deviation", worst, flush=True)
+
+
+def test_deformed_fp32_bulk_mixed_plan_and_scan(qmc):
+    # Euclidean sector without cancellation: FP32 bulk; undeformed sector whose F changes
+    # sign: stays FP64 (bit-level parity); deformed sector: FP32 bulk
+    rng = np.random.default_rng(11)
+    euc = W._two_loop_sector(rng, 4, 1009, 0)
+    phys0 = _mixed_sector(rng, 3, 1013, lam=0.0)
+    phys = _mixed_sector(rng, 5, 1019, lam=0.125)
+    secs = [euc, phys0, phys]
+    shifts = [W.uniform_shifts(rng, 16, s.d) for s in secs]
+    prob = W.Problem(sectors=secs, order_lo=-2, m=16, shifts=shifts)
+    _, worst = _compare32(qmc, prob, fp64_sectors=(1,))
+    print("mixed plan FP32 bulk worst rel. deviation", worst, flush=True)
+    scan = W.physical_scan(seed=1, n_points=3, n_sectors=5, d_lo=3, d_hi=8, n=2003, m=8)
+    plan = qmc.Plan(scan)
+    lam, _, rc = plan.choose_deformation(509)
+    assert rc == 0
+    for s, sec in enumerate(scan.sectors):
+        sec.deform_lambda = float(lam[s])
+    _, worst = _compare32(qmc, scan)
+    print("scan FP32 bulk worst rel. deviation", worst, flush=True)
+
+
+def test_bubble_above_threshold_fp32_bulk(qmc):
+    s, m2 = 10.0, 1.0
+    beta = math.sqrt(1 - 4 * m2 / s)
+    f_terms = [(m2, (0,)), (-s, (1,)), (s, (2,))]
+    sec = W.custom_sector(1, [(1.0, (0,))], f_terms, logc=[[0.0, 1.0]],
+                          transform="korobov3", n=1000003, deform_lambda=0.5)
+    exact = (math.log(m2) - 2 + beta * math.log((1 + beta) / (1 - beta))
+             - 1j * math.pi * beta)
+    rng = np.random.default_rng(1)
+    prob = W.Problem(sectors=[sec], order_lo=0, m=16, shifts=[W.uniform_shifts(rng, 16, 1)])
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
+    lam, _, rc = plan.choose_deformation(10007)
+    assert rc == 0
+    _, mean, err = plan.integrate()
+    mean = mean.cpu().numpy()[0, 0]
+    print("bubble FP32 bulk", mean, exact, flush=True)
+    assert abs(mean[0] - exact.real) <= 1e-5 * abs(exact)
+    assert abs(mean[1] - exact.imag) <= 1e-5 * abs(exact)
