@@ -176,10 +176,9 @@ __device__ __forceinline__ C2 det_sym(C2 (&A)[D * (D + 1) / 2]) {
 
 // The orders f_k = det x^p U^a F^b sum_m c_km (log F)^m on the contour point z, given
 // U(z) and F(z): powers, roots, the division and the logarithm in FP64.
-template <int D>
+template <int D, int NK>
 __device__ __forceinline__ void deform_finish(const SectorScalars &ss, cptr<SectorDev> sd, C2 det,
-                                              const C2 (&z)[D], C2 U, C2 F,
-                                              C2 (&f)[QMC_MAX_ORDERS]) {
+                                              const C2 (&z)[D], C2 U, C2 F, C2 (&f)[NK]) {
   const int flags = ss.flags;
   cptr<SectorDev> sx = launder_after(sd, F.r);
   C2 num = det, den{1.0, 0.0};
@@ -208,20 +207,17 @@ __device__ __forceinline__ void deform_finish(const SectorScalars &ss, cptr<Sect
   const C2 B = (flags & SF_DEN) ? cmul(num, crecip(den)) : num;
   const int M = ss.max_log;
   cptr<SectorDev> sl = launder_after(sd, B.r);
-  const int K = sl->n_orders;
   if (flags & SF_LOG) {
     const C2 L = clog_minus_i0(F);
 #pragma unroll
-    for (int k = 0; k < QMC_MAX_ORDERS; ++k) {
-      if (k >= K) break;
+    for (int k = 0; k < NK; ++k) {
       C2 v{sl->logc[k][M], 0.0};
       for (int m = M - 1; m >= 0; --m) v = cfma(v, L, C2{sl->logc[k][m], 0.0});
       f[k] = cmul(B, v);
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < QMC_MAX_ORDERS; ++k) {
-      if (k >= K) break;
+    for (int k = 0; k < NK; ++k) {
       const double c0 = sl->logc[k][0];
       f[k] = C2{B.r * c0, B.i * c0};
     }
@@ -229,17 +225,15 @@ __device__ __forceinline__ void deform_finish(const SectorScalars &ss, cptr<Sect
 }
 
 // J f_k(z(x)) for every order; returns whether the sample violates the sign check.
-template <int D>
+template <int D, int NK>
 __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<SectorDev> sd,
                                                  cptr<double> coef, int grad_off, int hess_off,
-                                                 double lam, const double (&x)[D],
-                                                 C2 (&f)[QMC_MAX_ORDERS]) {
+                                                 double lam, const double (&x)[D], C2 (&f)[NK]) {
   LoadChain ch{x[0], x[0]};
   double g[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) g[j] = horner2<D>(coef + grad_off + j * dense_len2(D), x, ch);
   double sq[D];
-  C2 z[D];
   C2 A[D * (D + 1) / 2];
 #pragma unroll
   for (int j = 0; j < D; ++j) {
@@ -247,7 +241,6 @@ __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<S
     // korobov3 evaluated with fused multiply-adds can round x a few ulp above 1 near
     // y = 1, making s a tiny negative number; the symmetric scaling takes its root
     sq[j] = sqrt(__builtin_fmax(s, 0.0));
-    z[j] = C2{x[j], -lam * s * g[j]};
     A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
   }
   {
@@ -263,10 +256,14 @@ __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<S
       }
   }
   const C2 det = det_sym<D>(A);
+  // the contour point, formed after the elimination so that it is not live across it
+  C2 z[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) z[j] = C2{x[j], -lam * (x[j] * (1.0 - x[j])) * g[j]};
   const C2 U = poly_c<D>(coef + ss.u_off, ss.u_deg, z, ch);
   const C2 F = poly_c<D>(coef + ss.f_off, ss.f_deg, z, ch);
   const bool viol = F.i > 0.0 && F.i * F.i > 0x1p-80 * __builtin_fma(F.r, F.r, F.i * F.i);
-  deform_finish<D>(ss, sd, det, z, U, F, f);
+  deform_finish<D, NK>(ss, sd, det, z, U, F, f);
   return viol;
 }
 
@@ -358,11 +355,11 @@ __device__ __forceinline__ float horner1f(cptr<float> c, const float (&x)[D], Lo
 
 // integrand_deform with the polynomial bulk in FP32.  The sign check uses the FP32
 // value of F(z) with a margin above FP32 rounding: Im F(z) > 2^-20 |F(z)|.
-template <int D>
+template <int D, int NK>
 __device__ __forceinline__ bool integrand_deform_f32(const SectorScalars &ss, cptr<SectorDev> sd,
                                                      cptr<float> coef, int grad_off, int hess_off,
                                                      double lam, const double (&x)[D],
-                                                     C2 (&f)[QMC_MAX_ORDERS]) {
+                                                     C2 (&f)[NK]) {
   float xf[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) xf[j] = (float)x[j];
@@ -372,15 +369,11 @@ __device__ __forceinline__ bool integrand_deform_f32(const SectorScalars &ss, cp
   for (int j = 0; j < D; ++j)
     g[j] = (double)horner2f<D>(coef + grad_off + j * dense_len2(D), xf, ch);
   double sq[D];
-  C2 z[D];
-  C2f zf[D];
   C2 A[D * (D + 1) / 2];
 #pragma unroll
   for (int j = 0; j < D; ++j) {
     const double s = x[j] * (1.0 - x[j]);
     sq[j] = sqrt(__builtin_fmax(s, 0.0));
-    z[j] = C2{x[j], -lam * s * g[j]};
-    zf[j] = C2f{xf[j], (float)z[j].i};
     A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
   }
   {
@@ -396,17 +389,24 @@ __device__ __forceinline__ bool integrand_deform_f32(const SectorScalars &ss, cp
       }
   }
   const C2 det = det_sym<D>(A);
+  C2 z[D];
+  C2f zf[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    z[j] = C2{x[j], -lam * (x[j] * (1.0 - x[j])) * g[j]};
+    zf[j] = C2f{xf[j], (float)z[j].i};
+  }
   const C2f Uf = poly_cf<D>(coef + ss.u_off32, ss.u_deg, zf, ch);
   const C2f Ff = poly_cf<D>(coef + ss.f_off32, ss.f_deg, zf, ch);
   const C2 U{(double)Uf.r, (double)Uf.i}, F{(double)Ff.r, (double)Ff.i};
   const bool viol = F.i > 0.0 && F.i * F.i > 0x1p-40 * __builtin_fma(F.r, F.r, F.i * F.i);
-  deform_finish<D>(ss, sd, det, z, U, F, f);
+  deform_finish<D, NK>(ss, sd, det, z, U, F, f);
   return viol;
 }
 
 // One workgroup's share of a sector on the deformed contour: the loop structure of
 // the real-contour block (one shift per pass), with 2 K accumulator columns.
-template <int D, bool F32>
+template <int D, bool F32, int NK>
 __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_begin, int tile,
                                              int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
   const SectorDev *__restrict__ sd = a.sectors + s;
@@ -422,7 +422,7 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
   const double lam = sd->lambda;
   const int grad_off = sd->grad_off, hess_off = sd->hess_off;
   const SectorScalars ss = load_scalars(sd);
-  const int KC = a.K;   // 2 K columns
+  constexpr int KC = 2 * NK;   // (re, im) columns of the NK orders
   const uint64_t B = blockDim.x;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -435,9 +435,9 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
 
 #pragma unroll 1
   for (int l0 = 0; l0 < tile; ++l0) {
-    DD acc[2 * QMC_MAX_ORDERS];
+    DD acc[KC];
 #pragma unroll
-    for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) acc[c] = DD{0.0, 0.0};
+    for (int c = 0; c < KC; ++c) acc[c] = DD{0.0, 0.0};
     const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
     double k[D];
 #pragma unroll
@@ -446,9 +446,9 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
     int64_t it = 0;
 #pragma unroll 1
     while (it < n_iter) {
-      double part[2 * QMC_MAX_ORDERS];
+      double part[KC];
 #pragma unroll
-      for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) part[c] = 0.0;
+      for (int c = 0; c < KC; ++c) part[c] = 0.0;
       const int64_t it_end = (n_iter - it < kFold) ? n_iter : it + kFold;
 #pragma unroll 1
       for (; it < it_end; ++it, i += B) {
@@ -463,33 +463,30 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
           y[j] = shifted(q, shl[j]);
         }
         const double W = apply_transform<D>(kind, w_scale, y, x);
-        C2 f[QMC_MAX_ORDERS];
-#pragma unroll
-        for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) f[kk] = C2{0.0, 0.0};
+        C2 f[NK];
         bool bad;
         if (F32) {
           const cptr<float> cl32 = launder_uniform(a.coef32);
-          bad = integrand_deform_f32<D>(ss, (cptr<SectorDev>)sd, launder_after_f(cl32, (float)W),
+          bad = integrand_deform_f32<D, NK>(ss, (cptr<SectorDev>)sd, launder_after_f(cl32, (float)W),
                                         grad_off, hess_off, lam, x, f);
         } else {
           const cptr<double> cl = launder_uniform(a.coef);
-          bad = integrand_deform<D>(ss, (cptr<SectorDev>)sd, launder_after(cl, W), grad_off,
+          bad = integrand_deform<D, NK>(ss, (cptr<SectorDev>)sd, launder_after(cl, W), grad_off,
                                     hess_off, lam, x, f);
         }
         const bool use = (i < i_end) && (W != 0.0);
         viol += (use && bad) ? 1u : 0u;
 #pragma unroll
-        for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) {
+        for (int kk = 0; kk < NK; ++kk) {
           part[2 * kk] += use ? W * f[kk].r : 0.0;
           part[2 * kk + 1] += use ? W * f[kk].i : 0.0;
         }
       }
 #pragma unroll
-      for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) dd_add(acc[c], part[c]);
+      for (int c = 0; c < KC; ++c) dd_add(acc[c], part[c]);
     }
 #pragma unroll
-    for (int c = 0; c < 2 * QMC_MAX_ORDERS; ++c) {
-      if (c >= KC) break;
+    for (int c = 0; c < KC; ++c) {
       const DD r = wave_reduce(acc[c]);
       if (lane == 0) {
         red[wave][l0 * KC + c][0] = r.s;
@@ -503,8 +500,9 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
   if (lane == 0 && viol != 0) atomicAdd(a.sign_count + s, (unsigned long long)viol);
 }
 
-template <int D, bool F32>
-__global__ __launch_bounds__(256) void qmc_deform_kernel(LaunchArgs a, int64_t block_base) {
+template <int D, bool F32, int NK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 6 ? 2 : 1)))
+void qmc_deform_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   const int64_t b = block_base + blockIdx.x;
   const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
@@ -514,7 +512,7 @@ __global__ __launch_bounds__(256) void qmc_deform_kernel(LaunchArgs a, int64_t b
   const int tile_id = (int)(local / nch);
   const int64_t chunk_id = local - (int64_t)tile_id * nch;
   const int T = a.shift_tile;
-  deform_block<D, F32>(a, s, tile_id * T, T, chunk_id, red);
+  deform_block<D, F32, NK>(a, s, tile_id * T, T, chunk_id, red);
   __syncthreads();
   const int nwaves = blockDim.x >> 6;
   const int cols = T * a.K;
@@ -532,18 +530,28 @@ __global__ void qmc_clear_u64_kernel(unsigned long long *p, int64_t count) {
   if (i < count) p[i] = 0ull;
 }
 
+template <int D, bool F32>
+static void launch_deform_k(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
+  dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
+  switch (a.K / 2) {
+    case 1: hipLaunchKernelGGL((qmc_deform_kernel<D, F32, 1>), grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL((qmc_deform_kernel<D, F32, 2>), grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL((qmc_deform_kernel<D, F32, 3>), grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL((qmc_deform_kernel<D, F32, 4>), grid, blk, 0, st, a, dl.base); break;
+  }
+}
+
 template <bool F32>
 static void launch_deform_p(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
-  dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
   switch (dl.d) {
-    case 1: hipLaunchKernelGGL((qmc_deform_kernel<1, F32>), grid, blk, 0, st, a, dl.base); break;
-    case 2: hipLaunchKernelGGL((qmc_deform_kernel<2, F32>), grid, blk, 0, st, a, dl.base); break;
-    case 3: hipLaunchKernelGGL((qmc_deform_kernel<3, F32>), grid, blk, 0, st, a, dl.base); break;
-    case 4: hipLaunchKernelGGL((qmc_deform_kernel<4, F32>), grid, blk, 0, st, a, dl.base); break;
-    case 5: hipLaunchKernelGGL((qmc_deform_kernel<5, F32>), grid, blk, 0, st, a, dl.base); break;
-    case 6: hipLaunchKernelGGL((qmc_deform_kernel<6, F32>), grid, blk, 0, st, a, dl.base); break;
-    case 7: hipLaunchKernelGGL((qmc_deform_kernel<7, F32>), grid, blk, 0, st, a, dl.base); break;
-    default: hipLaunchKernelGGL((qmc_deform_kernel<8, F32>), grid, blk, 0, st, a, dl.base); break;
+    case 1: launch_deform_k<1, F32>(a, dl, st); break;
+    case 2: launch_deform_k<2, F32>(a, dl, st); break;
+    case 3: launch_deform_k<3, F32>(a, dl, st); break;
+    case 4: launch_deform_k<4, F32>(a, dl, st); break;
+    case 5: launch_deform_k<5, F32>(a, dl, st); break;
+    case 6: launch_deform_k<6, F32>(a, dl, st); break;
+    case 7: launch_deform_k<7, F32>(a, dl, st); break;
+    default: launch_deform_k<8, F32>(a, dl, st); break;
   }
 }
 
