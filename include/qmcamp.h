@@ -303,14 +303,25 @@ qmc_status qmc_lattice_points(uint64_t n, int32_t d, uint64_t a, const double *s
  * Weighted sums of integrals A_t = sum_i C_ti I_i (Sec. 2.1.3; coefficient rows may be
  * sparse, Sec. 2.4): row t holds the entries row_ptr[t] .. row_ptr[t+1]-1 of col
  * (integral index) and coef_re / coef_im.  n_sums >= 1.
+ * Coefficients may depend on the regulator (Sec. 2.4): with n_terms = P > 1 each entry
+ * holds the P Laurent coefficients c_p of eps^(coef_order_lo + p), p < P, stored
+ * [nnz][P] (qmc_coef_series produces them from expressions), and the sums are the
+ * products of series
+ *   A_t,j = sum_i sum_{p <= j} c_ti,p I_i,j-p,   j < n_orders,
+ * i.e. output order j is eps^(order_lo + coef_order_lo + j); each term's variance is
+ * |c|^2 var(I_i,j-p), the epsilon orders of an integral counted as independent.
+ * Terms with p >= n_orders never contribute.  n_terms = 0 or 1 with coef_order_lo = 0:
+ * constant coefficients.
  */
 typedef struct {
     int32_t n_sums;
-    int32_t reserved0;
+    int32_t n_terms;                  /* P: Laurent terms per coefficient (0 or 1: one) */
     const int64_t *row_ptr;           /* [n_sums + 1] */
     const int32_t *col;               /* [nnz] integral indices (< the problem's n_integrals) */
-    const double *coef_re;            /* [nnz] */
-    const double *coef_im;            /* [nnz], may be NULL (real coefficients) */
+    const double *coef_re;            /* [nnz][P] */
+    const double *coef_im;            /* [nnz][P], may be NULL (real coefficients) */
+    int32_t coef_order_lo;            /* epsilon power of term p = 0 */
+    int32_t reserved0;
 } qmc_amplitude;
 
 enum { QMC_AMP_HOST = 0, QMC_AMP_DEVICE = 1 };
@@ -360,6 +371,8 @@ typedef struct {
  * (the Lagrange solution of Eq. adaptive-solution with one consistent index), keep the
  * largest size any target asks for and never shrink, round up to the table and
  * re-integrate the sectors whose lattice changed.  Synchronous on `stream`.
+ * With regulator-dependent coefficients the closed form's |C|^2 w_s becomes the sum over
+ * the contributing terms, sum_p |c_p|^2 w_s,j-p.
  * Outputs (host, caller-owned): value and error [n_sums][n_orders][2] (re, im);
  * n_final [n_sectors] (may be NULL); stats (may be NULL).  Returns QMC_OK (converged
  * or not: see stats), QMC_E_TIMEOUT with valid results when the time limit stopped it,
@@ -477,6 +490,30 @@ qmc_status qmc_flow_samples(qmc_plan_t plan, int32_t sector, uint64_t n, uint64_
  * u or x is not inside (0, 1)).  dev_flow NULL detaches.  The flow buffer must stay
  * valid while attached.  Synchronous. */
 qmc_status qmc_flow_attach(qmc_plan_t plan, int32_t sector, const void *dev_flow, void *stream);
+
+/*
+ * qmc_coef_series -- a coefficient of a weighted sum given as an arithmetic expression
+ * (Sec. 2.4): the symbols are replaced by the caller's values, the expression is
+ * expanded into a Laurent series in the regulator in exact rational arithmetic, and
+ * the series coefficients are rounded to the nearest double.  Host only (no HIP call).
+ *   expr: numbers (integer, decimal, exponent notation; exact), symbols, the regulator
+ *     named `regulator`, the imaginary unit I, + - * / and ^ (or **) with integer
+ *     exponents, parentheses.  Functions and non-integer powers are rejected (they do
+ *     not give rational series).
+ *   names[k], values[k], k < n_symbols: symbol values, each an expression that may use
+ *     the regulator, I and symbols given before it, e.g. "3/2", "-0.25", "1+2*I",
+ *     "4-2*eps".
+ *   Writes *leading_order (may be NULL): the lowest order with a non-zero coefficient
+ *     (INT32_MAX for an identically zero expression), and for j < n_terms
+ *     re[j] + i im[j] = the coefficient of regulator^(order_lo + j).
+ * Errors: QMC_E_INVAL (syntax, unknown or repeated symbol, division by zero, an exponent
+ * that is not an integer or depends on the regulator,
+ * a non-zero term below order_lo when n_terms > 0 -- *leading_order is still set --,
+ * a coefficient outside the double range, numbers beyond 2^21 bits), QMC_E_NOMEM.
+ */
+qmc_status qmc_coef_series(const char *expr, const char *regulator, int32_t n_symbols,
+                           const char *const *names, const char *const *values, int32_t order_lo,
+                           int32_t n_terms, int32_t *leading_order, double *re, double *im);
 
 /*
  * qmc_enable_timing / qmc_read_timing -- kernel timing for measurement: while enabled,

@@ -429,6 +429,29 @@ def amplitude(coef, ival, ierr, ival_im=None, ierr_im=None):
     return re, im, np.sqrt(var_re), np.sqrt(var_im)
 
 
+def amplitude_series(coef, ival, ierr):
+    """Sum with regulator-dependent coefficients (Sec. 2.4): coef [NI, P] holds the Laurent
+    terms c_p of each integral's coefficient, and the product of series gives
+        A_j = sum_i sum_{p <= j} c_ip I_i,j-p,   var(Re A_j) = sum (Re c_ip)^2 var(I_i,j-p)
+    (likewise Im), the orders of an integral counted as independent (the per-order
+    propagation of Sec. 2.1.3, Eq. 4, applied term by term).  Real integrals.
+    Returns (re, im, err_re, err_im), each of shape [K]."""
+    C = np.asarray(coef, dtype=np.complex128)
+    ir = np.asarray(ival, dtype=np.float64)
+    er = np.asarray(ierr, dtype=np.float64)
+    NI, K = ir.shape
+    re, im, vre, vim = (np.zeros(K) for _ in range(4))
+    for j in range(K):
+        for i in range(NI):
+            for p in range(min(C.shape[1], j + 1)):
+                c = C[i, p]
+                re[j] += c.real * ir[i, j - p]
+                im[j] += c.imag * ir[i, j - p]
+                vre[j] += c.real ** 2 * er[i, j - p] ** 2
+                vim[j] += c.imag ** 2 * er[i, j - p] ** 2
+    return re, im, np.sqrt(vre), np.sqrt(vim)
+
+
 def eps_rel(re, im, dre, dim):
     """epsilon_rel = sqrt((dR^2 + dI^2) / (R^2 + I^2)) (Sec. 3.2, timing notes)."""
     return np.sqrt((np.asarray(dre) ** 2 + np.asarray(dim) ** 2) /
@@ -464,13 +487,19 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
     processed in order keeping each sector's largest request; sizes never shrink and
     are rounded up to the table of available lattices).
 
-    coef: complex [n_sums, n_integrals].  lattice_n: ascending sizes; lattice_a:
+    coef: complex [n_sums, n_integrals], or [n_sums, n_integrals, P] Laurent terms of
+    regulator-dependent coefficients (Sec. 2.4; see amplitude_series: a target (t, j)
+    weighs sector s by sum_p |c_p|^2 w_s,j-p).  lattice_n: ascending sizes; lattice_a:
     [L, 8] Korobov parameter per size and dimension (column d-1).  tau: cost per
     evaluation of each sector.  Returns (value [T, K] complex, error [T, K] complex
     (err_re + 1j err_im), n_final [S], rounds, converged).
     """
-    C = np.atleast_2d(np.asarray(coef, dtype=np.complex128))
-    T, NI = C.shape
+    C = np.asarray(coef, dtype=np.complex128)
+    if C.ndim == 1:
+        C = C[None, :]
+    if C.ndim == 2:
+        C = C[:, :, None]
+    T, NI, P = C.shape
     S = len(problem.sectors)
     K = problem.K
     lad = [int(v) for v in lattice_n]
@@ -513,7 +542,7 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
         errs = np.zeros((T, K), dtype=np.complex128)
         unmet = []
         for t in range(T):
-            re, im, dre, dim_ = amplitude(C[t], ival, ierr)
+            re, im, dre, dim_ = amplitude_series(C[t], ival, ierr)
             vals[t] = re + 1j * im
             errs[t] = dre + 1j * dim_
             for k in range(K):
@@ -533,12 +562,16 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
             V = max(epsrel ** 2 * mag2, epsabs ** 2)
             if not V > 0:
                 continue
-            c2 = np.array([abs(C[t, problem.sectors[s].integral]) ** 2 for s in range(S)])
-            w = err[:, k] ** 2 * n_cur ** alpha
-            use = c2 * w > 0
+            # |C|^2 w_s summed over the coefficient terms that reach order k
+            cw = np.zeros(S)
+            for s in range(S):
+                ci = C[t, problem.sectors[s].integral]
+                cw[s] = sum(abs(ci[p]) ** 2 * err[s, k - p] ** 2
+                            for p in range(min(P, k + 1))) * n_cur[s] ** alpha
+            use = cw > 0
             if not use.any():
                 continue
-            n_opt, _ = allocate(c2[use], w[use], tau[use], V, alpha)
+            n_opt, _ = allocate(np.ones(int(use.sum())), cw[use], tau[use], V, alpha)
             want[use] = np.maximum(want[use], n_opt)
         new = [max(lidx[s], ceil_index(want[s])) for s in range(S)]
         active = [new[s] != lidx[s] for s in range(S)]

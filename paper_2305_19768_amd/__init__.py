@@ -311,19 +311,26 @@ class Plan:
     def amp_evaluate(self, coef, epsrel: float, epsabs: float = 0.0, lattice_n=None,
                      lattice_a=None, tau=None, alpha: float = 2.0, n_presample: int = 10000,
                      max_rounds: int = 50, timeout_s: float = 0.0, mode: int = QMC_AMP_HOST,
-                     stream=None):
+                     stream=None, coef_order_lo: int = 0):
         """Adaptive evaluation of weighted sums A_t = sum_i C_ti I_i (see amp_evaluate in
         include/qmcamp.h).  coef: complex [n_sums, n_integrals] (or [n_integrals] for one
-        sum).  Returns (value complex [n_sums, K], error complex [n_sums, K] as
-        (err_re + 1j err_im), n_final [S], stats dict)."""
-        C = np.atleast_2d(np.asarray(coef, dtype=np.complex128))
-        T, NI = C.shape
+        sum), or [n_sums, n_integrals, P] Laurent terms of eps^(coef_order_lo + p).
+        Returns (value complex [n_sums, K], error complex [n_sums, K] as
+        (err_re + 1j err_im), n_final [S], stats dict); order j of the values is
+        eps^(order_lo + coef_order_lo + j)."""
+        C = np.asarray(coef, dtype=np.complex128)
+        if C.ndim == 1:
+            C = C[None, :]
+        if C.ndim == 2:
+            C = C[:, :, None]
+        T, NI, P = C.shape
         rows, cols, cre, cim = [0], [], [], []
         for t in range(T):
-            nz = np.nonzero(C[t])[0]
+            nz = np.nonzero(np.any(C[t] != 0, axis=1))[0]
             cols.extend(int(i) for i in nz)
-            cre.extend(float(C[t, i].real) for i in nz)
-            cim.extend(float(C[t, i].imag) for i in nz)
+            for i in nz:
+                cre.extend(float(v) for v in C[t, i].real)
+                cim.extend(float(v) for v in C[t, i].imag)
             rows.append(len(cols))
         row_ptr = np.array(rows, dtype=np.int64)
         col = np.array(cols, dtype=np.int32)
@@ -331,6 +338,8 @@ class Plan:
         ci = np.array(cim, dtype=np.float64)
         A = Amplitude()
         A.n_sums = T
+        A.n_terms = P
+        A.coef_order_lo = int(coef_order_lo)
         A.row_ptr = row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         A.col = col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         A.coef_re = cr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -360,6 +369,63 @@ class Plan:
         stats = {f: getattr(st, f) for f, _ in AmpStats._fields_}
         stats["status"] = rc
         return (val[..., 0] + 1j * val[..., 1], err[..., 0] + 1j * err[..., 1], nfin, stats)
+
+    def amp_evaluate_expressions(self, sums, symbols=None, regulator: str = "eps", **kw):
+        """Named weighted sums with coefficients given as expressions (Sec. 2.4).
+        sums: {name: row} (or a list of rows, named 0, 1, ...); a row is a list with one
+        entry per integral or a dict {integral index: entry}; entries are expression
+        strings or numbers, "0" or 0 for absent integrals.  The coefficients are expanded
+        exactly in the regulator (qmc_coef_series) from the lowest leading order of all
+        entries over the plan's K orders, then evaluated by amp_evaluate (keyword
+        arguments passed on).  Returns ({name: {"orders": [eps powers], "value": complex
+        [K], "error": complex [K]}}, n_final, stats)."""
+        named = dict(sums) if isinstance(sums, dict) else dict(enumerate(sums))
+        NI = self.problem.n_integrals
+        rows = {}
+        for name, row in named.items():
+            items = row.items() if isinstance(row, dict) else enumerate(row)
+            ent = {}
+            for i, e in items:
+                if not 0 <= int(i) < NI:
+                    raise ValueError(f"sum {name!r}: integral {i} outside [0, {NI})")
+                e = e if isinstance(e, str) else repr(e)
+                lead, _ = coef_series(e, regulator, symbols, 0, 0)
+                if lead is not None:
+                    ent[int(i)] = (e, lead)
+            rows[name] = ent
+        leads = [lead for ent in rows.values() for _, lead in ent.values()]
+        lo = min(leads) if leads else 0
+        C = np.zeros((len(rows), NI, self.K), dtype=np.complex128)
+        for t, ent in enumerate(rows.values()):
+            for i, (e, _) in ent.items():
+                C[t, i] = coef_series(e, regulator, symbols, lo, self.K)[1]
+        val, err, nfin, stats = self.amp_evaluate(C, coef_order_lo=lo, **kw)
+        orders = [self.problem.order_lo + lo + j for j in range(self.K)]
+        out = {name: {"orders": orders, "value": val[t], "error": err[t]}
+               for t, name in enumerate(rows)}
+        return out, nfin, stats
+
+
+def coef_series(expr: str, regulator: str = "eps", symbols=None, order_lo: int = 0,
+                n_terms: int = 1):
+    """Laurent series of a coefficient expression in the regulator, evaluated exactly
+    with the symbol values `symbols` ({name: value expression or number}) and rounded
+    to doubles (qmc_coef_series).  Returns (leading order or None for an identically zero
+    expression, complex coefficients [n_terms] of regulator^(order_lo + j))."""
+    names = list((symbols or {}).keys())
+    vals = [str(v) if not isinstance(v, str) else v for v in (symbols or {}).values()]
+    cn = (ctypes.c_char_p * max(1, len(names)))(*[n.encode() for n in names])
+    cv = (ctypes.c_char_p * max(1, len(vals)))(*[v.encode() for v in vals])
+    re = np.zeros(max(1, n_terms))
+    im = np.zeros(max(1, n_terms))
+    lead = ctypes.c_int32(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().qmc_coef_series(expr.encode(), regulator.encode(), len(names), cn, cv,
+                                 int(order_lo), int(n_terms), ctypes.byref(lead),
+                                 re.ctypes.data_as(dp), im.ctypes.data_as(dp)),
+           "qmc_coef_series")
+    lo = None if lead.value == 2 ** 31 - 1 else int(lead.value)
+    return lo, (re + 1j * im)[:n_terms]
 
 
 def korobov_search(plan: Plan, n: int, d: int, candidates: Sequence[int]):

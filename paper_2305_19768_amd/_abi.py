@@ -62,11 +62,12 @@ class Options(ctypes.Structure):
 
 
 class Amplitude(ctypes.Structure):
-    _fields_ = [("n_sums", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("n_sums", ctypes.c_int32), ("n_terms", ctypes.c_int32),
                 ("row_ptr", ctypes.POINTER(ctypes.c_int64)),
                 ("col", ctypes.POINTER(ctypes.c_int32)),
                 ("coef_re", ctypes.POINTER(ctypes.c_double)),
-                ("coef_im", ctypes.POINTER(ctypes.c_double))]
+                ("coef_im", ctypes.POINTER(ctypes.c_double)),
+                ("coef_order_lo", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class AmpOptions(ctypes.Structure):
@@ -165,6 +166,12 @@ def lib():
         L.qmc_last_error.restype = ctypes.c_char_p
         L.qmc_version.argtypes = []
         L.qmc_version.restype = ctypes.c_char_p
+        cpp = ctypes.POINTER(ctypes.c_char_p)
+        L.qmc_coef_series.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int32, cpp, cpp,
+                                      ctypes.c_int32, ctypes.c_int32, i32p,
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
+        L.qmc_coef_series.restype = ctypes.c_int
         _lib = L
     return _lib
 

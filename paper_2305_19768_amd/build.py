@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqmcamp.so")
 SOURCES = ["qmc_kernels.hip", "qmc_amp_kernels.hip", "qmc_deform_kernels.hip",
-           "qmc_flow_kernels.hip", "qmc_api.cpp", "qmc_amp.cpp", "qmc_flow.cpp"]
+           "qmc_flow_kernels.hip", "qmc_api.cpp", "qmc_amp.cpp", "qmc_flow.cpp",
+           "qmc_coef.cpp"]
 ARCH = os.environ.get("QMC_OFFLOAD_ARCH", "gfx950")
 
 

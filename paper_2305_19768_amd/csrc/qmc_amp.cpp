@@ -45,7 +45,7 @@ size_t ladder_ceil(const std::vector<uint64_t> &lad, double want, bool *limited)
 // Batched form: the rounds run on the device (round kernel, persistent integrand
 // kernel, reduction, statistics); the host queues a few rounds at a time and only reads
 // the state word between them.
-qmc_status amp_device(qmc_plan_s *p, int T, int NI, const std::vector<double> &cre,
+qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<double> &cre,
                       const std::vector<double> &cim, const std::vector<double> &c2,
                       const std::vector<uint64_t> &lad, const qmc_amp_options *opt,
                       const std::vector<double> &tau, void *stream, double *value, double *error,
@@ -80,8 +80,9 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, const std::vector<double> &c
   int32_t *d_integral = (int32_t *)take(4 * S), *d_dims = (int32_t *)take(4 * S);
   int32_t *d_lidx = (int32_t *)take(4 * S), *d_active = (int32_t *)take(4 * S);
   double *d_want = (double *)take(8 * S), *d_tau = (double *)take(8 * S);
-  double *d_c2 = (double *)take(8 * kAmpMaxSums * NI), *d_cre = (double *)take(8 * kAmpMaxSums * NI);
-  double *d_cim = (double *)take(8 * kAmpMaxSums * NI);
+  double *d_c2 = (double *)take(8 * kAmpMaxSums * NI * K);
+  double *d_cre = (double *)take(8 * kAmpMaxSums * NI * K);
+  double *d_cim = (double *)take(8 * kAmpMaxSums * NI * K);
   double *d_I = (double *)take(8 * NI * K), *d_VI = (double *)take(8 * NI * K);
   double *d_Are = (double *)take(8 * kAmpMaxSums * K), *d_Aim = (double *)take(8 * kAmpMaxSums * K);
   double *d_Vre = (double *)take(8 * kAmpMaxSums * K), *d_Vim = (double *)take(8 * kAmpMaxSums * K);
@@ -125,6 +126,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, const std::vector<double> &c
   g.block = p->block;
   g.n_lattice = (int32_t)lad.size();
   g.max_rounds = opt->max_rounds;
+  g.P = P;
   g.epsrel = opt->epsrel;
   g.epsabs = opt->epsabs;
   g.alpha = opt->alpha;
@@ -249,13 +251,21 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
     if (amp->row_ptr[t + 1] < amp->row_ptr[t]) return fail(QMC_E_INVAL, "row_ptr not ascending");
   const int64_t nnz = amp->row_ptr[T];
   if (nnz > 0 && (!amp->col || !amp->coef_re)) return fail(QMC_E_INVAL, "missing coefficients");
+  if (amp->n_terms < 0 || amp->n_terms > 64)
+    return fail(QMC_E_INVAL, "n_terms = %d outside [0, 64]", amp->n_terms);
+  if (amp->coef_order_lo < -1000 || amp->coef_order_lo > 1000)
+    return fail(QMC_E_INVAL, "coef_order_lo = %d outside [-1000, 1000]", amp->coef_order_lo);
+  const int Pin = amp->n_terms > 0 ? amp->n_terms : 1;
+  const int P = std::min(Pin, K);   // term p reaches output order j >= p only
   for (int64_t e = 0; e < nnz; ++e) {
     if (amp->col[e] < 0 || amp->col[e] >= NI)
       return fail(QMC_E_INVAL, "coefficient %lld: integral %d outside [0, %d)", (long long)e,
                   amp->col[e], NI);
-    const double im = amp->coef_im ? amp->coef_im[e] : 0.0;
-    if (!std::isfinite(amp->coef_re[e]) || !std::isfinite(im))
-      return fail(QMC_E_INVAL, "coefficient %lld is not finite", (long long)e);
+    for (int q = 0; q < Pin; ++q) {
+      const double im = amp->coef_im ? amp->coef_im[e * Pin + q] : 0.0;
+      if (!std::isfinite(amp->coef_re[e * Pin + q]) || !std::isfinite(im))
+        return fail(QMC_E_INVAL, "coefficient %lld (term %d) is not finite", (long long)e, q);
+    }
   }
   // ---- validate the options
   if (!(opt->epsrel >= 0.0) || !(opt->epsabs >= 0.0) || (opt->epsrel == 0.0 && opt->epsabs == 0.0))
@@ -289,19 +299,21 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
     tau[s] = opt->tau ? opt->tau[s] : cost_model(p->sec[s]);
     if (!(tau[s] > 0.0) || !std::isfinite(tau[s])) return fail(QMC_E_INVAL, "tau[%d] must be > 0", s);
   }
-  // coefficient |C|^2 of each sector's integral in each sum
-  std::vector<double> c2((size_t)T * NI, 0.0), cre((size_t)T * NI, 0.0), cim((size_t)T * NI, 0.0);
+  // coefficient terms c_p and |c_p|^2 of each integral in each sum, [T][NI][P]
+  const size_t TNP = (size_t)T * NI * P;
+  std::vector<double> c2(TNP, 0.0), cre(TNP, 0.0), cim(TNP, 0.0);
   for (int t = 0; t < T; ++t)
-    for (int64_t e = amp->row_ptr[t]; e < amp->row_ptr[t + 1]; ++e) {
-      const double re = amp->coef_re[e], im = amp->coef_im ? amp->coef_im[e] : 0.0;
-      cre[(size_t)t * NI + amp->col[e]] += re;
-      cim[(size_t)t * NI + amp->col[e]] += im;
-    }
+    for (int64_t e = amp->row_ptr[t]; e < amp->row_ptr[t + 1]; ++e)
+      for (int q = 0; q < P; ++q) {
+        const size_t at = ((size_t)t * NI + amp->col[e]) * P + q;
+        cre[at] += amp->coef_re[e * Pin + q];
+        cim[at] += amp->coef_im ? amp->coef_im[e * Pin + q] : 0.0;
+      }
   for (size_t i = 0; i < c2.size(); ++i) c2[i] = cre[i] * cre[i] + cim[i] * cim[i];
 
   if (opt->mode == QMC_AMP_DEVICE)
-    return amp_device(p, T, NI, cre, cim, c2, lad, opt, tau, stream, value, error, n_final, stats,
-                      t_start);
+    return amp_device(p, T, NI, P, cre, cim, c2, lad, opt, tau, stream, value, error, n_final,
+                      stats, t_start);
   // ---- presample
   bool limited = false;
   std::vector<size_t> lidx(S, ladder_ceil(lad, (double)std::max<uint64_t>(opt->n_presample, 2), &limited));
@@ -346,14 +358,16 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
     for (int t = 0; t < T; ++t)
       for (int k = 0; k < K; ++k) {
         double re = 0.0, im = 0.0, vre = 0.0, vim = 0.0;
-        for (int i = 0; i < NI; ++i) {
-          const double cr = cre[(size_t)t * NI + i], ci = cim[(size_t)t * NI + i];
-          const double v = I[(size_t)i * K + k], vv = VI[(size_t)i * K + k];
-          re += cr * v;
-          im += ci * v;
-          vre += cr * cr * vv;
-          vim += ci * ci * vv;
-        }
+        for (int i = 0; i < NI; ++i)
+          for (int q = 0; q < P && q <= k; ++q) {
+            const size_t at = ((size_t)t * NI + i) * P + q;
+            const double cr = cre[at], ci = cim[at];
+            const double v = I[(size_t)i * K + k - q], vv = VI[(size_t)i * K + k - q];
+            re += cr * v;
+            im += ci * v;
+            vre += cr * cr * vv;
+            vim += ci * ci * vv;
+          }
         const size_t at = (size_t)t * K + k;
         Are[at] = re;
         Aim[at] = im;
@@ -387,19 +401,24 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
       const double mag2 = Are[at] * Are[at] + Aim[at] * Aim[at];
       const double V = std::max(opt->epsrel * opt->epsrel * mag2, opt->epsabs * opt->epsabs);
       if (!(V > 0.0)) continue;
+      // cw[s] = |C|^2 w_s of the closed form: sum over the coefficient terms reaching
+      // this order of |c_p|^2 var_s,k-p n_s^alpha
       double sum = 0.0;
-      std::vector<double> w(S, 0.0), cc(S, 0.0);
+      std::vector<double> cw(S, 0.0);
       for (int s = 0; s < S; ++s) {
-        cc[s] = c2[(size_t)tg.t * NI + p->sec[s].integral];
-        const double var = err[(size_t)s * K + tg.k] * err[(size_t)s * K + tg.k];
-        w[s] = var * std::pow((double)n[s], al);
-        if (cc[s] * w[s] > 0.0) sum += std::pow(cc[s] * w[s] * std::pow(tau[s], al), 1.0 / (al + 1.0));
+        double acc = 0.0;
+        for (int q = 0; q < P && q <= tg.k; ++q) {
+          const double e = err[(size_t)s * K + tg.k - q];
+          acc += c2[((size_t)tg.t * NI + p->sec[s].integral) * P + q] * e * e;
+        }
+        cw[s] = acc * std::pow((double)n[s], al);
+        if (cw[s] > 0.0) sum += std::pow(cw[s] * std::pow(tau[s], al), 1.0 / (al + 1.0));
       }
       if (!(sum > 0.0)) continue;
       const double lam = (1.0 / al) * std::pow(sum / V, (al + 1.0) / al);
       for (int s = 0; s < S; ++s)
-        if (cc[s] * w[s] > 0.0)
-          want[s] = std::max(want[s], std::pow(al * w[s] * lam * cc[s] / tau[s], 1.0 / (al + 1.0)));
+        if (cw[s] > 0.0)
+          want[s] = std::max(want[s], std::pow(al * cw[s] * lam / tau[s], 1.0 / (al + 1.0)));
     }
     bool any = false;
     for (int s = 0; s < S; ++s) {

@@ -62,6 +62,17 @@ __device__ void set_lattice(const AmpArgs &g, int s, int l) {
   L.active = 1;
 }
 
+// |C|^2 w_s of the closed form for target (sum tt, order k): the coefficient terms that
+// reach order k, each with the variance of the order it multiplies, times n_s^alpha.
+__device__ double amp_cw(const AmpArgs &g, int tt, int k, int s, double al) {
+  double acc = 0.0;
+  for (int q = 0; q < g.P && q <= k; ++q) {
+    const double e = g.err[s * g.K + k - q];
+    acc += g.c2[(tt * g.NI + g.integral[s]) * g.P + q] * e * e;
+  }
+  return acc * pow((double)g.lattice_n[g.lidx[s]], al);
+}
+
 __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g) {
   AmpState *st = g.state;
   if (st->done) return;
@@ -89,14 +100,16 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
     for (int idx = t; idx < T * K; idx += kRoundThreads) {
       const int tt = idx / K, k = idx - tt * K;
       double re = 0.0, im = 0.0, vre = 0.0, vim = 0.0;
-      for (int i = 0; i < NI; ++i) {
-        const double cr = g.cre[tt * NI + i], ci = g.cim[tt * NI + i];
-        const double v = g.I[i * K + k], vv = g.VI[i * K + k];
-        re += cr * v;
-        im += ci * v;
-        vre += cr * cr * vv;
-        vim += ci * ci * vv;
-      }
+      for (int i = 0; i < NI; ++i)
+        for (int q = 0; q < g.P && q <= k; ++q) {
+          const int at = (tt * NI + i) * g.P + q;
+          const double cr = g.cre[at], ci = g.cim[at];
+          const double v = g.I[i * K + k - q], vv = g.VI[i * K + k - q];
+          re += cr * v;
+          im += ci * v;
+          vre += cr * cr * vv;
+          vim += ci * ci * vv;
+        }
       g.Are[idx] = re;
       g.Aim[idx] = im;
       g.Vre[idx] = vre;
@@ -138,20 +151,15 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
       if (!(V > 0.0)) continue;
       double part = 0.0;
       for (int s = t; s < S; s += kRoundThreads) {
-        const double cc = g.c2[tt * NI + g.integral[s]];
-        const double e = g.err[s * K + k];
-        const double w = e * e * pow((double)g.lattice_n[g.lidx[s]], al);
-        if (cc * w > 0.0) part += pow(cc * w * pow(g.tau[s], al), 1.0 / (al + 1.0));
+        const double cw = amp_cw(g, tt, k, s, al);
+        if (cw > 0.0) part += pow(cw * pow(g.tau[s], al), 1.0 / (al + 1.0));
       }
       const double sum = block_sum_ordered(part, shd);
       if (!(sum > 0.0)) continue;
       const double lam = (1.0 / al) * pow(sum / V, (al + 1.0) / al);
       for (int s = t; s < S; s += kRoundThreads) {
-        const double cc = g.c2[tt * NI + g.integral[s]];
-        const double e = g.err[s * K + k];
-        const double w = e * e * pow((double)g.lattice_n[g.lidx[s]], al);
-        if (cc * w > 0.0)
-          g.want[s] = fmax(g.want[s], pow(al * w * lam * cc / g.tau[s], 1.0 / (al + 1.0)));
+        const double cw = amp_cw(g, tt, k, s, al);
+        if (cw > 0.0) g.want[s] = fmax(g.want[s], pow(al * cw * lam / g.tau[s], 1.0 / (al + 1.0)));
       }
       __syncthreads();
     }

@@ -88,7 +88,7 @@ static void layout(qmc_plan_s *p) {
      // kAmpMaxLattice table entries
     const size_t S = p->S, NI = p->n_integrals, K = p->K;
     p->amp_bytes = align256(sizeof(AmpState)) + 4 * align256(4 * S) + 2 * align256(8 * S) +
-                   3 * align256(8 * kAmpMaxSums * NI) + 2 * align256(8 * NI * K) +
+                   3 * align256(8 * kAmpMaxSums * NI * K) + 2 * align256(8 * NI * K) +
                    4 * align256(8 * kAmpMaxSums * K) + align256(4 * kAmpMaxSums * K) +
                    align256(8 * kAmpMaxLattice) + align256(8 * kAmpMaxLattice * QMC_MAX_DIM);
     p->off_amp = take(p->amp_bytes);

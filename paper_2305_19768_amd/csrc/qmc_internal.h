@@ -136,7 +136,8 @@ struct AmpState {
 
 struct AmpArgs {
   AmpState *state;
-  int32_t S, K, T, NI, m, tile, block, n_lattice, max_rounds, pad;
+  int32_t S, K, T, NI, m, tile, block, n_lattice, max_rounds;
+  int32_t P;                       // Laurent terms per coefficient (tables [T][NI][P])
   double epsrel, epsabs, alpha;
   const int32_t *integral, *dims, *order;
   int32_t *lidx, *active, *unmet;

@@ -58,6 +58,56 @@ def test_synthetic_amplitude_parity(qmc, mode):
     _compare(qmc, prob, coef, sizes, a_tab, tau, 2e-6, 1009, mode=mode)
 
 
+def _series_coefficients(qmc, exprs, symbols, K):
+    """Laurent terms of the coefficient expressions from the library's exact expansion,
+    checked bit for bit against the oracle's exact rational functions."""
+    from oracle import coef as OC
+    leads = [qmc.coef_series(e, symbols=symbols, n_terms=0)[0] for e in exprs]
+    lo = min(l for l in leads if l is not None)
+    C = np.zeros((len(exprs), K), dtype=np.complex128)
+    for i, e in enumerate(exprs):
+        C[i] = qmc.coef_series(e, symbols=symbols, order_lo=lo, n_terms=K)[1]
+        want = [OC.to_complex(t) for t in OC.series(e, symbols=symbols, order_lo=lo, n_terms=K)[1]]
+        assert list(C[i]) == want
+    return C, lo
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_regulator_dependent_coefficients_parity(qmc, mode):
+    # coefficients with poles and zeros in eps (d = 4 - 2 eps): the sums are products of
+    # series; same rounds, final lattices and values as the oracle's loop
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    exprs, symbols = W.coefficient_expressions(seed=5, n_integrals=6)
+    C, lo = _series_coefficients(qmc, exprs, symbols, prob.K)
+    assert lo == -1
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    coef = np.stack([C, 0.5j * C])                  # two sums, [T, NI, P]
+    _compare(qmc, prob, coef, sizes, a_tab, tau, 2e-6, 1009, mode=mode, coef_order_lo=lo)
+
+
+def test_named_sums_from_expressions(qmc):
+    # named, sparse and dense rows of expressions give the same sums as the numeric route
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    exprs, symbols = W.coefficient_expressions(seed=5, n_integrals=6)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+    sums = {"dense": exprs, "sparse": {0: exprs[0], 3: f"I*({exprs[3]})"}}
+    out, nfin, st = plan.amp_evaluate_expressions(sums, symbols, epsrel=2e-6, lattice_n=sizes,
+                                                  lattice_a=a_tab, tau=tau, n_presample=1009)
+    C, lo = _series_coefficients(qmc, exprs, symbols, prob.K)
+    Cs = np.zeros_like(C)
+    Cs[0], Cs[3] = C[0], 1j * C[3]
+    ov, oe, on, orounds, _ = oracle.adaptive_amplitude(prob, np.stack([C, Cs]), sizes, a_tab,
+                                                       tau, epsrel=2e-6, n_presample=1009)
+    assert out["dense"]["orders"] == [prob.order_lo + lo + j for j in range(prob.K)]
+    assert st["rounds"] == orounds and np.array_equal(nfin, on)
+    for t, name in enumerate(("dense", "sparse")):
+        scale = np.abs(ov[t]) + np.abs(oe[t])
+        assert np.all(np.abs(out[name]["value"] - ov[t]) <= 1e-12 * scale)
+
+
 def test_device_mode_fp32_meets_target(qmc):
     # batched form with the FP32 integrand: same target met, values within FP32 bar of oracle
     prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)

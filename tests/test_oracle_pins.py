@@ -358,6 +358,36 @@ def test_amplitude_variance_propagation_and_eps_rel():
     assert oracle.eps_rel(3.0, 4.0, 0.3, 0.4) == pytest.approx(0.1)
 
 
+def test_amplitude_series_is_the_product_of_series():
+    # regulator-dependent coefficients (Sec. 2.4): the orders of A are the Cauchy product
+    # of the coefficient's and the integrals' Laurent series (numpy's convolution), the
+    # variance the sum over contributing terms with independent orders (Monte Carlo)
+    rng = np.random.default_rng(4)
+    NI, K, P = 3, 4, 3
+    C = rng.normal(size=(NI, P)) + 1j * rng.normal(size=(NI, P))
+    ival = rng.normal(size=(NI, K))
+    ierr = rng.uniform(0.05, 0.3, size=(NI, K))
+    re, im, dre, dim = oracle.amplitude_series(C, ival, ierr)
+    want = sum(np.convolve(C[i], ival[i])[:K] for i in range(NI))
+    assert np.allclose(re, want.real, rtol=1e-13, atol=1e-13)
+    assert np.allclose(im, want.imag, rtol=1e-13, atol=1e-13)
+    samp = ival[None] + ierr[None] * rng.normal(size=(100000, NI, K))
+    # the convolution with c_i as a lower-triangular Toeplitz matrix
+    Tm = np.zeros((NI, K, K), dtype=np.complex128)
+    for i in range(NI):
+        for j in range(K):
+            for p in range(min(P, j + 1)):
+                Tm[i, j, j - p] = C[i, p]
+    A = np.einsum("sik,ijk->sj", samp, Tm)
+    assert np.allclose(np.std(A.real, axis=0), dre, rtol=0.02)
+    assert np.allclose(np.std(A.imag, axis=0), dim, rtol=0.02)
+    # one constant term reduces to the per-order rule
+    r1 = oracle.amplitude_series(C[:, :1], ival, ierr)
+    r0 = oracle.amplitude(C[:, 0], ival, ierr)
+    for a, b in zip(r1, r0):
+        assert np.allclose(a, b, rtol=1e-14)
+
+
 # --------------------------------------------------------------- allocation
 
 def test_allocation_satisfies_constraint_and_stationarity():

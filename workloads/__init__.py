@@ -325,6 +325,36 @@ def amplitude(seed: int = 0, n_integrals: int = 20, n_sectors: int = 500, d_lo: 
                    amp_coef=np.array(coefs, dtype=np.complex128), name="amplitude", seed=seed)
 
 
+def coefficient_expressions(seed: int = 0, n_integrals: int = 20):
+    """Coefficient strings of an amplitude in the form reduction programs produce them:
+    c_i = P_i(s)/Q_i(s) * R_i(d) with three kinematic invariants s1..s3 (decimals in
+    [1, 10]), P_i with integer coefficients in [-9, 9] and Q_i = 1 + non-negative integer
+    coefficients on monomials of degree <= 2, and R_i(d) a rational factor in the
+    space-time dimension d = 4 - 2 eps (some with a pole in eps).  Returns (expressions
+    [n_integrals], symbol values {name: value string})."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 31])))
+    mons = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (1, 1, 0), (0, 1, 1),
+            (0, 0, 2)]
+    d_factors = ["1", "(d-2)/(d-3)", "1/(d-4)", "(3*d-10)/(2*(d-4))", "(d-4)/(d-6)",
+                 "(d-1)^2/((d-3)*(d-5))"]
+
+    def mono(e):
+        f = [f"s{j + 1}^{p}" if p > 1 else f"s{j + 1}" for j, p in enumerate(e) if p]
+        return "*".join(f) if f else "1"
+
+    exprs = []
+    for _ in range(n_integrals):
+        k = int(rng.integers(2, 6))
+        pick = rng.choice(len(mons), size=k, replace=False)
+        num = " + ".join(f"({int(rng.integers(-9, 10))})*{mono(mons[i])}" for i in pick)
+        den = "1 + " + " + ".join(f"{int(rng.integers(0, 10))}*{mono(mons[i])}"
+                                  for i in rng.choice(len(mons), size=3, replace=False))
+        exprs.append(f"({num})/({den})*{d_factors[int(rng.integers(0, len(d_factors)))]}")
+    symbols = {f"s{j + 1}": f"{int(rng.integers(1000, 10001)) / 1000:.3f}" for j in range(3)}
+    symbols["d"] = "4-2*eps"
+    return exprs, symbols
+
+
 def custom_sector(d, u_terms, f_terms, x_pow2=None, u_pow=0, f_pow2=0, logc=((1.0,),),
                   n=1009, a=1, transform="none", integral=0, deform_lambda=0.0) -> Sector:
     """A hand-specified sector: u_terms / f_terms are lists of (coef, exponent tuple)."""
