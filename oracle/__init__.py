@@ -82,6 +82,11 @@ def lib():
                                        ctypes.c_int, ctypes.c_uint64, _u64p, _dp, ctypes.c_int,
                                        ctypes.c_int, _dp, _dp, _i64p, _i64p]
         L.or_sums_deformed.restype = ctypes.c_int
+        L.or_integrand_deformed.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_int,
+                                            _u8p, _dp, _i32p, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double,
+                                            ctypes.c_uint64, _dp, _dp, _i32p]
+        L.or_integrand_deformed.restype = ctypes.c_int
         L.or_sign_violations.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_uint64, _u64p, _dp, ctypes.c_int,
                                          ctypes.c_int]
@@ -229,6 +234,21 @@ def deform_point(sec, x, lam: Optional[float] = None):
                               _p(xt, _dp), _p(zt, _dp), _p(Jt, _dp), _p(Ft, _dp))
         z[t], J[t], F[t] = zt, Jt, Ft
     return (z[..., 0] + 1j * z[..., 1], J[:, 0] + 1j * J[:, 1], F[:, 0] + 1j * F[:, 1])
+
+
+def integrand_deformed(sec, x, lam: Optional[float] = None):
+    """J(x) f_k(z(x)) on the deformed contour at real points x [count, d] (complex
+    [count, K]) and whether each sample violates the sign check (bool [count])."""
+    A = _SectorArrays(sec)
+    lam = float(sec.deform_lambda if lam is None else lam)
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, A.d)
+    out = np.empty((x.shape[0], A.K, 2))
+    viol = np.empty(x.shape[0], dtype=np.int32)
+    rc = lib().or_integrand_deformed(*A.head(), lam, x.shape[0], _p(x, _dp), _p(out, _dp),
+                                     _p(viol, _i32p))
+    if rc != 0:
+        raise ValueError("invalid sector")
+    return out[..., 0] + 1j * out[..., 1], viol.astype(bool)
 
 
 def sector_sums_deformed(sec, shifts, n: Optional[int] = None, a: Optional[int] = None,

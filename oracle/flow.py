@@ -53,17 +53,20 @@ def mask(d: int, layer: int) -> np.ndarray:
     return ((np.arange(d) % 2) == (layer % 2)).astype(np.float64)
 
 
-def init_params(d: int, seed: int = 0, zero_last: bool = True, scale: float = 1.0):
-    """Per layer (W1 [64, d], b1 [64], W2 [64, 64], b2 [64], W3 [2d, 64], b3 [2d]);
+def init_params(d: int, seed: int = 0, zero_last: bool = True, scale: float = 1.0,
+                n_cond: int = 0):
+    """Per layer (W1 [64, d + n_cond], b1 [64], W2 [64, 64], b2 [64], W3 [2d, 64], b3 [2d]);
     Glorot-uniform hidden weights, zero biases, and (zero_last) a zero last layer so the
-    flow starts as the identity.  All weights are bfloat16 values (stored as float64)."""
+    flow starts as the identity.  All weights are bfloat16 values (stored as float64).
+    A conditional flow (n_cond > 0) feeds n_cond conditioning features (kinematic
+    invariants of the sector) to every layer's network beside the masked coordinates."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
     params = []
     for _ in range(LAYERS):
         def glorot(o, i):
             lim = scale * np.sqrt(6.0 / (i + o))
             return bf16(rng.uniform(-lim, lim, size=(o, i)))
-        W1, W2 = glorot(HIDDEN, d), glorot(HIDDEN, HIDDEN)
+        W1, W2 = glorot(HIDDEN, d + n_cond), glorot(HIDDEN, HIDDEN)
         W3 = np.zeros((2 * d, HIDDEN)) if zero_last else glorot(2 * d, HIDDEN)
         params.append([W1, np.zeros(HIDDEN), W2, np.zeros(HIDDEN), W3, np.zeros(2 * d)])
     return params
@@ -78,9 +81,17 @@ def mlp(p, v, bf=False):
     return h2 @ r(W3).T + b3
 
 
-def _st(p, z, layer, d, bf):
+def _net_input(z, m, cond):
+    v = z * m
+    if cond is None:
+        return v
+    c = np.broadcast_to(np.asarray(cond, dtype=np.float64), (z.shape[0], np.shape(cond)[-1]))
+    return np.concatenate([v, c], axis=1)
+
+
+def _st(p, z, layer, d, bf, cond=None):
     m = mask(d, layer)
-    o = mlp(p, z * m, bf)
+    o = mlp(p, _net_input(z, m, cond), bf)
     s = S_SCALE * np.tanh(o[:, :d]) * (1.0 - m)
     t = o[:, d:] * (1.0 - m)
     return s, t
@@ -94,14 +105,15 @@ def sigmoid(z):
     return 1.0 / (1.0 + np.exp(-z))
 
 
-def density_direction(params, x, bf=False):
-    """u = G(x) and log q(x) for rows x [N, d] in (0, 1)^d."""
+def density_direction(params, x, bf=False, cond=None):
+    """u = G(x) and log q(x) for rows x [N, d] in (0, 1)^d (conditioning features cond
+    [N, c] or [c] for a conditional flow)."""
     x = np.asarray(x, dtype=np.float64)
     d = x.shape[1]
     z = logit(x)
     ssum = np.zeros(x.shape[0])
     for l, p in enumerate(params):
-        s, t = _st(p, z, l, d, bf)
+        s, t = _st(p, z, l, d, bf, cond)
         z = z * np.exp(s) + t
         ssum += s.sum(axis=1)
     u = sigmoid(z)
@@ -109,14 +121,14 @@ def density_direction(params, x, bf=False):
     return u, logq
 
 
-def sampling_direction(params, u, bf=False):
+def sampling_direction(params, u, bf=False, cond=None):
     """x = T(u) and log J_T(u) for rows u [N, d] in (0, 1)^d."""
     u = np.asarray(u, dtype=np.float64)
     d = u.shape[1]
     z = logit(u)
     ssum = np.zeros(u.shape[0])
     for l in reversed(range(len(params))):
-        s, t = _st(params[l], z, l, d, bf)
+        s, t = _st(params[l], z, l, d, bf, cond)
         z = (z - t) * np.exp(-s)
         ssum += s.sum(axis=1)
     x = sigmoid(z)
@@ -124,7 +136,7 @@ def sampling_direction(params, u, bf=False):
     return x, logJ
 
 
-def weighted_nll_and_grad(params, x, w):
+def weighted_nll_and_grad(params, x, w, cond=None):
     """Loss L = -sum_i w_i log q(x_i) / sum_i w_i and its gradient with respect to every
     parameter (float64, no bfloat16 rounding), by reverse-mode differentiation with
     torch on the CPU.  Returns (L, grads in the layout of params)."""
@@ -135,9 +147,11 @@ def weighted_nll_and_grad(params, x, w):
     d = xt.shape[1]
     z = torch.log(xt) - torch.log1p(-xt)
     ssum = torch.zeros(xt.shape[0], dtype=torch.float64)
+    ct = None if cond is None else torch.tensor(
+        np.broadcast_to(np.asarray(cond, dtype=np.float64), (xt.shape[0], np.shape(cond)[-1])).copy())
     for l, (W1, b1, W2, b2, W3, b3) in enumerate(tp):
         m = torch.tensor(mask(d, l))
-        v = z * m
+        v = z * m if ct is None else torch.cat([z * m, ct], dim=1)
         h1 = torch.tanh(v @ W1.T + b1)
         h2 = torch.tanh(h1 @ W2.T + b2)
         o = h2 @ W3.T + b3
@@ -179,18 +193,20 @@ def adam_init(params):
     return (0, z, [[np.zeros_like(a) for a in p] for p in params])
 
 
-def sector_sums(sec, shifts, params, n=None, a=None, bf=True):
+def sector_sums(sec, shifts, params, n=None, a=None, bf=True, cond=None, deformed=False):
     """Per-shift estimates of a sector integrated through the flow:
         Q[l, k] = (1/n) sum_i W(y_i) J_T(u_i) f_k(T(u_i)),   u_i = phi(y_i)
     with the sector's periodizing transform phi (weight W) and the flow's sampling
-    direction T; a sample with a coordinate of u or x outside (0, 1) contributes 0.
-    Lattice points, phi and f come from the C oracle; sums are exact (math.fsum).
+    direction T (conditioned on `cond` for a conditional flow); a sample with a
+    coordinate of u or x outside (0, 1) contributes 0.  deformed: f is the integrand on
+    the deformed contour, J(x) f(z(x)) (complex).  Lattice points, phi and f come from
+    the C oracle; sums are exact (math.fsum, real and imaginary parts separately).
     Returns (Q, S) with S[l, k] = (1/n) sum_i |W J f_k| (tolerance scale)."""
     import math
-    from . import integrand, korobov_vector, points, transform
+    from . import integrand, integrand_deformed, korobov_vector, points, transform
     n = int(sec.n if n is None else n)
     z = korobov_vector(n, sec.a if a is None else a, sec.d)
-    out = np.empty((len(shifts), sec.K))
+    out = np.empty((len(shifts), sec.K), dtype=np.complex128 if deformed else np.float64)
     scale = np.empty((len(shifts), sec.K))
     for l, sh in enumerate(np.asarray(shifts, dtype=np.float64)):
         y = points(n, z, sh)
@@ -199,15 +215,18 @@ def sector_sums(sec, shifts, params, n=None, a=None, bf=True):
         in_u = np.all((u > 0.0) & (u < 1.0), axis=1)
         uu = np.where(in_u[:, None], u, 0.5)
         with np.errstate(divide="ignore"):      # x rounded onto a face: excluded below
-            x, logJ = sampling_direction(params, uu, bf)
+            x, logJ = sampling_direction(params, uu, bf, cond)
         in_x = np.all((x > 0.0) & (x < 1.0), axis=1)
         xx = np.where(in_x[:, None], x, 0.5)
-        f = integrand(sec, xx)
+        f = integrand_deformed(sec, xx)[0] if deformed else integrand(sec, xx)
         Wt = W * np.exp(logJ)
         use = in_u & in_x & (Wt != 0.0)
         for k in range(sec.K):
             c = np.where(use, Wt * f[:, k], 0.0)
-            out[l, k] = math.fsum(c) / n
+            if deformed:
+                out[l, k] = complex(math.fsum(c.real), math.fsum(c.imag)) / n
+            else:
+                out[l, k] = math.fsum(c) / n
             scale[l, k] = math.fsum(np.abs(c)) / n
     return out, scale
 
@@ -218,9 +237,10 @@ def flatten(params) -> np.ndarray:
                            for a in p]).astype(np.float32)
 
 
-def unflatten(v, d):
+def unflatten(v, d, n_cond=0):
     v = np.asarray(v, dtype=np.float64)
-    shapes = [(HIDDEN, d), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (2 * d, HIDDEN), (2 * d,)]
+    shapes = [(HIDDEN, d + n_cond), (HIDDEN,), (HIDDEN, HIDDEN), (HIDDEN,), (2 * d, HIDDEN),
+              (2 * d,)]
     out, o = [], 0
     for _ in range(LAYERS):
         layer = []

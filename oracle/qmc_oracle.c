@@ -455,6 +455,31 @@ static void integrand_deformed(const integrand_t *g, double lambda, const double
     *Fz_out = F;
 }
 
+/* J f_k(z(x)) at real points x [count][d]: out[(t*K + k)*2 + {0,1}]; viol[t] = 1 where
+ * the sample violates the sign check (may be NULL). */
+int or_integrand_deformed(int d, int n_u, const uint8_t *u_exp, const double *u_coef, int n_f,
+                          const uint8_t *f_exp, const double *f_coef, const int32_t *x_pow2,
+                          int u_pow, int f_pow2, int K, int M, const double *logc,
+                          double lambda, uint64_t count, const double *x, double *out,
+                          int32_t *viol)
+{
+    if (d < 1 || d > 16 || K < 1 || K > 16)
+        return OR_INVAL;
+    integrand_t g = {d, n_u, n_f, u_pow, f_pow2, K, M, u_exp, u_coef, f_exp, f_coef,
+                     x_pow2, logc};
+    cplx fk[16], F;
+    for (uint64_t t = 0; t < count; ++t) {
+        integrand_deformed(&g, lambda, x + t * (uint64_t)d, fk, &F);
+        for (int k = 0; k < K; ++k) {
+            out[(t * K + k) * 2] = creal(fk[k]);
+            out[(t * K + k) * 2 + 1] = cimag(fk[k]);
+        }
+        if (viol)
+            viol[t] = sign_violated(F);
+    }
+    return OR_OK;
+}
+
 /* z [d] (re, im), J (re, im), F(z) (re, im) at one real point x. */
 void or_deform_point(int d, int n_f, const uint8_t *f_exp, const double *f_coef,
                      double lambda, const double *x, double *z_out, double *J_out,

@@ -133,3 +133,71 @@ def test_training_lowers_variance_of_peaked_integrand():
     plain = f(u)
     assert abs(gval.mean() - plain.mean()) < 4 * gval.std() / np.sqrt(len(u))
     assert gval.var() < 0.5 * plain.var()
+
+
+# ------------------------------------------------------ conditional flows (scan)
+def test_conditional_flow_reduces_and_depends_on_condition():
+    # zero weights on the conditioning columns give the unconditional flow exactly;
+    # non-zero ones make the map depend on the condition, and every conditional map is
+    # still an exact bijection with cancelling log-determinants
+    d, c = 4, 2
+    p = F.init_params(d, seed=8, zero_last=False, scale=1.5, n_cond=c)
+    p0 = [[a.copy() for a in q] for q in p]
+    for q in p0:
+        q[0][:, d:] = 0.0
+    pu = [[q[0][:, :d]] + q[1:] for q in p0]
+    u = np.random.default_rng(8).uniform(0.02, 0.98, size=(30, d))
+    cond = np.array([0.3, -0.7])
+    x0, l0 = F.sampling_direction(p0, u, cond=cond)
+    xu, lu = F.sampling_direction(pu, u)
+    assert np.array_equal(x0, xu) and np.array_equal(l0, lu)
+    x1, l1 = F.sampling_direction(p, u, cond=cond)
+    x2, _ = F.sampling_direction(p, u, cond=np.array([-0.5, 0.9]))
+    assert np.max(np.abs(x1 - x2)) > 1e-3
+    u1, q1 = F.density_direction(p, x1, cond=cond)
+    assert np.allclose(u1, u, atol=1e-12) and np.allclose(l1 + q1, 0, atol=1e-10)
+    # per-point conditions: row t of the batch uses cond[t]
+    cs = np.random.default_rng(9).uniform(-1, 1, size=(30, c))
+    xb, _ = F.sampling_direction(p, u, cond=cs)
+    for t in (0, 7, 29):
+        xt, _ = F.sampling_direction(p, u[t:t + 1], cond=cs[t])
+        assert np.allclose(xb[t], xt[0], atol=1e-15)
+
+
+def test_conditional_gradient_against_finite_differences():
+    d, c = 3, 2
+    p = F.init_params(d, seed=10, zero_last=False, scale=1.0, n_cond=c)
+    rng = np.random.default_rng(10)
+    x = rng.uniform(0.05, 0.95, size=(64, d))
+    w = rng.uniform(0.1, 2.0, size=64)
+    cs = rng.uniform(-1, 1, size=(64, c))
+    L, grads = F.weighted_nll_and_grad(p, x, w, cond=cs)
+    for (layer, idx) in [(0, (3, d)), (2, (10, d + 1)), (1, (5, 0))]:
+        h = 1e-6
+        pp = [[a.copy() for a in q] for q in p]
+        pp[layer][0][idx] += h
+        lp = -np.sum(w * F.density_direction(pp, x, cond=cs)[1]) / np.sum(w)
+        pp[layer][0][idx] -= 2 * h
+        lm = -np.sum(w * F.density_direction(pp, x, cond=cs)[1]) / np.sum(w)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) < 1e-6 * (1 + abs(fd)), (layer, idx)
+    v = F.flatten(p)
+    assert len(v) == 4 * (64 * (d + c) + 64 + 64 * 64 + 64 + 2 * d * 64 + 2 * d)
+    back = F.unflatten(v.astype(np.float64), d, n_cond=c)
+    assert all(np.array_equal(a.astype(np.float32), b.astype(np.float32))
+               for q, r in zip(p, back) for a, b in zip(q, r))
+
+
+def test_deformed_sums_through_identity_flow_equal_the_contour_sums():
+    # the flow composition on the deformed contour: with an identity flow the sums are
+    # those of the plain deformed-contour oracle (a different code path in C)
+    import oracle
+    import workloads as W
+    prob = W.physical_scan(seed=2, n_points=1, n_sectors=2, d_lo=3, d_hi=4, n=1009, m=4)
+    for s, sec in enumerate(prob.sectors):
+        sec.deform_lambda, _ = oracle.choose_lambda(sec, prob.shifts[s], 0.5, 1009, sec.a)
+        p = F.init_params(sec.d, seed=s, n_cond=2)          # identity (zero last layer)
+        Q, S = F.sector_sums(sec, prob.shifts[s], p, bf=True, cond=np.array([0.1, 0.2]),
+                             deformed=True)
+        Qd, Sd, _, _ = oracle.sector_sums_deformed(sec, prob.shifts[s])
+        assert np.allclose(Q, Qd, rtol=1e-12, atol=1e-12 * np.max(Sd))
