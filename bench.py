@@ -236,6 +236,77 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
                           "sectors_violating_at_full_n": int(np.count_nonzero(viol32))}}
 
 
+def scan_flow_leg(qmc, torch, n_points: int = 10, train_points: int = 3, batches: int = 16,
+                  epochs: int = 3):
+    """Kinematics-conditioned flows on the physical scan: one conditional flow per base
+    sector, its networks fed the scaled invariants ((s1, s2) - 5.5) / 4.5, trained on the
+    deformed integrand's samples (one shift, n = 65521) of the first train_points
+    kinematic points, then applied at every point of the scan; per (sector, point) the
+    flow is kept only where its shift variance at equal n is lower than plain QMC's
+    (the fallback).  Reports training time, the share of instances that keep the flow,
+    variance ratios, the cost of the flow-transformed evaluation and sign-check counts."""
+    import numpy as np
+    import workloads
+    prob = workloads.physical_scan(seed=0, n_points=n_points)
+    kin = prob.kinematics
+    nb = len(prob.sectors) // n_points
+    plan = qmc.Plan(prob)
+    plan.choose_deformation(4099)
+    plan.choose_deformation(65521)
+    _, m0, e0 = plan.integrate(check=False)
+    plan.enable_timing(True)
+    plan.integrate(check=False)
+    k_plain, _ = plan.read_timing()
+    plan.enable_timing(False)
+    cond = (kin - 5.5) / 4.5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flows = []
+    for b in range(nb):
+        sec = prob.sectors[b]
+        xs, ws, cs = [], [], []
+        for pnt in range(train_points):
+            x, w = plan.flow_samples(pnt * nb + b, sec.n, sec.a, shift=0)
+            xs.append(x)
+            ws.append(w)
+            cs.append(torch.tensor(cond[pnt], dtype=torch.float64, device="cuda")
+                      .reshape(1, 2).expand(sec.n, 2))
+        fl = qmc.flow.Flow(sec.d, params=qmc.flow.glorot_params(sec.d, seed=b, n_cond=2), n_cond=2)
+        fl.train(torch.cat(xs), torch.cat(ws), batches=batches, epochs=epochs, lr=2e-3,
+                 cond=torch.cat(cs))
+        flows.append(fl)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    for s in range(len(prob.sectors)):
+        pnt, b = divmod(s, nb)
+        plan.attach_flow(s, flows[b], cond=cond[pnt])
+    _, m1, e1 = plan.integrate(check=False)
+    viol = plan.sign_violations()
+    plan.enable_timing(True)
+    plan.integrate(check=False)
+    k_flow, _ = plan.read_timing()
+    plan.enable_timing(False)
+    v0 = (e0.cpu().numpy() ** 2).sum(axis=(1, 2))
+    v1 = (e1.cpu().numpy() ** 2).sum(axis=(1, 2))
+    ratio = v0 / np.maximum(v1, 1e-300)        # > 1: the flow lowers the shift variance
+    keep = (ratio > 1.0) & (viol == 0)         # fallback: plain QMC elsewhere
+    train_mask = np.zeros(len(prob.sectors), dtype=bool)
+    train_mask[: train_points * nb] = True
+    cost = k_flow / k_plain
+    return {"workload": f"physical_scan: {n_points} kinematic points x {nb} sectors; one "
+                        f"conditional flow per base sector (features (s1, s2)), trained on "
+                        f"{train_points} points x 65521 samples ({batches} batches x {epochs} "
+                        f"epochs), applied at every point",
+            "training_wall_s": train_s,
+            "instances_flow_kept": int(keep.sum()), "instances": int(len(keep)),
+            "kept_at_unseen_points": int(keep[~train_mask].sum()),
+            "variance_ratio_plain_over_flow": {"median": float(np.median(ratio)),
+                                               "max": float(ratio.max())},
+            "cost_ratio_flow_over_plain": float(cost),
+            "flow_complex_evals_per_s": prob.evals() / (k_flow / 1e3),
+            "sectors_violating_with_flow": int(np.count_nonzero(viol))}
+
+
 def flow_leg(qmc, torch, batches: int = 64, epochs: int = 3):
     """Learned transform against korobov3 on the d = 6 sectors of the two-loop integral:
     per sector a flow trained on 1e6 QMC samples (one shift, n = nextprime(1e6)), then the
@@ -353,6 +424,8 @@ def main():
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
     ap.add_argument("--no-flow", action="store_true", help="skip the learned-transform leg")
     ap.add_argument("--no-median", action="store_true", help="skip the median-rule leg")
+    ap.add_argument("--no-scan-flow", action="store_true",
+                    help="skip the kinematics-conditioned flow leg on the physical scan")
     ap.add_argument("--scan-points", type=int, default=10,
                     help="kinematic points of the deformed-contour scan leg (0 = skip)")
     ap.add_argument("--amp-repeats", type=int, default=3)
@@ -475,6 +548,8 @@ def main():
         result["median_rule"] = median_leg(qmc, torch)
     if args.scan_points > 0:
         result["physical_scan"] = scan_leg(qmc, torch, args.scan_points, max(1, args.steps // 4))
+        if not args.no_scan_flow:
+            result["physical_scan"]["conditional_flow"] = scan_flow_leg(qmc, torch, args.scan_points)
     if not args.no_cpu:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         result["cpu_baseline"] = cpu_baseline(prob, threads)

@@ -61,6 +61,7 @@ enum { QMC_PREC_FP64 = 0, QMC_PREC_FP32 = 1 };
 #define QMC_MAX_SHIFTS 64
 #define QMC_FLOW_LAYERS 4  /* affine coupling layers of a learned flow transform */
 #define QMC_FLOW_HIDDEN 64 /* hidden width of each coupling layer's network */
+#define QMC_FLOW_MAX_COND 4 /* conditioning features of a conditional flow (d + n_cond <= 16) */
 
 /*
  * One sector integrand, expanded in epsilon (Sec. 2.3 and 3: sector-decomposed
@@ -425,10 +426,17 @@ qmc_status qmc_autotune(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, i
  * J_T(u) = 1/q(x).  The networks run on the matrix cores in bfloat16 with float32
  * accumulation; the coupling updates, logit and sigmoid are float64.
  *
- * Parameters (host float32, qmc_flow_param_count(d) values) are laid out per layer as
- * W1 [64][d], b1 [64], W2 [64][64], b2 [64], W3 [2d][64] (rows s then t), b3 [2d].  A flow's
- * device state (parameters, Adam moments, gradient, packed operands) is a caller-owned,
- * 256-byte aligned device buffer of qmc_flow_bytes(d) bytes.
+ * Conditional flows (a flow shared by the points of a kinematic scan): n_cond
+ * conditioning features c (0 <= n_cond <= QMC_FLOW_MAX_COND, d + n_cond <= 16) are
+ * appended to every layer's network input, (m_l z, c), so W1 has d + n_cond columns; the
+ * features are the caller's (e.g. scaled kinematic invariants), given per sample in
+ * training and per sector when attached.
+ *
+ * Parameters (host float32, qmc_flow_param_count(d, n_cond) values) are laid out per
+ * layer as W1 [64][d + n_cond], b1 [64], W2 [64][64], b2 [64], W3 [2d][64] (rows s then
+ * t), b3 [2d].  A flow's device state (parameters, Adam moments, gradient, packed
+ * operands) is a caller-owned, 256-byte aligned device buffer of qmc_flow_bytes(d,
+ * n_cond) bytes.  Every call names the flow's (d, n_cond).
  */
 enum { QMC_FLOW_SAMPLE = 0, QMC_FLOW_DENSITY = 1 };
 
@@ -438,58 +446,72 @@ typedef struct {
     int32_t reserved0;
 } qmc_flow_adam;
 
-int64_t qmc_flow_param_count(int32_t d);          /* -1 if d is outside [1, QMC_MAX_DIM] */
-size_t qmc_flow_bytes(int32_t d);                  /* 0 if d is out of range */
+/* -1 / 0 if d is outside [1, QMC_MAX_DIM] or n_cond outside [0, QMC_FLOW_MAX_COND] */
+int64_t qmc_flow_param_count(int32_t d, int32_t n_cond);
+size_t qmc_flow_bytes(int32_t d, int32_t n_cond);
 
 /* Upload parameters, zero the Adam moments and gradient, pack the matrix-core operands.
  * Synchronous.  Errors: QMC_E_INVAL (NULL, misaligned, non-finite parameter). */
-qmc_status qmc_flow_load(void *dev_flow, int32_t d, const float *params, void *stream);
+qmc_status qmc_flow_load(void *dev_flow, int32_t d, int32_t n_cond, const float *params,
+                         void *stream);
 
 /* Copy parameters and/or the last gradient (either may be NULL) to the host.  Synchronous. */
-qmc_status qmc_flow_read(const void *dev_flow, int32_t d, float *params, float *grad, void *stream);
+qmc_status qmc_flow_read(const void *dev_flow, int32_t d, int32_t n_cond, float *params,
+                         float *grad, void *stream);
 
 /* dev_out[i][j], dev_logdet[i] for dev_in [count][d] (device float64, coordinates in
- * (0, 1)): QMC_FLOW_SAMPLE gives x = T(u) and log J_T(u); QMC_FLOW_DENSITY gives u = G(x)
- * and log q(x).  Asynchronous. */
-qmc_status qmc_flow_transform(const void *dev_flow, int32_t d, int32_t direction,
-                              const double *dev_in, int64_t count, void *stream, double *dev_out,
-                              double *dev_logdet);
+ * (0, 1)) and dev_cond [count][n_cond] (device float64; NULL when n_cond = 0):
+ * QMC_FLOW_SAMPLE gives x = T(u) and log J_T(u); QMC_FLOW_DENSITY gives u = G(x) and
+ * log q(x).  Asynchronous. */
+qmc_status qmc_flow_transform(const void *dev_flow, int32_t d, int32_t n_cond, int32_t direction,
+                              const double *dev_in, const double *dev_cond, int64_t count,
+                              void *stream, double *dev_out, double *dev_logdet);
 
 /* Device scratch bytes of qmc_flow_gradient over `count` points. */
-size_t qmc_flow_scratch_bytes(int32_t d, int64_t count);
+size_t qmc_flow_scratch_bytes(int32_t d, int32_t n_cond, int64_t count);
 
-/* Gradient of L = -(1/w_sum) sum_i w_i log q(x_i) (weighted maximum likelihood of samples
- * x [count][d] with weights w [count], device float64) into the flow's gradient buffer;
- * *dev_loss (device, may be NULL) receives L.  Asynchronous; deterministic. */
-qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, const double *dev_x, const double *dev_w,
-                             int64_t count, double w_sum, void *dev_scratch, size_t scratch_bytes,
-                             void *stream, double *dev_loss);
+/* Gradient of L = -(1/w_sum) sum_i w_i log q(x_i | c_i) (weighted maximum likelihood of
+ * samples x [count][d] with weights w [count] and conditioning features cond
+ * [count][n_cond] or NULL, device float64) into the flow's gradient buffer; *dev_loss
+ * (device, may be NULL) receives L.  Asynchronous; deterministic. */
+qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, int32_t n_cond, const double *dev_x,
+                             const double *dev_w, const double *dev_cond, int64_t count,
+                             double w_sum, void *dev_scratch, size_t scratch_bytes, void *stream,
+                             double *dev_loss);
 
 /* One Adam update of the parameters from the gradient buffer; repacks the operands. */
-qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, const qmc_flow_adam *opt, void *stream);
+qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, int32_t n_cond, const qmc_flow_adam *opt,
+                              void *stream);
 
 /* Training: `epochs` passes over `batches` strided minibatches (batch b: samples
  * b, b + batches, ...), one gradient and one Adam step each (steps numbered from
  * opt->step).  w_sum: sum of all weights.  dev_loss_history (device, may be NULL) gets
- * each step's loss.  Scratch: qmc_flow_scratch_bytes(d, count / batches).  Asynchronous. */
-qmc_status qmc_flow_train(void *dev_flow, int32_t d, const double *dev_x, const double *dev_w,
-                          int64_t count, double w_sum, const qmc_flow_adam *opt, int32_t batches,
-                          int32_t epochs, void *dev_scratch, size_t scratch_bytes, void *stream,
+ * each step's loss.  Scratch: qmc_flow_scratch_bytes(d, n_cond, count / batches).
+ * Asynchronous. */
+qmc_status qmc_flow_train(void *dev_flow, int32_t d, int32_t n_cond, const double *dev_x,
+                          const double *dev_w, const double *dev_cond, int64_t count, double w_sum,
+                          const qmc_flow_adam *opt, int32_t batches, int32_t epochs,
+                          void *dev_scratch, size_t scratch_bytes, void *stream,
                           double *dev_loss_history);
 
-/* Training samples of a sector of a real plan: for the points i < n of the Korobov
- * lattice (n, a) with the plan's shift `shift`, dev_x[i][j] = phi(y_i)_j (the sector's
- * periodizing transform) and dev_w[i] = W(y_i) ||(f_k(x_i))_k||_2, the weight for which
- * the optimal model density is proportional to the root of the summed squares of the
- * orders (0 where W = 0 or f is not finite).  Asynchronous. */
+/* Training samples of a sector: for the points i < n of the Korobov lattice (n, a) with
+ * the plan's shift `shift`, dev_x[i][j] = phi(y_i)_j (the sector's periodizing transform)
+ * and dev_w[i] = W(y_i) ||(f_k(x_i))_k||_2, the weight for which the optimal model
+ * density is proportional to the root of the summed squares of the orders (0 where
+ * W = 0 or f is not finite).  In a complex plan f is the deformed-contour integrand
+ * J f(z(x)) and the norm runs over the real and imaginary parts of every order.
+ * Asynchronous. */
 qmc_status qmc_flow_samples(qmc_plan_t plan, int32_t sector, uint64_t n, uint64_t a, int32_t shift,
                             void *stream, double *dev_x, double *dev_w);
 
-/* Integrate `sector` of a real plan through the flow: per lattice sample y,
- * u = phi(y) with weight W, x = T(u), contribution W J_T(u) f(x) (0 when a coordinate of
- * u or x is not inside (0, 1)).  dev_flow NULL detaches.  The flow buffer must stay
+/* Integrate `sector` through the flow: per lattice sample y, u = phi(y) with weight W,
+ * x = T(u | cond), contribution W J_T(u) f(x) (0 when a coordinate of u or x is not
+ * inside (0, 1)); in a complex plan f is the deformed-contour integrand (FP64) and the
+ * sign check counts as without a flow.  cond: host [n_cond] conditioning features of
+ * this sector (NULL when n_cond = 0).  dev_flow NULL detaches.  The flow buffer must stay
  * valid while attached.  Synchronous. */
-qmc_status qmc_flow_attach(qmc_plan_t plan, int32_t sector, const void *dev_flow, void *stream);
+qmc_status qmc_flow_attach(qmc_plan_t plan, int32_t sector, const void *dev_flow, int32_t n_cond,
+                           const double *cond, void *stream);
 
 /*
  * qmc_coef_series -- a coefficient of a weighted sum given as an arithmetic expression

@@ -149,13 +149,20 @@ class Plan:
                "qmc_flow_samples")
         return x, w
 
-    def attach_flow(self, sector: int, flow, stream=None):
-        """Integrate `sector` through `flow` (a paper_2305_19768_amd.flow.Flow), or detach
+    def attach_flow(self, sector: int, flow, cond=None, stream=None):
+        """Integrate `sector` through `flow` (a paper_2305_19768_amd.flow.Flow; for a
+        conditional flow, cond holds the sector's n_cond conditioning features), or detach
         with None.  The plan keeps a reference to the flow while attached."""
         if not hasattr(self, "_flows"):
             self._flows = {}
         ptr = None if flow is None else ctypes.c_void_p(flow.ptr)
-        _check(lib().qmc_flow_attach(self._h, int(sector), ptr, _stream_ptr(stream)),
+        nc = 0 if flow is None else flow.n_cond
+        cv = np.ascontiguousarray([] if cond is None else cond, dtype=np.float64).reshape(-1)
+        if flow is not None and cv.size != nc:
+            raise ValueError(f"flow takes {nc} conditioning features, got {cv.size}")
+        _check(lib().qmc_flow_attach(self._h, int(sector), ptr, nc,
+                                     cv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                     if nc else None, _stream_ptr(stream)),
                "qmc_flow_attach")
         if flow is None:
             self._flows.pop(int(sector), None)

@@ -243,9 +243,9 @@ template <int D, int K, int S, bool F32>
 __device__ __forceinline__ void run_item(const LaunchArgs &a, int s, int l_begin, int T,
                                          int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
   if (F32 && (a.sectors[s].flags & SF_F32OK))
-    integrate_block<D, K, S, true, true>(a, s, l_begin, T, chunk_id, red);
+    integrate_block<D, K, S, true, true, false>(a, s, l_begin, T, chunk_id, red);
   else
-    integrate_block<D, K, S, true, false>(a, s, l_begin, T, chunk_id, red);
+    integrate_block<D, K, S, true, false, false>(a, s, l_begin, T, chunk_id, red);
 }
 
 // The work item is the same for every lane; make that explicit so that the sector's

@@ -229,9 +229,10 @@ static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t
 }
 
 // 0: generic path, 1: fast path in FP64, 2: fast path in FP32, 3: deformed (complex plan),
-// 4: attached flow transform, 5: deformed with the FP32 polynomial bulk.
+// 4: attached flow transform, 5: deformed with the FP32 polynomial bulk, 6: deformed with
+// an attached flow transform.
 static int path_class(const qmc_plan_s *p, int s) {
-  if (p->cplx) return (p->sec[s].flags & SF_CF32) ? 5 : 3;
+  if (p->cplx) return p->sec[s].flow ? 6 : (p->sec[s].flags & SF_CF32) ? 5 : 3;
   if (p->sec[s].flow) return 4;
   const int f = p->sec[s].flags;
   if (!(f & SF_FAST)) return 0;
@@ -591,7 +592,8 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     p->begin[t] = b;
     const int cls = path_class(p, s);
     const int fast = (cls == 1 || cls == 2) ? 1 : 0, f32 = (cls == 2 || cls == 5) ? 1 : 0;
-    const int deform = (cls == 3 || cls == 5) ? 1 : 0, flow = cls == 4 ? 1 : 0;
+    const int deform = (cls == 3 || cls == 5 || cls == 6) ? 1 : 0;
+    const int flow = (cls == 4 || cls == 6) ? 1 : 0;
     if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
         dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].deform != deform || dl[n_dl - 1].flow != flow) {
       if (n_dl == 4 * QMC_MAX_DIM) return fail(QMC_E_STATE, "too many launch classes");

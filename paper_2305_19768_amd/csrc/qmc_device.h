@@ -695,7 +695,9 @@ constexpr int kFold = 8;
 // registers.  Each accumulator is a plain partial over at most kFold points folded
 // into a (sum, compensation) pair.  After each pass the pairs are reduced over the
 // wavefront and staged in LDS.
-template <int D, int K, int S, bool FAST, bool F32>
+// REGCONST: hold the korobov_3 coefficients in registers for the whole block (fewer
+// instructions per point; the persistent kernel, tighter on registers, uses literals).
+template <int D, int K, int S, bool FAST, bool F32, bool REGCONST = true>
 __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int l_begin, int tile,
                                                 int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
   const SectorDev *__restrict__ sd = a.sectors + s;
@@ -715,7 +717,8 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
   // every lane runs the same number of iterations; lanes past i_end contribute 0
   const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
 
-  const KorobovConsts kc = korobov3_consts();
+  KorobovConsts kc{35.0, -84.0, 70.0, -20.0};
+  if constexpr (REGCONST) kc = korobov3_consts();
   // lattice state of this thread at its first point i0: k_j = i0 z_j mod n
   double k0[D];
   const uint64_t i0 = i_begin + threadIdx.x;

@@ -17,159 +17,178 @@ void plan_reorder(qmc_plan_s *p);
 }  // namespace qmc
 
 static bool dim_ok(int32_t d) { return d >= 1 && d <= QMC_MAX_DIM; }
+static bool shape_ok(int32_t d, int32_t c) {
+  return dim_ok(d) && c >= 0 && c <= kFlowMaxCond && d + c <= kFlowIn;
+}
+#define CHECK_SHAPE(d, c)                                                                     \
+  if (!shape_ok(d, c))                                                                        \
+    return fail(QMC_E_INVAL, "flow shape d = %d, n_cond = %d outside d in [1, %d], n_cond in " \
+                             "[0, %d]", d, c, QMC_MAX_DIM, kFlowMaxCond);
 
 extern "C" {
 
-int64_t qmc_flow_param_count(int32_t d) { return dim_ok(d) ? flow_params(d) : -1; }
+int64_t qmc_flow_param_count(int32_t d, int32_t n_cond) {
+  return shape_ok(d, n_cond) ? flow_params(d, n_cond) : -1;
+}
 
-size_t qmc_flow_bytes(int32_t d) { return dim_ok(d) ? (size_t)flow_total_bytes(d) : 0; }
+size_t qmc_flow_bytes(int32_t d, int32_t n_cond) {
+  return shape_ok(d, n_cond) ? (size_t)flow_total_bytes(d, n_cond) : 0;
+}
 
-qmc_status qmc_flow_load(void *dev_flow, int32_t d, const float *params, void *stream) {
+qmc_status qmc_flow_load(void *dev_flow, int32_t d, int32_t c, const float *params, void *stream) {
   g_last_error.clear();
   if (!dev_flow || !params) return fail(QMC_E_INVAL, "NULL argument");
-  if (!dim_ok(d)) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  CHECK_SHAPE(d, c);
   if (((uintptr_t)dev_flow & 255) != 0) return fail(QMC_E_INVAL, "flow buffer not 256-byte aligned");
-  const int64_t P = flow_params(d);
+  const int64_t P = flow_params(d, c);
   for (int64_t k = 0; k < P; ++k)
     if (!std::isfinite(params[k])) return fail(QMC_E_INVAL, "parameter %lld not finite", (long long)k);
   hipStream_t st = (hipStream_t)stream;
   FlowHeader h;
   std::memset(&h, 0, sizeof h);
   h.d = d;
+  h.n_cond = c;
   char *f = (char *)dev_flow;
   int e;
   if ((e = hipMemcpyAsync(f, &h, sizeof h, hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "upload flow header");
-  if ((e = hipMemcpyAsync(f + flow_off_params(d), params, sizeof(float) * P,
+  if ((e = hipMemcpyAsync(f + flow_off_params(d, c), params, sizeof(float) * P,
                           hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "upload flow parameters");
   // Adam moments and gradient: zero with a fill kernel (capturable, no memset nodes)
-  if ((e = launch_flow_clear((float *)(f + flow_off_m(d)),
-                             (flow_off_pack(d) - flow_off_m(d)) / 4, stream)) != hipSuccess)
+  if ((e = launch_flow_clear((float *)(f + flow_off_m(d, c)),
+                             (flow_off_pack(d, c) - flow_off_m(d, c)) / 4, stream)) != hipSuccess)
     return hip_fail(e, "clear flow state");
-  if ((e = launch_flow_pack(dev_flow, d, stream)) != hipSuccess) return hip_fail(e, "pack flow");
+  if ((e = launch_flow_pack(dev_flow, d, c, stream)) != hipSuccess) return hip_fail(e, "pack flow");
   // the header copy reads a stack object: finish before returning
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
   return QMC_OK;
 }
 
-qmc_status qmc_flow_read(const void *dev_flow, int32_t d, float *params, float *grad,
+qmc_status qmc_flow_read(const void *dev_flow, int32_t d, int32_t c, float *params, float *grad,
                          void *stream) {
   g_last_error.clear();
   if (!dev_flow) return fail(QMC_E_INVAL, "NULL flow");
-  if (!dim_ok(d)) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  CHECK_SHAPE(d, c);
   hipStream_t st = (hipStream_t)stream;
-  const int64_t P = flow_params(d);
+  const int64_t P = flow_params(d, c);
   const char *f = (const char *)dev_flow;
   int e;
-  if (params && (e = hipMemcpyAsync(params, f + flow_off_params(d), sizeof(float) * P,
+  if (params && (e = hipMemcpyAsync(params, f + flow_off_params(d, c), sizeof(float) * P,
                                     hipMemcpyDeviceToHost, st)) != hipSuccess)
     return hip_fail(e, "read flow parameters");
-  if (grad && (e = hipMemcpyAsync(grad, f + flow_off_grad(d), sizeof(float) * P,
+  if (grad && (e = hipMemcpyAsync(grad, f + flow_off_grad(d, c), sizeof(float) * P,
                                   hipMemcpyDeviceToHost, st)) != hipSuccess)
     return hip_fail(e, "read flow gradient");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
   return QMC_OK;
 }
 
-qmc_status qmc_flow_transform(const void *dev_flow, int32_t d, int32_t direction,
-                              const double *dev_in, int64_t count, void *stream,
-                              double *dev_out, double *dev_logdet) {
+qmc_status qmc_flow_transform(const void *dev_flow, int32_t d, int32_t c, int32_t direction,
+                              const double *dev_in, const double *dev_cond, int64_t count,
+                              void *stream, double *dev_out, double *dev_logdet) {
   g_last_error.clear();
-  if (!dev_flow || (count > 0 && (!dev_in || !dev_out || !dev_logdet)))
+  if (!dev_flow || (count > 0 && (!dev_in || !dev_out || !dev_logdet || (c > 0 && !dev_cond))))
     return fail(QMC_E_INVAL, "NULL argument");
-  if (!dim_ok(d)) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  CHECK_SHAPE(d, c);
   if (direction != QMC_FLOW_SAMPLE && direction != QMC_FLOW_DENSITY)
     return fail(QMC_E_INVAL, "unknown direction %d", direction);
   if (count < 0) return fail(QMC_E_INVAL, "count < 0");
-  int e = launch_flow_transform(dev_flow, d, dev_in, count, dev_out, dev_logdet,
+  int e = launch_flow_transform(dev_flow, d, c, dev_in, dev_cond, count, dev_out, dev_logdet,
                                 direction == QMC_FLOW_SAMPLE ? 0 : 1, stream);
   if (e != hipSuccess) return hip_fail(e, "flow transform launch");
   return QMC_OK;
 }
 
-size_t qmc_flow_scratch_bytes(int32_t d, int64_t count) {
-  if (!dim_ok(d) || count < 1) return 0;
+size_t qmc_flow_scratch_bytes(int32_t d, int32_t c, int64_t count) {
+  if (!shape_ok(d, c) || count < 1) return 0;
   const int64_t waves = flow_grad_waves(count);
   return align256(sizeof(double) * 8 * kFlowLayers * (size_t)count) +
-         align256(sizeof(float) * (size_t)waves * flow_params(d)) +
+         align256(sizeof(float) * (size_t)waves * flow_params(d, c)) +
          align256(sizeof(double) * (size_t)waves) + 256;
 }
 
 // gradient of L = -(1 / w_sum) sum_i w_i log q(x_i) over samples offset + i * stride
-static qmc_status flow_gradient(void *dev_flow, int32_t d, const double *x, const double *w,
-                                int64_t count, int64_t offset, int64_t stride, double w_sum,
-                                void *scratch, size_t bytes, void *stream, double *dev_loss) {
-  if (bytes < qmc_flow_scratch_bytes(d, count))
+static qmc_status flow_gradient(void *dev_flow, int32_t d, int32_t c, const double *x,
+                                const double *w, const double *cond, int64_t count,
+                                int64_t offset, int64_t stride, double w_sum, void *scratch,
+                                size_t bytes, void *stream, double *dev_loss) {
+  if (bytes < qmc_flow_scratch_bytes(d, c, count))
     return fail(QMC_E_NOMEM, "scratch of %zu bytes, %zu needed", bytes,
-                qmc_flow_scratch_bytes(d, count));
+                qmc_flow_scratch_bytes(d, c, count));
   char *s = (char *)scratch;
   const int64_t waves = flow_grad_waves(count);
   double *zs = (double *)s;
   float *gpart = (float *)(s + align256(sizeof(double) * 8 * kFlowLayers * (size_t)count));
-  double *lpart = (double *)((char *)gpart + align256(sizeof(float) * (size_t)waves * flow_params(d)));
-  int e = launch_flow_grad(dev_flow, d, x, w, count, offset, stride, 1.0 / w_sum, zs, gpart,
-                           lpart, dev_loss, stream);
+  double *lpart =
+      (double *)((char *)gpart + align256(sizeof(float) * (size_t)waves * flow_params(d, c)));
+  int e = launch_flow_grad(dev_flow, d, c, x, w, cond, count, offset, stride, 1.0 / w_sum, zs,
+                           gpart, lpart, dev_loss, stream);
   if (e != hipSuccess) return hip_fail(e, "flow gradient launch");
   return QMC_OK;
 }
 
-qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, const double *dev_x, const double *dev_w,
-                             int64_t count, double w_sum, void *dev_scratch, size_t scratch_bytes,
-                             void *stream, double *dev_loss) {
+qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, int32_t c, const double *dev_x,
+                             const double *dev_w, const double *dev_cond, int64_t count,
+                             double w_sum, void *dev_scratch, size_t scratch_bytes, void *stream,
+                             double *dev_loss) {
   g_last_error.clear();
-  if (!dev_flow || !dev_x || !dev_w || !dev_scratch) return fail(QMC_E_INVAL, "NULL argument");
-  if (!dim_ok(d)) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  if (!dev_flow || !dev_x || !dev_w || !dev_scratch || (c > 0 && !dev_cond))
+    return fail(QMC_E_INVAL, "NULL argument");
+  CHECK_SHAPE(d, c);
   if (count < 1) return fail(QMC_E_INVAL, "count must be >= 1");
   if (!(w_sum > 0.0) || !std::isfinite(w_sum)) return fail(QMC_E_INVAL, "w_sum must be > 0");
-  return flow_gradient(dev_flow, d, dev_x, dev_w, count, 0, 1, w_sum, dev_scratch, scratch_bytes,
-                       stream, dev_loss);
+  return flow_gradient(dev_flow, d, c, dev_x, dev_w, dev_cond, count, 0, 1, w_sum, dev_scratch,
+                       scratch_bytes, stream, dev_loss);
 }
 
-qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, const qmc_flow_adam *opt, void *stream) {
+qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, int32_t c, const qmc_flow_adam *opt,
+                              void *stream) {
   g_last_error.clear();
   if (!dev_flow || !opt) return fail(QMC_E_INVAL, "NULL argument");
-  if (!dim_ok(d)) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  CHECK_SHAPE(d, c);
   if (!(opt->lr > 0.0f) || !(opt->beta1 >= 0.0f && opt->beta1 < 1.0f) ||
       !(opt->beta2 >= 0.0f && opt->beta2 < 1.0f) || !(opt->eps > 0.0f))
     return fail(QMC_E_INVAL, "Adam parameters out of range");
   if (opt->step < 1) return fail(QMC_E_INVAL, "step must be >= 1");
   const float c1 = 1.0f - std::pow(opt->beta1, (float)opt->step);
   const float c2 = 1.0f - std::pow(opt->beta2, (float)opt->step);
-  int e = launch_flow_adam(dev_flow, d, opt->lr, opt->beta1, opt->beta2, opt->eps, c1, c2, stream);
+  int e = launch_flow_adam(dev_flow, d, c, opt->lr, opt->beta1, opt->beta2, opt->eps, c1, c2,
+                           stream);
   if (e != hipSuccess) return hip_fail(e, "Adam launch");
   return QMC_OK;
 }
 
-qmc_status qmc_flow_train(void *dev_flow, int32_t d, const double *dev_x, const double *dev_w,
-                          int64_t count, double w_sum, const qmc_flow_adam *opt, int32_t batches,
-                          int32_t epochs, void *dev_scratch, size_t scratch_bytes, void *stream,
+qmc_status qmc_flow_train(void *dev_flow, int32_t d, int32_t c, const double *dev_x,
+                          const double *dev_w, const double *dev_cond, int64_t count, double w_sum,
+                          const qmc_flow_adam *opt, int32_t batches, int32_t epochs,
+                          void *dev_scratch, size_t scratch_bytes, void *stream,
                           double *dev_loss_history) {
   g_last_error.clear();
-  if (!dev_flow || !dev_x || !dev_w || !dev_scratch || !opt)
+  if (!dev_flow || !dev_x || !dev_w || !dev_scratch || !opt || (c > 0 && !dev_cond))
     return fail(QMC_E_INVAL, "NULL argument");
-  if (!dim_ok(d)) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  CHECK_SHAPE(d, c);
   if (batches < 1 || epochs < 1 || count < batches)
     return fail(QMC_E_INVAL, "need 1 <= batches <= count and epochs >= 1");
   if (!(w_sum > 0.0) || !std::isfinite(w_sum)) return fail(QMC_E_INVAL, "w_sum must be > 0");
   // batch b holds samples b, b + batches, b + 2 batches, ...: lattice points in index
   // order fill the cube in slabs, so strided batches are spread over the whole cube
   const int64_t per = count / batches;
-  if (scratch_bytes < qmc_flow_scratch_bytes(d, per))
+  if (scratch_bytes < qmc_flow_scratch_bytes(d, c, per))
     return fail(QMC_E_NOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes,
-                qmc_flow_scratch_bytes(d, per));
+                qmc_flow_scratch_bytes(d, c, per));
   qmc_flow_adam a = *opt;
   int64_t t = 0;
   for (int32_t ep = 0; ep < epochs; ++ep)
     for (int32_t b = 0; b < batches; ++b, ++t) {
       // the batch's weights are normalised by the share of the total it should carry
       const double wsum_b = w_sum * (double)per / (double)count;
-      qmc_status st = flow_gradient(dev_flow, d, dev_x, dev_w, per, b, batches, wsum_b,
-                                    dev_scratch, scratch_bytes, stream,
+      qmc_status st = flow_gradient(dev_flow, d, c, dev_x, dev_w, dev_cond, per, b, batches,
+                                    wsum_b, dev_scratch, scratch_bytes, stream,
                                     dev_loss_history ? dev_loss_history + t : nullptr);
       if (st != QMC_OK) return st;
       a.step = opt->step + (int32_t)t;
-      if ((st = qmc_flow_adam_step(dev_flow, d, &a, stream)) != QMC_OK) return st;
+      if ((st = qmc_flow_adam_step(dev_flow, d, c, &a, stream)) != QMC_OK) return st;
     }
   return QMC_OK;
 }
@@ -179,7 +198,6 @@ qmc_status qmc_flow_samples(qmc_plan_t p, int32_t sector, uint64_t n, uint64_t a
   g_last_error.clear();
   if (!p || !dev_x || !dev_w) return fail(QMC_E_INVAL, "NULL argument");
   if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
-  if (p->cplx) return fail(QMC_E_INVAL, "flow transforms need a real plan");
   if (sector < 0 || sector >= p->S) return fail(QMC_E_INVAL, "sector %d out of range", sector);
   if (shift < 0 || shift >= p->m) return fail(QMC_E_INVAL, "shift %d out of range", shift);
   if (n < 2 || n >= (1ull << 53)) return fail(QMC_E_INVAL, "n outside [2, 2^53)");
@@ -200,6 +218,7 @@ qmc_status qmc_flow_samples(qmc_plan_t p, int32_t sector, uint64_t n, uint64_t a
   for (int j = 0; j < d; ++j)
     fa.shift[j] = p->shifts[((size_t)sector * p->m + shift) * QMC_MAX_DIM + j];
   fa.K = p->K;
+  fa.cplx = p->cplx;
   fa.x = dev_x;
   fa.w = dev_w;
   int e = launch_flow_samples(fa, d, stream);
@@ -207,15 +226,32 @@ qmc_status qmc_flow_samples(qmc_plan_t p, int32_t sector, uint64_t n, uint64_t a
   return QMC_OK;
 }
 
-qmc_status qmc_flow_attach(qmc_plan_t p, int32_t sector, const void *dev_flow, void *stream) {
+qmc_status qmc_flow_attach(qmc_plan_t p, int32_t sector, const void *dev_flow, int32_t n_cond,
+                           const double *cond, void *stream) {
   g_last_error.clear();
   if (!p) return fail(QMC_E_INVAL, "NULL plan");
   if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
-  if (p->cplx) return fail(QMC_E_INVAL, "flow transforms need a real plan");
   if (sector < 0 || sector >= p->S) return fail(QMC_E_INVAL, "sector %d out of range", sector);
   if (dev_flow && ((uintptr_t)dev_flow & 255) != 0)
     return fail(QMC_E_INVAL, "flow buffer not 256-byte aligned");
-  p->sec[sector].flow = (uint64_t)(uintptr_t)dev_flow;
+  if (dev_flow) {
+    CHECK_SHAPE(p->dims[sector], n_cond);
+    if (n_cond > 0 && !cond) return fail(QMC_E_INVAL, "NULL conditioning features");
+    for (int32_t k = 0; k < n_cond; ++k)
+      if (!std::isfinite(cond[k])) return fail(QMC_E_INVAL, "conditioning feature %d not finite", k);
+    // the kernels locate the operands from (d, n_cond): they must be the flow's own
+    FlowHeader h;
+    int e0 = hipMemcpyAsync(&h, dev_flow, sizeof h, hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e0 == hipSuccess) e0 = hipStreamSynchronize((hipStream_t)stream);
+    if (e0 != hipSuccess) return hip_fail(e0, "read flow header");
+    if (h.d != p->dims[sector] || h.n_cond != n_cond)
+      return fail(QMC_E_INVAL, "flow of shape (d = %d, n_cond = %d) attached as (%d, %d)", h.d,
+                  h.n_cond, p->dims[sector], n_cond);
+  }
+  SectorDev &sd = p->sec[sector];
+  sd.flow = (uint64_t)(uintptr_t)dev_flow;
+  sd.flow_cond = dev_flow ? n_cond : 0;
+  for (int k = 0; k < kFlowMaxCond; ++k) sd.cond[k] = (dev_flow && k < n_cond) ? cond[k] : 0.0;
   plan_reorder(p);
   hipStream_t st = (hipStream_t)stream;
   int e;

@@ -11,25 +11,29 @@ namespace qmc {
 
 constexpr int kFlowLayers = QMC_FLOW_LAYERS;   // affine coupling layers
 constexpr int kFlowHidden = QMC_FLOW_HIDDEN;   // hidden width of each layer's network
-constexpr int kFlowIn = 16;                    // network input, padded (d <= 8 used)
+constexpr int kFlowIn = 16;                    // network input, padded (d + n_cond <= 16)
 constexpr int kFlowOut = 16;                   // network output rows: s (d), t (d), zero rest
+constexpr int kFlowMaxCond = QMC_FLOW_MAX_COND;
 
-// Parameters of one coupling layer in the natural layout (float32):
-//   W1 [64][d], b1 [64], W2 [64][64], b2 [64], W3 [2d][64], b3 [2d]
-__host__ __device__ constexpr int64_t flow_layer_params(int d) {
-  return (int64_t)kFlowHidden * d + kFlowHidden + kFlowHidden * kFlowHidden + kFlowHidden +
+// Parameters of one coupling layer in the natural layout (float32), for d coordinates
+// and c conditioning features (network input width d + c):
+//   W1 [64][d + c], b1 [64], W2 [64][64], b2 [64], W3 [2d][64], b3 [2d]
+__host__ __device__ constexpr int64_t flow_layer_params(int d, int c) {
+  return (int64_t)kFlowHidden * (d + c) + kFlowHidden + kFlowHidden * kFlowHidden + kFlowHidden +
          2 * d * kFlowHidden + 2 * d;
 }
-__host__ __device__ constexpr int64_t flow_params(int d) { return kFlowLayers * flow_layer_params(d); }
+__host__ __device__ constexpr int64_t flow_params(int d, int c) {
+  return kFlowLayers * flow_layer_params(d, c);
+}
 
 // Offsets (in floats) of the blocks of layer l's parameters.
 struct FlowParamOffsets {
   int64_t W1, b1, W2, b2, W3, b3;
 };
-__host__ __device__ inline FlowParamOffsets flow_offsets(int d, int l) {
+__host__ __device__ inline FlowParamOffsets flow_offsets(int d, int c, int l) {
   FlowParamOffsets o;
-  o.W1 = (int64_t)l * flow_layer_params(d);
-  o.b1 = o.W1 + (int64_t)kFlowHidden * d;
+  o.W1 = (int64_t)l * flow_layer_params(d, c);
+  o.b1 = o.W1 + (int64_t)kFlowHidden * (d + c);
   o.W2 = o.b1 + kFlowHidden;
   o.b2 = o.W2 + kFlowHidden * kFlowHidden;
   o.W3 = o.b2 + kFlowHidden;
@@ -56,32 +60,37 @@ __host__ __device__ constexpr int flow_perm(int ks, int slot) {
   return 32 * ks + ((slot & 7) < 4 ? 4 * (slot >> 3) + (slot & 7) : 16 + 4 * (slot >> 3) + (slot & 7) - 4);
 }
 
-// Device state of one flow (caller-owned buffer of qmc_flow_bytes(d) bytes).
+// Device state of one flow (caller-owned buffer of qmc_flow_bytes(d, c) bytes).
 struct FlowHeader {
-  int32_t d, step;   // dimension, Adam steps taken
-  int32_t pad[62];
+  int32_t d, step, n_cond;   // dimension, Adam steps taken, conditioning features
+  int32_t pad[61];
 };
-__host__ __device__ inline int64_t flow_off_params(int) { return 256; }
-__host__ __device__ inline int64_t flow_off_m(int d) { return 256 + 4 * ((flow_params(d) + 63) / 64 * 64); }
-__host__ __device__ inline int64_t flow_off_v(int d) { return flow_off_m(d) + 4 * ((flow_params(d) + 63) / 64 * 64); }
-__host__ __device__ inline int64_t flow_off_grad(int d) { return flow_off_v(d) + 4 * ((flow_params(d) + 63) / 64 * 64); }
-__host__ __device__ inline int64_t flow_off_pack(int d) { return flow_off_grad(d) + 4 * ((flow_params(d) + 63) / 64 * 64); }
-__host__ __device__ inline int64_t flow_total_bytes(int d) {
-  return flow_off_pack(d) + 2 * (int64_t)kFlowLayers * kPackLayer;
+__host__ __device__ inline int64_t flow_padded(int d, int c) {
+  return 4 * ((flow_params(d, c) + 63) / 64 * 64);
+}
+__host__ __device__ inline int64_t flow_off_params(int, int) { return 256; }
+__host__ __device__ inline int64_t flow_off_m(int d, int c) { return 256 + flow_padded(d, c); }
+__host__ __device__ inline int64_t flow_off_v(int d, int c) { return flow_off_m(d, c) + flow_padded(d, c); }
+__host__ __device__ inline int64_t flow_off_grad(int d, int c) { return flow_off_v(d, c) + flow_padded(d, c); }
+__host__ __device__ inline int64_t flow_off_pack(int d, int c) { return flow_off_grad(d, c) + flow_padded(d, c); }
+__host__ __device__ inline int64_t flow_total_bytes(int d, int c) {
+  return flow_off_pack(d, c) + 2 * (int64_t)kFlowLayers * kPackLayer;
 }
 
-int launch_flow_pack(void *flow, int d, void *stream);
-int launch_flow_transform(const void *flow, int d, const double *u, int64_t count, double *x,
-                          double *logJ, int dir, void *stream);
+int launch_flow_pack(void *flow, int d, int c, void *stream);
+int launch_flow_transform(const void *flow, int d, int c, const double *u, const double *cond,
+                          int64_t count, double *x, double *logJ, int dir, void *stream);
 int flow_grad_waves(int64_t count);
-int launch_flow_grad(void *flow, int d, const double *x, const double *w, int64_t count,
-                     int64_t offset, int64_t stride, double inv_wsum, double *zs, float *gpart,
-                     double *lpart, double *loss, void *stream);
-int launch_flow_adam(void *flow, int d, float lr, float b1, float b2, float eps, float c1,
+int launch_flow_grad(void *flow, int d, int c, const double *x, const double *w,
+                     const double *cond, int64_t count, int64_t offset, int64_t stride,
+                     double inv_wsum, double *zs, float *gpart, double *lpart, double *loss,
+                     void *stream);
+int launch_flow_adam(void *flow, int d, int c, float lr, float b1, float b2, float eps, float c1,
                      float c2, void *stream);
 int launch_flow_clear(float *p, int64_t count, void *stream);
 
-// Training samples of one sector (see qmc_flow_samples).
+// Training samples of one sector (see qmc_flow_samples); on the deformed contour (cplx)
+// the weight is W |J f| over the orders of the complex integrand.
 struct FlowSampleArgs {
   const SectorDev *sd;
   const double *coef;
@@ -90,6 +99,7 @@ struct FlowSampleArgs {
   uint64_t z[QMC_MAX_DIM];
   double shift[QMC_MAX_DIM];
   int K;
+  int cplx;
   double *x, *w;
 };
 int launch_flow_samples(const FlowSampleArgs &fa, int d, void *stream);

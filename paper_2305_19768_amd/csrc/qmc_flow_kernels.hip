@@ -7,7 +7,8 @@
 // activations and s = 0.25 tanh(o_s).  The sampling direction replaces x = u after the
 // periodizing transform, x = T(u), with weight J_T(u) = 1 / q(x).  Training maximises
 // the weighted log-likelihood of QMC samples of the integrand (weights |W f|), which
-// needs no derivative of the integrand.
+// needs no derivative of the integrand.  A conditional flow appends c conditioning
+// features (kinematic invariants of the sector) to every network input: (m_l z, cond).
 //
 // Matrix-core mapping: the points of a wavefront are the N dimension of every product,
 // in four groups of 16 (bfloat16 16x16x16 and 16x16x32 products, float32 accumulation).
@@ -16,7 +17,7 @@
 // registers are exactly the B operand of the next product, so the network runs from
 // registers.  Only the network input and output pass through LDS, where each lane
 // hands its point's coordinates to the lanes that feed them to the matrix core.
-#include "qmc_device.h"
+#include "qmc_deform.h"
 #include "qmc_flow.h"
 
 namespace qmc {
@@ -60,11 +61,12 @@ struct FlowBias {
   float b1[kFlowHidden], b2[kFlowHidden], b3[kFlowOut];
 };
 
-__device__ __forceinline__ void stage_bias(const char *flow, int d, FlowBias *sb, int tid, int nt) {
-  const float *P = (const float *)(flow + flow_off_params(d));
+__device__ __forceinline__ void stage_bias(const char *flow, int d, int c, FlowBias *sb, int tid,
+                                           int nt) {
+  const float *P = (const float *)(flow + flow_off_params(d, c));
   for (int e = tid; e < kFlowLayers * (2 * kFlowHidden + kFlowOut); e += nt) {
     const int l = e / (2 * kFlowHidden + kFlowOut), r = e % (2 * kFlowHidden + kFlowOut);
-    const FlowParamOffsets o = flow_offsets(d, l);
+    const FlowParamOffsets o = flow_offsets(d, c, l);
     float v;
     if (r < kFlowHidden) v = P[o.b1 + r];
     else if (r < 2 * kFlowHidden) v = P[o.b2 + r - kFlowHidden];
@@ -158,15 +160,26 @@ __device__ __forceinline__ bool conditioning(int j, int l) { return (j & 1) == (
 
 // One coupling layer applied to the lane's point (z in logit space, d coordinates),
 // all lanes of the workgroup together.  dir 0: sampling (inverse affine), 1: density.
+// Network input of layer l for the lane's point: the kept coordinates, then the c
+// conditioning features, zero elsewhere.
 template <int DMAX>
-__device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBias &bs,
-                                         FlowXchg &xc, int d, int l, int dir, int lane,
-                                         double (&z)[DMAX], double &ssum) {
+__device__ __forceinline__ void put_input(unsigned short *zin, const double (&z)[DMAX], int d, int c,
+                                          const float (&cond)[kFlowMaxCond], int l) {
 #pragma unroll
   for (int j = 0; j < kFlowIn; ++j) {
-    const bool use = j < d && j < DMAX && conditioning(j, l);
-    xc.zin[lane * kFlowIn + j] = use ? bf_bits((float)z[j < DMAX ? j : 0]) : (unsigned short)0;
+    unsigned short v = 0;
+    if (j < d && j < DMAX && conditioning(j, l)) v = bf_bits((float)z[j < DMAX ? j : 0]);
+    else if (j >= d && j < d + c) v = bf_bits(cond[(j - d) & (kFlowMaxCond - 1)]);
+    zin[j] = v;
   }
+}
+
+template <int DMAX>
+__device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBias &bs,
+                                         FlowXchg &xc, int d, int c, const float (&cond)[kFlowMaxCond],
+                                         int l, int dir, int lane, double (&z)[DMAX],
+                                         double &ssum) {
+  put_input<DMAX>(xc.zin + lane * kFlowIn, z, d, c, cond, l);
   __syncthreads();
   v4f o[4];
   flow_mlp<false>(pk, bs, xc.zin, lane, o, nullptr, nullptr);
@@ -189,17 +202,18 @@ __device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBia
 
 // ------------------------------------------------------------------- packing
 
-__global__ void flow_pack_kernel(char *flow, int d) {
+__global__ void flow_pack_kernel(char *flow, int d, int c) {
   const int l = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kPackLayer) return;
-  const float *P = (const float *)(flow + flow_off_params(d));
-  const FlowParamOffsets o = flow_offsets(d, l);
+  const float *P = (const float *)(flow + flow_off_params(d, c));
+  const FlowParamOffsets o = flow_offsets(d, c, l);
+  const int din = d + c;   // network inputs
   float v = 0.0f;
   if (e < kPackF2) {                      // W1: rows hidden, k = inputs
     const int rb = e / 256, lane = (e / 4) % 64, el = e % 4;
     const int row = 16 * rb + lane % 16, k = 4 * (lane / 16) + el;
-    v = k < d ? P[o.W1 + row * d + k] : 0.0f;
+    v = k < din ? P[o.W1 + row * din + k] : 0.0f;
   } else if (e < kPackF3) {               // W2: rows hidden, k = hidden (permuted)
     const int t = e - kPackF2, rb = t / 1024, ks = (t / 512) % 2, lane = (t / 8) % 64, j = t % 8;
     const int row = 16 * rb + lane % 16, slot = 8 * (lane / 16) + j;
@@ -219,27 +233,30 @@ __global__ void flow_pack_kernel(char *flow, int d) {
   } else {                                // W1^T: rows inputs, k = hidden (permuted)
     const int t = e - kPackB1, ks = t / 512, lane = (t / 8) % 64, j = t % 8;
     const int row = lane % 16, slot = 8 * (lane / 16) + j;
-    v = row < d ? P[o.W1 + flow_perm(ks, slot) * d + row] : 0.0f;
+    v = row < din ? P[o.W1 + flow_perm(ks, slot) * din + row] : 0.0f;
   }
-  ((unsigned short *)(flow + flow_off_pack(d)))[(int64_t)l * kPackLayer + e] = bf_bits(v);
+  ((unsigned short *)(flow + flow_off_pack(d, c)))[(int64_t)l * kPackLayer + e] = bf_bits(v);
 }
 
 // ----------------------------------------------------------- transform alone
 
 // dir 0: u -> x = T(u) and log J_T(u); dir 1: x -> u = G(x) and log q(x).  Points with a
 // coordinate outside (0, 1) give NaN outputs.
-__global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, int d,
-                                                             const double *in, int64_t count,
-                                                             double *out, double *logdet,
-                                                             int dir) {
+__global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, int d, int c,
+                                                             const double *in, const double *cond,
+                                                             int64_t count, double *out,
+                                                             double *logdet, int dir) {
   __shared__ FlowBias sb[kFlowLayers];
   __shared__ FlowXchg xc[4];
-  stage_bias(flow, d, sb, threadIdx.x, blockDim.x);
+  stage_bias(flow, d, c, sb, threadIdx.x, blockDim.x);
   __syncthreads();
-  const unsigned short *pk = (const unsigned short *)(flow + flow_off_pack(d));
+  const unsigned short *pk = (const unsigned short *)(flow + flow_off_pack(d, c));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = i < count;
+  float cf[kFlowMaxCond];
+#pragma unroll
+  for (int k = 0; k < kFlowMaxCond; ++k) cf[k] = (valid && k < c) ? (float)cond[i * c + k] : 0.0f;
   double z[8], a[8];
   double lsum = 0.0;
 #pragma unroll
@@ -251,7 +268,7 @@ __global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, i
   double ssum = 0.0;
   for (int step = 0; step < kFlowLayers; ++step) {
     const int l = dir == 0 ? kFlowLayers - 1 - step : step;
-    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], xc[wave], d, l, dir, lane, z, ssum);
+    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], xc[wave], d, c, cf, l, dir, lane, z, ssum);
   }
   double rsum = 0.0;
 #pragma unroll
@@ -274,8 +291,9 @@ __global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, i
 // scratch, summed over wavefronts in a fixed order by flow_reduce_kernel.
 struct FlowTrainArgs {
   char *flow;
-  int d;
+  int d, c;                // coordinates, conditioning features
   const double *x, *w;
+  const double *cond;      // [samples][c] or NULL
   int64_t count;     // points of this batch: sample index offset + i * stride
   int64_t offset, stride;
   double inv_wsum;
@@ -303,17 +321,17 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
   __shared__ FlowBias sb[kFlowLayers];
   __shared__ FlowXchg xc[4];
   __shared__ FlowBack bk[4];
-  const int d = a.d;
-  stage_bias(a.flow, d, sb, threadIdx.x, blockDim.x);
+  const int d = a.d, c = a.c, din = d + c;
+  stage_bias(a.flow, d, c, sb, threadIdx.x, blockDim.x);
   __syncthreads();
-  const unsigned short *pk = (const unsigned short *)(a.flow + flow_off_pack(d));
+  const unsigned short *pk = (const unsigned short *)(a.flow + flow_off_pack(d, c));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, g = lane >> 4;
   const int64_t gw = (int64_t)blockIdx.x * 4 + wave;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in_range = i < a.count;
   const int64_t gi = a.offset + i * a.stride;   // sample index
-  const int64_t P = flow_params(d);
+  const int64_t P = flow_params(d, c);
   FlowXchg &X = xc[wave];
   FlowBack &Bk = bk[wave];
   // a sample on (or rounded beyond) a face of the cube carries no weight
@@ -325,7 +343,10 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
     if (j < d) inside = inside && xs[j] > 0.0 && xs[j] < 1.0;
   }
   const bool valid = inside;
-  const double wi = valid ? a.w[gi] * a.inv_wsum : 0.0;
+  double wi = valid ? a.w[gi] * a.inv_wsum : 0.0;
+  float cf[kFlowMaxCond];
+#pragma unroll
+  for (int k = 0; k < kFlowMaxCond; ++k) cf[k] = (in_range && k < c) ? (float)a.cond[gi * c + k] : 0.0f;
 
   // forward, density direction
   double z[8];
@@ -341,16 +362,24 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
     if (valid)
 #pragma unroll
       for (int j = 0; j < 8; ++j) a.zs[((int64_t)l * a.count + i) * 8 + j] = z[j];
-    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], X, d, l, 1, lane, z, ssum);
+    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], X, d, c, cf, l, 1, lane, z, ssum);
   }
+  double uu[8];
+  bool u_in = true;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    uu[j] = 1.0 / (1.0 + exp(-z[j]));
+    if (j < d) u_in = u_in && uu[j] > 0.0 && uu[j] < 1.0;
+  }
+  // a sample whose image rounds onto a face of the cube carries no weight either
+  if (!u_in) wi = 0.0;
   double dz[8], lu = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double u = 1.0 / (1.0 + exp(-z[j]));
-    if (j < d) lu += log(u * (1.0 - u));
-    dz[j] = j < d ? -wi * (1.0 - 2.0 * u) : 0.0;   // d/dz of -w log(u (1 - u))
+    if (j < d && u_in) lu += log(uu[j] * (1.0 - uu[j]));
+    dz[j] = j < d ? -wi * (1.0 - 2.0 * uu[j]) : 0.0;   // d/dz of -w log(u (1 - u))
   }
-  double lq = valid ? -wi * (lu - lx + ssum) : 0.0;
+  double lq = (valid && u_in) ? -wi * (lu - lx + ssum) : 0.0;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) lq += __shfl_xor(lq, o, 64);
   if (lane == 0) a.lpart[gw] = lq;
@@ -359,15 +388,11 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
   const v4f zero = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int l = kFlowLayers - 1; l >= 0; --l) {
     const unsigned short *pl = pk + (int64_t)l * kPackLayer;
-    const FlowParamOffsets po = flow_offsets(d, l);
+    const FlowParamOffsets po = flow_offsets(d, c, l);
     double zl[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) zl[j] = valid ? a.zs[((int64_t)l * a.count + i) * 8 + j] : 0.0;
-#pragma unroll
-    for (int j = 0; j < kFlowIn; ++j) {
-      const bool use = j < d && conditioning(j, l);
-      X.zin[lane * kFlowIn + j] = use ? bf_bits((float)zl[j < 8 ? j : 0]) : (unsigned short)0;
-    }
+    put_input<8>(X.zin + lane * kFlowIn, zl, d, c, cf, l);
     __syncthreads();
     v4f o[4], h1[4][4], h2[4][4];
     flow_mlp<true>(pl, sb[l], X.zin, lane, o, h1, h2);
@@ -545,7 +570,7 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii)
-          if (p < d) G[po.W1 + (16 * r + 4 * g + ii) * d + p] = acc[r][ii];
+          if (p < din) G[po.W1 + (16 * r + 4 * g + ii) * din + p] = acc[r][ii];
       v8b Hb[4][2];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -576,11 +601,11 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
 }
 
 // grad[k] = sum over wavefronts of gpart[w][k] (fixed order); loss likewise.
-__global__ void flow_reduce_kernel(char *flow, int d, const float *gpart, const double *lpart,
-                                   int64_t waves, double *loss) {
-  const int64_t P = flow_params(d);
+__global__ void flow_reduce_kernel(char *flow, int d, int c, const float *gpart,
+                                   const double *lpart, int64_t waves, double *loss) {
+  const int64_t P = flow_params(d, c);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float *grad = (float *)(flow + flow_off_grad(d));
+  float *grad = (float *)(flow + flow_off_grad(d, c));
   if (k < P) {
     double s = 0.0;
     for (int64_t w = 0; w < waves; ++w) s += (double)gpart[w * P + k];
@@ -595,15 +620,15 @@ __global__ void flow_reduce_kernel(char *flow, int d, const float *gpart, const 
 
 // Adam (Kingma and Ba 2015) on the float32 master parameters; c1, c2 are the bias
 // corrections 1 - beta^t of this step.
-__global__ void flow_adam_kernel(char *flow, int d, float lr, float b1, float b2, float eps,
+__global__ void flow_adam_kernel(char *flow, int d, int c, float lr, float b1, float b2, float eps,
                                  float c1, float c2) {
-  const int64_t P = flow_params(d);
+  const int64_t P = flow_params(d, c);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
-  float *prm = (float *)(flow + flow_off_params(d));
-  float *m = (float *)(flow + flow_off_m(d));
-  float *v = (float *)(flow + flow_off_v(d));
-  const float gk = ((const float *)(flow + flow_off_grad(d)))[k];
+  float *prm = (float *)(flow + flow_off_params(d, c));
+  float *m = (float *)(flow + flow_off_m(d, c));
+  float *v = (float *)(flow + flow_off_v(d, c));
+  const float gk = ((const float *)(flow + flow_off_grad(d, c)))[k];
   const float mk = b1 * m[k] + (1.0f - b1) * gk;
   const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
   m[k] = mk;
@@ -629,13 +654,18 @@ struct FlowIntegrateLds {
 };
 
 // A workgroup's share of a sector with an attached flow: per sample y, u = phi(y) with
-// weight W (the sector's periodizing transform), x = T(u) and J_T(u) by the flow, then
-// the integrand at x; W J_T f accumulated as on the real contour.  A sample with a
-// coordinate of u or x outside (0, 1) contributes 0.
-template <int D>
+// weight W (the sector's periodizing transform), x = T(u | cond) and J_T(u) by the flow,
+// then the integrand at x; W J_T f accumulated as on the real contour.  A sample with a
+// coordinate of u or x outside (0, 1) contributes 0.  CPLX: the integrand is the
+// deformed-contour one, J f(z(x)) in FP64, accumulated as (re, im) columns, with the
+// sign check counted as on the contour without a flow.  All QMC_MAX_ORDERS orders are
+// formed (the tables are zero beyond the plan's); the first a.K columns are kept.
+template <int D, bool CPLX>
 __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_begin, int tile,
                                            int64_t chunk_id, double (*red)[kMaxTile * 4][2],
                                            FlowIntegrateLds &L) {
+  constexpr int NK = QMC_MAX_ORDERS;
+  constexpr int KC = CPLX ? 2 * NK : NK;
   const SectorDev *__restrict__ sd = a.sectors + s;
   const LatticeDev *__restrict__ lt = a.lat + s;
   const uint64_t n = lt->n;
@@ -647,7 +677,13 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
   const int kind = sd->transform;
   const double w_scale = sd->w_scale;
   const SectorScalars ss = load_scalars(sd);
-  const int K = a.K;
+  const int K = a.K;   // columns kept
+  const int fc = sd->flow_cond;
+  float cf[kFlowMaxCond];
+#pragma unroll
+  for (int k = 0; k < kFlowMaxCond; ++k) cf[k] = k < fc ? (float)sd->cond[k] : 0.0f;
+  const double lam = sd->lambda;
+  const int grad_off = sd->grad_off, hess_off = sd->hess_off;
   const uint64_t B = blockDim.x;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -656,12 +692,13 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
   const uint64_t i0 = i_begin + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < D; ++j) k0[j] = (double)mulmod(i0 % n, lt->z[j], n);
+  uint32_t viol = 0;
 
 #pragma unroll 1
   for (int l0 = 0; l0 < tile; ++l0) {
-    DD acc[QMC_MAX_ORDERS];
+    DD acc[KC];
 #pragma unroll
-    for (int c = 0; c < QMC_MAX_ORDERS; ++c) acc[c] = DD{0.0, 0.0};
+    for (int c = 0; c < KC; ++c) acc[c] = DD{0.0, 0.0};
     const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
     double k[D];
 #pragma unroll
@@ -692,7 +729,7 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
       double ssum = 0.0;
       for (int step = 0; step < kFlowLayers; ++step) {
         const int l = kFlowLayers - 1 - step;
-        coupling<D>(L.pack[l], L.bias[l], L.xc[wave], D, l, 0, lane, z, ssum);
+        coupling<D>(L.pack[l], L.bias[l], L.xc[wave], D, fc, cf, l, 0, lane, z, ssum);
       }
       double x[1][D], rsum = 0.0;
 #pragma unroll
@@ -703,25 +740,42 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
         rsum += log(x[0][j] * (1.0 - x[0][j]));
       }
       const double W = Wk * exp(rsum - lsum - ssum);
-      double f[1][QMC_MAX_ORDERS];
-      integrand<D, QMC_MAX_ORDERS, 1>(ss, (cptr<SectorDev>)sd, launder_after(cl, W), x, f);
       const bool use = (i < i_end) && inside && (W != 0.0);
+      if constexpr (CPLX) {
+        C2 f[NK];
+        const bool bad = integrand_deform<D, NK>(ss, (cptr<SectorDev>)sd, launder_after(cl, W),
+                                                 grad_off, hess_off, lam, x[0], f);
+        viol += (use && bad) ? 1u : 0u;
 #pragma unroll
-      for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) dd_add(acc[kk], use ? W * f[0][kk] : 0.0);
+        for (int kk = 0; kk < NK; ++kk) {
+          dd_add(acc[2 * kk], use ? W * f[kk].r : 0.0);
+          dd_add(acc[2 * kk + 1], use ? W * f[kk].i : 0.0);
+        }
+      } else {
+        double f[1][NK];
+        integrand<D, NK, 1>(ss, (cptr<SectorDev>)sd, launder_after(cl, W), x, f);
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) dd_add(acc[kk], use ? W * f[0][kk] : 0.0);
+      }
     }
 #pragma unroll
-    for (int kk = 0; kk < QMC_MAX_ORDERS; ++kk) {
-      if (kk >= K) break;
-      const DD r = wave_reduce(acc[kk]);
+    for (int c = 0; c < KC; ++c) {
+      if (c >= K) break;
+      const DD r = wave_reduce(acc[c]);
       if (lane == 0) {
-        red[wave][l0 * K + kk][0] = r.s;
-        red[wave][l0 * K + kk][1] = r.c;
+        red[wave][l0 * K + c][0] = r.s;
+        red[wave][l0 * K + c][1] = r.c;
       }
     }
   }
+  if constexpr (CPLX) {   // sign-check violations: one vector atomic per wave
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) viol += (uint32_t)__shfl_xor((int)viol, o, 64);
+    if (lane == 0 && viol != 0) atomicAdd(a.sign_count + s, (unsigned long long)viol);
+  }
 }
 
-template <int D>
+template <int D, bool CPLX>
 __global__ __launch_bounds__(256) void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   __shared__ FlowIntegrateLds L;
@@ -730,14 +784,14 @@ __global__ __launch_bounds__(256) void qmc_flow_integrate_kernel(LaunchArgs a, i
   const LatticeDev *__restrict__ lt = a.lat + s;
   const char *flow = (const char *)a.sectors[s].flow;
   {   // stage the flow's forward operands and biases
-    const int d = a.sectors[s].d;
-    const uint4 *src = (const uint4 *)(flow + flow_off_pack(d));
+    const int d = a.sectors[s].d, c = a.sectors[s].flow_cond;
+    const uint4 *src = (const uint4 *)(flow + flow_off_pack(d, c));
     for (int l = 0; l < kFlowLayers; ++l) {
       const uint4 *sl = src + (int64_t)l * kPackLayer / 8;
       uint4 *dl = (uint4 *)L.pack[l];
       for (int e = threadIdx.x; e < kPackFwd / 8; e += blockDim.x) dl[e] = sl[e];
     }
-    stage_bias(flow, d, L.bias, threadIdx.x, blockDim.x);
+    stage_bias(flow, d, c, L.bias, threadIdx.x, blockDim.x);
   }
   __syncthreads();
   const int64_t local = b - lt->block_begin;
@@ -745,7 +799,7 @@ __global__ __launch_bounds__(256) void qmc_flow_integrate_kernel(LaunchArgs a, i
   const int tile_id = (int)(local / nch);
   const int64_t chunk_id = local - (int64_t)tile_id * nch;
   const int T = a.shift_tile;
-  flow_block<D>(a, s, tile_id * T, T, chunk_id, red, L);
+  flow_block<D, CPLX>(a, s, tile_id * T, T, chunk_id, red, L);
   __syncthreads();
   const int nwaves = blockDim.x >> 6;
   const int cols = T * a.K;
@@ -759,7 +813,8 @@ __global__ __launch_bounds__(256) void qmc_flow_integrate_kernel(LaunchArgs a, i
 }
 
 // Training samples of one sector: x_i = phi(y_i) for the points of lattice (n, z) with
-// one shift, and weights w_i = W(y_i) ||f(x_i)||_2 over the orders (0 where W = 0).
+// one shift, and weights w_i = W(y_i) ||f(x_i)||_2 over the orders (0 where W = 0); on
+// the deformed contour f is J f(z(x)) and the norm runs over real and imaginary parts.
 template <int D>
 __global__ __launch_bounds__(256) void qmc_flow_samples_kernel(FlowSampleArgs a) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -770,31 +825,47 @@ __global__ __launch_bounds__(256) void qmc_flow_samples_kernel(FlowSampleArgs a)
   for (int j = 0; j < D; ++j)
     y[j] = shifted(quotient((double)mulmod(i, a.z[j], a.n), a.n_d, a.inv_n), a.shift[j]);
   const double W = apply_transform<D>(a.sd->transform, a.sd->w_scale, y, x[0]);
-  double f[1][QMC_MAX_ORDERS];
-  integrand<D, QMC_MAX_ORDERS, 1>(ss, (cptr<SectorDev>)a.sd, launder_after(launder_uniform(a.coef), W), x, f);
   double nrm = 0.0;
+  const cptr<double> cl = launder_after(launder_uniform(a.coef), W);
+  if (a.cplx) {
+    C2 f[QMC_MAX_ORDERS];
+    integrand_deform<D, QMC_MAX_ORDERS>(ss, (cptr<SectorDev>)a.sd, cl, a.sd->grad_off,
+                                        a.sd->hess_off, a.sd->lambda, x[0], f);
 #pragma unroll
-  for (int k = 0; k < QMC_MAX_ORDERS; ++k)
-    if (k < a.K) nrm = __builtin_fma(f[0][k], f[0][k], nrm);
+    for (int k = 0; k < QMC_MAX_ORDERS; ++k)
+      if (k < a.K) nrm = __builtin_fma(f[k].r, f[k].r, __builtin_fma(f[k].i, f[k].i, nrm));
+  } else {
+    double f[1][QMC_MAX_ORDERS];
+    integrand<D, QMC_MAX_ORDERS, 1>(ss, (cptr<SectorDev>)a.sd, cl, x, f);
+#pragma unroll
+    for (int k = 0; k < QMC_MAX_ORDERS; ++k)
+      if (k < a.K) nrm = __builtin_fma(f[0][k], f[0][k], nrm);
+  }
   const double wi = W != 0.0 ? W * sqrt(nrm) : 0.0;
 #pragma unroll
   for (int j = 0; j < D; ++j) a.x[i * D + j] = x[0][j];
   a.w[i] = isfinite(wi) ? wi : 0.0;
 }
 
-int launch_flow_integrate(const LaunchArgs &a, const DimLaunch &dl, void *stream) {
-  hipStream_t st = (hipStream_t)stream;
+template <bool CPLX>
+static void launch_flow_integrate_p(const LaunchArgs &a, const DimLaunch &dl, hipStream_t st) {
   dim3 grid((unsigned)dl.blocks), blk((unsigned)a.block);
   switch (dl.d) {
-    case 1: hipLaunchKernelGGL(qmc_flow_integrate_kernel<1>, grid, blk, 0, st, a, dl.base); break;
-    case 2: hipLaunchKernelGGL(qmc_flow_integrate_kernel<2>, grid, blk, 0, st, a, dl.base); break;
-    case 3: hipLaunchKernelGGL(qmc_flow_integrate_kernel<3>, grid, blk, 0, st, a, dl.base); break;
-    case 4: hipLaunchKernelGGL(qmc_flow_integrate_kernel<4>, grid, blk, 0, st, a, dl.base); break;
-    case 5: hipLaunchKernelGGL(qmc_flow_integrate_kernel<5>, grid, blk, 0, st, a, dl.base); break;
-    case 6: hipLaunchKernelGGL(qmc_flow_integrate_kernel<6>, grid, blk, 0, st, a, dl.base); break;
-    case 7: hipLaunchKernelGGL(qmc_flow_integrate_kernel<7>, grid, blk, 0, st, a, dl.base); break;
-    default: hipLaunchKernelGGL(qmc_flow_integrate_kernel<8>, grid, blk, 0, st, a, dl.base); break;
+    case 1: hipLaunchKernelGGL((qmc_flow_integrate_kernel<1, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    case 2: hipLaunchKernelGGL((qmc_flow_integrate_kernel<2, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    case 3: hipLaunchKernelGGL((qmc_flow_integrate_kernel<3, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    case 4: hipLaunchKernelGGL((qmc_flow_integrate_kernel<4, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    case 5: hipLaunchKernelGGL((qmc_flow_integrate_kernel<5, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    case 6: hipLaunchKernelGGL((qmc_flow_integrate_kernel<6, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    case 7: hipLaunchKernelGGL((qmc_flow_integrate_kernel<7, CPLX>), grid, blk, 0, st, a, dl.base); break;
+    default: hipLaunchKernelGGL((qmc_flow_integrate_kernel<8, CPLX>), grid, blk, 0, st, a, dl.base); break;
   }
+}
+
+int launch_flow_integrate(const LaunchArgs &a, const DimLaunch &dl, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (dl.deform) launch_flow_integrate_p<true>(a, dl, st);
+  else launch_flow_integrate_p<false>(a, dl, st);
   return (int)hipGetLastError();
 }
 
@@ -816,46 +887,48 @@ int launch_flow_samples(const FlowSampleArgs &fa, int d, void *stream) {
 
 // ------------------------------------------------------------------ launchers
 
-int launch_flow_pack(void *flow, int d, void *stream) {
+int launch_flow_pack(void *flow, int d, int c, void *stream) {
   hipLaunchKernelGGL(flow_pack_kernel, dim3((kPackLayer + 255) / 256, kFlowLayers), dim3(256), 0,
-                     (hipStream_t)stream, (char *)flow, d);
+                     (hipStream_t)stream, (char *)flow, d, c);
   return (int)hipGetLastError();
 }
 
-int launch_flow_transform(const void *flow, int d, const double *u, int64_t count, double *x,
-                          double *logJ, int dir, void *stream) {
+int launch_flow_transform(const void *flow, int d, int c, const double *u, const double *cond,
+                          int64_t count, double *x, double *logJ, int dir, void *stream) {
   if (count <= 0) return 0;
   hipLaunchKernelGGL(flow_transform_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, (const char *)flow, d, u, count, x, logJ, dir);
+                     (hipStream_t)stream, (const char *)flow, d, c, u, cond, count, x, logJ, dir);
   return (int)hipGetLastError();
 }
 
 int flow_grad_waves(int64_t count) { return (int)((count + 255) / 256) * 4; }
 
-int launch_flow_grad(void *flow, int d, const double *x, const double *w, int64_t count,
-                     int64_t offset, int64_t stride, double inv_wsum, double *zs, float *gpart,
-                     double *lpart, double *loss, void *stream) {
+int launch_flow_grad(void *flow, int d, int c, const double *x, const double *w,
+                     const double *cond, int64_t count, int64_t offset, int64_t stride,
+                     double inv_wsum, double *zs, float *gpart, double *lpart, double *loss,
+                     void *stream) {
   hipStream_t st = (hipStream_t)stream;
-  FlowTrainArgs a{(char *)flow, d, x, w, count, offset, stride, inv_wsum, zs, gpart, lpart};
+  FlowTrainArgs a{(char *)flow, d, c, x, w, cond, count, offset, stride, inv_wsum, zs, gpart,
+                  lpart};
   const unsigned blocks = (unsigned)((count + 255) / 256);
   hipLaunchKernelGGL(flow_grad_kernel, dim3(blocks), dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  const int64_t P = flow_params(d);
+  const int64_t P = flow_params(d, c);
   hipLaunchKernelGGL(flow_reduce_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st,
-                     (char *)flow, d, (const float *)gpart, (const double *)lpart,
+                     (char *)flow, d, c, (const float *)gpart, (const double *)lpart,
                      (int64_t)blocks * 4, loss);
   return (int)hipGetLastError();
 }
 
-int launch_flow_adam(void *flow, int d, float lr, float b1, float b2, float eps, float c1,
+int launch_flow_adam(void *flow, int d, int c, float lr, float b1, float b2, float eps, float c1,
                      float c2, void *stream) {
-  const int64_t P = flow_params(d);
+  const int64_t P = flow_params(d, c);
   hipLaunchKernelGGL(flow_adam_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, (char *)flow, d, lr, b1, b2, eps, c1, c2);
+                     (hipStream_t)stream, (char *)flow, d, c, lr, b1, b2, eps, c1, c2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  return launch_flow_pack(flow, d, stream);
+  return launch_flow_pack(flow, d, c, stream);
 }
 
 int launch_flow_clear(float *p, int64_t count, void *stream) {

@@ -55,6 +55,8 @@ struct alignas(16) SectorDev {
                                    // D(D+1)/2 tables d2F/dx_j dx_k, k >= j (degree-1 layout)
   double lambda;                   // complex plans: contour deformation parameter (>= 0)
   uint64_t flow;                   // device address of an attached flow transform, or 0
+  int32_t flow_cond, pad1;         // conditioning features of the attached flow
+  double cond[QMC_FLOW_MAX_COND];  // their values for this sector
 };
 
 // Per-call lattice record of a sector.

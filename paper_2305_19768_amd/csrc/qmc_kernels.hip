@@ -258,8 +258,8 @@ int launch_integrate(const LaunchArgs &a, void *stream) {
   for (int t = 0; t < a.n_dim_launches; ++t) {
     const DimLaunch &dl = a.dims[t];
     if (dl.blocks == 0) continue;
-    e = dl.deform ? (hipError_t)launch_deform(a, dl, st)
-                  : dl.flow ? (hipError_t)launch_flow_integrate(a, dl, st) : launch_class(a, dl, st);
+    e = dl.flow ? (hipError_t)launch_flow_integrate(a, dl, st)
+                : dl.deform ? (hipError_t)launch_deform(a, dl, st) : launch_class(a, dl, st);
     if (e != hipSuccess) return (int)e;
   }
   if (a.ev_stop && (e = hipEventRecord((hipEvent_t)a.ev_stop, st)) != hipSuccess) return (int)e;
