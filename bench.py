@@ -68,7 +68,7 @@ def algorithmic_flops(sec, m: int) -> float:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("qmc_kernels.hip", "qmc_internal.h"):
+    for name in ("qmc_kernels.hip", "qmc_device.h", "qmc_internal.h"):
         with open(os.path.join(ROOT, "paper_2305_19768_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -20,6 +20,16 @@ Parity status of each function (what pins it, in ``tests/test_oracle_pins.py``):
   p2                truncated dual-lattice sum on small n, Korobov-space identities
   estimate/amplitude/eps_rel  textbook mean/variance, propagation of independent variances
   allocate          constraint + stationarity residuals, brute-force constrained minimum
+  amplitude_series  Cauchy product of Laurent series (numpy convolution), Monte-Carlo
+                    variance of independent orders, reduction to constant coefficients
+  median_rule       brute force over the candidates (test_oracle_pins.py)
+  deformed contour  (sector_sums_deformed, integrand_deformed, choose_lambda) closed-form
+                    timelike bubble, Cauchy invariance at Euclidean points, lambda = 0
+                    branch (test_oracle_deform.py)
+  coef.py           exact rational functions, closed-form series, float(Fraction)
+                    rounding (test_oracle_coef.py)
+  flow.py           identity, invertibility, finite differences, Gauss-Legendre
+                    unbiasedness, conditional reduction (test_oracle_flow.py)
 """
 
 from __future__ import annotations

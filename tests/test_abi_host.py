@@ -161,3 +161,17 @@ def test_launch_shape_validation(L):
     # timing needs a bound workspace: refused before any device call
     assert L.qmc_autotune(h, None, None, 1, 0, None, None) == -7
     L.qmc_plan_free(h)
+
+
+def test_flow_shapes_and_sizes(L):
+    # parameter counts of (conditional) flows: per layer 64 (d + c) + 64 + 64^2 + 64 + 2d 64 + 2d
+    def per(d, c):
+        return 4 * (64 * (d + c) + 64 + 64 * 64 + 64 + 2 * d * 64 + 2 * d)
+    assert L.qmc_flow_param_count(6, 0) == per(6, 0) == 21552
+    assert L.qmc_flow_param_count(6, 2) == per(6, 2)
+    assert L.qmc_flow_param_count(8, 4) == per(8, 4)
+    for d, c in [(0, 0), (9, 0), (3, 5), (6, -1)]:
+        assert L.qmc_flow_param_count(d, c) == -1
+        assert L.qmc_flow_bytes(d, c) == 0
+    assert L.qmc_flow_bytes(6, 2) > 4 * 4 * per(6, 2)     # params, two moments, gradient, pack
+    assert L.qmc_flow_scratch_bytes(6, 2, 0) == 0
