@@ -224,6 +224,10 @@ static hipError_t launch_d(const LaunchArgs &a, const DimLaunch &dl, hipStream_t
     if (a.shifts_per_pass == 1) return launch_ds<D, 1, true, true>(a, dl, st);
     return launch_ds<D, 2, true, true>(a, dl, st);   // FP32 kernels: 1 or 2 shifts per pass
   }
+  // FP64 at d >= 7: one shift per pass whatever the shape asks (with two the lattice
+  // state, both shifts' points and accumulators overflow the registers: spills and half
+  // the occupancy); the sums are the same, shift by shift
+  if (D >= 7) return launch_ds<D, 1, true, false>(a, dl, st);
   switch (a.shifts_per_pass) {
     case 1: return launch_ds<D, 1, true, false>(a, dl, st);
     case 4: return launch_ds<D, 4, true, false>(a, dl, st);
