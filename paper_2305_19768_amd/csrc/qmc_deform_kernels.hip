@@ -122,7 +122,7 @@ __device__ __forceinline__ void deform_block(const LaunchArgs &a, int s, int l_b
 }
 
 template <int D, bool F32, int NK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 6 ? 2 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void qmc_deform_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   const int64_t b = block_base + blockIdx.x;
