@@ -247,6 +247,7 @@ def scan_flow_leg(qmc, torch, n_points: int = 10, train_points: int = 3, batches
     variance ratios, the cost of the flow-transformed evaluation and sign-check counts."""
     import numpy as np
     import workloads
+    train_points = max(1, min(train_points, n_points - 1))   # leave unseen points
     prob = workloads.physical_scan(seed=0, n_points=n_points)
     kin = prob.kinematics
     nb = len(prob.sectors) // n_points

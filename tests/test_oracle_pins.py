@@ -257,6 +257,28 @@ def test_convergence_order_at_least_one():
     assert slope < -1.0, (slope, errs)
 
 
+@pytest.mark.parametrize("transform", ["none", "korobov3"])
+def test_error_estimate_is_calibrated(transform):
+    """The shift-based error (Sec. 2.1.3: standard error of the mean of m random-shift
+    estimates) covers the exact value like a t-interval: over 200 independent shift sets
+    with m = 16, |mean - exact| <= 2 err in about 94% of the cases (t with 15 degrees of
+    freedom) and the standardised deviations have unit spread.  Integrand
+    (1 + x1)^-1 (1 + x2)^-2 on a small lattice (n = 101), exact value log(2)/2."""
+    sec = W.custom_sector(2, [(1, (0, 0)), (1, (1, 0))], [(1, (0, 0)), (1, (0, 1))],
+                          u_pow=-1, f_pow2=-4, n=101, a=40, transform=transform)
+    exact = math.log(2) / 2
+    z = []
+    for seed in range(200):
+        sh = W.uniform_shifts(np.random.default_rng(1000 + seed), 16, 2)
+        Q, _ = oracle.sector_sums(sec, sh)
+        m, e = oracle.estimate(Q)
+        z.append((m[0] - exact) / e[0])
+    z = np.array(z)
+    cover = np.mean(np.abs(z) <= 2.0)
+    assert 0.86 <= cover <= 0.99, cover
+    assert 0.8 <= np.std(z) <= 1.3 and abs(np.mean(z)) < 0.35
+
+
 def test_zero_weight_samples_are_skipped_and_nonfinite_is_reported():
     # With korobov3, y = 0 gives W = 0: F = x1 vanishes there but the sample is skipped.
     sec = W.custom_sector(1, [], [(1, (1,))], f_pow2=-2, n=11, a=1, transform="korobov3")
