@@ -348,7 +348,8 @@ struct SectorScalars {
   int u_off, f_off, u_off32, f_off32;
 };
 
-__device__ __forceinline__ SectorScalars load_scalars(const SectorDev *sd) {
+template <typename P>
+__device__ __forceinline__ SectorScalars load_scalars(P sd) {
   SectorScalars r;
   r.flags = sd->flags;
   r.u_deg = sd->u_deg;
@@ -753,6 +754,11 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
         const cptr<float> cl32 = launder_uniform(a.coef32);
         const cptr<LatticeDev> ltl = launder_uniform(lt);
         const cptr<double> shl = launder_uniform(sh);
+        // per-sector scalars re-read each iteration (scalar loads) rather than kept live
+        // across it, where they would be spilled and restored with vector instructions
+        const cptr<SectorDev> sdl = launder_uniform(sd);
+        const SectorScalars ss = load_scalars(sdl);
+        const double n_d = ltl->n_d, inv_n = ltl->inv_n, w_scale = sdl->w_scale;
         double q[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
