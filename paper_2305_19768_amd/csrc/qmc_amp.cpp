@@ -79,6 +79,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   AmpState *dst = (AmpState *)take(sizeof(AmpState));
   int32_t *d_integral = (int32_t *)take(4 * S), *d_dims = (int32_t *)take(4 * S);
   int32_t *d_lidx = (int32_t *)take(4 * S), *d_active = (int32_t *)take(4 * S);
+  int32_t *d_iptr = (int32_t *)take(4 * (NI + 1)), *d_isec = (int32_t *)take(4 * S);
   double *d_want = (double *)take(8 * S), *d_tau = (double *)take(8 * S);
   double *d_c2 = (double *)take(8 * kAmpMaxSums * NI * K);
   double *d_cre = (double *)take(8 * kAmpMaxSums * NI * K);
@@ -101,6 +102,14 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
     integral[s] = p->sec[s].integral;
     lidx[s] = (int32_t)l0;
   }
+  // sectors grouped by integral, ascending within each (the order of the sums)
+  std::vector<int32_t> iptr(NI + 1, 0), isec(S);
+  for (int s = 0; s < S; ++s) ++iptr[integral[s] + 1];
+  for (int c = 0; c < NI; ++c) iptr[c + 1] += iptr[c];
+  {
+    std::vector<int32_t> fill(iptr.begin(), iptr.end() - 1);
+    for (int s = 0; s < S; ++s) isec[fill[integral[s]]++] = s;
+  }
   AmpState init;
   std::memset(&init, 0, sizeof init);
   hipStream_t st = (hipStream_t)stream;
@@ -109,6 +118,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   };
   if ((e = up(dst, &init, sizeof init)) || (e = up(d_integral, integral.data(), 4 * S)) ||
       (e = up(d_dims, p->dims.data(), 4 * S)) || (e = up(d_lidx, lidx.data(), 4 * S)) ||
+      (e = up(d_iptr, iptr.data(), 4 * (NI + 1))) || (e = up(d_isec, isec.data(), 4 * S)) ||
       (e = up(d_tau, tau.data(), 8 * S)) || (e = up(d_c2, c2.data(), 8 * c2.size())) ||
       (e = up(d_cre, cre.data(), 8 * cre.size())) || (e = up(d_cim, cim.data(), 8 * cim.size())) ||
       (e = up(d_ln, lad.data(), 8 * lad.size())) ||
@@ -131,6 +141,8 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   g.epsabs = opt->epsabs;
   g.alpha = opt->alpha;
   g.integral = d_integral;
+  g.int_ptr = d_iptr;
+  g.int_sec = d_isec;
   g.dims = d_dims;
   g.order = (const int32_t *)(p->ws + p->off_order);
   g.lidx = d_lidx;

@@ -28,6 +28,23 @@ __device__ __forceinline__ double block_sum_ordered(double v, double *sh) {
   return r;
 }
 
+// Exclusive prefix sum over the workgroup (exact integers); *total gets the sum.
+__device__ __forceinline__ int64_t block_scan_excl(int64_t v, int64_t *sh, int64_t *total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kRoundThreads; off <<= 1) {
+    const int64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const int64_t incl = sh[t];
+  *total = sh[kRoundThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
 __device__ __forceinline__ int block_or(int v, int *sh) {
   if (threadIdx.x == 0) *sh = 0;
   __syncthreads();
@@ -77,6 +94,7 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
   AmpState *st = g.state;
   if (st->done) return;
   __shared__ double shd[kRoundThreads];
+  __shared__ int64_t shl[kRoundThreads];
   __shared__ int shi;
   const int t = threadIdx.x;
   const int S = g.S, K = g.K, T = g.T, NI = g.NI;
@@ -86,11 +104,11 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
     for (int idx = t; idx < NI * K; idx += kRoundThreads) {
       const int c = idx / K, k = idx - c * K;
       double v = 0.0, var = 0.0;
-      for (int s = 0; s < S; ++s)
-        if (g.integral[s] == c) {
-          v += g.mean[s * K + k];
-          var += g.err[s * K + k] * g.err[s * K + k];
-        }
+      for (int r = g.int_ptr[c]; r < g.int_ptr[c + 1]; ++r) {   // its sectors, ascending
+        const int s = g.int_sec[r];
+        v += g.mean[s * K + k];
+        var += g.err[s * K + k] * g.err[s * K + k];
+      }
       g.I[idx] = v;
       g.VI[idx] = var;
     }
@@ -204,31 +222,41 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
     }
   }
   const double total_pts = block_sum_ordered(pts, shd);
-  if (t == 0) {
-    const int tiles = g.m / g.tile;
-    const double per_block = (double)kTargetBlocksDevice * g.block;
-    int64_t ppt = (int64_t)ceil(total_pts * tiles / per_block);
-    if (ppt < 1) ppt = 1;
-    const int64_t chunk = ppt * g.block;
-    int64_t b = 0, evals = 0;
-    for (int q = 0; q < S; ++q) {
-      const int s = g.order[q];
-      LatticeDev &L = g.lat[s];
-      L.chunk = chunk;
-      if (g.active[s]) {
-        L.n_chunks = (int32_t)((L.n + chunk - 1) / chunk);
-        evals += (int64_t)L.n * g.m;
-      } else {
-        L.n_chunks = 0;
-      }
-      L.block_begin = b;
-      g.block_begin[q] = b;
-      b += (int64_t)L.n_chunks * tiles;
+  const int tiles = g.m / g.tile;
+  const double per_block = (double)kTargetBlocksDevice * g.block;
+  int64_t ppt = (int64_t)ceil(total_pts * tiles / per_block);
+  if (ppt < 1) ppt = 1;
+  const int64_t chunk = ppt * g.block;
+  // each thread takes a contiguous run of the workgroup order; an exclusive scan of the
+  // runs' workgroup counts places every sector's range
+  const int run = (S + kRoundThreads - 1) / kRoundThreads;
+  const int q0 = min(S, t * run), q1 = min(S, q0 + run);
+  int64_t nb = 0, ev = 0;
+  for (int q = q0; q < q1; ++q) {
+    const int s = g.order[q];
+    if (g.active[s]) {
+      const int64_t n = (int64_t)g.lat[s].n;
+      nb += (n + chunk - 1) / chunk * tiles;
+      ev += n * g.m;
     }
-    g.block_begin[S] = b;
-    st->total_blocks = b;
+  }
+  int64_t total_b, total_ev;
+  int64_t b = block_scan_excl(nb, shl, &total_b);
+  block_scan_excl(ev, shl, &total_ev);
+  for (int q = q0; q < q1; ++q) {
+    const int s = g.order[q];
+    LatticeDev &L = g.lat[s];
+    L.chunk = chunk;
+    L.n_chunks = g.active[s] ? (int32_t)((L.n + chunk - 1) / chunk) : 0;
+    L.block_begin = b;
+    g.block_begin[q] = b;
+    b += (int64_t)L.n_chunks * tiles;
+  }
+  if (t == 0) {
+    g.block_begin[S] = total_b;
+    st->total_blocks = total_b;
     st->work_counter = 0;
-    st->evaluations += evals;
+    st->evaluations += total_ev;
     st->rounds += 1;
   }
 }

@@ -142,6 +142,7 @@ struct AmpArgs {
   int32_t P;                       // Laurent terms per coefficient (tables [T][NI][P])
   double epsrel, epsabs, alpha;
   const int32_t *integral, *dims, *order;
+  const int32_t *int_ptr, *int_sec;   // sectors of integral c: int_sec[int_ptr[c] .. int_ptr[c+1]), ascending
   int32_t *lidx, *active, *unmet;
   double *want;
   const double *tau, *c2, *cre, *cim;
