@@ -64,9 +64,12 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   if ((int)lad.size() > kAmpMaxLattice)
     return fail(QMC_E_INVAL, "device mode: at most %d lattice sizes", kAmpMaxLattice);
   const bool f32 = p->precision == QMC_PREC_FP32;
-  int &grid = p->persistent_grid[f32 ? 1 : 0];
+  bool all_f32 = true;
+  for (int s = 0; s < S; ++s) all_f32 = all_f32 && (p->sec[s].flags & SF_F32OK);
+  const int variant = !f32 ? kPersistentF64 : all_f32 ? kPersistentF32 : kPersistentF32Mixed;
+  int &grid = p->persistent_grid[variant];
   int e;
-  if (!grid && (e = persistent_grid(p->d_max, f32, p->block, &grid)) != hipSuccess)
+  if (!grid && (e = persistent_grid(p->d_max, variant, K, p->block, &grid)) != hipSuccess)
     return hip_fail(e, "occupancy query");
   // ---- device tables in the workspace
   char *base = p->ws + p->off_amp;
@@ -195,7 +198,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   for (;;) {
     for (int r = 0; r < 4; ++r) {   // queue a few rounds; finished rounds return at once
       if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");
-      if ((e = launch_persistent(la, dst, p->d_max, f32, (unsigned)grid, stream)) != hipSuccess)
+      if ((e = launch_persistent(la, dst, p->d_max, variant, (unsigned)grid, stream)) != hipSuccess)
         return hip_fail(e, "persistent kernel");
       if ((e = launch_reduce_stats(la, stream)) != hipSuccess) return hip_fail(e, "reduction");
     }

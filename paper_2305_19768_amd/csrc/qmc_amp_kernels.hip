@@ -267,13 +267,20 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
 // workgroup takes the next work item (sector, chunk, shift tile) from the round's
 // atomic counter until none is left, and writes its compensated partial exactly where
 // the per-dimension launch would, so the reduction and its order are unchanged.
-template <int D, int K, int S, bool F32>
+// F32 with FB: sectors without SF_F32OK fall back to the FP64 form; F32 without FB: every
+// sector of the launch has SF_F32OK, and the FP64 form (whose registers would set the
+// occupancy of the whole kernel) is not compiled in.
+template <int D, int K, int S, bool F32, bool FB>
 __device__ __forceinline__ void run_item(const LaunchArgs &a, int s, int l_begin, int T,
                                          int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
-  if (F32 && (a.sectors[s].flags & SF_F32OK))
+  if constexpr (F32 && !FB) {
     integrate_block<D, K, S, true, true, false>(a, s, l_begin, T, chunk_id, red);
-  else
-    integrate_block<D, K, S, true, false, false>(a, s, l_begin, T, chunk_id, red);
+  } else {
+    if (F32 && (a.sectors[s].flags & SF_F32OK))
+      integrate_block<D, K, S, true, true, false>(a, s, l_begin, T, chunk_id, red);
+    else
+      integrate_block<D, K, S, true, false, false>(a, s, l_begin, T, chunk_id, red);
+  }
 }
 
 // The work item is the same for every lane; make that explicit so that the sector's
@@ -284,8 +291,17 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int DMAX, int K, int S, bool F32>
-__global__ __launch_bounds__(256) void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
+// Waves per SIMD asked of the compiler: four (128 VGPRs) for the pure-FP32 and the FP64
+// (one shift per pass) forms up to d = 7, which fit with at most a few spills; no
+// constraint otherwise (the mixed form and d = 8 need more registers).
+template <int DMAX, bool F32, bool FB>
+constexpr int persistent_waves() {
+  return DMAX <= 7 && (!F32 || !FB) ? 4 : 1;
+}
+
+template <int DMAX, int K, int S, bool F32, bool FB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<DMAX, F32, FB>())))
+void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   __shared__ int64_t item;
   if (st->done) return;
@@ -305,14 +321,14 @@ __global__ __launch_bounds__(256) void qmc_persistent_kernel(LaunchArgs a, AmpSt
     const int64_t chunk_id = local - (int64_t)tile_id * nch;
     const int l_begin = tile_id * T;
     switch (a.sectors[s].d) {
-      case 1: run_item<1, K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      case 2: if (DMAX >= 2) run_item<(DMAX >= 2 ? 2 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      case 3: if (DMAX >= 3) run_item<(DMAX >= 3 ? 3 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      case 4: if (DMAX >= 4) run_item<(DMAX >= 4 ? 4 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      case 5: if (DMAX >= 5) run_item<(DMAX >= 5 ? 5 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      case 6: if (DMAX >= 6) run_item<(DMAX >= 6 ? 6 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      case 7: if (DMAX >= 7) run_item<(DMAX >= 7 ? 7 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
-      default: if (DMAX >= 8) run_item<(DMAX >= 8 ? 8 : 1), K, S, F32>(a, s, l_begin, T, chunk_id, red); break;
+      case 1: run_item<1, K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      case 2: if (DMAX >= 2) run_item<(DMAX >= 2 ? 2 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      case 3: if (DMAX >= 3) run_item<(DMAX >= 3 ? 3 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      case 4: if (DMAX >= 4) run_item<(DMAX >= 4 ? 4 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      case 5: if (DMAX >= 5) run_item<(DMAX >= 5 ? 5 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      case 6: if (DMAX >= 6) run_item<(DMAX >= 6 ? 6 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      case 7: if (DMAX >= 7) run_item<(DMAX >= 7 ? 7 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
+      default: if (DMAX >= 8) run_item<(DMAX >= 8 ? 8 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
     }
     __syncthreads();
     const int nwaves = blockDim.x >> 6;
@@ -333,37 +349,47 @@ int launch_amp_round(const AmpArgs &g, void *stream) {
   return (int)hipGetLastError();
 }
 
-template <int DMAX, bool F32>
-static hipError_t launch_pk(const LaunchArgs &a, AmpState *st, unsigned grid, hipStream_t s) {
-  switch (a.K) {
-    case 1: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 1, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
-    case 2: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 2, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
-    case 3: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 3, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
-    default: hipLaunchKernelGGL((qmc_persistent_kernel<DMAX, 4, 2, F32>), dim3(grid), dim3(a.block), 0, s, a, st); break;
+// FP64: one shift per pass (at d = 7, 124 registers instead of 209: twice the waves);
+// FP32: two.
+template <int DMAX, bool F32, bool FB>
+static const void *pk_fn(int K) {
+  switch (K) {
+    case 1: return (const void *)qmc_persistent_kernel<DMAX, 1, F32 ? 2 : 1, F32, FB>;
+    case 2: return (const void *)qmc_persistent_kernel<DMAX, 2, F32 ? 2 : 1, F32, FB>;
+    case 3: return (const void *)qmc_persistent_kernel<DMAX, 3, F32 ? 2 : 1, F32, FB>;
+    default: return (const void *)qmc_persistent_kernel<DMAX, 4, F32 ? 2 : 1, F32, FB>;
   }
-  return hipGetLastError();
 }
 
-int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, bool f32, unsigned grid,
+template <int DMAX>
+static const void *pk_variant(int variant, int K) {
+  if (variant == kPersistentF64) return pk_fn<DMAX, false, true>(K);
+  if (variant == kPersistentF32Mixed) return pk_fn<DMAX, true, true>(K);
+  return pk_fn<DMAX, true, false>(K);
+}
+
+static const void *persistent_fn(int d_max, int variant, int K) {
+  if (d_max <= 4) return pk_variant<4>(variant, K);
+  if (d_max <= 6) return pk_variant<6>(variant, K);
+  if (d_max <= 7) return pk_variant<7>(variant, K);
+  return pk_variant<8>(variant, K);
+}
+
+int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, int variant, unsigned grid,
                       void *stream) {
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e;
-  if (d_max <= 4) e = f32 ? launch_pk<4, true>(a, st, grid, s) : launch_pk<4, false>(a, st, grid, s);
-  else if (d_max <= 6) e = f32 ? launch_pk<6, true>(a, st, grid, s) : launch_pk<6, false>(a, st, grid, s);
-  else e = f32 ? launch_pk<8, true>(a, st, grid, s) : launch_pk<8, false>(a, st, grid, s);
-  return (int)e;
+  LaunchArgs la = a;
+  AmpState *sp = st;
+  void *args[] = {&la, &sp};
+  return (int)hipLaunchKernel(persistent_fn(d_max, variant, a.K), dim3(grid), dim3(a.block), args,
+                              0, (hipStream_t)stream);
 }
 
-int persistent_grid(int d_max, bool f32, int block, int *grid) {
+int persistent_grid(int d_max, int variant, int K, int block, int *grid) {
   int dev = 0, cus = 0, per = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return (int)e;
-  const void *fn;
-  if (d_max <= 4) fn = f32 ? (const void *)qmc_persistent_kernel<4, 3, 2, true> : (const void *)qmc_persistent_kernel<4, 3, 2, false>;
-  else if (d_max <= 6) fn = f32 ? (const void *)qmc_persistent_kernel<6, 3, 2, true> : (const void *)qmc_persistent_kernel<6, 3, 2, false>;
-  else fn = f32 ? (const void *)qmc_persistent_kernel<8, 3, 2, true> : (const void *)qmc_persistent_kernel<8, 3, 2, false>;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, block, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, persistent_fn(d_max, variant, K), block, 0);
   if (e != hipSuccess) return (int)e;
   *grid = cus * (per > 0 ? per : 1);
   return 0;

@@ -1030,7 +1030,7 @@ qmc_status qmc_set_launch_shape(qmc_plan_t p, const qmc_launch_shape *sh) {
   p->tile = sh->shift_tile;
   p->spp = spp;
   p->target_blocks = sh->target_blocks;
-  p->persistent_grid[0] = p->persistent_grid[1] = 0;   // occupancy depends on the block size
+  for (int &g : p->persistent_grid) g = 0;   // occupancy depends on the block size
   p->lat_valid = false;
   return QMC_OK;
 }

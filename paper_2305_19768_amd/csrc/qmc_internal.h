@@ -154,9 +154,12 @@ struct AmpArgs {
 };
 
 int launch_amp_round(const AmpArgs &g, void *stream);
-int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, bool f32, unsigned grid,
+// Persistent kernel variants: FP64; FP32 with the FP64 form for sectors without
+// SF_F32OK; FP32 only (every sector has SF_F32OK).
+enum : int { kPersistentF64 = 0, kPersistentF32Mixed = 1, kPersistentF32 = 2 };
+int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, int variant, unsigned grid,
                       void *stream);
-int persistent_grid(int d_max, bool f32, int block, int *grid);
+int persistent_grid(int d_max, int variant, int K, int block, int *grid);
 
 // Returns a hipError_t value (0 = success).
 int launch_points(const PointsArgs &pa, unsigned grid, void *stream);

@@ -38,7 +38,7 @@ struct qmc_plan_s {
   std::vector<uint64_t> n_default, a_default;
   std::vector<int32_t> dims;
   std::vector<int32_t> order;          // sectors in workgroup order: by dimension, then index
-  int32_t persistent_grid[2] = {0, 0};  // resident workgroups of the persistent kernel (FP64, FP32)
+  int32_t persistent_grid[3] = {0, 0, 0};  // resident workgroups per persistent-kernel variant
   // options
   int32_t m = 0, precision = 0, block = 256, tile = 8, spp = 2;
   uint64_t n_max = 0;

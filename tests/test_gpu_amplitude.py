@@ -125,6 +125,36 @@ def test_device_mode_fp32_meets_target(qmc):
     assert np.all(np.abs(val[0] - ov[0]) <= 5 * (np.abs(err[0]) + np.abs(oe[0])))
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_device_mode_fp32_against_fp64(qmc, mixed):
+    # The FP32 batched form against the FP64 one on the same ladder: same rounds and final
+    # lattices, sums within the FP32 bar on their scale.  mixed: one sector's F gets a
+    # negative coefficient (F stays positive on the cube), so it has no FP32 form and the
+    # persistent kernel must carry the FP64 one beside it.
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=7, m=8, n0=1009)
+    if mixed:
+        sec = prob.sectors[5]
+        c0 = float(sec.f_coef[np.flatnonzero(sec.f_exp.sum(axis=1) == 0)[0]])
+        i = int(np.flatnonzero(sec.f_exp.sum(axis=1) > 0)[0])
+        sec.f_coef[i] = -0.5 * min(c0, float(sec.f_coef[i]))
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    out = {}
+    for prec in (qmc.QMC_PREC_FP64, qmc.QMC_PREC_FP32):
+        plan = qmc.Plan(prob, n_max=int(sizes[-1]), precision=prec)
+        out[prec] = plan.amp_evaluate(prob.amp_coef, epsrel=5e-4, lattice_n=sizes,
+                                      lattice_a=a_tab, tau=tau, n_presample=1009, mode=1)
+        del plan
+    v64, e64, n64, s64 = out[qmc.QMC_PREC_FP64]
+    v32, e32, n32, s32 = out[qmc.QMC_PREC_FP32]
+    assert s32["converged"] == 1 and s32["rounds"] == s64["rounds"]
+    assert np.array_equal(n32, n64)
+    scale = np.abs(v64) + np.abs(e64)
+    dev = np.abs(v32 - v64) / scale
+    print("mixed", mixed, "max rel deviation", dev.max(), flush=True)
+    assert np.all(dev <= 1e-5)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_timeout_returns_valid_partial_results(qmc, mode):
     # non-integer powers of U and F keep the lattice error well above 1e-15 on every rung,
