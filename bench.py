@@ -115,7 +115,9 @@ def amplitude_leg(qmc, torch, repeats: int):
     amplitude (20 integrals, 500 sectors, d 3..7, 32 shifts, FP64 oracle-pinned method),
     for the plain FP64 host loop and the batched on-device forms in FP64 and FP32.  The
     lattice table (prime sizes, P_2-chosen Korobov parameters) is built once beforehand,
-    as a precomputed table would be; each timed call starts from the presampling round."""
+    as a precomputed table would be, and each form's launch shape is chosen by the
+    autotuner on the presampling lattices; each timed call starts from the presampling
+    round."""
     import numpy as np
     import workloads
     prob = workloads.amplitude(seed=0)
@@ -131,8 +133,13 @@ def amplitude_leg(qmc, torch, repeats: int):
            "lattice_sizes": [int(sizes[0]), int(sizes[-1]), len(sizes)],
            "table_setup_s": setup_s}
     vals = {}
+    # launch shape of each form from the autotuner, timed on the presampling lattices
+    l0 = int(np.searchsorted(sizes, 10007))
+    n_tune = [int(sizes[l0])] * len(prob.sectors)
+    a_tune = [int(table[l0, s.d - 1]) for s in prob.sectors]
     for name, (prec, mode) in forms.items():
         plan = qmc.Plan(prob, precision=prec, n_max=int(sizes[-1]))
+        shape = plan.autotune(n=n_tune, a=a_tune, reps=3, use_cache=False)
         times = []
         for _ in range(repeats + 1):              # first call warms up
             torch.cuda.synchronize()
@@ -146,7 +153,8 @@ def amplitude_leg(qmc, torch, repeats: int):
         vals[name] = (val[0], err[0])
         out[name] = {"wall_s": float(np.median(times[1:])), "rounds": st["rounds"],
                      "converged": st["converged"], "evaluations": st["evaluations"],
-                     "max_rel_err": float(np.max(rel)), "max_n": int(np.max(nfin))}
+                     "max_rel_err": float(np.max(rel)), "max_n": int(np.max(nfin)),
+                     "launch": {k: shape[k] for k in ("block", "shift_tile", "shifts_per_pass")}}
         print(f"# amplitude {name}: {out[name]}", file=sys.stderr, flush=True)
         del plan
     v64, e64 = vals["fp64_host"]
