@@ -373,6 +373,43 @@ def flow_leg(qmc, torch, batches: int = 64, epochs: int = 3):
             "flow_network_frac_of_bf16_peak": evals * flops_eval / (k_flow / 1e3) / 2.5e15}
 
 
+def one_loop_leg(qmc, torch, steps: int = 3):
+    """Throughput variant of the one-loop sector: the same integrand (x1^(1/2) U^-1
+    F^(-1-eps), two orders, korobov3, 16 shifts) on a lattice of n = 2^31 - 1 points whose
+    Korobov parameter minimises P_2 over 64 random candidates (device search, timed
+    separately).  The x1^(1/2) factor keeps it on the general integrand path, in FP64."""
+    import numpy as np
+    import workloads
+    n = 2 ** 31 - 1
+    prob = workloads.one_loop_sector(seed=0, n=n)
+    plan = qmc.Plan(prob, n_max=n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, p2 = plan.korobov_search(n, 3, [int(c) for c in prob.sectors[0].a_candidates])
+    search_s = time.perf_counter() - t0
+    plan.integrate(n=[n], a=[a])                   # warm-up
+    times, kms = [], []
+    for _ in range(steps):
+        plan.enable_timing(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, mean, err = plan.integrate(n=[n], a=[a], check=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        kms.append(plan.read_timing()[0])
+        plan.enable_timing(False)
+    plan.check_status()
+    evals = n * prob.m
+    mean, err = mean.cpu().numpy()[0], err.cpu().numpy()[0]
+    return {"workload": "one_loop_sector: d = 3, n = 2^31 - 1, a = argmin P_2 over 64 random "
+                        "candidates, 16 shifts, 2 orders, korobov3, FP64 (general path)",
+            "a": a, "p2": p2, "p2_search_s": search_s,
+            "value": evals / float(np.median(times)), "unit": "evals/s",
+            "ms_per_step": float(np.median(times)) * 1e3,
+            "kernel_ms": float(np.median(kms)), "evals_per_step": evals,
+            "estimate": [float(v) for v in mean], "error": [float(v) for v in err]}
+
+
 def median_leg(qmc, torch, r: int = 11, seed: int = 0):
     """Median QMC rule (Sec. 2.2): per sector r generating vectors drawn from U_n and the
     median of their unshifted estimates, all candidates of all sectors in one launch,
@@ -433,6 +470,8 @@ def main():
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
     ap.add_argument("--no-flow", action="store_true", help="skip the learned-transform leg")
     ap.add_argument("--no-median", action="store_true", help="skip the median-rule leg")
+    ap.add_argument("--no-one-loop", action="store_true",
+                    help="skip the one-loop throughput leg (n = 2^31 - 1)")
     ap.add_argument("--no-scan-flow", action="store_true",
                     help="skip the kinematics-conditioned flow leg on the physical scan")
     ap.add_argument("--scan-points", type=int, default=10,
@@ -549,6 +588,8 @@ def main():
         "launch": plan.launch_shape(),
         "autotune": tune,
     }
+    if not args.no_one_loop:
+        result["one_loop_throughput"] = one_loop_leg(qmc, torch)
     if not args.no_amp:
         result["amplitude_time_to_1e-4"] = amplitude_leg(qmc, torch, args.amp_repeats)
     if not args.no_flow:
