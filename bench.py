@@ -151,12 +151,15 @@ def amplitude_leg(qmc, torch, repeats: int):
             times.append(time.perf_counter() - t1)
         rel = np.abs(err[0]) / np.abs(val[0])
         vals[name] = (val[0], err[0])
+        if name == "fp64_host":
+            nfin64 = np.asarray(nfin)
         out[name] = {"wall_s": float(np.median(times[1:])), "rounds": st["rounds"],
                      "converged": st["converged"], "evaluations": st["evaluations"],
                      "max_rel_err": float(np.max(rel)), "max_n": int(np.max(nfin)),
                      "launch": {k: shape[k] for k in ("block", "shift_tile", "shifts_per_pass")}}
         print(f"# amplitude {name}: {out[name]}", file=sys.stderr, flush=True)
         del plan
+    out["fp32_flow"] = amplitude_flow_form(qmc, torch, prob, sizes, table, nfin64)
     v64, e64 = vals["fp64_host"]
     for name in ("fp64_device", "fp32_device"):
         v, e = vals[name]
@@ -166,6 +169,73 @@ def amplitude_leg(qmc, torch, repeats: int):
     out["speedup_fp32_device_vs_fp64_host"] = (out["fp64_host"]["wall_s"] /
                                               out["fp32_device"]["wall_s"])
     return out
+
+
+def amplitude_flow_form(qmc, torch, prob, sizes, table, nfin64, n_flow: int = 8,
+                        batches: int = 16, epochs: int = 3):
+    """The FP32 form with learned transforms, training and selection inside the timed
+    region: flows for the n_flow sectors that carry the most work in the FP64 run (final
+    lattice size x dimension), trained on QMC samples of the ladder's 2e5-point rung; a
+    flow is kept where it lowers the work to a given error: under the n^-2 variance decay
+    the allocation assumes, the square root of the variance ratio at the sector's final
+    lattice must exceed the cost ratio per evaluation (plain korobov3 is the fallback); then the
+    amplitude evaluation with the kept flows in the host-loop form (the batched form
+    integrates no flow-transformed sectors)."""
+    import dataclasses
+    import numpy as np
+    import workloads
+    cost = nfin64.astype(np.float64) * np.array([s.d for s in prob.sectors])
+    pick = [int(s) for s in np.argsort(-cost)[:n_flow]]
+    l_tr = int(np.searchsorted(sizes, 200000))
+    n_tr = int(sizes[l_tr])
+    sub = workloads.Problem(sectors=[dataclasses.replace(prob.sectors[s], integral=0)
+                                     for s in pick],
+                            order_lo=prob.order_lo, m=prob.m, shifts=[prob.shifts[s] for s in pick])
+    n_fin = [int(nfin64[s]) for s in pick]
+    a_fin = [int(table[int(np.searchsorted(sizes, n)), prob.sectors[s].d - 1])
+             for s, n in zip(pick, n_fin)]
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32, n_max=int(sizes[-1]))
+    psub = qmc.Plan(sub, precision=qmc.QMC_PREC_FP32, n_max=int(sizes[-1]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flows = []
+    for k, s in enumerate(pick):
+        d = prob.sectors[s].d
+        x, w = psub.flow_samples(k, n_tr, int(table[l_tr, d - 1]), shift=0)
+        fl = qmc.flow.Flow(d, seed=s)
+        fl.train(x, w, batches=batches, epochs=epochs, lr=2e-3)
+        flows.append(fl)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # per-sector choice at the final lattices: variance and cost with and without the flow
+    psub.enable_timing(True)
+    _, _, e0 = psub.integrate(n=n_fin, a=a_fin)
+    k_plain, _ = psub.read_timing()
+    for k, fl in enumerate(flows):
+        psub.attach_flow(k, fl)
+    psub.enable_timing(True)
+    _, _, e1 = psub.integrate(n=n_fin, a=a_fin)
+    k_flow, _ = psub.read_timing()
+    ratio = (e0.cpu().numpy() ** 2).sum(axis=1) / (e1.cpu().numpy() ** 2).sum(axis=1)
+    cost_ratio = k_flow / k_plain
+    keep = [k for k in range(len(pick)) if np.sqrt(ratio[k]) > cost_ratio]
+    for k in keep:
+        plan.attach_flow(pick[k], flows[k])
+    torch.cuda.synchronize()
+    select_s = time.perf_counter() - t0 - train_s
+    t1 = time.perf_counter()
+    val, err, nfin, st = plan.amp_evaluate(prob.amp_coef, epsrel=1e-4, lattice_n=sizes,
+                                           lattice_a=table, n_presample=10007,
+                                           mode=qmc.QMC_AMP_HOST)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    rel = np.abs(err[0]) / np.abs(val[0])
+    return {"flows_trained": len(pick), "training_samples": n_tr, "flows_kept": len(keep),
+            "variance_ratio_plain_over_flow": [float(r) for r in ratio],
+            "cost_ratio_flow_over_plain": float(cost_ratio),
+            "training_s": train_s, "selection_s": select_s, "evaluation_s": t2 - t1,
+            "wall_s": t2 - t0, "rounds": st["rounds"], "converged": st["converged"],
+            "max_rel_err": float(np.max(rel))}
 
 
 def scan_leg(qmc, torch, n_points: int, steps: int):
@@ -366,7 +436,9 @@ def flow_leg(qmc, torch, batches: int = 64, epochs: int = 3):
                                                "max": float(ratio.max())},
             "sectors_flow_wins": int(np.count_nonzero(ratio > 1.0)),
             "cost_ratio_flow_over_plain": float(cost),
-            "cost_adjusted_ratio_median": float(np.median(ratio / cost)),
+            # work to a given error under the n^-2 variance decay the allocation assumes:
+            # (cost per evaluation) x (lattice size), the size scaling as sqrt(variance)
+            "cost_adjusted_ratio_median": float(np.median(np.sqrt(ratio) / cost)),
             "training_wall_s": train_s,
             "flow_evals_per_s": evals / (k_flow / 1e3), "plain_evals_per_s": evals / (k_plain / 1e3),
             "flow_network_tflops": evals * flops_eval / (k_flow / 1e3) / 1e12,

@@ -25,14 +25,19 @@ struct Target {
 };
 
 // Cost of one evaluation in the units of the dense polynomial work: the slots the
-// nested Horner visits for U and F, the transform and the logarithm.
+// nested Horner visits for U and F, the transform and the logarithm; an attached flow
+// transform adds its four coupling networks, measured at 60-75 times a plain d = 6
+// evaluation (about 230 units).
+constexpr double kFlowCost = 16000.0;
+
 double cost_model(const SectorDev &sd) {
   const int d = sd.d;
   auto slots = [d](int deg) {
     const double c1 = d, c2 = d * (d + 1) / 2.0, c3 = d * (d + 1) * (d + 2) / 6.0;
     return 1.0 + c1 + (deg >= 2 ? c2 : 0.0) + (deg >= 3 ? c3 : 0.0);
   };
-  return slots(sd.u_deg) + slots(sd.f_deg) + 10.0 * d + ((sd.flags & SF_LOG) ? 40.0 : 0.0) + 20.0;
+  return slots(sd.u_deg) + slots(sd.f_deg) + 10.0 * d + ((sd.flags & SF_LOG) ? 40.0 : 0.0) +
+         20.0 + (sd.flow ? kFlowCost : 0.0);
 }
 
 size_t ladder_ceil(const std::vector<uint64_t> &lad, double want, bool *limited) {
