@@ -481,6 +481,25 @@ qmc_status qmc_bind_workspace(qmc_plan_t p, void *dev, size_t bytes, void *strea
   p->lat_valid = false;
   hipStream_t st = (hipStream_t)stream;
   int e;
+  if (!p->side.fork) {
+    hipEvent_t f;
+    if ((e = hipEventCreateWithFlags(&f, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "create fork event");
+    p->side.fork = f;
+    for (int i = 0; i < kSideStreams; ++i) {
+      hipStream_t s;
+      hipEvent_t j;
+      if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "create side stream");
+      if ((e = hipEventCreateWithFlags(&j, hipEventDisableTiming)) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return hip_fail(e, "create join event");
+      }
+      p->side.stream[i] = s;
+      p->side.join[i] = j;
+      p->side.n = i + 1;
+    }
+  }
   if ((e = hipMemcpyAsync(p->ws + p->off_sec, p->sec.data(), sizeof(SectorDev) * p->S,
                           hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "upload sectors");
@@ -674,7 +693,7 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
   if (p->cplx && (e = launch_clear_u64(la.sign_count, p->S, stream)) != hipSuccess)
     return hip_fail(e, "sign-check counter reset");
-  if ((e = launch_integrate(la, stream)) != hipSuccess) return hip_fail(e, "integrate launch");
+  if ((e = launch_integrate(la, stream, &p->side)) != hipSuccess) return hip_fail(e, "integrate launch");
   return QMC_OK;
 }
 
@@ -847,7 +866,7 @@ qmc_status qmc_median_lattice(qmc_plan_t p, const uint64_t *n_in, int32_t r,
   la.d_max = p->d_max;
   la.precision = p->precision;
   if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
-  if ((e = launch_integrate(la, stream)) != hipSuccess) return hip_fail(e, "median launch");
+  if ((e = launch_integrate(la, stream, &p->side)) != hipSuccess) return hip_fail(e, "median launch");
   std::vector<double> q((size_t)V * K);
   int32_t code = 0;
   if ((e = hipMemcpyAsync(q.data(), w + ML.q, sizeof(double) * q.size(), hipMemcpyDeviceToHost, st)) ||

@@ -163,7 +163,17 @@ int persistent_grid(int d_max, int variant, int K, int block, int *grid);
 
 // Returns a hipError_t value (0 = success).
 int launch_points(const PointsArgs &pa, unsigned grid, void *stream);
-int launch_integrate(const LaunchArgs &a, void *stream);
+// Side streams on which the per-dimension launches of one integration run beside the
+// caller's stream (default priority, non-blocking), with the events that fork them off
+// it and join them back.  n = 0: every launch on the caller's stream.
+constexpr int kSideStreams = 3;
+struct SideStreams {
+  int n;
+  void *stream[kSideStreams];
+  void *fork;
+  void *join[kSideStreams];
+};
+int launch_integrate(const LaunchArgs &a, void *stream, const SideStreams *side = nullptr);
 // complex plans: the deformed-contour integrand kernel for one dimension class, and
 // the clearing of the per-sector sign-check counters
 int launch_deform(const LaunchArgs &a, const DimLaunch &dl, void *stream);

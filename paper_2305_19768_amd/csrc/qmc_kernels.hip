@@ -255,16 +255,41 @@ bool tile_supported(int shift_tile, int shifts_per_pass, int block) {
   return shift_tile % shifts_per_pass == 0;
 }
 
-int launch_integrate(const LaunchArgs &a, void *stream) {
+int launch_integrate(const LaunchArgs &a, void *stream, const SideStreams *side) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   if (a.ev_start && (e = hipEventRecord((hipEvent_t)a.ev_start, st)) != hipSuccess) return (int)e;
+  // The per-dimension launches are independent (disjoint workgroup partials, atomic
+  // status): the first runs on the caller's stream, the others round-robin on the side
+  // streams, so that the tail of one launch overlaps the others instead of idling CUs.
+  int active = 0;
+  for (int t = 0; t < a.n_dim_launches; ++t) active += a.dims[t].blocks != 0;
+  const int n_side = (side && active > 1) ? side->n : 0;
+  if (n_side && (e = hipEventRecord((hipEvent_t)side->fork, st)) != hipSuccess) return (int)e;
+  int k = 0, used = 0;
   for (int t = 0; t < a.n_dim_launches; ++t) {
     const DimLaunch &dl = a.dims[t];
     if (dl.blocks == 0) continue;
-    e = dl.flow ? (hipError_t)launch_flow_integrate(a, dl, st)
-                : dl.deform ? (hipError_t)launch_deform(a, dl, st) : launch_class(a, dl, st);
+    hipStream_t ls = st;
+    if (n_side && k > 0) {
+      const int i = (k - 1) % n_side;
+      if (i >= used) {
+        if ((e = hipStreamWaitEvent((hipStream_t)side->stream[i], (hipEvent_t)side->fork, 0)) !=
+            hipSuccess)
+          return (int)e;
+        used = i + 1;
+      }
+      ls = (hipStream_t)side->stream[i];
+    }
+    ++k;
+    e = dl.flow ? (hipError_t)launch_flow_integrate(a, dl, ls)
+                : dl.deform ? (hipError_t)launch_deform(a, dl, ls) : launch_class(a, dl, ls);
     if (e != hipSuccess) return (int)e;
+  }
+  for (int i = 0; i < used; ++i) {
+    if ((e = hipEventRecord((hipEvent_t)side->join[i], (hipStream_t)side->stream[i])) != hipSuccess ||
+        (e = hipStreamWaitEvent(st, (hipEvent_t)side->join[i], 0)) != hipSuccess)
+      return (int)e;
   }
   if (a.ev_stop && (e = hipEventRecord((hipEvent_t)a.ev_stop, st)) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(qmc_reduce_kernel, dim3((unsigned)(a.n_sectors * a.m)), dim3(64), 0, st, a);

@@ -60,8 +60,16 @@ struct qmc_plan_s {
   bool timing = false;
   std::vector<hipEvent_t> ev;   // pairs: start, stop
   size_t ev_used = 0;
+  // side streams of the concurrent per-dimension launches (created when the workspace
+  // is bound, on the workspace's device)
+  qmc::SideStreams side{};
   ~qmc_plan_s() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (int i = 0; i < side.n; ++i) {
+      (void)hipEventDestroy((hipEvent_t)side.join[i]);
+      (void)hipStreamDestroy((hipStream_t)side.stream[i]);
+    }
+    if (side.fork) (void)hipEventDestroy((hipEvent_t)side.fork);
   }
 };
 
