@@ -651,7 +651,7 @@ def main():
                    "lattice_points_per_step": int(sum(s.n for s in prob.sectors))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "qmc_integrate_kernel<D,3,S> (d = 4, 5, 6)",
+                     "traffic": traffic, "kernel": "qmc_integrate_kernel<D,3,2> (d = 4, 5, 6; concurrent launches, kernel_ms is their joint span)",
                      "kernel_ms": kernel_ms / max(launches, 1),
                      "algorithmic_flops_per_launch": flops_launch,
                      "flops_per_eval": flops_launch / evals},
