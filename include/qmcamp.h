@@ -159,7 +159,8 @@ size_t qmc_workspace_bytes(qmc_plan_t plan);
 /*
  * qmc_bind_workspace -- hand the plan a caller-owned device buffer of at least
  * qmc_workspace_bytes() bytes (256-byte aligned) and upload the packed tables on
- * `stream`.  The buffer must stay valid until the plan is freed or rebound.
+ * `stream`.  The buffer must stay valid until the plan is freed or rebound.  The first
+ * bind also creates the plan's side streams and events on the current device.
  * Errors: QMC_E_INVAL (NULL / misaligned), QMC_E_NOMEM (too small), QMC_E_DEVICE.
  */
 qmc_status qmc_bind_workspace(qmc_plan_t plan, void *dev_workspace, size_t bytes, void *stream);
@@ -195,7 +196,11 @@ qmc_status qmc_set_shifts(qmc_plan_t plan, const double *shifts, void *stream);
  * regardless.  Sums are compensated (TwoSum) within each
  * thread, across the wavefront and across workgroups, in a fixed order, so results
  * are bitwise reproducible.  Non-finite sums are reported by qmc_query_status, not
- * here (the call does not synchronize).
+ * here (the call does not synchronize).  The launches of the different dimension
+ * classes run concurrently on up to three side streams of the plan (created by
+ * qmc_bind_workspace, non-blocking, default priority, destroyed by qmc_plan_free),
+ * forked from `stream` and joined back to it with events inside the call: work queued
+ * on `stream` afterwards sees every result, as with a single stream.
  */
 qmc_status qmc_integrate(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, void *stream,
                          double *dev_q, double *dev_mean, double *dev_err);
