@@ -599,6 +599,7 @@ def main():
     kernel_ms, launches = plan.read_timing()
     plan.enable_timing(False)
     plan.check_status()
+    mean64, err64 = out[1].cpu().numpy().copy(), out[2].cpu().numpy().copy()
 
     fp32 = None
     if not args.no_fp32:
@@ -619,10 +620,18 @@ def main():
         torch.cuda.synchronize()
         e32 = time.perf_counter() - t1
         plan32.check_status()
+        import numpy as np
+        mean32 = out[1].cpu().numpy()
+        dev = np.abs(mean32 - mean64)
+        rel = dev / np.abs(mean64)
         fp32 = {"value": prob.evals() * args.steps / e32, "unit": "evals/s",
                 "ms_per_step": e32 / args.steps * 1e3,
                 "note": "FP32 integrand, FP64 lattice points and accumulation",
-                "launch": tune32}
+                "launch": tune32,
+                # the FP32 form's error against the FP64 form, per result (sector, order)
+                "rel_dev_vs_fp64": {"median": float(np.median(rel)), "max": float(rel.max()),
+                                    "per_sector_max": [float(f"{v:.3g}") for v in rel.max(axis=1)]},
+                "dev_over_fp64_shift_error_max": float((dev / err64).max())}
         del plan32
 
     if args.copy_probe:
