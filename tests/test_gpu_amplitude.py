@@ -125,6 +125,18 @@ def test_device_mode_fp32_meets_target(qmc):
     assert np.all(np.abs(val[0] - ov[0]) <= 5 * (np.abs(err[0]) + np.abs(oe[0])))
 
 
+def test_device_mode_with_more_sectors_than_round_threads(qmc):
+    # 600 sectors: each thread of the round kernel takes a run of two or three sectors
+    # when it lays out the next round's workgroups; rounds, final lattices and sums as
+    # in the oracle's adaptive loop
+    prob = W.amplitude(seed=4, n_integrals=12, n_sectors=600, d_lo=2, d_hi=4, m=4, n0=1009)
+    sizes, a_tab = ladder(seed=3)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    val, err, nfin, st = _compare(qmc, prob, np.array([prob.amp_coef]), sizes, a_tab, tau, 1e-5,
+                                  1009, mode=1)
+    assert st["rounds"] >= 3 and np.count_nonzero(nfin > 1009) > 100
+
+
 @pytest.mark.parametrize("mixed", [False, True])
 def test_device_mode_fp32_against_fp64(qmc, mixed):
     # The FP32 batched form against the FP64 one on the same ladder: same rounds and final

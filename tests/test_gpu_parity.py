@@ -297,3 +297,16 @@ def test_one_loop_throughput_size(qmc):
     g = _gauss_3d_one_loop(prob, 96)
     print("estimate", mean, "error", err, "gauss", g, flush=True)
     assert np.all(np.abs(mean - g) < 5 * err + 1e-12 * np.abs(g))
+
+
+def test_many_dimension_classes_run_concurrently(qmc):
+    """Eight dimension classes (d = 1..8) in one plan: the class launches share the
+    caller's stream and the plan's three side streams (round-robin), and every sector
+    still matches the oracle; a second call agrees bit for bit."""
+    rng = np.random.default_rng(21)
+    secs = [W._two_loop_sector(rng, d, W.next_prime(600 + 97 * d), 0) for d in range(1, 9)]
+    prob = W.Problem(sectors=secs, order_lo=-2, m=4,
+                     shifts=[W.uniform_shifts(rng, 4, s.d) for s in secs])
+    plan, q, _, _ = _parity(qmc, prob)
+    q2 = plan.integrate()[0].cpu().numpy()
+    assert np.array_equal(q.view(np.uint64), q2.view(np.uint64))
