@@ -158,6 +158,16 @@ struct FlowBack {
 
 __device__ __forceinline__ bool conditioning(int j, int l) { return (j & 1) == (l & 1); }
 
+// Orders the LDS exchanges of one wavefront, which stay within the wave's own FlowXchg /
+// FlowBack area: a wave's LDS operations complete in issue order, so the lanes only need
+// the compiler not to move accesses across this point (no workgroup barrier: the other
+// waves of the workgroup run on independently).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One coupling layer applied to the lane's point (z in logit space, d coordinates),
 // all lanes of the workgroup together.  dir 0: sampling (inverse affine), 1: density.
 // Network input of layer l for the lane's point: the kept coordinates, then the c
@@ -180,7 +190,7 @@ __device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBia
                                          int l, int dir, int lane, double (&z)[DMAX],
                                          double &ssum) {
   put_input<DMAX>(xc.zin + lane * kFlowIn, z, d, c, cond, l);
-  __syncthreads();
+  wave_sync();
   v4f o[4];
   flow_mlp<false>(pk, bs, xc.zin, lane, o, nullptr, nullptr);
   const int p = lane & 15, g = lane >> 4;
@@ -188,7 +198,7 @@ __device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBia
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int i = 0; i < 4; ++i) xc.out[(16 * q + p) * kFlowOut + 4 * g + i] = o[q][i];
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (j >= d || conditioning(j, l)) continue;
@@ -197,7 +207,7 @@ __device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBia
     z[j] = dir == 0 ? (z[j] - t) * exp(-s) : __builtin_fma(z[j], exp(s), t);
     ssum += s;
   }
-  __syncthreads();
+  wave_sync();
 }
 
 // ------------------------------------------------------------------- packing
@@ -393,14 +403,14 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) zl[j] = valid ? a.zs[((int64_t)l * a.count + i) * 8 + j] : 0.0;
     put_input<8>(X.zin + lane * kFlowIn, zl, d, c, cf, l);
-    __syncthreads();
+    wave_sync();
     v4f o[4], h1[4][4], h2[4][4];
     flow_mlp<true>(pl, sb[l], X.zin, lane, o, h1, h2);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) X.out[(16 * q + p) * kFlowOut + 4 * g + ii] = o[q][ii];
-    __syncthreads();
+    wave_sync();
     // coupling backward on the lane's own point: gradient of the 2d network outputs
     float dof[kFlowOut];
 #pragma unroll
@@ -425,7 +435,7 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
       for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft, 64);
       if (lane == 0 && r < 2 * d) G[po.b3 + r] = v;
     }
-    __syncthreads();
+    wave_sync();
 
     // dh2 = (W3^T do) (1 - h2^2)
     v4f dh[4][4];
@@ -457,12 +467,12 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
         if (g == q)
 #pragma unroll
           for (int r = 0; r < kFlowOut; ++r) Bk.tb[r * 16 + p] = Bk.gout[lane * kFlowOut + r];
-        __syncthreads();
+        wave_sync();
         const v4s Ao = *(const v4s *)(Bk.tb + p * 16 + 4 * g);
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           acc[c] = mfma16(Ao, *(const v4s *)(Bk.ta + (16 * c + p) * 16 + 4 * g), acc[c]);
-        __syncthreads();
+        wave_sync();
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c)
@@ -514,7 +524,7 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
       for (int q = 0; q < 4; ++q) {
         put_tile(Bk.ta, h1[q], p, g);
         put_tile(Bk.tb, dh[q], p, g);
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const v4s Bh = *(const v4s *)(Bk.ta + (16 * c + p) * 16 + 4 * g);
@@ -522,7 +532,7 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
           for (int r = 0; r < 4; ++r)
             acc[r][c] = mfma16(*(const v4s *)(Bk.tb + (16 * r + p) * 16 + 4 * g), Bh, acc[r][c]);
         }
-        __syncthreads();
+        wave_sync();
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -559,12 +569,12 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
         if (g == q)
 #pragma unroll
           for (int r = 0; r < kFlowIn; ++r) Bk.tb[r * 16 + p] = X.zin[lane * kFlowIn + r];
-        __syncthreads();
+        wave_sync();
         const v4s Bv = *(const v4s *)(Bk.tb + p * 16 + 4 * g);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           acc[r] = mfma16(*(const v4s *)(Bk.ta + (16 * r + p) * 16 + 4 * g), Bv, acc[r]);
-        __syncthreads();
+        wave_sync();
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -591,11 +601,11 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) X.out[(16 * q + p) * kFlowOut + 4 * g + ii] = dv[q][ii];
-      __syncthreads();
+      wave_sync();
 #pragma unroll
       for (int j = 0; j < 8; ++j)
         if (j < d && conditioning(j, l)) dz[j] += (double)X.out[lane * kFlowOut + j];
-      __syncthreads();
+      wave_sync();
     }
   }
 }
