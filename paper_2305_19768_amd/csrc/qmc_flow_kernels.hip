@@ -785,8 +785,11 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
   }
 }
 
+// Two waves per SIMD (256 registers, a few spilled at d >= 4): with one, every latency of
+// the network's LDS exchanges, matrix products and transcendentals was exposed.
 template <int D, bool CPLX>
-__global__ __launch_bounds__(256) void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   __shared__ FlowIntegrateLds L;
   const int64_t b = block_base + blockIdx.x;
