@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qmc_integrate_kernel_two_loop_traffic.json")
 
 
@@ -624,8 +625,13 @@ def main():
         mean32 = out[1].cpu().numpy()
         dev = np.abs(mean32 - mean64)
         rel = dev / np.abs(mean64)
+        flops32 = sum(algorithmic_flops(sec, m) * sec.n * m for sec in prob.sectors)
         fp32 = {"value": prob.evals() * args.steps / e32, "unit": "evals/s",
                 "ms_per_step": e32 / args.steps * 1e3,
+                "roofline": {"bound": "alu", "achieved": flops32 / (e32 / args.steps) / 1e12,
+                             "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": flops32 / (e32 / args.steps) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                             "timing": "wall clock of the step"},
                 "note": "FP32 integrand, FP64 lattice points and accumulation",
                 "launch": tune32,
                 # the FP32 form's error against the FP64 form, per result (sector, order)
