@@ -106,9 +106,16 @@ def cpu_baseline(problem, threads: int):
         list(ex.map(run, order))
     dt = time.perf_counter() - t0
     evals = int(sum(s.n for s in problem.sectors))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"all {len(problem.sectors)} sectors x 1 of {problem.m} shifts "
-                      f"({evals} evaluations, FP64 scalar C, {dt:.1f} s)"}
+                      f"({evals} evaluations, FP64 scalar C, {dt:.1f} s)",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def amplitude_leg(qmc, torch, repeats: int):
