@@ -339,7 +339,12 @@ enum { QMC_AMP_HOST = 0, QMC_AMP_DEVICE = 1 };
  * Korobov parameter of size lattice_n[l] for a sector of dimension d is
  * lattice_a[l * QMC_MAX_DIM + d - 1].  tau: per-sector cost of one evaluation (any
  * unit), or NULL for the library's cost model (dense polynomial slots + transform +
- * logarithm work).
+ * logarithm work, plus the network of an attached flow).
+ * mode QMC_AMP_DEVICE runs every round on the device: a round kernel, one persistent
+ * kernel over the sectors without a flow (these must be korobov3 with integer powers of
+ * U and F) and one over the flow-transformed sectors, then the reduction; the host only
+ * polls the state between batches of rounds.  QMC_AMP_HOST integrates each round with
+ * qmc_integrate.  Both give the same rounds and lattice sizes.
  */
 typedef struct {
     double epsrel, epsabs;

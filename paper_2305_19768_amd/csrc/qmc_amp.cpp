@@ -58,23 +58,33 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
                       std::chrono::steady_clock::time_point t_start) {
   const int S = p->S, K = p->K;
   for (int s = 0; s < S; ++s)
-    if (p->sec[s].flow)
-      return fail(QMC_E_INVAL, "device mode does not integrate flow-transformed sectors "
-                               "(sector %d has a flow attached); use the host mode", s);
-  for (int s = 0; s < S; ++s)
-    if (!(p->sec[s].flags & SF_FAST))
+    if (!p->sec[s].flow && !(p->sec[s].flags & SF_FAST))
       return fail(QMC_E_INVAL, "device mode evaluates sectors of the common shape only "
-                               "(korobov3, integer powers of U and F); sector %d is not", s);
+                               "(korobov3, integer powers of U and F, or a flow attached); "
+                               "sector %d is not", s);
   if (T > kAmpMaxSums) return fail(QMC_E_INVAL, "device mode: at most %d sums", kAmpMaxSums);
   if ((int)lad.size() > kAmpMaxLattice)
     return fail(QMC_E_INVAL, "device mode: at most %d lattice sizes", kAmpMaxLattice);
   const bool f32 = p->precision == QMC_PREC_FP32;
+  // workgroup order of the batched form: the sectors without a flow (for the persistent
+  // kernel), then those with one (for the flow persistent kernel), each in plan order
+  std::vector<int32_t> order_dev;
+  order_dev.reserve(S);
+  for (int q = 0; q < S; ++q)
+    if (!p->sec[p->order[q]].flow) order_dev.push_back(p->order[q]);
+  const int n_plain = (int)order_dev.size();
+  for (int q = 0; q < S; ++q)
+    if (p->sec[p->order[q]].flow) order_dev.push_back(p->order[q]);
   bool all_f32 = true;
-  for (int s = 0; s < S; ++s) all_f32 = all_f32 && (p->sec[s].flags & SF_F32OK);
+  for (int s = 0; s < S; ++s)
+    all_f32 = all_f32 && (p->sec[s].flow || (p->sec[s].flags & SF_F32OK));
   const int variant = !f32 ? kPersistentF64 : all_f32 ? kPersistentF32 : kPersistentF32Mixed;
   int &grid = p->persistent_grid[variant];
   int e;
   if (!grid && (e = persistent_grid(p->d_max, variant, K, p->block, &grid)) != hipSuccess)
+    return hip_fail(e, "occupancy query");
+  int flow_grid = 0;
+  if (n_plain < S && (e = persistent_flow_grid(p->block, &flow_grid)) != hipSuccess)
     return hip_fail(e, "occupancy query");
   // ---- device tables in the workspace
   char *base = p->ws + p->off_amp;
@@ -88,6 +98,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   int32_t *d_integral = (int32_t *)take(4 * S), *d_dims = (int32_t *)take(4 * S);
   int32_t *d_lidx = (int32_t *)take(4 * S), *d_active = (int32_t *)take(4 * S);
   int32_t *d_iptr = (int32_t *)take(4 * (NI + 1)), *d_isec = (int32_t *)take(4 * S);
+  int32_t *d_order = (int32_t *)take(4 * S);
   double *d_want = (double *)take(8 * S), *d_tau = (double *)take(8 * S);
   double *d_c2 = (double *)take(8 * kAmpMaxSums * NI * K);
   double *d_cre = (double *)take(8 * kAmpMaxSums * NI * K);
@@ -127,6 +138,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   if ((e = up(dst, &init, sizeof init)) || (e = up(d_integral, integral.data(), 4 * S)) ||
       (e = up(d_dims, p->dims.data(), 4 * S)) || (e = up(d_lidx, lidx.data(), 4 * S)) ||
       (e = up(d_iptr, iptr.data(), 4 * (NI + 1))) || (e = up(d_isec, isec.data(), 4 * S)) ||
+      (e = up(d_order, order_dev.data(), 4 * S)) ||
       (e = up(d_tau, tau.data(), 8 * S)) || (e = up(d_c2, c2.data(), 8 * c2.size())) ||
       (e = up(d_cre, cre.data(), 8 * cre.size())) || (e = up(d_cim, cim.data(), 8 * cim.size())) ||
       (e = up(d_ln, lad.data(), 8 * lad.size())) ||
@@ -152,7 +164,8 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   g.int_ptr = d_iptr;
   g.int_sec = d_isec;
   g.dims = d_dims;
-  g.order = (const int32_t *)(p->ws + p->off_order);
+  g.order = d_order;
+  g.n_plain = n_plain;
   g.lidx = d_lidx;
   g.active = d_active;
   g.unmet = d_unmet;
@@ -181,7 +194,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   la.shifts = (const double *)(p->ws + p->off_shift);
   la.lat = (const LatticeDev *)(p->ws + p->off_lat);
   la.block_begin = (const int64_t *)(p->ws + p->off_begin);
-  la.order = (const int32_t *)(p->ws + p->off_order);
+  la.order = d_order;
   la.partial = (double *)(p->ws + p->off_partial);
   la.q = (double *)(p->ws + p->off_q);
   la.mean = (double *)(p->ws + p->off_mean);
@@ -205,6 +218,9 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
       if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");
       if ((e = launch_persistent(la, dst, p->d_max, variant, (unsigned)grid, stream)) != hipSuccess)
         return hip_fail(e, "persistent kernel");
+      if (n_plain < S &&
+          (e = launch_persistent_flow(la, dst, (unsigned)flow_grid, stream)) != hipSuccess)
+        return hip_fail(e, "flow persistent kernel");
       if ((e = launch_reduce_stats(la, stream)) != hipSuccess) return hip_fail(e, "reduction");
     }
     if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");

@@ -250,12 +250,15 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
     L.n_chunks = g.active[s] ? (int32_t)((L.n + chunk - 1) / chunk) : 0;
     L.block_begin = b;
     g.block_begin[q] = b;
+    if (q == g.n_plain) st->plain_blocks = b;
     b += (int64_t)L.n_chunks * tiles;
   }
   if (t == 0) {
     g.block_begin[S] = total_b;
     st->total_blocks = total_b;
+    if (g.n_plain == S) st->plain_blocks = total_b;
     st->work_counter = 0;
+    st->flow_counter = 0;
     st->evaluations += total_ev;
     st->rounds += 1;
   }
@@ -263,8 +266,8 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
 
 // -------------------------------------------------------- persistent kernel
 
-// Every sector of the fast path, all dimensions up to DMAX, in one launch: each
-// workgroup takes the next work item (sector, chunk, shift tile) from the round's
+// Every sector of the fast path without a flow, all dimensions up to DMAX, in one launch:
+// each workgroup takes the next work item (sector, chunk, shift tile) from the round's
 // atomic counter until none is left, and writes its compensated partial exactly where
 // the per-dimension launch would, so the reduction and its order are unchanged.
 // F32 with FB: sectors without SF_F32OK fall back to the FP64 form; F32 without FB: every
@@ -305,7 +308,7 @@ void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   __shared__ int64_t item;
   if (st->done) return;
-  const int64_t total = st->total_blocks;
+  const int64_t total = st->plain_blocks;   // the flow sectors' items follow
   const int T = a.shift_tile;
   for (;;) {
     __syncthreads();

@@ -87,7 +87,7 @@ static void layout(qmc_plan_s *p) {
   {  // batched amplitude evaluation: state and tables, bounded by kAmpMaxSums sums and
      // kAmpMaxLattice table entries
     const size_t S = p->S, NI = p->n_integrals, K = p->K;
-    p->amp_bytes = align256(sizeof(AmpState)) + 5 * align256(4 * S) + align256(4 * (NI + 1)) +
+    p->amp_bytes = align256(sizeof(AmpState)) + 6 * align256(4 * S) + align256(4 * (NI + 1)) +
                    2 * align256(8 * S) +
                    3 * align256(8 * kAmpMaxSums * NI * K) + 2 * align256(8 * NI * K) +
                    4 * align256(8 * kAmpMaxSums * K) + align256(4 * kAmpMaxSums * K) +

@@ -785,6 +785,19 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
   }
 }
 
+// The forward operands and biases of sector s's flow, into the workgroup's LDS.
+__device__ __forceinline__ void stage_flow(const LaunchArgs &a, int s, FlowIntegrateLds &L) {
+  const char *flow = (const char *)a.sectors[s].flow;
+  const int d = a.sectors[s].d, c = a.sectors[s].flow_cond;
+  const uint4 *src = (const uint4 *)(flow + flow_off_pack(d, c));
+  for (int l = 0; l < kFlowLayers; ++l) {
+    const uint4 *sl = src + (int64_t)l * kPackLayer / 8;
+    uint4 *dl = (uint4 *)L.pack[l];
+    for (int e = threadIdx.x; e < kPackFwd / 8; e += blockDim.x) dl[e] = sl[e];
+  }
+  stage_bias(flow, d, c, L.bias, threadIdx.x, blockDim.x);
+}
+
 // Two waves per SIMD (256 registers, a few spilled at d >= 4): with one, every latency of
 // the network's LDS exchanges, matrix products and transcendentals was exposed.
 template <int D, bool CPLX>
@@ -795,17 +808,7 @@ void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
   const int64_t b = block_base + blockIdx.x;
   const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
   const LatticeDev *__restrict__ lt = a.lat + s;
-  const char *flow = (const char *)a.sectors[s].flow;
-  {   // stage the flow's forward operands and biases
-    const int d = a.sectors[s].d, c = a.sectors[s].flow_cond;
-    const uint4 *src = (const uint4 *)(flow + flow_off_pack(d, c));
-    for (int l = 0; l < kFlowLayers; ++l) {
-      const uint4 *sl = src + (int64_t)l * kPackLayer / 8;
-      uint4 *dl = (uint4 *)L.pack[l];
-      for (int e = threadIdx.x; e < kPackFwd / 8; e += blockDim.x) dl[e] = sl[e];
-    }
-    stage_bias(flow, d, c, L.bias, threadIdx.x, blockDim.x);
-  }
+  stage_flow(a, s, L);
   __syncthreads();
   const int64_t local = b - lt->block_begin;
   const int nch = lt->n_chunks;
@@ -822,6 +825,60 @@ void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
     double *out = a.partial + (b * cols + threadIdx.x) * 2;
     out[0] = r.s;
     out[1] = r.c;
+  }
+}
+
+// The batched form's flow-transformed sectors (real contour): the round's work items
+// [plain_blocks, total_blocks) drained from their own atomic counter, one item per
+// workgroup at a time; a workgroup restages the flow's operands only when its sector
+// changes.  Every workgroup exits once the counter passes the round's total.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void qmc_persistent_flow_kernel(LaunchArgs a, AmpState *st) {
+  __shared__ double red[kMaxWaves][kMaxTile * 4][2];
+  __shared__ FlowIntegrateLds L;
+  __shared__ int64_t item;
+  __shared__ int staged;
+  if (st->done) return;
+  const int64_t begin = st->plain_blocks, total = st->total_blocks;
+  if (threadIdx.x == 0) staged = -1;
+  const int T = a.shift_tile;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = begin + (int64_t)atomicAdd(&st->flow_counter, 1u);
+    __syncthreads();
+    const int64_t b = item;
+    if (b >= total) break;
+    const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
+    if (s != staged) {
+      stage_flow(a, s, L);
+      __syncthreads();
+      if (threadIdx.x == 0) staged = s;
+    }
+    const LatticeDev *__restrict__ lt = a.lat + s;
+    const int64_t local = b - lt->block_begin;
+    const int nch = lt->n_chunks;
+    const int tile_id = (int)(local / nch);
+    const int64_t chunk_id = local - (int64_t)tile_id * nch;
+    switch (a.sectors[s].d) {
+      case 1: flow_block<1, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      case 2: flow_block<2, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      case 3: flow_block<3, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      case 4: flow_block<4, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      case 5: flow_block<5, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      case 6: flow_block<6, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      case 7: flow_block<7, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+      default: flow_block<8, false>(a, s, tile_id * T, T, chunk_id, red, L); break;
+    }
+    __syncthreads();
+    const int nwaves = blockDim.x >> 6;
+    const int cols = T * a.K;
+    if ((int)threadIdx.x < cols) {
+      DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
+      for (int w = 1; w < nwaves; ++w) r = dd_combine(r, DD{red[w][threadIdx.x][0], red[w][threadIdx.x][1]});
+      double *out = a.partial + (b * cols + threadIdx.x) * 2;
+      out[0] = r.s;
+      out[1] = r.c;
+    }
   }
 }
 
@@ -873,6 +930,24 @@ static void launch_flow_integrate_p(const LaunchArgs &a, const DimLaunch &dl, hi
     case 7: hipLaunchKernelGGL((qmc_flow_integrate_kernel<7, CPLX>), grid, blk, 0, st, a, dl.base); break;
     default: hipLaunchKernelGGL((qmc_flow_integrate_kernel<8, CPLX>), grid, blk, 0, st, a, dl.base); break;
   }
+}
+
+int launch_persistent_flow(const LaunchArgs &a, AmpState *st, unsigned grid, void *stream) {
+  hipLaunchKernelGGL(qmc_persistent_flow_kernel, dim3(grid), dim3(a.block), 0,
+                     (hipStream_t)stream, a, st);
+  return (int)hipGetLastError();
+}
+
+int persistent_flow_grid(int block, int *grid) {
+  int dev = 0, cus = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return (int)e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)qmc_persistent_flow_kernel,
+                                                   block, 0);
+  if (e != hipSuccess) return (int)e;
+  *grid = cus * (per > 0 ? per : 1);
+  return 0;
 }
 
 int launch_flow_integrate(const LaunchArgs &a, const DimLaunch &dl, void *stream) {

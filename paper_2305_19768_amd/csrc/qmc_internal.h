@@ -133,13 +133,16 @@ struct AmpState {
   int64_t evaluations;
   int64_t total_blocks;  // work items of the current round
   double max_eps;
-  double pad;
+  int64_t plain_blocks;  // work items of the sectors without a flow (they come first)
+  uint32_t flow_counter; // flow persistent kernel's next work item (after plain_blocks)
+  int32_t pad;
 };
 
 struct AmpArgs {
   AmpState *state;
   int32_t S, K, T, NI, m, tile, block, n_lattice, max_rounds;
   int32_t P;                       // Laurent terms per coefficient (tables [T][NI][P])
+  int32_t n_plain;                 // sectors without a flow: the first n_plain of `order`
   double epsrel, epsabs, alpha;
   const int32_t *integral, *dims, *order;
   const int32_t *int_ptr, *int_sec;   // sectors of integral c: int_sec[int_ptr[c] .. int_ptr[c+1]), ascending
@@ -160,6 +163,10 @@ enum : int { kPersistentF64 = 0, kPersistentF32Mixed = 1, kPersistentF32 = 2 };
 int launch_persistent(const LaunchArgs &a, AmpState *st, int d_max, int variant, unsigned grid,
                       void *stream);
 int persistent_grid(int d_max, int variant, int K, int block, int *grid);
+// The batched form's sectors with an attached flow: work items [plain_blocks,
+// total_blocks) of the round, drained like the persistent kernel's.
+int launch_persistent_flow(const LaunchArgs &a, AmpState *st, unsigned grid, void *stream);
+int persistent_flow_grid(int block, int *grid);
 
 // Returns a hipError_t value (0 = success).
 int launch_points(const PointsArgs &pa, unsigned grid, void *stream);

@@ -125,6 +125,39 @@ def test_device_mode_fp32_meets_target(qmc):
     assert np.all(np.abs(val[0] - ov[0]) <= 5 * (np.abs(err[0]) + np.abs(oe[0])))
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_device_mode_with_flow_sectors_matches_host_mode(qmc, fp32):
+    # flows attached to three sectors: the batched form integrates them in the flow
+    # persistent kernel beside the plain sectors; same rounds and lattices as the host
+    # loop, sums equal to rounding order
+    from oracle import flow as OF
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    prec = qmc.QMC_PREC_FP32 if fp32 else qmc.QMC_PREC_FP64
+    out = {}
+    for mode in (qmc.QMC_AMP_HOST, qmc.QMC_AMP_DEVICE):
+        plan = qmc.Plan(prob, n_max=int(sizes[-1]), precision=prec)
+        flows = []
+        for s in (1, 5, 9):
+            d = prob.sectors[s].d
+            p = OF.init_params(d, seed=30 + s, zero_last=False, scale=0.7)
+            fl = qmc.flow.Flow(d, params=OF.flatten(p))
+            plan.attach_flow(s, fl)
+            flows.append(fl)
+        out[mode] = plan.amp_evaluate(prob.amp_coef, epsrel=2e-6, lattice_n=sizes,
+                                      lattice_a=a_tab, tau=tau, n_presample=1009, mode=mode)
+        del plan
+    vh, eh, nh, sh = out[qmc.QMC_AMP_HOST]
+    vd, ed, nd, sd = out[qmc.QMC_AMP_DEVICE]
+    print("rounds", sh["rounds"], sd["rounds"], "n", nh, nd, flush=True)
+    assert sd["rounds"] == sh["rounds"] and np.array_equal(nd, nh)
+    assert sd["evaluations"] == sh["evaluations"]
+    scale = np.abs(vh) + np.abs(eh)
+    assert np.all(np.abs(vd - vh) <= 1e-12 * scale)
+    assert np.allclose(ed.real, eh.real, rtol=1e-8, atol=1e-12 * np.max(scale))
+
+
 def test_device_mode_with_more_sectors_than_round_threads(qmc):
     # 600 sectors: each thread of the round kernel takes a run of two or three sectors
     # when it lays out the next round's workgroups; rounds, final lattices and sums as
