@@ -389,6 +389,9 @@ def scan_flow_leg(qmc, torch, n_points: int = 10, train_points: int = 3, batches
             "training_wall_s": train_s,
             "instances_flow_kept": int(keep.sum()), "instances": int(len(keep)),
             "kept_at_unseen_points": int(keep[~train_mask].sum()),
+            # kept and cheaper to a given error than plain QMC (sqrt of the variance ratio
+            # above the cost ratio, the n^-2 variance decay of the allocation)
+            "instances_flow_pays": int(np.count_nonzero(keep & (np.sqrt(ratio) > cost))),
             "variance_ratio_plain_over_flow": {"median": float(np.median(ratio)),
                                                "max": float(ratio.max())},
             "cost_ratio_flow_over_plain": float(cost),
