@@ -47,9 +47,10 @@ size_t ladder_ceil(const std::vector<uint64_t> &lad, double want, bool *limited)
   return lad.size() - 1;
 }
 
-// Batched form: the rounds run on the device (round kernel, persistent integrand
-// kernel, reduction, statistics); the host queues a few rounds at a time and only reads
-// the state word between them.
+// Batched form: the rounds run on the device (round kernel, persistent integrand kernel
+// over the plain sectors, a second one over the flow-transformed sectors, reduction,
+// statistics); the host queues a few rounds at a time and only reads the state word
+// between them.
 qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<double> &cre,
                       const std::vector<double> &cim, const std::vector<double> &c2,
                       const std::vector<uint64_t> &lad, const qmc_amp_options *opt,
