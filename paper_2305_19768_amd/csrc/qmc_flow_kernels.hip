@@ -608,20 +608,37 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
 }
 
 // grad[k] = sum over wavefronts of gpart[w][k] (fixed order); loss likewise.
-__global__ void flow_reduce_kernel(char *flow, int d, int c, const float *gpart,
-                                   const double *lpart, int64_t waves, double *loss) {
+// A workgroup of 256 takes 64 parameters; its four wavefronts sum the slices w = g,
+// g + 4, ... (g = wavefront) for them, and the four partial sums are added in order g =
+// 0..3.  The first workgroup also sums the loss over its 256 threads and a fixed tree.
+// Every assignment is fixed, so the sums are deterministic.
+constexpr int kReduceParams = 64;
+__global__ __launch_bounds__(256) void flow_reduce_kernel(char *flow, int d, int c,
+                                                          const float *gpart,
+                                                          const double *lpart, int64_t waves,
+                                                          double *loss) {
+  __shared__ double part[4][kReduceParams];
+  __shared__ double lp[256];
   const int64_t P = flow_params(d, c);
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int kk = threadIdx.x & (kReduceParams - 1), g = threadIdx.x / kReduceParams;
+  const int64_t k = (int64_t)blockIdx.x * kReduceParams + kk;
   float *grad = (float *)(flow + flow_off_grad(d, c));
-  if (k < P) {
-    double s = 0.0;
-    for (int64_t w = 0; w < waves; ++w) s += (double)gpart[w * P + k];
-    grad[k] = (float)s;
-  }
-  if (k == 0 && loss) {
-    double s = 0.0;
-    for (int64_t w = 0; w < waves; ++w) s += lpart[w];
-    *loss = s;
+  double s = 0.0;
+  if (k < P)
+    for (int64_t w = g; w < waves; w += 4) s += (double)gpart[w * P + k];
+  part[g][kk] = s;
+  __syncthreads();
+  if (g == 0 && k < P) grad[k] = (float)(((part[0][kk] + part[1][kk]) + part[2][kk]) + part[3][kk]);
+  if (blockIdx.x == 0 && loss) {
+    double t = 0.0;
+    for (int64_t w = threadIdx.x; w < waves; w += 256) t += lpart[w];
+    lp[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) lp[threadIdx.x] += lp[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = lp[0];
   }
 }
 
@@ -1000,7 +1017,8 @@ int launch_flow_grad(void *flow, int d, int c, const double *x, const double *w,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
   const int64_t P = flow_params(d, c);
-  hipLaunchKernelGGL(flow_reduce_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(flow_reduce_kernel, dim3((unsigned)((P + kReduceParams - 1) / kReduceParams)),
+                     dim3(256), 0, st,
                      (char *)flow, d, c, (const float *)gpart, (const double *)lpart,
                      (int64_t)blocks * 4, loss);
   return (int)hipGetLastError();
