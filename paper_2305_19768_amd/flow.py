@@ -3,6 +3,7 @@ marshalling only; every step runs in the library's kernels).  See the flow secti
 ``include/qmcamp.h`` for the transform, its parameter layout and the training rule."""
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -28,10 +29,21 @@ def _torch():
     return torch
 
 
-def _stream(stream=None):
+@contextlib.contextmanager
+def _ordered(stream=None):
+    """The stream to launch on, ordered after the current stream's work (where the inputs
+    were prepared) and before its later work (where the outputs are read and the
+    temporaries freed)."""
     torch = _torch()
-    st = torch.cuda.current_stream() if stream is None else stream
-    return ctypes.c_void_p(st.cuda_stream)
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        yield ctypes.c_void_p(cur.cuda_stream)
+        return
+    stream.wait_stream(cur)
+    try:
+        yield ctypes.c_void_p(stream.cuda_stream)
+    finally:
+        cur.wait_stream(stream)
 
 
 def param_count(d: int, n_cond: int = 0) -> int:
@@ -79,9 +91,10 @@ class Flow:
         P = param_count(self.d, self.n_cond)
         if v.size != P:
             raise ValueError(f"expected {P} parameters, got {v.size}")
-        _check(lib().qmc_flow_load(_dp(self.ptr), self.d, self.n_cond,
-                                   v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(stream)),
-               "qmc_flow_load")
+        with _ordered(stream) as sp:
+            _check(lib().qmc_flow_load(_dp(self.ptr), self.d, self.n_cond,
+                                       v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), sp),
+                   "qmc_flow_load")
 
     def read(self, stream=None):
         """(parameters, last gradient) as float32 host arrays."""
@@ -89,8 +102,9 @@ class Flow:
         prm = np.empty(P, dtype=np.float32)
         grd = np.empty(P, dtype=np.float32)
         fp = ctypes.POINTER(ctypes.c_float)
-        _check(lib().qmc_flow_read(_dp(self.ptr), self.d, self.n_cond, prm.ctypes.data_as(fp),
-                                   grd.ctypes.data_as(fp), _stream(stream)), "qmc_flow_read")
+        with _ordered(stream) as sp:
+            _check(lib().qmc_flow_read(_dp(self.ptr), self.d, self.n_cond, prm.ctypes.data_as(fp),
+                                       grd.ctypes.data_as(fp), sp), "qmc_flow_read")
         return prm, grd
 
     def _cond(self, cond, n):
@@ -118,10 +132,12 @@ class Flow:
         c = self._cond(cond, n)
         out = torch.empty_like(t)
         ld = torch.empty(n, dtype=torch.float64, device=self.device)
-        _check(lib().qmc_flow_transform(_dp(self.ptr), self.d, self.n_cond, direction,
-                                        _dp(t.data_ptr()), _dp(None if c is None else c.data_ptr()),
-                                        n, _stream(stream), _dp(out.data_ptr()),
-                                        _dp(ld.data_ptr())), "qmc_flow_transform")
+        with _ordered(stream) as sp:
+            _check(lib().qmc_flow_transform(_dp(self.ptr), self.d, self.n_cond, direction,
+                                            _dp(t.data_ptr()),
+                                            _dp(None if c is None else c.data_ptr()), n, sp,
+                                            _dp(out.data_ptr()), _dp(ld.data_ptr())),
+                   "qmc_flow_transform")
         return out, ld
 
     def _scratch(self, count):
@@ -139,18 +155,20 @@ class Flow:
         ws = float(wt.sum()) if w_sum is None else float(w_sum)
         sc, nb = self._scratch(xt.shape[0])
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
-        _check(lib().qmc_flow_gradient(_dp(self.ptr), self.d, self.n_cond, _dp(xt.data_ptr()),
-                                       _dp(wt.data_ptr()),
-                                       _dp(None if c is None else c.data_ptr()), xt.shape[0],
-                                       ctypes.c_double(ws), _dp(sc.data_ptr()),
-                                       ctypes.c_size_t(nb), _stream(stream), _dp(loss.data_ptr())),
-               "qmc_flow_gradient")
+        with _ordered(stream) as sp:
+            _check(lib().qmc_flow_gradient(_dp(self.ptr), self.d, self.n_cond,
+                                           _dp(xt.data_ptr()), _dp(wt.data_ptr()),
+                                           _dp(None if c is None else c.data_ptr()), xt.shape[0],
+                                           ctypes.c_double(ws), _dp(sc.data_ptr()),
+                                           ctypes.c_size_t(nb), sp, _dp(loss.data_ptr())),
+                   "qmc_flow_gradient")
         return float(loss.item())
 
     def adam_step(self, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         opt = _adam(lr, beta1, beta2, eps, step)
-        _check(lib().qmc_flow_adam_step(_dp(self.ptr), self.d, self.n_cond, ctypes.byref(opt),
-                                        _stream(stream)), "qmc_flow_adam_step")
+        with _ordered(stream) as sp:
+            _check(lib().qmc_flow_adam_step(_dp(self.ptr), self.d, self.n_cond,
+                                            ctypes.byref(opt), sp), "qmc_flow_adam_step")
 
     def train(self, x, w, batches: int, epochs: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
               step0: int = 1, stream=None, cond=None):
@@ -164,11 +182,13 @@ class Flow:
         sc, nb = self._scratch(xt.shape[0] // batches)
         hist = torch.zeros(batches * epochs, dtype=torch.float64, device=self.device)
         opt = _adam(lr, beta1, beta2, eps, step0)
-        _check(lib().qmc_flow_train(_dp(self.ptr), self.d, self.n_cond, _dp(xt.data_ptr()),
-                                    _dp(wt.data_ptr()), _dp(None if c is None else c.data_ptr()),
-                                    xt.shape[0], ctypes.c_double(ws), ctypes.byref(opt), batches,
-                                    epochs, _dp(sc.data_ptr()), ctypes.c_size_t(nb),
-                                    _stream(stream), _dp(hist.data_ptr())), "qmc_flow_train")
+        with _ordered(stream) as sp:
+            _check(lib().qmc_flow_train(_dp(self.ptr), self.d, self.n_cond, _dp(xt.data_ptr()),
+                                        _dp(wt.data_ptr()),
+                                        _dp(None if c is None else c.data_ptr()), xt.shape[0],
+                                        ctypes.c_double(ws), ctypes.byref(opt), batches, epochs,
+                                        _dp(sc.data_ptr()), ctypes.c_size_t(nb), sp,
+                                        _dp(hist.data_ptr())), "qmc_flow_train")
         return hist.cpu().numpy()
 
 

@@ -331,3 +331,20 @@ def test_attach_rejects_a_flow_of_another_shape(qmc):
     fl.n_cond = 2
     plan.attach_flow(0, fl, cond=[0.0, 0.5])
     plan.attach_flow(0, None)
+
+
+def test_training_on_another_stream_matches(qmc):
+    """Training launched on a second stream is ordered after the inputs prepared on the
+    current stream and before the losses read there: same losses and parameters, bit for
+    bit, as on the current stream."""
+    import torch
+    rng = np.random.default_rng(17)
+    x = torch.as_tensor(rng.uniform(0.02, 0.98, size=(4096, 3)), device="cuda")
+    w = torch.as_tensor(rng.uniform(0.1, 1.0, size=4096), device="cuda")
+    f1 = qmc.flow.Flow(3, seed=5)
+    h1 = f1.train(x, w, batches=4, epochs=2, lr=2e-3)
+    f2 = qmc.flow.Flow(3, seed=5)
+    side = torch.cuda.Stream()          # default priority
+    h2 = f2.train(x, w, batches=4, epochs=2, lr=2e-3, stream=side)
+    assert np.array_equal(h1, h2)
+    assert np.array_equal(f1.read()[0], f2.read()[0])
