@@ -619,7 +619,7 @@ def main():
     tune = None
     if not (args.no_tune or explicit):
         t0 = time.perf_counter()
-        tune = plan.autotune(reps=2)        # launch-shape search, outside the timed region
+        tune = plan.autotune(reps=4)        # launch-shape search, outside the timed region
         tune["seconds"] = time.perf_counter() - t0
         print(f"# autotuned launch shape {tune}", file=sys.stderr, flush=True)
     S, m, K = plan.S, plan.m, plan.K
@@ -653,7 +653,7 @@ def main():
             plan32.set_launch_shape(args.block or 256, args.tile or 16, min(args.spp or 2, 2),
                                     args.target or 16384)
         elif tune is not None:
-            tune32 = plan32.autotune(reps=2)
+            tune32 = plan32.autotune(reps=4)
         for _ in range(args.warmup):
             plan32.integrate(out=out, check=False)
         torch.cuda.synchronize()
