@@ -511,7 +511,7 @@ def allocate(c2, w, tau, V, alpha: float = 2.0):
 # ------------------------------------------------------------ adaptive sums
 
 def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=0.0,
-                       alpha=2.0, n_presample=10000, max_rounds=50, threads=8):
+                       alpha=2.0, n_presample=10000, max_rounds=50, threads=8, trace=None):
     """Adaptive evaluation of weighted sums of integrals, Sec. 2.1.3 (reading: the unit
     is a sector; its coefficient is its integral's; unmet (sum, order) targets are
     processed in order keeping each sector's largest request; sizes never shrink and
@@ -521,8 +521,14 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
     regulator-dependent coefficients (Sec. 2.4; see amplitude_series: a target (t, j)
     weighs sector s by sum_p |c_p|^2 w_s,j-p).  lattice_n: ascending sizes; lattice_a:
     [L, 8] Korobov parameter per size and dimension (column d-1).  tau: cost per
-    evaluation of each sector.  Returns (value [T, K] complex, error [T, K] complex
-    (err_re + 1j err_im), n_final [S], rounds, converged).
+    evaluation of each sector: an array [S], or [R, S] with row r the costs the
+    allocation after round r + 1 uses (the last row for later rounds).  Returns
+    (value [T, K] complex, error [T, K] complex (err_re + 1j err_im), n_final [S], rounds,
+    converged).  trace: if a list, one record per round is appended, holding what the
+    round measured and decided: n (lattice sizes integrated), mean and err [S, K],
+    tau [S], and per unmet target (t, k) its variance bound V and the closed-form sizes
+    n_opt [S] before the never-shrink maximum and the ladder ceiling (0 where a sector
+    does not contribute).
     """
     C = np.asarray(coef, dtype=np.complex128)
     if C.ndim == 1:
@@ -534,7 +540,7 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
     K = problem.K
     lad = [int(v) for v in lattice_n]
     la = np.asarray(lattice_a, dtype=np.uint64).reshape(len(lad), 8)
-    tau = np.asarray(tau, dtype=np.float64)
+    tau_rows = np.atleast_2d(np.asarray(tau, dtype=np.float64))
 
     def ceil_index(x):
         for l, v in enumerate(lad):
@@ -581,12 +587,18 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
                 eps = math.sqrt(var / mag2) if mag2 > 0 else (math.inf if var > 0 else 0.0)
                 if not (eps <= epsrel or math.sqrt(var) <= epsabs):
                     unmet.append((t, k, mag2))
+        tau = tau_rows[min(rounds - 1, tau_rows.shape[0] - 1)]
+        n_cur = np.array([lad[lidx[s]] for s in range(S)], dtype=np.float64)
+        rec = None
+        if trace is not None:
+            rec = {"n": n_cur.copy(), "mean": mean.copy(), "err": err.copy(),
+                   "tau": tau.copy(), "targets": []}
+            trace.append(rec)
         if not unmet:
             converged = True
             break
         if rounds > max_rounds:
             break
-        n_cur = np.array([lad[lidx[s]] for s in range(S)], dtype=np.float64)
         want = n_cur.copy()
         for t, k, mag2 in unmet:
             V = max(epsrel ** 2 * mag2, epsabs ** 2)
@@ -603,6 +615,10 @@ def adaptive_amplitude(problem, coef, lattice_n, lattice_a, tau, epsrel, epsabs=
                 continue
             n_opt, _ = allocate(np.ones(int(use.sum())), cw[use], tau[use], V, alpha)
             want[use] = np.maximum(want[use], n_opt)
+            if rec is not None:
+                full = np.zeros(S)
+                full[use] = n_opt
+                rec["targets"].append({"t": t, "k": k, "V": V, "n_opt": full})
         new = [max(lidx[s], ceil_index(want[s])) for s in range(S)]
         active = [new[s] != lidx[s] for s in range(S)]
         lidx = new

@@ -179,6 +179,62 @@ def test_closed_form_integrals(case):
     assert err[0] < 1e-7
 
 
+def box6_problem(S, T, n=65521, a=17364, m=8, seed=7):
+    """The one-loop massless box in D = 6 (finite) as a sum of sector integrals.
+
+    With Feynman parameters x_1..x_4 and Euclidean invariants S = -s > 0, T = -t > 0, the
+    box's parameter integral is J = int dx delta(1 - sum x) U^-2 F^-1, U = x1 + x2 + x3 + x4,
+    F = S x1 x3 + T x2 x4 (the D = 6 exponents N - D = -2 and -(N - D/2) = -1).  Its known
+    closed form is J(S, T) = (log^2(S/T) + pi^2) / (2 (S + T)).
+
+    Sector decomposition, derived by hand: the primary sector x1 = 1 (the others in [0,1]:
+    t2, t3, t4) has U = 1 + t2 + t3 + t4 and F = S t3 + T t2 t4, which vanishes on
+    {t3 = 0, t2 t4 = 0}.  Splitting (t3, t2) by which is larger and then (u3, t4):
+      (a)  t2 = t3 u2:             F = t3 (S + T u2 t4),  Jacobian t3
+      (b1) t3 = t2 u3, u3 = t4 v:  F = t2 t4 (S v + T),   Jacobian t2 t4
+      (b2) t3 = t2 u3, t4 = u3 w:  F = t2 u3 (S + T w),   Jacobian t2 u3
+    The Jacobian cancels F's monomial factor in each case, leaving U^-2 G^-1 with a
+    positive G: smooth on the cube.  x3 = 1 gives the same three (F is symmetric under
+    x1 <-> x3), x2 = 1 and x4 = 1 the same with S <-> T: 12 sectors, one integral."""
+    def three(S_, T_):
+        return [
+            # (a) variables (u2, t3, t4): U = 1 + u2 t3 + t3 + t4, G = S + T u2 t4
+            ([(1.0, (0, 0, 0)), (1.0, (1, 1, 0)), (1.0, (0, 1, 0)), (1.0, (0, 0, 1))],
+             [(S_, (0, 0, 0)), (T_, (1, 0, 1))]),
+            # (b1) variables (t2, v, t4): U = 1 + t2 + t2 v t4 + t4, G = S v + T
+            ([(1.0, (0, 0, 0)), (1.0, (1, 0, 0)), (1.0, (1, 1, 1)), (1.0, (0, 0, 1))],
+             [(T_, (0, 0, 0)), (S_, (0, 1, 0))]),
+            # (b2) variables (t2, u3, w): U = 1 + t2 + t2 u3 + u3 w, G = S + T w
+            ([(1.0, (0, 0, 0)), (1.0, (1, 0, 0)), (1.0, (1, 1, 0)), (1.0, (0, 1, 1))],
+             [(S_, (0, 0, 0)), (T_, (0, 0, 1))]),
+        ]
+    polys = three(S, T) * 2 + three(T, S) * 2
+    secs = [W.custom_sector(3, u, f, u_pow=-2, f_pow2=-2, n=n, a=a, transform="korobov3")
+            for u, f in polys]
+    rng = np.random.default_rng(seed)
+    shifts = [W.uniform_shifts(rng, m, 3) for _ in secs]
+    prob = W.Problem(sectors=secs, order_lo=0, m=m, shifts=shifts, n_integrals=1)
+    exact = (math.log(S / T) ** 2 + math.pi ** 2) / (2.0 * (S + T))
+    return prob, exact
+
+
+@pytest.mark.parametrize("S,T", [(1.0, 1.0), (3.7, 1.3), (0.2, 6.0)])
+def test_massless_box_six_dimensions_closed_form(S, T):
+    """Twelve sector integrals of the hand-decomposed D = 6 massless box sum to the closed
+    form: pins multi-dimensional sectors (d = 3, monomials of total degree up to 3, negative
+    powers of U and F) added into one integral with their variances."""
+    prob, exact = box6_problem(S, T)
+    means, errs = [], []
+    for s, sec in enumerate(prob.sectors):
+        Q, _ = oracle.sector_sums(sec, prob.shifts[s], threads=8)
+        mu, e = oracle.estimate(Q)
+        means.append(mu)
+        errs.append(e)
+    val, err = oracle.integral_values(prob, means, errs)
+    assert err[0, 0] < 1e-9 * exact
+    assert abs(val[0, 0] - exact) < 5 * err[0, 0] + 1e-12 * exact, (val[0, 0], exact, err[0, 0])
+
+
 def test_mixed_monomial_exponents_not_transposed():
     """F = 1 + x1^2 x2.  int int 1/F = pi/2 - log 2 exactly; with the prefactor sqrt(x1) the
     inner x2-integral is log(1+x1^2)/x1^2, leaving a 1-D integral done by adaptive quadrature.
@@ -378,6 +434,17 @@ def test_amplitude_variance_propagation_and_eps_rel():
     assert np.std(A.real) == pytest.approx(dre[0], rel=0.01)
     assert np.std(A.imag) == pytest.approx(dim[0], rel=0.01)
     assert oracle.eps_rel(3.0, 4.0, 0.3, 0.4) == pytest.approx(0.1)
+    # complex integrals (deformed contours): Re and Im of each integral independent
+    iim = np.array([[-0.7], [0.4]])
+    eim = np.array([[0.3], [0.05]])
+    re, im, dre, dim = oracle.amplitude(C, ival, ierr, iim, eim)
+    assert re[0] == pytest.approx(2.0 * 1.0 + (-1.0 * 0.5 - 3.0 * 0.4))
+    assert im[0] == pytest.approx(2.0 * -0.7 + (-1.0 * 0.4 + 3.0 * 0.5))
+    z = (ival[:, 0][None, :] + ierr[:, 0][None, :] * rng.normal(size=(200000, 2)) +
+         1j * (iim[:, 0][None, :] + eim[:, 0][None, :] * rng.normal(size=(200000, 2))))
+    A = z @ C
+    assert np.std(A.real) == pytest.approx(dre[0], rel=0.01)
+    assert np.std(A.imag) == pytest.approx(dim[0], rel=0.01)
 
 
 def test_amplitude_series_is_the_product_of_series():
