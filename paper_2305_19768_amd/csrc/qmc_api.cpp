@@ -229,6 +229,49 @@ static qmc_status pack_poly(int D, const qmc_problem *prob, int64_t off, int32_t
   return QMC_OK;
 }
 
+// FP32 eligibility of a fast-path sector (integer powers of U and F).  The FP32 form
+// evaluates U, F, num = U^u_num F^f_num, den = U^u_den F^f_den, B = num / den and
+// log F in FP32, so it needs (1) no cancellation: every coefficient of U and F is
+// non-negative, which makes both monotone on the cube, between their constant term
+// (at x = 0) and the sum of their coefficients (at x = 1), each evaluated with a
+// relative error of a few ulp per monomial; and (2) every one of those quantities,
+// and the weighted orders W B (log F)^m, inside FP32's normal range with a wide margin
+// (2^-100 .. 2^100; FP32 normals span 2^-126 .. 2^128), so that no intermediate is
+// denormal, zero or infinite.  The weight W is at most (140/64)^d and |log F| at most
+// max(|log min F|, |log max F|).  Other sectors keep the FP64 integrand.
+static bool fp32_range_ok(const SectorDev &sd, const std::vector<double> &coef, int D) {
+  double u_lo = coef[sd.u_off], u_hi = 0.0, f_lo = coef[sd.f_off], f_hi = 0.0;
+  for (int i = 0; i < dense_len(D); ++i) {
+    if (coef[sd.u_off + i] < 0.0 || coef[sd.f_off + i] < 0.0) return false;
+    u_hi += coef[sd.u_off + i];
+    f_hi += coef[sd.f_off + i];
+  }
+  if (!(f_lo > 0.0)) return false;                              // F vanishes at x = 0
+  if (!(u_lo > 0.0) && (sd.u_num > 0 || sd.u_den > 0)) return false;
+  const double lo = -100.0, hi = 100.0;
+  auto in = [&](double l2) { return l2 >= lo && l2 <= hi; };
+  const double lu_lo = (sd.u_num + sd.u_den) ? std::log2(u_lo) : 0.0, lu_hi = std::log2(u_hi);
+  const double lf_lo = std::log2(f_lo), lf_hi = std::log2(f_hi);
+  // every partial power of U and F (the FP32 products are built one factor at a time)
+  for (int t = 1; t <= std::max(sd.u_num, sd.u_den); ++t)
+    if (!in(t * lu_lo) || !in(t * lu_hi)) return false;
+  for (int t = 1; t <= std::max(sd.f_num, sd.f_den); ++t)
+    if (!in(t * lf_lo) || !in(t * lf_hi)) return false;
+  const double num_lo = sd.u_num * lu_lo + sd.f_num * lf_lo, num_hi = sd.u_num * lu_hi + sd.f_num * lf_hi;
+  const double den_lo = sd.u_den * lu_lo + sd.f_den * lf_lo, den_hi = sd.u_den * lu_hi + sd.f_den * lf_hi;
+  if (!in(num_lo) || !in(num_hi) || !in(den_lo) || !in(den_hi)) return false;
+  const double b_lo = num_lo - den_hi, b_hi = num_hi - den_lo;   // log2 of the range of B
+  const double w_hi = D * std::log2(140.0 / 64.0);
+  const double lmax = std::max(std::fabs(std::log(f_lo)), std::fabs(std::log(f_hi)));
+  double v_hi = 0.0;   // largest |sum_m c_km L^m| over the orders
+  for (int k = 0; k < sd.n_orders; ++k) {
+    double v = 0.0;
+    for (int m = 0; m <= QMC_MAX_LOG; ++m) v += std::fabs(sd.logc[k][m]) * std::pow(lmax, m);
+    v_hi = std::max(v_hi, v);
+  }
+  return in(b_lo) && in(b_hi + w_hi + std::log2(std::max(v_hi, 1.0)));
+}
+
 // 0: generic path, 1: fast path in FP64, 2: fast path in FP32, 3: deformed (complex plan),
 // 4: attached flow transform, 5: deformed with the FP32 polynomial bulk, 6: deformed with
 // an attached flow transform.
@@ -407,30 +450,11 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
     if (in.transform == QMC_TRANSFORM_KOROBOV3 && !(flags & (SF_XPOW | SF_HALF)) &&
         p->M <= p->K - 1)
       flags |= SF_FAST;
-    // FP32 eligibility: no cancellation in U or F on the cube and no vanishing divisor
-    if (flags & SF_FAST) {
-      bool ok = p->coef[sd.f_off] >= 1e-30;   // F >= its constant term > 0
-      for (int i = 0; i < dense_len(D) && ok; ++i)
-        ok = p->coef[sd.f_off + i] >= 0.0 && p->coef[sd.u_off + i] >= 0.0;
-      if (ok && sd.u_den > 0) ok = p->coef[sd.u_off] >= 1e-30;
-      if (ok) flags |= SF_F32OK;
-    }
+
     // FP32 bulk on the deformed contour: where the contour moves off the real cube F(z)
     // keeps a non-zero imaginary part inside it; on the real contour only without
     // cancellation (as for SF_F32OK)
-    if (p->cplx && p->precision == QMC_PREC_FP32) {
-      bool ok = in.deform_lambda > 0.0;
-      if (!ok) {
-        ok = p->coef[sd.f_off] >= 1e-30;
-        for (int i = 0; i < dense_len(D) && ok; ++i)
-          ok = p->coef[sd.f_off + i] >= 0.0 && p->coef[sd.u_off + i] >= 0.0;
-        if (ok && sd.u_den > 0) ok = p->coef[sd.u_off] >= 1e-30;
-      }
-      if (ok) flags |= SF_CF32;
-    }
-    sd.flags = flags;
-    sd.u_off32 = sd.u_off;
-    sd.f_off32 = sd.f_off;
+    // the log coefficients first: the FP32 range test below reads them
     for (int k = 0; k < QMC_MAX_ORDERS; ++k)
       for (int mm = 0; mm <= QMC_MAX_LOG; ++mm) {
         const double c = (k < p->K && mm <= p->M) ? in.logc[k][mm] : 0.0;
@@ -441,6 +465,19 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
         sd.logc[k][mm] = c;
         sd.logc32[k][mm] = (float)c;
       }
+    // FP32 eligibility: no cancellation in U or F on the cube, every FP32 intermediate
+    // inside the normal range
+    if ((flags & SF_FAST) && fp32_range_ok(sd, p->coef, D)) flags |= SF_F32OK;
+    if (p->cplx && p->precision == QMC_PREC_FP32) {
+      // real-contour sectors under the same rule as SF_F32OK (the deformed ones keep a
+      // non-zero imaginary part of F(z) inside the cube)
+      bool ok = in.deform_lambda > 0.0;
+      if (!ok) ok = fp32_range_ok(sd, p->coef, D);
+      if (ok) flags |= SF_CF32;
+    }
+    sd.flags = flags;
+    sd.u_off32 = sd.u_off;
+    sd.f_off32 = sd.f_off;
     p->n_default[s] = in.n;
     p->a_default[s] = in.a;
     nmax = std::max<uint64_t>(nmax, in.n);
@@ -697,6 +734,28 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   return QMC_OK;
 }
 
+}  // namespace qmc
+
+namespace qmc {
+qmc_status p2_check_args(uint64_t n, int32_t d, const uint64_t *cand, int32_t n_cand) {
+  if (n < 2 || n >= (1ull << 53)) return fail(QMC_E_INVAL, "n = %llu outside [2, 2^53)",
+                                              (unsigned long long)n);
+  if (d < 1 || d > QMC_MAX_DIM) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
+  if (n_cand < 1 || n_cand > kP2MaxCand)
+    return fail(QMC_E_INVAL, "n_cand = %d outside [1, %d]", n_cand, kP2MaxCand);
+  for (int32_t c = 0; c < n_cand; ++c)
+    if (cand[c] < 1 || cand[c] >= n)
+      return fail(QMC_E_INVAL, "candidate %d: a = %llu outside [1, n)", c,
+                  (unsigned long long)cand[c]);
+  return QMC_OK;
+}
+
+int64_t p2_chunks(uint64_t n, int32_t n_cand) {
+  // workgroups per candidate: about 128 points per thread, within the partial buffer
+  int64_t chunks = (int64_t)((n + 256 * 128 - 1) / (256 * 128));
+  const int64_t cap = (int64_t)(kP2PartialDoubles / 2) / n_cand;
+  return std::max<int64_t>(1, std::min<int64_t>(chunks, std::min<int64_t>(cap, 65535)));
+}
 }  // namespace qmc
 
 extern "C" {
@@ -1141,24 +1200,15 @@ qmc_status qmc_autotune(qmc_plan_t p, const uint64_t *n, const uint64_t *a, int3
   return QMC_OK;
 }
 
+
 qmc_status qmc_korobov_p2(qmc_plan_t p, uint64_t n, int32_t d, const uint64_t *cand,
                           int32_t n_cand, void *stream, double *dev_p2) {
   g_last_error.clear();
   if (!p || !cand || !dev_p2) return fail(QMC_E_INVAL, "NULL argument");
   if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
-  if (n < 2 || n >= (1ull << 53)) return fail(QMC_E_INVAL, "n = %llu outside [2, 2^53)",
-                                              (unsigned long long)n);
-  if (d < 1 || d > QMC_MAX_DIM) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
-  if (n_cand < 1 || n_cand > kP2MaxCand)
-    return fail(QMC_E_INVAL, "n_cand = %d outside [1, %d]", n_cand, kP2MaxCand);
-  for (int32_t c = 0; c < n_cand; ++c)
-    if (cand[c] < 1 || cand[c] >= n)
-      return fail(QMC_E_INVAL, "candidate %d: a = %llu outside [1, n)", c,
-                  (unsigned long long)cand[c]);
-  // workgroups per candidate: about 128 points per thread, within the partial buffer
-  int64_t chunks = (int64_t)((n + 256 * 128 - 1) / (256 * 128));
-  const int64_t cap = (int64_t)(kP2PartialDoubles / 2) / n_cand;
-  chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, std::min<int64_t>(cap, 65535)));
+  qmc_status chk = p2_check_args(n, d, cand, n_cand);
+  if (chk != QMC_OK) return chk;
+  const int64_t chunks = p2_chunks(n, n_cand);
   hipStream_t st = (hipStream_t)stream;
   int e = hipMemcpyAsync(p->ws + p->off_p2cand, cand, sizeof(uint64_t) * n_cand,
                          hipMemcpyHostToDevice, st);

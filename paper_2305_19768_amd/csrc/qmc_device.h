@@ -3,9 +3,13 @@
 // the integrand orders in FP64 and FP32, and the body of one integration workgroup.
 #pragma once
 
+// The header is also compiled at run time (hiprtc) for plan-specialised integrands,
+// where the runtime and integer types are built in.
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#endif
 
 #include "qmc_internal.h"
 
@@ -684,6 +688,44 @@ __device__ __forceinline__ int find_sector(const int64_t *__restrict__ begin, in
   return lo;
 }
 
+// The work of one workgroup of an integration launch: workgroup b of the launch's
+// global numbering holds sector s, shifts [l_begin, l_begin + tile) and one chunk of its
+// lattice points (workgroups are numbered sector by sector in workgroup order, each
+// sector's shift tiles one after another).
+struct BlockWork {
+  int64_t b, chunk_id;
+  int s, l_begin, tile;
+};
+
+__device__ __forceinline__ BlockWork block_work(const LaunchArgs &a, int64_t block_base) {
+  BlockWork w;
+  w.b = block_base + blockIdx.x;
+  w.s = a.order[find_sector(a.block_begin, a.n_sectors, w.b)];
+  const LatticeDev *__restrict__ lt = a.lat + w.s;
+  const int64_t local = w.b - lt->block_begin;
+  const int nch = lt->n_chunks;
+  const int tile_id = (int)(local / nch);
+  w.chunk_id = local - (int64_t)tile_id * nch;
+  w.tile = a.shift_tile;
+  w.l_begin = tile_id * w.tile;
+  return w;
+}
+
+// In-order combine of the waves' partials (one thread per (shift in tile, order)) into
+// the workgroup's partial; call after the workgroup barrier that follows the block.
+__device__ __forceinline__ void block_store(const LaunchArgs &a, const BlockWork &w,
+                                            double (*red)[kMaxTile * 4][2]) {
+  const int nwaves = blockDim.x >> 6;
+  const int cols = w.tile * a.K;
+  if ((int)threadIdx.x < cols) {
+    DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
+    for (int v = 1; v < nwaves; ++v) r = dd_combine(r, DD{red[v][threadIdx.x][0], red[v][threadIdx.x][1]});
+    double *out = a.partial + (w.b * cols + threadIdx.x) * 2;
+    out[0] = r.s;
+    out[1] = r.c;
+  }
+}
+
 // Maximum shifts per workgroup and waves per workgroup (LDS staging of the partials).
 
 // Lattice points a thread sums in plain FP64 before folding the partial into its
@@ -698,9 +740,26 @@ constexpr int kFold = 8;
 // wavefront and staged in LDS.
 // REGCONST: hold the korobov_3 coefficients in registers for the whole block (fewer
 // instructions per point; the persistent kernel, tighter on registers, uses literals).
-template <int D, int K, int S, bool FAST, bool F32, bool REGCONST = true>
+//
+// GEN: a plan-specialised integrand (generated straight-line code for one sector,
+// compiled at run time) with static members f64<S>(x, f, C) and f32<S>(x, f, C) that give
+// the orders f_k of S korobov3-transformed samples, reading the sector's coefficients in
+// the order of use from C = coefficient table + gen_off; NoGen selects the table-driven
+// forms.
+struct NoGen {};
+template <class T>
+struct IsGen {
+  static constexpr bool value = true;
+};
+template <>
+struct IsGen<NoGen> {
+  static constexpr bool value = false;
+};
+
+template <int D, int K, int S, bool FAST, bool F32, bool REGCONST = true, class GEN = NoGen>
 __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int l_begin, int tile,
-                                                int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
+                                                int64_t chunk_id, double (*red)[kMaxTile * 4][2],
+                                                int64_t gen_off = 0) {
   const SectorDev *__restrict__ sd = a.sectors + s;
   const LatticeDev *__restrict__ lt = a.lat + s;
   const uint64_t n = lt->n;
@@ -733,6 +792,10 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
     for (int u = 0; u < S; ++u)
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) acc[u][kk] = DD{0.0, 0.0};
+    // shifts of this pass inside the tile: S, or fewer on the last pass of a tile that is
+    // not a multiple of S; the surplus slots re-read the pass's first shift (in bounds)
+    // and their sums are dropped
+    const int live = (tile - l0 < S) ? tile - l0 : S;
     const double *__restrict__ sh = a.shifts + ((int64_t)s * a.m + l_begin + l0) * QMC_MAX_DIM;
     double k[D];
 #pragma unroll
@@ -772,9 +835,29 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
 #pragma unroll
         for (int u = 0; u < S; ++u)
 #pragma unroll
-          for (int j = 0; j < D; ++j) y[u][j] = shifted(q[j], shl[u * QMC_MAX_DIM + j]);
+          for (int j = 0; j < D; ++j)
+            y[u][j] = shifted(q[j], shl[(u < live ? u : 0) * QMC_MAX_DIM + j]);
         double f[S][K];
-        if (F32) {
+        if constexpr (IsGen<GEN>::value) {
+          if constexpr (F32) {
+            float yf[S][D], xf[S][D], Wf[S], ff[S][K];
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+#pragma unroll
+              for (int j = 0; j < D; ++j) yf[u][j] = (float)y[u][j];
+            korobov3_f32<D, S>((float)w_scale, yf, xf, Wf);
+            GEN::template f32<S>(xf, ff, launder_after_f(cl32 + gen_off, Wf[0]));
+#pragma unroll
+            for (int u = 0; u < S; ++u) {
+              W[u] = (double)Wf[u];
+#pragma unroll
+              for (int kk = 0; kk < K; ++kk) f[u][kk] = (double)(Wf[u] * ff[u][kk]);
+            }
+          } else {
+            korobov3_fast<D, S>(w_scale, kc, y, x, W);
+            GEN::template f64<S>(x, f, launder_after(cl + gen_off, W[0]));
+          }
+        } else if (F32) {
           float yf[S][D], xf[S][D], Wf[S], ff[S][K];
 #pragma unroll
           for (int u = 0; u < S; ++u)
@@ -815,7 +898,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
 #pragma unroll
       for (int kk = 0; kk < K; ++kk) {
         const DD r = wave_reduce(acc[u][kk]);
-        if (lane == 0) {
+        if (lane == 0 && u < live) {
           red[wave][(l0 + u) * K + kk][0] = r.s;
           red[wave][(l0 + u) * K + kk][1] = r.c;
         }

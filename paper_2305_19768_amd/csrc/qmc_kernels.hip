@@ -34,27 +34,10 @@ template <int D, int K, int S, bool FAST, bool F32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((D <= 4 && FAST && !F32) ? 4 : 1)))
 void qmc_integrate_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
-  const int64_t b = block_base + blockIdx.x;
-  const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
-  const LatticeDev *__restrict__ lt = a.lat + s;
-  const int64_t local = b - lt->block_begin;
-  const int nch = lt->n_chunks;
-  const int tile_id = (int)(local / nch);
-  const int64_t chunk_id = local - (int64_t)tile_id * nch;
-  const int T = a.shift_tile;
-  const int l_begin = tile_id * T;
-
-  integrate_block<D, K, S, FAST, F32>(a, s, l_begin, T, chunk_id, red);
+  const BlockWork w = block_work(a, block_base);
+  integrate_block<D, K, S, FAST, F32>(a, w.s, w.l_begin, w.tile, w.chunk_id, red);
   __syncthreads();
-  // in-order combine of the waves, one thread per (shift in tile, order)
-  const int nwaves = blockDim.x >> 6;
-  if ((int)threadIdx.x < T * K) {
-    DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
-    for (int w = 1; w < nwaves; ++w) r = dd_combine(r, DD{red[w][threadIdx.x][0], red[w][threadIdx.x][1]});
-    double *out = a.partial + (b * (T * K) + threadIdx.x) * 2;
-    out[0] = r.s;
-    out[1] = r.c;
-  }
+  block_store(a, w, red);
 }
 
 // Combine the workgroup partials of one (sector, shift) in workgroup order: one wave

@@ -22,6 +22,10 @@ constexpr int64_t kTargetBlocks = 16384;   // default workgroups per launch the 
 constexpr int64_t kTargetBlocksMax = 32768;   // largest target a launch shape may choose
 constexpr int32_t kP2MaxCand = 65536;
 constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
+// Arguments of a P_2 evaluation (n, d, candidates in [1, n)), and the workgroups per
+// candidate that fit the partial-sum buffer.
+qmc_status p2_check_args(uint64_t n, int32_t d, const uint64_t *cand, int32_t n_cand);
+int64_t p2_chunks(uint64_t n, int32_t n_cand);
 
 }  // namespace qmc
 

@@ -200,6 +200,30 @@ def test_device_mode_fp32_against_fp64(qmc, mixed):
     assert np.all(dev <= 1e-5)
 
 
+@pytest.mark.parametrize("m", [3, 5])
+def test_device_mode_fp32_with_odd_shift_count(qmc, m):
+    # an odd number of shifts gives an odd shift tile while the FP32 batched form takes
+    # two shifts per pass: the last pass of a tile has one live shift, whose partner slot
+    # re-reads a shift inside the tile and is dropped.  Same rounds and lattices as the
+    # FP64 batched form, sums within the FP32 bar.
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=m, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    out = {}
+    for prec in (qmc.QMC_PREC_FP64, qmc.QMC_PREC_FP32):
+        plan = qmc.Plan(prob, n_max=int(sizes[-1]), precision=prec)
+        assert plan.launch_shape()["shift_tile"] % 2 == 1
+        out[prec] = plan.amp_evaluate(prob.amp_coef, epsrel=5e-4, lattice_n=sizes,
+                                      lattice_a=a_tab, tau=tau, n_presample=1009, mode=1)
+        del plan
+    v64, e64, n64, s64 = out[qmc.QMC_PREC_FP64]
+    v32, e32, n32, s32 = out[qmc.QMC_PREC_FP32]
+    assert s32["rounds"] == s64["rounds"] and np.array_equal(n32, n64)
+    dev = np.abs(v32 - v64) / (np.abs(v64) + np.abs(e64))
+    print("m", m, "max rel deviation", dev.max(), flush=True)
+    assert np.all(dev <= 1e-5)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_timeout_returns_valid_partial_results(qmc, mode):
     # non-integer powers of U and F keep the lattice error well above 1e-15 on every rung,

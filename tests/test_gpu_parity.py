@@ -230,6 +230,49 @@ def test_fp32_form_keeps_fp64_for_cancelling_F(qmc):
     assert 1e-12 < rel.max() <= FP32_TOL
 
 
+def test_fp32_form_range_rule_keeps_fp64_for_tiny_F_constant(qmc):
+    """FP32 eligibility follows the range of the FP32 intermediates, not just the sign of
+    F's coefficients: F's constant 1e-14 with F^-3 puts the denominator near 1e-42, below
+    FP32's normal range, so that sector keeps the FP64 integrand (1e-12 bar, finite); the
+    same F with F^-1 (denominator >= 1e-14) is evaluated in FP32 (1e-5 bar)."""
+    f_terms = [(1e-14, (0, 0, 0)), (0.4, (1, 0, 0)), (0.3, (0, 1, 0)), (0.5, (0, 0, 1)),
+               (0.2, (1, 1, 0))]
+    u_terms = [(1.0, (0, 0, 0)), (1.0, (1, 0, 0)), (1.0, (0, 1, 0))]
+    logc = [[1, 0, 0], [0, -2, 0], [0, 0, 2]]
+    tiny = W.custom_sector(3, u_terms, f_terms, u_pow=1, f_pow2=-6, logc=logc, n=20011, a=5467,
+                           transform="korobov3")
+    mild = W.custom_sector(3, u_terms, f_terms, u_pow=1, f_pow2=-2, logc=logc, n=20011, a=5467,
+                           transform="korobov3")
+    rng = np.random.default_rng(13)
+    prob = W.Problem(sectors=[tiny, mild], order_lo=-2, m=8,
+                     shifts=[W.uniform_shifts(rng, 8, 3) for _ in range(2)])
+    q32 = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32).integrate()[0].cpu().numpy()
+    assert np.all(np.isfinite(q32))
+    Qo, So = oracle.sector_sums(tiny, prob.shifts[0], threads=4)
+    _check_sums(q32[0], Qo, So, what="F constant 1e-14, F^-3, FP32 plan")
+    Qm, Sm = oracle.sector_sums(mild, prob.shifts[1], threads=4)
+    rel = np.abs(q32[1] - Qm) / np.maximum(np.abs(Qm), Sm)
+    assert 1e-12 < rel.max() <= FP32_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_massless_box_six_dimensions(qmc, precision):
+    """The hand-decomposed D = 6 massless box (12 sectors, U^-2 G^-1): every per-shift sum
+    against the oracle, and the integral against its closed form."""
+    from test_oracle_pins import box6_problem
+    prob, exact = box6_problem(3.7, 1.3)
+    fp32 = precision == "fp32"
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32 if fp32 else qmc.QMC_PREC_FP64)
+    q, mean, err = plan.integrate()
+    q, mean, err = q.cpu().numpy(), mean.cpu().numpy(), err.cpu().numpy()
+    for s, sec in enumerate(prob.sectors):
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], threads=8)
+        _check_sums(q[s], Qo, So, tol=FP32_TOL if fp32 else TOL, what=f"box sector {s}")
+    total = mean[:, 0].sum()
+    sigma = math.sqrt(float((err[:, 0] ** 2).sum()))
+    assert abs(total - exact) < 5 * sigma + (1e-6 if fp32 else 1e-12) * exact, (total, exact)
+
+
 # ------------------------------------------------------------------- P_2
 
 def test_p2_values_match_oracle(qmc):
