@@ -69,7 +69,7 @@ def algorithmic_flops(sec, m: int) -> float:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("qmc_kernels.hip", "qmc_device.h", "qmc_internal.h"):
+    for name in ("qmc_kernels.hip", "qmc_device.h", "qmc_internal.h", "qmc_gen.cpp"):
         with open(os.path.join(ROOT, "paper_2305_19768_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -598,6 +598,8 @@ def main():
                     help="workgroups a launch aims at (0 = default); with --block/--tile/--spp "
                          "it fixes the launch shape and skips the autotuner")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-integrand measurement")
+    ap.add_argument("--no-specialize", action="store_true",
+                    help="time the table-driven kernels only (no plan-specialised kernels)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape (no autotuner search)")
     ap.add_argument("--no-amp", action="store_true", help="skip the amplitude wall-time leg")
@@ -634,6 +636,10 @@ def main():
                               args.target or 16384)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
+    spec_s = None
+    if not args.no_specialize:
+        spec_s = plan.specialize()          # generated per-sector kernels, before any timing
+        print(f"# specialised kernels compiled in {spec_s:.1f} s", file=sys.stderr, flush=True)
     tune = None
     if not (args.no_tune or explicit):
         t0 = time.perf_counter()
@@ -662,10 +668,32 @@ def main():
     plan.check_status()
     mean64, err64 = out[1].cpu().numpy().copy(), out[2].cpu().numpy().copy()
 
+    table = None
+    if spec_s is not None:
+        # the same plan and launch shape on the table-driven kernels, for comparison
+        plan.specialize(off=True)
+        for _ in range(args.warmup):
+            plan.integrate(out=out, check=False)
+        plan.enable_timing(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.integrate(out=out, check=False)
+        torch.cuda.synchronize()
+        et = time.perf_counter() - t1
+        kt_ms, kt_n = plan.read_timing()
+        plan.enable_timing(False)
+        plan.check_status()
+        table = {"value": prob.evals() * args.steps / et, "unit": "evals/s",
+                 "ms_per_step": et / args.steps * 1e3, "kernel_ms": kt_ms / max(kt_n, 1),
+                 "note": "table-driven kernels (dense degree-3 Horner), same plan and shape"}
+
     fp32 = None
     if not args.no_fp32:
         plan32 = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32, block=args.block,
                           shift_tile=args.tile, shifts_per_pass=args.spp)
+        if spec_s is not None:
+            plan32.specialize()
         tune32 = None
         if explicit:
             plan32.set_launch_shape(args.block or 256, args.tile or 16, min(args.spp or 2, 2),
@@ -693,7 +721,7 @@ def main():
                              "frac": flops32 / (e32 / args.steps) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
                              "timing": "wall clock of the step"},
                 "note": "FP32 integrand, FP64 lattice points and accumulation",
-                "launch": tune32,
+                "launch": tune32, "specialised": spec_s is not None,
                 # the FP32 form's error against the FP64 form, per result (sector, order)
                 "rel_dev_vs_fp64": {"median": float(np.median(rel)), "max": float(rel.max()),
                                     "per_sector_max": [float(f"{v:.3g}") for v in rel.max(axis=1)]},
@@ -727,12 +755,17 @@ def main():
                    "lattice_points_per_step": int(sum(s.n for s in prob.sectors))},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "qmc_integrate_kernel<D,3,2> (d = 4, 5, 6; concurrent launches, kernel_ms is their joint span)",
+                     "traffic": traffic,
+                     "kernel": ("qmc_gen_d{4,5,6}_f64_s2 (plan-specialised" if spec_s is not None
+                                else "qmc_integrate_kernel<D,3,2> (table-driven") +
+                               "; d = 4, 5, 6 concurrent launches, kernel_ms is their joint span)",
                      "kernel_ms": kernel_ms / max(launches, 1),
                      "algorithmic_flops_per_launch": flops_launch,
                      "flops_per_eval": flops_launch / evals},
         "fp32": fp32,
+        "table_driven": table,
         "plan_seconds": plan_s,
+        "specialize_seconds": spec_s,
         "korobov_p2_search_seconds": p2_search_s,
         "launch": plan.launch_shape(),
         "autotune": tune,

@@ -25,8 +25,10 @@
 #ifndef QMCAMP_H
 #define QMCAMP_H
 
+#ifndef __HIPCC_RTC__   /* run-time compiled kernels get the integer types built in */
 #include <stddef.h>
 #include <stdint.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -425,6 +427,38 @@ qmc_status qmc_autotune(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, i
                         int32_t use_cache, void *stream, qmc_launch_shape *best);
 
 /*
+ * qmc_specialize -- plan-specialised integrand kernels (the per-integral generated
+ * code of Sec. 2.1, where pySecDec compiles each integrand with its constants fixed):
+ * for every launch class of fast-path sectors (korobov3, integer powers of U and F, no
+ * powers of x, real plans) write straight-line code that evaluates only the monomials
+ * each sector has (multivariate Horner by greedy factorisation), with the powers of U
+ * and F and the log-F polynomial of every order fixed, compile it for gfx950 with the
+ * HIP run-time compiler and load it on the current device.  qmc_integrate then runs
+ * these kernels for those classes; the results equal the table-driven kernels' up to
+ * rounding order.  A class kernel is compiled for the shifts per pass of the launch
+ * shape at the time of the call and for the sectors the class holds then; under a
+ * different shape, or after a sector enters the class (a flow detached), that class
+ * runs the table-driven kernel until qmc_specialize is called again (kernels already
+ * compiled are kept).  The amplitude evaluation's persistent kernels are unaffected.
+ * flags: 0, QMC_SPEC_COMPILE_ONLY (generate and compile, load nothing: usable without
+ * a GPU) or QMC_SPEC_OFF (unload every specialised kernel of the plan).
+ * *seconds (may be NULL): wall time of the call.  Synchronous, host-side (no stream
+ * work).  Errors: QMC_E_INVAL, QMC_E_DEVICE (compiler or module-load failure; the
+ * message carries the compiler log).
+ */
+enum { QMC_SPEC_COMPILE_ONLY = 1, QMC_SPEC_OFF = 2 };
+qmc_status qmc_specialize(qmc_plan_t plan, int32_t flags, double *seconds);
+
+/*
+ * qmc_gen_source -- the generated source of launch class (d, f32 != 0) of the plan as
+ * qmc_specialize would compile it now (empty when the class has no fast-path
+ * sectors): copied NUL-terminated into buf[cap] (truncated to cap - 1 bytes; buf may
+ * be NULL), its full length in *len (may be NULL).  Host only.
+ */
+qmc_status qmc_gen_source(qmc_plan_t plan, int32_t d, int32_t f32, char *buf, size_t cap,
+                          size_t *len);
+
+/*
  * Learned coupling-flow transform (an alternative variable transform beside the
  * periodizing ones; not in the paper).  A flow for dimension d is a stack of
  * QMC_FLOW_LAYERS affine coupling layers in logit space of the unit cube: layer l keeps
@@ -483,7 +517,9 @@ size_t qmc_flow_scratch_bytes(int32_t d, int32_t n_cond, int64_t count);
 /* Gradient of L = -(1/w_sum) sum_i w_i log q(x_i | c_i) (weighted maximum likelihood of
  * samples x [count][d] with weights w [count] and conditioning features cond
  * [count][n_cond] or NULL, device float64) into the flow's gradient buffer; *dev_loss
- * (device, may be NULL) receives L.  Asynchronous; deterministic. */
+ * (device, may be NULL) receives L.  w_sum = 0: the library sums the weights on the
+ * device (compensated, fixed order; no host synchronisation; L and the gradient are 0
+ * if they sum to 0); w_sum > 0: the caller's normaliser.  Asynchronous; deterministic. */
 qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, int32_t n_cond, const double *dev_x,
                              const double *dev_w, const double *dev_cond, int64_t count,
                              double w_sum, void *dev_scratch, size_t scratch_bytes, void *stream,
@@ -495,7 +531,8 @@ qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, int32_t n_cond, const q
 
 /* Training: `epochs` passes over `batches` strided minibatches (batch b: samples
  * b, b + batches, ...), one gradient and one Adam step each (steps numbered from
- * opt->step).  w_sum: sum of all weights.  dev_loss_history (device, may be NULL) gets
+ * opt->step).  w_sum: sum of all weights, or 0 to have the library sum them on the
+ * device as qmc_flow_gradient does.  dev_loss_history (device, may be NULL) gets
  * each step's loss.  Scratch: qmc_flow_scratch_bytes(d, n_cond, count / batches).
  * Asynchronous. */
 qmc_status qmc_flow_train(void *dev_flow, int32_t d, int32_t n_cond, const double *dev_x,

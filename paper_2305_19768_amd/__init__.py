@@ -16,7 +16,7 @@ import numpy as np
 
 from . import flow  # noqa: F401  (learned flow transform)
 from ._abi import (QMC_MAX_DIM, QMC_MAX_LOG, QMC_MAX_ORDERS, QMC_PREC_FP32, QMC_PREC_FP64,
-                   TRANSFORMS, AmpOptions, AmpStats, Amplitude, LaunchShape, QmcError, lib,
+                   QMC_SPEC_COMPILE_ONLY, QMC_SPEC_OFF, TRANSFORMS, AmpOptions, AmpStats, Amplitude, LaunchShape, QmcError, lib,
                    options_struct,
                    problem_struct)
 
@@ -215,6 +215,18 @@ class Plan:
                          target_blocks: int = 16384):
         sh = LaunchShape(block, shift_tile, shifts_per_pass, target_blocks, 0.0)
         _check(lib().qmc_set_launch_shape(self._h, ctypes.byref(sh)), "qmc_set_launch_shape")
+
+    def specialize(self, off: bool = False) -> float:
+        """Compiles and loads plan-specialised integrand kernels for the fast-path launch
+        classes (see qmc_specialize); off=True unloads them.  Returns the seconds taken."""
+        sec = ctypes.c_double()
+        _check(lib().qmc_specialize(self._h, QMC_SPEC_OFF if off else 0, ctypes.byref(sec)),
+               "qmc_specialize")
+        return sec.value
+
+    def gen_source(self, d: int, f32: bool = False) -> str:
+        """Generated source of launch class (d, f32) as qmc_specialize would compile it."""
+        return gen_source(self._h, d, f32)
 
     def autotune(self, n=None, a=None, reps: int = 3, use_cache: bool = True, stream=None) -> dict:
         """Times the launch shapes of the integrand kernels on lattices n, a and keeps the
@@ -433,6 +445,36 @@ def coef_series(expr: str, regulator: str = "eps", symbols=None, order_lo: int =
            "qmc_coef_series")
     lo = None if lead.value == 2 ** 31 - 1 else int(lead.value)
     return lo, (re + 1j * im)[:n_terms]
+
+
+def host_plan(problem, m: Optional[int] = None, precision: int = QMC_PREC_FP64, seed: int = 0,
+              shifts_per_pass: int = 0):
+    """A plan handle without a workspace (host-only calls such as qmc_gen_source and
+    qmc_specialize(QMC_SPEC_COMPILE_ONLY)); free with lib().qmc_plan_free."""
+    keep, prob = problem_struct(problem)
+    opt = options_struct(problem.m if m is None else m, precision, seed, 0, 0, 0, shifts_per_pass)
+    h = ctypes.c_void_p()
+    _check(lib().qmc_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)), "qmc_plan")
+    return h
+
+
+def gen_source(handle, d: int, f32: bool = False) -> str:
+    """Generated source of launch class (d, f32) of a plan (see qmc_gen_source)."""
+    n = ctypes.c_size_t()
+    _check(lib().qmc_gen_source(handle, int(d), 1 if f32 else 0, None, 0, ctypes.byref(n)),
+           "qmc_gen_source")
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib().qmc_gen_source(handle, int(d), 1 if f32 else 0, buf, n.value + 1, None),
+           "qmc_gen_source")
+    return buf.value.decode()
+
+
+def specialize_compile_only(handle) -> float:
+    """qmc_specialize(QMC_SPEC_COMPILE_ONLY): generates and compiles every class kernel of
+    a plan without loading it (no GPU needed); returns the seconds taken."""
+    sec = ctypes.c_double()
+    _check(lib().qmc_specialize(handle, QMC_SPEC_COMPILE_ONLY, ctypes.byref(sec)), "qmc_specialize")
+    return sec.value
 
 
 def korobov_search(plan: Plan, n: int, d: int, candidates: Sequence[int]):

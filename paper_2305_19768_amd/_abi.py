@@ -14,6 +14,8 @@ QMC_MAX_ORDERS = 4
 QMC_MAX_LOG = 4
 QMC_PREC_FP64 = 0
 QMC_PREC_FP32 = 1
+QMC_SPEC_COMPILE_ONLY = 1
+QMC_SPEC_OFF = 2
 TRANSFORMS = {"none": 0, "baker": 1, "korobov1": 2, "korobov2": 3, "korobov3": 4,
               "korobov4": 5, "korobov5": 6, "korobov6": 7}
 
@@ -138,6 +140,11 @@ def lib():
         L.qmc_autotune.argtypes = [vp, u64p, u64p, ctypes.c_int32, ctypes.c_int32, vp,
                                    ctypes.POINTER(LaunchShape)]
         L.qmc_autotune.restype = ctypes.c_int
+        L.qmc_specialize.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+        L.qmc_specialize.restype = ctypes.c_int
+        L.qmc_gen_source.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_char_p,
+                                     ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.qmc_gen_source.restype = ctypes.c_int
         from . import flow as _flow
         _flow.bind(L)
         L.qmc_korobov_p2.argtypes = [vp, ctypes.c_uint64, ctypes.c_int32, u64p, ctypes.c_int32,

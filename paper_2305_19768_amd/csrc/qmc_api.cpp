@@ -662,6 +662,7 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
       dl[n_dl].deform = deform;
       dl[n_dl].flow = flow;
       dl[n_dl].pad = 0;
+      dl[n_dl].gen = (fast && !deform && !flow) ? gen_lookup(p, p->dims[s], f32 != 0) : 0;
       ++n_dl;
     }
     const int64_t nb = (int64_t)L.n_chunks * tiles;
@@ -1088,8 +1089,9 @@ static std::string tune_key(const qmc_plan_s *p) {
     flows += sd.flow != 0;
   }
   char buf[256];
-  std::snprintf(buf, sizeof buf, "S%d d%d K%d M%d p%d m%d c%d f%lld u%lld", p->S, p->d_max, p->K,
-                p->M, p->precision, p->m, p->cplx, flows, mono);
+  // the plan-specialised kernels (qmc_specialize) change which kernels a shape runs
+  std::snprintf(buf, sizeof buf, "S%d d%d K%d M%d p%d m%d c%d f%lld u%lld g%zu", p->S, p->d_max,
+                p->K, p->M, p->precision, p->m, p->cplx, flows, mono, p->gen.size());
   return buf;
 }
 

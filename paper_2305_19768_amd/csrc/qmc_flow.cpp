@@ -108,11 +108,22 @@ size_t qmc_flow_scratch_bytes(int32_t d, int32_t c, int64_t count) {
          align256(sizeof(double) * (size_t)waves) + 256;
 }
 
-// gradient of L = -(1 / w_sum) sum_i w_i log q(x_i) over samples offset + i * stride
+// Scratch layout of a gradient over `count` points: layer inputs, per-wavefront
+// gradients, per-wavefront losses, then the on-device weight sum (one double).
+static size_t wsum_offset(int32_t d, int32_t c, int64_t count) {
+  const int64_t waves = flow_grad_waves(count);
+  return align256(sizeof(double) * 8 * kFlowLayers * (size_t)count) +
+         align256(sizeof(float) * (size_t)waves * flow_params(d, c)) +
+         align256(sizeof(double) * (size_t)waves);
+}
+
+// gradient of L = -scale sum_i w_i log q(x_i) over samples offset + i * stride, where
+// scale = inv_wsum, or inv_wsum / *dev_wsum when the weight sum is on the device
 static qmc_status flow_gradient(void *dev_flow, int32_t d, int32_t c, const double *x,
                                 const double *w, const double *cond, int64_t count,
-                                int64_t offset, int64_t stride, double w_sum, void *scratch,
-                                size_t bytes, void *stream, double *dev_loss) {
+                                int64_t offset, int64_t stride, double inv_wsum,
+                                const double *dev_wsum, void *scratch, size_t bytes, void *stream,
+                                double *dev_loss) {
   if (bytes < qmc_flow_scratch_bytes(d, c, count))
     return fail(QMC_E_NOMEM, "scratch of %zu bytes, %zu needed", bytes,
                 qmc_flow_scratch_bytes(d, c, count));
@@ -122,9 +133,23 @@ static qmc_status flow_gradient(void *dev_flow, int32_t d, int32_t c, const doub
   float *gpart = (float *)(s + align256(sizeof(double) * 8 * kFlowLayers * (size_t)count));
   double *lpart =
       (double *)((char *)gpart + align256(sizeof(float) * (size_t)waves * flow_params(d, c)));
-  int e = launch_flow_grad(dev_flow, d, c, x, w, cond, count, offset, stride, 1.0 / w_sum, zs,
-                           gpart, lpart, dev_loss, stream);
+  int e = launch_flow_grad(dev_flow, d, c, x, w, cond, count, offset, stride, inv_wsum, dev_wsum,
+                           zs, gpart, lpart, dev_loss, stream);
   if (e != hipSuccess) return hip_fail(e, "flow gradient launch");
+  return QMC_OK;
+}
+
+// w_sum > 0: the caller's normaliser; 0: the weights are summed on the device into the
+// scratch's last slot (*dev_wsum set), with no host synchronisation.
+static qmc_status weight_sum(int32_t d, int32_t c, int64_t per, const double *dev_w, int64_t count,
+                             double w_sum, void *scratch, void *stream, const double **dev_wsum) {
+  *dev_wsum = nullptr;
+  if (w_sum > 0.0 && std::isfinite(w_sum)) return QMC_OK;
+  if (w_sum != 0.0) return fail(QMC_E_INVAL, "w_sum must be > 0 (or 0: summed on the device)");
+  double *slot = (double *)((char *)scratch + wsum_offset(d, c, per));
+  int e = launch_flow_wsum(dev_w, count, slot, stream);
+  if (e != hipSuccess) return hip_fail(e, "weight sum launch");
+  *dev_wsum = slot;
   return QMC_OK;
 }
 
@@ -137,9 +162,17 @@ qmc_status qmc_flow_gradient(void *dev_flow, int32_t d, int32_t c, const double 
     return fail(QMC_E_INVAL, "NULL argument");
   CHECK_SHAPE(d, c);
   if (count < 1) return fail(QMC_E_INVAL, "count must be >= 1");
-  if (!(w_sum > 0.0) || !std::isfinite(w_sum)) return fail(QMC_E_INVAL, "w_sum must be > 0");
-  return flow_gradient(dev_flow, d, c, dev_x, dev_w, dev_cond, count, 0, 1, w_sum, dev_scratch,
-                       scratch_bytes, stream, dev_loss);
+  if (!(w_sum >= 0.0) || !std::isfinite(w_sum))
+    return fail(QMC_E_INVAL, "w_sum must be > 0 (or 0: summed on the device)");
+  if (scratch_bytes < qmc_flow_scratch_bytes(d, c, count))
+    return fail(QMC_E_NOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes,
+                qmc_flow_scratch_bytes(d, c, count));
+  const double *dev_wsum;
+  qmc_status st = weight_sum(d, c, count, dev_w, count, w_sum, dev_scratch, stream, &dev_wsum);
+  if (st != QMC_OK) return st;
+  return flow_gradient(dev_flow, d, c, dev_x, dev_w, dev_cond, count, 0, 1,
+                       dev_wsum ? 1.0 : 1.0 / w_sum, dev_wsum, dev_scratch, scratch_bytes, stream,
+                       dev_loss);
 }
 
 qmc_status qmc_flow_adam_step(void *dev_flow, int32_t d, int32_t c, const qmc_flow_adam *opt,
@@ -170,21 +203,27 @@ qmc_status qmc_flow_train(void *dev_flow, int32_t d, int32_t c, const double *de
   CHECK_SHAPE(d, c);
   if (batches < 1 || epochs < 1 || count < batches)
     return fail(QMC_E_INVAL, "need 1 <= batches <= count and epochs >= 1");
-  if (!(w_sum > 0.0) || !std::isfinite(w_sum)) return fail(QMC_E_INVAL, "w_sum must be > 0");
+  if (!(w_sum >= 0.0) || !std::isfinite(w_sum))
+    return fail(QMC_E_INVAL, "w_sum must be > 0 (or 0: summed on the device)");
   // batch b holds samples b, b + batches, b + 2 batches, ...: lattice points in index
   // order fill the cube in slabs, so strided batches are spread over the whole cube
   const int64_t per = count / batches;
   if (scratch_bytes < qmc_flow_scratch_bytes(d, c, per))
     return fail(QMC_E_NOMEM, "scratch of %zu bytes, %zu needed", scratch_bytes,
                 qmc_flow_scratch_bytes(d, c, per));
+  const double *dev_wsum;
+  qmc_status st0 = weight_sum(d, c, per, dev_w, count, w_sum, dev_scratch, stream, &dev_wsum);
+  if (st0 != QMC_OK) return st0;
+  // the batch's weights are normalised by the share of the total it should carry,
+  // w_sum * per / count
+  const double share = (double)count / (double)per;
+  const double inv_b = dev_wsum ? share : share / w_sum;
   qmc_flow_adam a = *opt;
   int64_t t = 0;
   for (int32_t ep = 0; ep < epochs; ++ep)
     for (int32_t b = 0; b < batches; ++b, ++t) {
-      // the batch's weights are normalised by the share of the total it should carry
-      const double wsum_b = w_sum * (double)per / (double)count;
       qmc_status st = flow_gradient(dev_flow, d, c, dev_x, dev_w, dev_cond, per, b, batches,
-                                    wsum_b, dev_scratch, scratch_bytes, stream,
+                                    inv_b, dev_wsum, dev_scratch, scratch_bytes, stream,
                                     dev_loss_history ? dev_loss_history + t : nullptr);
       if (st != QMC_OK) return st;
       a.step = opt->step + (int32_t)t;

@@ -81,10 +81,14 @@ int launch_flow_pack(void *flow, int d, int c, void *stream);
 int launch_flow_transform(const void *flow, int d, int c, const double *u, const double *cond,
                           int64_t count, double *x, double *logJ, int dir, void *stream);
 int flow_grad_waves(int64_t count);
+// inv_wsum: 1 / (sum of weights) when dev_wsum is NULL; else the weights are divided
+// on the device by *dev_wsum and the result multiplied by inv_wsum (a batch's share).
 int launch_flow_grad(void *flow, int d, int c, const double *x, const double *w,
                      const double *cond, int64_t count, int64_t offset, int64_t stride,
-                     double inv_wsum, double *zs, float *gpart, double *lpart, double *loss,
-                     void *stream);
+                     double inv_wsum, const double *dev_wsum, double *zs, float *gpart,
+                     double *lpart, double *loss, void *stream);
+// *out = sum of w[0 .. count) (one workgroup, fixed order)
+int launch_flow_wsum(const double *w, int64_t count, double *out, void *stream);
 int launch_flow_adam(void *flow, int d, int c, float lr, float b1, float b2, float eps, float c1,
                      float c2, void *stream);
 int launch_flow_clear(float *p, int64_t count, void *stream);

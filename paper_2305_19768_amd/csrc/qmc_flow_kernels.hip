@@ -612,13 +612,17 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
 // g + 4, ... (g = wavefront) for them, and the four partial sums are added in order g =
 // 0..3.  The first workgroup also sums the loss over its 256 threads and a fixed tree.
 // Every assignment is fixed, so the sums are deterministic.
+// With wsum (device) set, the per-sample weights entered unnormalised and both sums are
+// multiplied by scale / *wsum (0 when the weights sum to zero); else by scale.
 constexpr int kReduceParams = 64;
 __global__ __launch_bounds__(256) void flow_reduce_kernel(char *flow, int d, int c,
                                                           const float *gpart,
                                                           const double *lpart, int64_t waves,
-                                                          double *loss) {
+                                                          double *loss, const double *wsum,
+                                                          double scale) {
   __shared__ double part[4][kReduceParams];
   __shared__ double lp[256];
+  if (wsum) scale = (*wsum > 0.0) ? scale / *wsum : 0.0;
   const int64_t P = flow_params(d, c);
   const int kk = threadIdx.x & (kReduceParams - 1), g = threadIdx.x / kReduceParams;
   const int64_t k = (int64_t)blockIdx.x * kReduceParams + kk;
@@ -628,7 +632,8 @@ __global__ __launch_bounds__(256) void flow_reduce_kernel(char *flow, int d, int
     for (int64_t w = g; w < waves; w += 4) s += (double)gpart[w * P + k];
   part[g][kk] = s;
   __syncthreads();
-  if (g == 0 && k < P) grad[k] = (float)(((part[0][kk] + part[1][kk]) + part[2][kk]) + part[3][kk]);
+  if (g == 0 && k < P)
+    grad[k] = (float)((((part[0][kk] + part[1][kk]) + part[2][kk]) + part[3][kk]) * scale);
   if (blockIdx.x == 0 && loss) {
     double t = 0.0;
     for (int64_t w = threadIdx.x; w < waves; w += 256) t += lpart[w];
@@ -638,8 +643,31 @@ __global__ __launch_bounds__(256) void flow_reduce_kernel(char *flow, int d, int
       if ((int)threadIdx.x < o) lp[threadIdx.x] += lp[threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) *loss = lp[0];
+    if (threadIdx.x == 0) *loss = lp[0] * scale;
   }
+}
+
+// Sum of the training weights w[0 .. count) into *out: one workgroup; thread t sums
+// the samples t, t + 256, ... with TwoSum compensation, then a fixed tree over the
+// threads' (sum, compensation) pairs (deterministic).
+__global__ __launch_bounds__(256) void flow_wsum_kernel(const double *w, int64_t count,
+                                                        double *out) {
+  __shared__ double ps[256], pc[256];
+  DD acc{0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < count; i += 256) dd_add(acc, w[i]);
+  ps[threadIdx.x] = acc.s;
+  pc[threadIdx.x] = acc.c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const DD r = dd_combine(DD{ps[threadIdx.x], pc[threadIdx.x]},
+                              DD{ps[threadIdx.x + o], pc[threadIdx.x + o]});
+      ps[threadIdx.x] = r.s;
+      pc[threadIdx.x] = r.c;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = ps[0] + pc[0];
 }
 
 // Adam (Kingma and Ba 2015) on the float32 master parameters; c1, c2 are the bias
@@ -1005,13 +1033,19 @@ int launch_flow_transform(const void *flow, int d, int c, const double *u, const
 
 int flow_grad_waves(int64_t count) { return (int)((count + 255) / 256) * 4; }
 
+int launch_flow_wsum(const double *w, int64_t count, double *out, void *stream) {
+  hipLaunchKernelGGL(flow_wsum_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, w, count, out);
+  return (int)hipGetLastError();
+}
+
 int launch_flow_grad(void *flow, int d, int c, const double *x, const double *w,
                      const double *cond, int64_t count, int64_t offset, int64_t stride,
-                     double inv_wsum, double *zs, float *gpart, double *lpart, double *loss,
-                     void *stream) {
+                     double inv_wsum, const double *dev_wsum, double *zs, float *gpart,
+                     double *lpart, double *loss, void *stream) {
   hipStream_t st = (hipStream_t)stream;
-  FlowTrainArgs a{(char *)flow, d, c, x, w, cond, count, offset, stride, inv_wsum, zs, gpart,
-                  lpart};
+  // with a device weight sum the kernel takes the raw weights and the reduction scales
+  FlowTrainArgs a{(char *)flow, d, c, x, w, cond, count, offset, stride,
+                  dev_wsum ? 1.0 : inv_wsum, zs, gpart, lpart};
   const unsigned blocks = (unsigned)((count + 255) / 256);
   hipLaunchKernelGGL(flow_grad_kernel, dim3(blocks), dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
@@ -1020,7 +1054,7 @@ int launch_flow_grad(void *flow, int d, int c, const double *x, const double *w,
   hipLaunchKernelGGL(flow_reduce_kernel, dim3((unsigned)((P + kReduceParams - 1) / kReduceParams)),
                      dim3(256), 0, st,
                      (char *)flow, d, c, (const float *)gpart, (const double *)lpart,
-                     (int64_t)blocks * 4, loss);
+                     (int64_t)blocks * 4, loss, dev_wsum, dev_wsum ? inv_wsum : 1.0);
   return (int)hipGetLastError();
 }
 

@@ -2,9 +2,11 @@
 // kernels of the lattice QMC library.  Not part of the C ABI.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
-#include "../../include/qmcamp.h"
+#include "qmcamp.h"
 
 namespace qmc {
 
@@ -83,6 +85,7 @@ struct DimLaunch {
   int64_t base, blocks;
   int32_t d, fast, f32, deform;   // deform: complex plan (every sector on the deformed path)
   int32_t flow, pad;              // flow: sectors with an attached learned transform
+  uint64_t gen;                   // host handle of a plan-specialised kernel for the class, or 0
 };
 
 struct LaunchArgs {

@@ -268,8 +268,17 @@ int launch_integrate(const LaunchArgs &a, void *stream, const SideStreams *side)
       ls = (hipStream_t)side->stream[i];
     }
     ++k;
-    e = dl.flow ? (hipError_t)launch_flow_integrate(a, dl, ls)
-                : dl.deform ? (hipError_t)launch_deform(a, dl, ls) : launch_class(a, dl, ls);
+    if (dl.gen) {
+      // plan-specialised kernel of the class (same arguments as qmc_integrate_kernel)
+      LaunchArgs args = a;
+      int64_t base = dl.base;
+      void *params[] = {&args, &base};
+      e = hipModuleLaunchKernel((hipFunction_t)dl.gen, (unsigned)dl.blocks, 1, 1, (unsigned)a.block,
+                                1, 1, 0, ls, params, nullptr);
+    } else {
+      e = dl.flow ? (hipError_t)launch_flow_integrate(a, dl, ls)
+                  : dl.deform ? (hipError_t)launch_deform(a, dl, ls) : launch_class(a, dl, ls);
+    }
     if (e != hipSuccess) return (int)e;
   }
   for (int i = 0; i < used; ++i) {

@@ -27,6 +27,14 @@ constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
 qmc_status p2_check_args(uint64_t n, int32_t d, const uint64_t *cand, int32_t n_cand);
 int64_t p2_chunks(uint64_t n, int32_t n_cand);
 
+// A plan-specialised class kernel (run-time compiled): launch class (d, f32) with spp
+// shifts per pass, covering exactly the listed sectors.
+struct GenKernel {
+  int32_t d, f32, spp;
+  void *mod, *fn;                 // hipModule_t, hipFunction_t
+  std::vector<int> sectors;
+};
+
 }  // namespace qmc
 
 struct qmc_plan_s {
@@ -67,7 +75,10 @@ struct qmc_plan_s {
   // side streams of the concurrent per-dimension launches (created when the workspace
   // is bound, on the workspace's device)
   qmc::SideStreams side{};
+  // plan-specialised kernels (qmc_specialize)
+  std::vector<qmc::GenKernel> gen;
   ~qmc_plan_s() {
+    for (qmc::GenKernel &g : gen) (void)hipModuleUnload((hipModule_t)g.mod);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (int i = 0; i < side.n; ++i) {
       (void)hipEventDestroy((hipEvent_t)side.join[i]);
@@ -82,6 +93,10 @@ namespace qmc {
 // Integrate the sectors with active[s] != 0 (all if active is NULL) on lattices n, a;
 // inactive sectors keep their previous Q.  Writes Q to dev_q (or the workspace) and
 // the statistics of every sector to dev_mean / dev_err.
+// Handle of the plan-specialised kernel of launch class (d, f32) under the plan's
+// current launch shape, if one was compiled for exactly the class's current sectors; 0
+// otherwise (the table-driven kernel runs).
+uint64_t gen_lookup(const qmc_plan_s *p, int d, bool f32);
 qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n, const uint64_t *a,
                              const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
                              double *dev_err, const uint64_t *zvec = nullptr);

@@ -152,7 +152,7 @@ class Flow:
         xt = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
         wt = torch.as_tensor(w, dtype=torch.float64, device=self.device).contiguous()
         c = self._cond(cond, xt.shape[0])
-        ws = float(wt.sum()) if w_sum is None else float(w_sum)
+        ws = 0.0 if w_sum is None else float(w_sum)   # 0: the library sums w on the device
         sc, nb = self._scratch(xt.shape[0])
         loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         with _ordered(stream) as sp:
@@ -178,7 +178,7 @@ class Flow:
         xt = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
         wt = torch.as_tensor(w, dtype=torch.float64, device=self.device).contiguous()
         c = self._cond(cond, xt.shape[0])
-        ws = float(wt.sum())
+        ws = 0.0   # the library sums the weights on the device
         sc, nb = self._scratch(xt.shape[0] // batches)
         hist = torch.zeros(batches * epochs, dtype=torch.float64, device=self.device)
         opt = _adam(lr, beta1, beta2, eps, step0)

@@ -1,0 +1,114 @@
+"""GPU parity of the plan-specialised (run-time generated and compiled) integrand kernels
+against the CPU oracle, through the C ABI (qmc_specialize, then qmc_integrate).
+
+Bars as in test_gpu_parity: per-shift sums within 1e-12 (FP64) or 1e-5 (FP32 integrand
+form) of max(|Q_oracle|, (1/n) sum |W f|).  Also: the specialised and table-driven
+kernels agree on the same plan; a launch shape the kernels were not compiled for, and a
+sector that joins a class after specialisation, run on the table-driven kernels.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import flow as OF
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def qmc():
+    import __graft_entry__ as g
+    g._ensure_built()
+    import torch
+    import paper_2305_19768_amd as q
+    torch.cuda.set_device(0)
+    return q
+
+
+def _check(q_gpu, prob, tol, sectors=None, shift_range=None):
+    for s in (range(len(prob.sectors)) if sectors is None else sectors):
+        sec = prob.sectors[s]
+        kw = {} if shift_range is None else {"shift_range": shift_range}
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], threads=8, **kw)
+        got = q_gpu[s] if shift_range is None else q_gpu[s, shift_range[0]:shift_range[1]]
+        rel = np.abs(got - Qo) / np.maximum(np.abs(Qo), So)
+        print(f"sector {s}: d={sec.d} n={sec.n} max rel {rel.max():.2e}", flush=True)
+        assert rel.max() <= tol, (s, rel.max())
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL), ("fp32", 1e-5)])
+def test_specialized_two_loop_parity(qmc, precision, tol):
+    prob = W.two_loop_integral(seed=0, n_scale=0.01)   # 40 sectors, d 4..6, n in [1e3, 1e5]
+    prec = qmc.QMC_PREC_FP32 if precision == "fp32" else qmc.QMC_PREC_FP64
+    plan = qmc.Plan(prob, precision=prec)
+    sec_s = plan.specialize()
+    print(f"specialised in {sec_s:.2f} s", flush=True)
+    q, mean, err = plan.integrate()
+    _check(q.cpu().numpy(), prob, tol)
+
+
+@pytest.mark.parametrize("d,K,M,u_pow,f_pow2", [(1, 1, 0, 0, -2), (3, 2, 1, -1, -4), (5, 3, 2, 2, -6),
+                                                (7, 4, 3, 1, -8), (8, 4, 1, 0, 4), (6, 3, 0, 3, 0)])
+def test_specialized_fast_path_shapes(qmc, d, K, M, u_pow, f_pow2):
+    rng = np.random.default_rng(7 * d + K)
+    ue, uc = W.random_polynomial(rng, d, 6, 2)
+    fe, fc = W.random_polynomial(rng, d, 15, 3)
+    sec = W.Sector(d=d, u_exp=ue, u_coef=uc, f_exp=fe, f_coef=fc,
+                   x_pow2=np.zeros(d, np.int32), u_pow=u_pow, f_pow2=f_pow2,
+                   logc=rng.uniform(-1, 1, size=(K, M + 1)), n=20011,
+                   a=int(rng.integers(2, 20009)), transform="korobov3")
+    prob = W.single_problem(sec, m=8, seed=d)
+    for spp in (1, 2, 4):
+        plan = qmc.Plan(prob, shifts_per_pass=spp)
+        plan.specialize()
+        print(f"d={d} K={K} spp={spp}", flush=True)
+        _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
+
+
+def test_specialized_agrees_with_table_driven(qmc):
+    prob = W.two_loop_integral(seed=7, n_sectors=12, n_scale=0.02)
+    plan = qmc.Plan(prob)
+    q0 = plan.integrate()[0].cpu().numpy()
+    plan.specialize()
+    q1 = plan.integrate()[0].cpu().numpy()
+    q2 = plan.integrate()[0].cpu().numpy()
+    assert np.array_equal(q1, q2)                        # run-to-run bitwise
+    assert np.allclose(q1, q0, rtol=1e-12, atol=0.0)     # same sums up to rounding order
+    plan.specialize(off=True)
+    assert np.array_equal(plan.integrate()[0].cpu().numpy(), q0)
+
+
+def test_unspecialised_shape_and_class_fall_back(qmc):
+    prob = W.two_loop_integral(seed=8, n_sectors=6, n_scale=0.01, m=8)
+    plan = qmc.Plan(prob)
+    # a flow on sector 0 at specialisation time: its class kernel has no case for it
+    fl = qmc.flow.Flow(prob.sectors[0].d, params=OF.flatten(OF.init_params(prob.sectors[0].d, seed=3)))
+    plan.attach_flow(0, fl)
+    plan.specialize()
+    plan.attach_flow(0, None)        # sector 0 rejoins its class: table-driven for that class
+    _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
+    plan.set_launch_shape(256, 8, 1)  # compiled for two shifts per pass: table-driven
+    _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
+    plan.specialize()                # now compiled for one shift per pass as well
+    _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL), ("fp32", 1e-5)])
+def test_specialized_largest_sector_full_size(qmc, precision, tol):
+    prob = W.two_loop_integral(seed=0)
+    prec = qmc.QMC_PREC_FP32 if precision == "fp32" else qmc.QMC_PREC_FP64
+    plan = qmc.Plan(prob, precision=prec)
+    a = [plan.korobov_search(s.n, s.d, [int(c) for c in s.a_candidates])[0] for s in prob.sectors]
+    plan.set_launch_shape(256, 2, 2, 32768)   # the benchmark's shape
+    plan.specialize()
+    q = plan.integrate(a=a)[0].cpu().numpy()
+    assert np.all(np.isfinite(q))
+    s = int(np.argmax([sec.n for sec in prob.sectors]))
+    sec = dataclasses.replace(prob.sectors[s], a=int(a[s]))
+    one = dataclasses.replace(prob, sectors=[sec], shifts=[prob.shifts[s]])
+    _check(q[s:s + 1], one, tol, shift_range=(0, 2))
