@@ -43,7 +43,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libqmc_oracle.so")
+# QMC_ORACLE_LIBRARY selects another build of the oracle (the sanitizer build)
+_LIB_PATH = os.environ.get("QMC_ORACLE_LIBRARY") or os.path.join(_HERE, "libqmc_oracle.so")
 _lib = None
 
 TRANSFORM_CODES = {"none": 0, "baker": 1, "korobov1": 2, "korobov2": 3, "korobov3": 4,

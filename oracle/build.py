@@ -17,9 +17,9 @@ def flags():
             "-mfpmath=sse", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
-def compile_lib(src: str, out: str, verbose: bool = False, extra=None) -> str:
+def compile_lib(src: str, out: str, verbose: bool = False, extra=None, cc: str = "gcc") -> str:
     """Compiles one C source of the oracle to the shared object `out` (atomically)."""
-    cmd = ["gcc", *flags(), *(extra or []), "-o", out + ".tmp", src, "-lm"]
+    cmd = [cc, *flags(), *(extra or []), "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -29,6 +29,15 @@ def compile_lib(src: str, out: str, verbose: bool = False, extra=None) -> str:
 
 def build(verbose: bool = False) -> str:
     return compile_lib(SRC, LIB, verbose)
+
+
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer, compiled by the
+    ROCm clang so that it shares one ASan runtime with the sanitized HIP library."""
+    cc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "llvm", "bin", "clang")
+    return compile_lib(SRC, out, verbose, cc=cc,
+                       extra=["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                              "-fno-omit-frame-pointer", "-g"])
 
 
 if __name__ == "__main__":

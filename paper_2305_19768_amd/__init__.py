@@ -43,7 +43,7 @@ def _stream_ptr(stream=None):
 
 def _check(rc: int, what: str):
     if rc != 0:
-        raise QmcError(rc, f"{what}: {lib().qmc_last_error().decode()}")
+        raise QmcError(rc, f"{what}: {lib().qmc_last_error().decode(errors='replace')}")
 
 
 class Plan:

@@ -7,7 +7,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqmcamp.so")
+# QMC_LIBRARY selects another build of the same library (the sanitizer build of the
+# host code); the default is the in-tree libqmcamp.so.
+LIB_PATH = os.environ.get("QMC_LIBRARY") or os.path.join(HERE, "libqmcamp.so")
 
 QMC_MAX_DIM = 8
 QMC_MAX_ORDERS = 4

@@ -484,8 +484,9 @@ qmc_status qmc_plan(const qmc_problem *prob, const qmc_options *opt, qmc_plan_t 
   }
   p->n_max = opt->n_max ? opt->n_max : nmax;
   if (p->n_max < 2 || p->n_max >= (1ull << 53)) {
+    const unsigned long long bad = (unsigned long long)p->n_max;
     delete p;
-    return fail(QMC_E_INVAL, "n_max = %llu outside [2, 2^53)", (unsigned long long)p->n_max);
+    return fail(QMC_E_INVAL, "n_max = %llu outside [2, 2^53)", bad);
   }
   // built-in shifts
   p->shifts.assign((size_t)p->S * p->m * QMC_MAX_DIM, 0.0);

@@ -19,7 +19,7 @@ _dp = ctypes.c_void_p
 
 def _check(rc, what):
     if rc != 0:
-        raise QmcError(rc, f"{what}: {lib().qmc_last_error().decode()}")
+        raise QmcError(rc, f"{what}: {lib().qmc_last_error().decode(errors='replace')}")
 
 
 def _torch():

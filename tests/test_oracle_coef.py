@@ -150,3 +150,25 @@ def test_library_errors(lib):
     assert lib.coef_series("1/eps", order_lo=0, n_terms=0)[0] == -1
     with pytest.raises(lib.QmcError, match="double range"):
         lib.coef_series(f"{2 ** 1100}")
+
+
+def test_library_survives_malformed_expressions(lib):
+    """Token soup, truncated and unbalanced strings, stray bytes: every call returns a
+    series or raises QmcError (the parser takes caller strings; under the sanitizer
+    build a memory error here aborts the run)."""
+    rng = random.Random(2024)
+    toks = ["eps", "s", "I", "1", "0", "7", "0.5", "1e3", "2.5e-3", "1e", ".", "e", "+", "-", "*",
+            "/", "^", "**", "^-2", "(", ")", "((", "))", " ", "x", "$", "\t", "12345678901234567890",
+            "1/0", "eps^-3", ",", "é", "\\", "''", "^^", "--", "**-"]
+    accepted = 0
+    for _ in range(3000):
+        e = "".join(rng.choice(toks) for _ in range(rng.randint(0, 24)))
+        if rng.random() < 0.1 and e:
+            e = e[:rng.randint(0, len(e))]
+        try:
+            lead, v = lib.coef_series(e, symbols={"s": "3/2"}, order_lo=-8, n_terms=3)
+        except lib.QmcError:
+            continue
+        accepted += 1
+        assert len(v) == 3
+    assert accepted > 30
