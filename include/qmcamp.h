@@ -129,7 +129,18 @@ typedef struct {
                                          U(z) and F(z) in FP32 and the Jacobian, powers,
                                          logarithm and sign check from those in FP64
                                          (sign check margin 2^-20 |F| instead of 2^-40).
-                                         Lattice points and sums are FP64 throughout. */
+                                         Lattice points and sums are FP64 throughout.
+                                         Error of the FP32 form (real plans): the first
+                                         integration (and the first after qmc_set_shifts
+                                         or a flow change) integrates every sector on a
+                                         calibration lattice (n = 1021, Korobov parameter
+                                         of least P_2) with both forms and the plan's
+                                         shifts, synchronizing the stream once; per
+                                         (sector, order) the shift differences
+                                         D_l = Q32_l - Q64_l give the bound
+                                         |mean D| + 3 x its standard error, which every
+                                         err output of the plan then includes (0 for
+                                         sectors evaluated in FP64). */
     uint64_t seed;                    /* seed of the built-in shift generator */
     uint64_t n_max;                   /* largest lattice size any call will use (sizes the
                                          workspace); 0 = max of the sectors' n */
@@ -170,11 +181,12 @@ qmc_status qmc_bind_workspace(qmc_plan_t plan, void *dev_workspace, size_t bytes
 /*
  * qmc_set_shifts -- replace the shifts with caller values: host array
  * shifts[s][l][j], s < n_sectors, l < m, j < QMC_MAX_DIM (only j < d_s is read),
- * each in [0, 1).  Copied to the workspace on `stream`.
+ * each in [0, 1).  Copied to the workspace on `stream` (without a bound workspace they
+ * are kept on the host and uploaded when one is bound).
  * Built-in shifts (used until this is called): Delta_{s,l,j} =
  * (splitmix64(seed, (s << 32) | (l << 8) | j) >> 11) * 2^-53, where splitmix64(seed, c)
  * is the (c+1)-th output of Steele-Lea-Flood's SplitMix64 started from state `seed`.
- * Errors: QMC_E_INVAL (value outside [0,1) or not finite), QMC_E_STATE, QMC_E_DEVICE.
+ * Errors: QMC_E_INVAL (value outside [0,1) or not finite), QMC_E_DEVICE.
  */
 qmc_status qmc_set_shifts(qmc_plan_t plan, const double *shifts, void *stream);
 
@@ -339,15 +351,25 @@ enum { QMC_AMP_HOST = 0, QMC_AMP_DEVICE = 1 };
  * must reach relative error epsrel (error definition of the Sec. 3.2 timing notes) or absolute error
  * epsabs.  Lattice sizes come from the ascending table lattice_n[n_lattice]; the
  * Korobov parameter of size lattice_n[l] for a sector of dimension d is
- * lattice_a[l * QMC_MAX_DIM + d - 1].  tau: per-sector cost of one evaluation (any
- * unit), or NULL for the library's cost model (dense polynomial slots + transform +
- * logarithm work, plus the network of an attached flow).
+ * lattice_a[l * QMC_MAX_DIM + d - 1].
+ * tau: per-sector cost of one evaluation (any unit), fixed for the whole evaluation; or
+ * NULL: measured while the evaluation runs (Sec. 2.1.3, tau_i estimated on-line) --
+ * every workgroup adds its duration on the device's constant 100 MHz clock to its
+ * sector, and a sector's cost is its ticks per evaluation (n_s m per round) summed
+ * over the rounds it was integrated in so far; a sector not yet integrated takes the
+ * library's cost model (polynomial slots + transform + logarithm work, plus the network
+ * of an attached flow).  Only cost ratios matter to the allocation.
+ * tau_used: NULL, or a host array [max_rounds][n_sectors] whose row r receives the
+ * costs the allocation after round r + 1 used (rows of allocations that did not take
+ * place are left as they were; device mode writes at most QMC_AMP_TAU_ROWS rows).
  * mode QMC_AMP_DEVICE runs every round on the device: a round kernel, one persistent
  * kernel over the sectors without a flow (these must be korobov3 with integer powers of
  * U and F) and one over the flow-transformed sectors, then the reduction; the host only
  * polls the state between batches of rounds.  QMC_AMP_HOST integrates each round with
- * qmc_integrate.  Both give the same rounds and lattice sizes.
+ * qmc_integrate.  With the same fixed costs both give the same rounds and lattice sizes
+ * (measured costs differ between runs and forms).
  */
+#define QMC_AMP_TAU_ROWS 64
 typedef struct {
     double epsrel, epsabs;
     double timeout_s;                 /* wall-clock limit, <= 0: none */
@@ -359,7 +381,8 @@ typedef struct {
     int32_t reserved0;
     const uint64_t *lattice_n;        /* [n_lattice], ascending, each <= the plan's n_max */
     const uint64_t *lattice_a;        /* [n_lattice][QMC_MAX_DIM] */
-    const double *tau;                /* [n_sectors] or NULL */
+    const double *tau;                /* [n_sectors] or NULL (measured) */
+    double *tau_used;                 /* output, [max_rounds][n_sectors] or NULL */
 } qmc_amp_options;
 
 typedef struct {
@@ -391,6 +414,10 @@ typedef struct {
  * or not: see stats), QMC_E_TIMEOUT with valid results when the time limit stopped it,
  * QMC_E_INVAL / QMC_E_NONFINITE / QMC_E_DEVICE on failure.  Complex (deformed) plans
  * are not accepted (QMC_E_INVAL).
+ * FP32 plans: the sectors' errors include the FP32 form's rounding bound (see the
+ * precision option), which no lattice size lowers; a target whose bound, propagated
+ * like the errors from the calibration estimates, exceeds half of max(epsrel |A|,
+ * epsabs) is refused before any work with QMC_E_INVAL (evaluate those sums in FP64).
  */
 qmc_status amp_evaluate(qmc_plan_t plan, const qmc_amplitude *amp, const qmc_amp_options *opt,
                         void *stream, double *value, double *error, uint64_t *n_final,

@@ -67,8 +67,8 @@ class Plan:
         _check(lib().qmc_plan(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(h)), "qmc_plan")
         self._h = h
         self.complex = bool(lib().qmc_plan_complex(h))
-        nbytes = int(lib().qmc_workspace_bytes(h))
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        nbytes = int(lib().qmc_workspace_bytes(h))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         _check(lib().qmc_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
                                         ctypes.c_size_t(nbytes), _stream_ptr()),
@@ -330,13 +330,15 @@ class Plan:
     def amp_evaluate(self, coef, epsrel: float, epsabs: float = 0.0, lattice_n=None,
                      lattice_a=None, tau=None, alpha: float = 2.0, n_presample: int = 10000,
                      max_rounds: int = 50, timeout_s: float = 0.0, mode: int = QMC_AMP_HOST,
-                     stream=None, coef_order_lo: int = 0):
+                     stream=None, coef_order_lo: int = 0, return_tau: bool = False):
         """Adaptive evaluation of weighted sums A_t = sum_i C_ti I_i (see amp_evaluate in
         include/qmcamp.h).  coef: complex [n_sums, n_integrals] (or [n_integrals] for one
         sum), or [n_sums, n_integrals, P] Laurent terms of eps^(coef_order_lo + p).
         Returns (value complex [n_sums, K], error complex [n_sums, K] as
         (err_re + 1j err_im), n_final [S], stats dict); order j of the values is
-        eps^(order_lo + coef_order_lo + j)."""
+        eps^(order_lo + coef_order_lo + j).  tau=None measures the costs while the
+        evaluation runs; return_tau=True adds stats["tau_used"] [allocations, S], the
+        costs each allocation used."""
         C = np.asarray(coef, dtype=np.complex128)
         if C.ndim == 1:
             C = C[None, :]
@@ -374,6 +376,10 @@ class Plan:
         if tau is not None:
             tau_arr = np.ascontiguousarray(tau, dtype=np.float64)
             O.tau = tau_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        tau_used = None
+        if return_tau:
+            tau_used = np.full((max_rounds, self.S), np.nan)
+            O.tau_used = tau_used.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         val = np.zeros((T, self.K, 2))
         err = np.zeros((T, self.K, 2))
         nfin = np.zeros(self.S, dtype=np.uint64)
@@ -387,6 +393,11 @@ class Plan:
             _check(rc, "amp_evaluate")
         stats = {f: getattr(st, f) for f, _ in AmpStats._fields_}
         stats["status"] = rc
+        if tau_used is not None:   # the rows the allocations wrote
+            rows = 0
+            while rows < len(tau_used) and not np.isnan(tau_used[rows]).any():
+                rows += 1
+            stats["tau_used"] = tau_used[:rows].copy()
         return (val[..., 0] + 1j * val[..., 1], err[..., 0] + 1j * err[..., 1], nfin, stats)
 
     def amp_evaluate_expressions(self, sums, symbols=None, regulator: str = "eps", **kw):

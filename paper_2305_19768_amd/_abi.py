@@ -82,7 +82,8 @@ class AmpOptions(ctypes.Structure):
                 ("reserved0", ctypes.c_int32),
                 ("lattice_n", ctypes.POINTER(ctypes.c_uint64)),
                 ("lattice_a", ctypes.POINTER(ctypes.c_uint64)),
-                ("tau", ctypes.POINTER(ctypes.c_double))]
+                ("tau", ctypes.POINTER(ctypes.c_double)),
+                ("tau_used", ctypes.POINTER(ctypes.c_double))]
 
 
 class AmpStats(ctypes.Structure):

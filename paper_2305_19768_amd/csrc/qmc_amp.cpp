@@ -101,6 +101,8 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   int32_t *d_iptr = (int32_t *)take(4 * (NI + 1)), *d_isec = (int32_t *)take(4 * S);
   int32_t *d_order = (int32_t *)take(4 * S);
   double *d_want = (double *)take(8 * S), *d_tau = (double *)take(8 * S);
+  double *d_tick_sum = (double *)take(8 * S), *d_eval_sum = (double *)take(8 * S);
+  double *d_trace = (double *)take(8 * (size_t)S * QMC_AMP_TAU_ROWS);
   double *d_c2 = (double *)take(8 * kAmpMaxSums * NI * K);
   double *d_cre = (double *)take(8 * kAmpMaxSums * NI * K);
   double *d_cim = (double *)take(8 * kAmpMaxSums * NI * K);
@@ -132,6 +134,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   }
   AmpState init;
   std::memset(&init, 0, sizeof init);
+  const std::vector<double> zeros(S, 0.0);
   hipStream_t st = (hipStream_t)stream;
   auto up = [&](void *dst_, const void *src, size_t bytes) {
     return bytes ? hipMemcpyAsync(dst_, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
@@ -140,9 +143,12 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
       (e = up(d_dims, p->dims.data(), 4 * S)) || (e = up(d_lidx, lidx.data(), 4 * S)) ||
       (e = up(d_iptr, iptr.data(), 4 * (NI + 1))) || (e = up(d_isec, isec.data(), 4 * S)) ||
       (e = up(d_order, order_dev.data(), 4 * S)) ||
-      (e = up(d_tau, tau.data(), 8 * S)) || (e = up(d_c2, c2.data(), 8 * c2.size())) ||
+      (e = up(d_tau, tau.data(), 8 * S)) || (e = up(d_tick_sum, zeros.data(), 8 * S)) ||
+      (e = up(d_eval_sum, zeros.data(), 8 * S)) || (e = up(d_c2, c2.data(), 8 * c2.size())) ||
       (e = up(d_cre, cre.data(), 8 * cre.size())) || (e = up(d_cim, cim.data(), 8 * cim.size())) ||
       (e = up(d_ln, lad.data(), 8 * lad.size())) ||
+      (e = up(d_trace, opt->tau_used,
+              opt->tau_used ? 8 * (size_t)S * std::min(opt->max_rounds, QMC_AMP_TAU_ROWS) : 0)) ||
       (e = up(d_la, opt->lattice_a, 8 * lad.size() * QMC_MAX_DIM)))
     return hip_fail(e, "upload amplitude tables");
   AmpArgs g;
@@ -172,6 +178,12 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   g.unmet = d_unmet;
   g.want = d_want;
   g.tau = d_tau;
+  g.ticks = (unsigned long long *)(p->ws + p->off_ticks);
+  g.tick_sum = d_tick_sum;
+  g.eval_sum = d_eval_sum;
+  g.measure_tau = opt->tau ? 0 : 1;
+  g.tau_trace = opt->tau_used ? d_trace : nullptr;
+  g.trace_rows = std::min(opt->max_rounds, QMC_AMP_TAU_ROWS);
   g.c2 = d_c2;
   g.cre = d_cre;
   g.cim = d_cim;
@@ -201,6 +213,8 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   la.mean = (double *)(p->ws + p->off_mean);
   la.err = (double *)(p->ws + p->off_err);
   la.status = (int32_t *)(p->ws + p->off_status);
+  p->static_status = nullptr;   // qmc_query_status reads the workspace's status word
+  p->static_sign = nullptr;
   la.n_sectors = S;
   la.m = p->m;
   la.K = K;
@@ -210,8 +224,20 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   la.d_max = p->d_max;
   la.precision = p->precision;
   la.done = &dst->done;
+  la.sector_ticks = g.ticks;
+  if (f32) {   // the sectors' errors include the FP32 form's rounding bound
+    if (!p->bound_in_ws) {
+      if ((e = hipMemcpyAsync(p->ws + p->off_bound, p->f32_bound.data(),
+                              sizeof(double) * p->f32_bound.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess)
+        return hip_fail(e, "upload the FP32 bound");
+      p->bound_in_ws = true;
+    }
+    la.f32_bound = (const double *)(p->ws + p->off_bound);
+  }
   p->lat_valid = false;   // the device rewrites the lattice records
   if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
+  if ((e = launch_clear_u64(g.ticks, S, stream)) != hipSuccess) return hip_fail(e, "tick reset");
   AmpState hs;
   bool timed_out = false;
   for (;;) {
@@ -243,9 +269,16 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
       (e = hipMemcpyAsync(Aim.data(), d_Aim, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
       (e = hipMemcpyAsync(Vre.data(), d_Vre, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
       (e = hipMemcpyAsync(Vim.data(), d_Vim, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
-      (e = hipMemcpyAsync(lidx.data(), d_lidx, 4 * S, hipMemcpyDeviceToHost, st)) ||
-      (e = hipStreamSynchronize(st)))
+      (e = hipMemcpyAsync(lidx.data(), d_lidx, 4 * S, hipMemcpyDeviceToHost, st)))
     return hip_fail(e, "read results");
+  // the trace rows the rounds could have written (the others still hold the caller's
+  // values, uploaded at the start)
+  const int rows = std::min<int>(hs.rounds, g.trace_rows);
+  if (opt->tau_used && rows > 0 &&
+      (e = hipMemcpyAsync(opt->tau_used, d_trace, 8 * (size_t)S * rows, hipMemcpyDeviceToHost,
+                          st)) != hipSuccess)
+    return hip_fail(e, "read costs");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "read results");
   for (int i = 0; i < T * K; ++i) {
     value[2 * i] = Are[i];
     value[2 * i + 1] = Aim[i];
@@ -347,10 +380,59 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
         cim[at] += amp->coef_im ? amp->coef_im[e * Pin + q] : 0.0;
       }
   for (size_t i = 0; i < c2.size(); ++i) c2[i] = cre[i] * cre[i] + cim[i] * cim[i];
+  // FP32 plans: the rounding bound of the FP32 form, measured on the calibration lattice,
+  // is a floor that no lattice size lowers.  A target below twice the floor the bound
+  // sets for a sum (propagated like the errors, from the calibration estimates) is
+  // refused before any work: such sums need the FP64 form.
+  if (p->precision == QMC_PREC_FP32) {
+    if (!p->cal_valid) {
+      qmc_status r = fp32_calibrate(p, stream);
+      if (r != QMC_OK) return r;
+    }
+    std::vector<double> Ic((size_t)NI * K, 0.0), B2((size_t)NI * K, 0.0);
+    for (int s = 0; s < S; ++s)
+      for (int k = 0; k < K; ++k) {
+        const double b = p->f32_bound[(size_t)s * K + k];
+        Ic[(size_t)p->sec[s].integral * K + k] += p->cal_mean[(size_t)s * K + k];
+        B2[(size_t)p->sec[s].integral * K + k] += b * b;
+      }
+    for (int t = 0; t < T; ++t)
+      for (int k = 0; k < K; ++k) {
+        double re = 0.0, im = 0.0, fl2 = 0.0;
+        for (int i = 0; i < NI; ++i)
+          for (int q = 0; q < P && q <= k; ++q) {
+            const size_t at = ((size_t)t * NI + i) * P + q;
+            re += cre[at] * Ic[(size_t)i * K + k - q];
+            im += cim[at] * Ic[(size_t)i * K + k - q];
+            fl2 += c2[at] * B2[(size_t)i * K + k - q];
+          }
+        const double floor = std::sqrt(fl2);
+        const double allowed = std::max(opt->epsrel * std::sqrt(re * re + im * im), opt->epsabs);
+        if (floor > 0.0 && 2.0 * floor > allowed)
+          return fail(QMC_E_INVAL,
+                      "sum %d, order %d: the FP32 form's rounding bound (%.3g, relative %.3g) "
+                      "exceeds half the requested error; evaluate in FP64", t, k, floor,
+                      floor / std::sqrt(re * re + im * im));
+      }
+  }
 
   if (opt->mode == QMC_AMP_DEVICE)
     return amp_device(p, T, NI, P, cre, cim, c2, lad, opt, tau, stream, value, error, n_final,
                       stats, t_start);
+  // measured costs: the integrand kernels add every workgroup's ticks to its sector
+  const bool measure = opt->tau == nullptr;
+  unsigned long long *dev_ticks = (unsigned long long *)(p->ws + p->off_ticks);
+  std::vector<unsigned long long> ticks(S, 0);
+  std::vector<double> tick_sum(S, 0.0), eval_sum(S, 0.0);
+  struct TicksOff {   // the plan records ticks only inside this loop
+    qmc_plan_s *p;
+    ~TicksOff() { p->ticks_on = false; }
+  } ticks_off{p};
+  if (measure) {
+    int e = launch_clear_u64(dev_ticks, S, stream);
+    if (e != hipSuccess) return hip_fail(e, "tick reset");
+    p->ticks_on = true;
+  }
   // ---- presample
   bool limited = false;
   std::vector<size_t> lidx(S, ladder_ceil(lad, (double)std::max<uint64_t>(opt->n_presample, 2), &limited));
@@ -382,7 +464,21 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
     if ((e = hipMemcpyAsync(err.data(), dev_err, sizeof(double) * err.size(),
                             hipMemcpyDeviceToHost, st)) != hipSuccess)
       return hip_fail(e, "read sector errors");
+    if (measure) {
+      if ((e = hipMemcpyAsync(ticks.data(), dev_ticks, sizeof(unsigned long long) * S,
+                              hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return hip_fail(e, "read sector ticks");
+      if ((e = launch_clear_u64(dev_ticks, S, stream)) != hipSuccess) return hip_fail(e, "tick reset");
+    }
     if ((r = qmc_query_status(p, stream, nullptr, nullptr, nullptr)) != QMC_OK) return r;
+    if (measure)
+      for (int s = 0; s < S; ++s) {
+        if (active[s]) {
+          tick_sum[s] += (double)ticks[s];
+          eval_sum[s] += (double)n[s] * (double)m;
+        }
+        if (tick_sum[s] > 0.0) tau[s] = tick_sum[s] / eval_sum[s];
+      }
     // ---- integrals and sums
     std::vector<double> I((size_t)NI * K, 0.0), VI((size_t)NI * K, 0.0);
     for (int s = 0; s < S; ++s)
@@ -430,6 +526,7 @@ extern "C" qmc_status amp_evaluate(qmc_plan_t p, const qmc_amplitude *amp,
     }
     if (rounds > opt->max_rounds) break;
     // ---- allocation (sequential over the unmet targets, largest request kept)
+    if (opt->tau_used) std::memcpy(opt->tau_used + (size_t)(rounds - 1) * S, tau.data(), 8 * (size_t)S);
     const double al = opt->alpha;
     std::vector<double> want(S);
     for (int s = 0; s < S; ++s) want[s] = (double)n[s];

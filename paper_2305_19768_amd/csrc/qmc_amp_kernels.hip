@@ -100,6 +100,19 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
   const int S = g.S, K = g.K, T = g.T, NI = g.NI;
 
   if (st->rounds > 0) {
+    // ---- costs: the ticks of the round just integrated join the running sums; a
+    // sector's cost is its ticks per evaluation so far (the prior until it has any)
+    for (int s = t; s < S; s += kRoundThreads) {
+      if (g.measure_tau) {
+        if (g.active[s]) {
+          g.tick_sum[s] += (double)g.ticks[s];
+          g.eval_sum[s] += (double)g.lattice_n[g.lidx[s]] * (double)g.m;
+        }
+        if (g.tick_sum[s] > 0.0) g.tau[s] = g.tick_sum[s] / g.eval_sum[s];
+      }
+      g.ticks[s] = 0;
+    }
+    __syncthreads();
     // ---- integrals (sum of sectors, variances added) and sums, in a fixed order
     for (int idx = t; idx < NI * K; idx += kRoundThreads) {
       const int c = idx / K, k = idx - c * K;
@@ -158,6 +171,9 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
       return;
     }
     // ---- allocation: unmet targets in order, largest request per sector kept
+    const int row = st->rounds - 1;   // the costs this allocation uses
+    if (g.tau_trace && row < g.trace_rows)
+      for (int s = t; s < S; s += kRoundThreads) g.tau_trace[(int64_t)row * S + s] = g.tau[s];
     const double al = g.alpha;
     for (int s = t; s < S; s += kRoundThreads) g.want[s] = (double)g.lattice_n[g.lidx[s]];
     __syncthreads();
@@ -316,6 +332,7 @@ void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
     __syncthreads();
     const int64_t b = wave_uniform(item);
     if (b >= total) break;
+    const uint64_t t0 = ticks_now();
     const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
     const LatticeDev *__restrict__ lt = a.lat + s;
     const int64_t local = b - lt->block_begin;
@@ -342,6 +359,7 @@ void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
       out[0] = r.s;
       out[1] = r.c;
     }
+    ticks_add(a, s, t0);
   }
 }
 

@@ -88,7 +88,7 @@ static void layout(qmc_plan_s *p) {
      // kAmpMaxLattice table entries
     const size_t S = p->S, NI = p->n_integrals, K = p->K;
     p->amp_bytes = align256(sizeof(AmpState)) + 6 * align256(4 * S) + align256(4 * (NI + 1)) +
-                   2 * align256(8 * S) +
+                   4 * align256(8 * S) + align256(8 * S * QMC_AMP_TAU_ROWS) +
                    3 * align256(8 * kAmpMaxSums * NI * K) + 2 * align256(8 * NI * K) +
                    4 * align256(8 * kAmpMaxSums * K) + align256(4 * kAmpMaxSums * K) +
                    align256(8 * kAmpMaxLattice) + align256(8 * kAmpMaxLattice * QMC_MAX_DIM);
@@ -103,6 +103,11 @@ static void layout(qmc_plan_s *p) {
   p->off_err = take(sizeof(double) * (size_t)p->S * p->KC);
   p->off_status = take(256);
   p->off_sign = take(sizeof(unsigned long long) * (size_t)p->S);
+  p->off_ticks = take(sizeof(unsigned long long) * (size_t)p->S);
+  // FP32 calibration: Q of both forms [2][S][m][KC], their means and errors [2][S][KC],
+  // and the resulting bound [S][KC]
+  p->off_cal = take(sizeof(double) * (2 * (size_t)p->S * p->m * p->KC + 2 * (size_t)p->S * p->KC));
+  p->off_bound = take(sizeof(double) * (size_t)p->S * p->KC);
   p->off_partial = take(sizeof(double) * p->partial_doubles);
   p->off_p2cand = take(sizeof(uint64_t) * kP2MaxCand);
   p->off_p2part = take(sizeof(double) * kP2PartialDoubles);
@@ -564,7 +569,6 @@ qmc_status qmc_bind_workspace(qmc_plan_t p, void *dev, size_t bytes, void *strea
 qmc_status qmc_set_shifts(qmc_plan_t p, const double *shifts, void *stream) {
   g_last_error.clear();
   if (!p || !shifts) return fail(QMC_E_INVAL, "NULL argument");
-  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
   for (int s = 0; s < p->S; ++s)
     for (int l = 0; l < p->m; ++l)
       for (int j = 0; j < p->dims[s]; ++j) {
@@ -578,6 +582,8 @@ qmc_status qmc_set_shifts(qmc_plan_t p, const double *shifts, void *stream) {
         const size_t at = ((size_t)s * p->m + l) * QMC_MAX_DIM + j;
         p->shifts[at] = j < p->dims[s] ? shifts[at] : 0.0;
       }
+  p->cal_valid = false;
+  if (!p->ws) return QMC_OK;   // kept on the host until a workspace is bound
   int e = hipMemcpyAsync(p->ws + p->off_shift, p->shifts.data(), sizeof(double) * p->shifts.size(),
                          hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "upload shifts");
@@ -588,12 +594,129 @@ qmc_status qmc_set_shifts(qmc_plan_t p, const double *shifts, void *stream) {
 
 namespace qmc {
 
+// Calibration lattice of the FP32 rounding bound: n = 1021 (prime) with the Korobov
+// parameter of least P_2 per dimension (exhaustive over a in [1, n/2], smallest a on
+// ties), computed once per process on the host.
+constexpr uint64_t kCalN = 1021;
+
+static uint64_t cal_korobov(int d) {
+  static std::mutex mu;
+  static uint64_t cache[QMC_MAX_DIM + 1] = {};
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache[d]) return cache[d];
+  const double two_pi2 = 2.0 * M_PI * M_PI;
+  double best = INFINITY;
+  uint64_t best_a = 1;
+  for (uint64_t a = 1; a <= kCalN / 2; ++a) {
+    uint64_t z[QMC_MAX_DIM];
+    z[0] = 1;
+    for (int j = 1; j < d; ++j) z[j] = z[j - 1] * a % kCalN;
+    double sum = 0.0;
+    for (uint64_t k = 0; k < kCalN; ++k) {
+      double prod = 1.0;
+      for (int j = 0; j < d; ++j) {
+        const double x = (double)(k * z[j] % kCalN) / (double)kCalN;
+        prod *= 1.0 + two_pi2 * (x * x - x + 1.0 / 6.0);
+      }
+      sum += prod;
+    }
+    const double p2 = sum / (double)kCalN - 1.0;
+    if (p2 < best * (1.0 - 1e-12)) {
+      best = p2;
+      best_a = a;
+    }
+  }
+  cache[d] = best_a;
+  return best_a;
+}
+
+qmc_status fp32_calibrate(qmc_plan_s *p, void *stream, char *static_base, size_t static_cap) {
+  if (p->precision != QMC_PREC_FP32 || p->cplx) return QMC_OK;
+  const size_t S = p->S, KC = p->KC, m = p->m;
+  p->f32_bound.assign(S * KC, 0.0);
+  p->cal_mean.assign(S * KC, 0.0);
+  bool any = false;
+  for (size_t s = 0; s < S; ++s)
+    any = any || (!p->sec[s].flow && (p->sec[s].flags & SF_FAST) && (p->sec[s].flags & SF_F32OK));
+  if (!any) {
+    p->cal_valid = true;
+    return QMC_OK;
+  }
+  // the two forms' Q, means and errors
+  const size_t qn = S * m * KC, need = sizeof(double) * (2 * qn + 2 * S * KC);
+  char *cal;
+  size_t cap = static_cap;
+  if (static_base) {
+    if (align256(need) > static_cap) return fail(QMC_E_NOMEM, "static scratch too small for the FP32 calibration");
+    cap = static_cap - align256(need);
+    cal = static_base + cap;
+  } else {
+    cal = p->ws + p->off_cal;
+  }
+  double *q64 = (double *)cal, *q32 = q64 + qn, *mean = q32 + qn, *err = mean + S * KC;
+  const uint64_t n_c = std::min<uint64_t>(kCalN, p->n_max);
+  std::vector<uint64_t> n(S, n_c), a(S);
+  for (size_t s = 0; s < S; ++s) a[s] = n_c == kCalN ? cal_korobov(p->dims[s]) : 1;
+  const int prec = p->precision;
+  const bool timing = p->timing;
+  p->in_cal = true;
+  p->timing = false;
+  p->precision = QMC_PREC_FP64;
+  qmc_status r = integrate_sectors(p, n.data(), a.data(), nullptr, stream, q64, mean, err, nullptr,
+                                   static_base, cap);
+  p->precision = prec;
+  if (r == QMC_OK)
+    r = integrate_sectors(p, n.data(), a.data(), nullptr, stream, q32, mean, err, nullptr,
+                          static_base, cap);
+  p->in_cal = false;
+  p->timing = timing;
+  if (r != QMC_OK) return r;
+  std::vector<double> h64(qn), h32(qn);
+  hipStream_t st = (hipStream_t)stream;
+  int e;
+  if ((e = hipMemcpyAsync(h64.data(), q64, sizeof(double) * qn, hipMemcpyDeviceToHost, st)) ||
+      (e = hipMemcpyAsync(h32.data(), q32, sizeof(double) * qn, hipMemcpyDeviceToHost, st)) ||
+      (e = hipStreamSynchronize(st)))
+    return hip_fail(e, "read the FP32 calibration");
+  // per (sector, column): the shift differences D_l = Q32_l - Q64_l on the same points
+  // estimate the FP32 form's error; bound = |mean D| + 3 x its standard error
+  for (size_t s = 0; s < S; ++s)
+    for (size_t k = 0; k < KC; ++k) {
+      double md = 0.0, m64 = 0.0;
+      for (size_t l = 0; l < m; ++l) {
+        const size_t at = (s * m + l) * KC + k;
+        md += h32[at] - h64[at];
+        m64 += h64[at];
+      }
+      md /= (double)m;
+      double ss = 0.0;
+      for (size_t l = 0; l < m; ++l) {
+        const size_t at = (s * m + l) * KC + k;
+        const double dl = h32[at] - h64[at] - md;
+        ss += dl * dl;
+      }
+      const double se = m > 1 ? std::sqrt(ss / ((double)(m - 1) * (double)m)) : std::fabs(md);
+      p->f32_bound[s * KC + k] = std::fabs(md) + 3.0 * se;
+      p->cal_mean[s * KC + k] = m64 / (double)m;
+    }
+  p->cal_valid = true;
+  p->bound_in_ws = false;   // uploaded by the next integration on the workspace
+  return QMC_OK;
+}
+
 qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t *a_in,
                              const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
-                             double *dev_err, const uint64_t *zvec) {
+                             double *dev_err, const uint64_t *zvec, char *static_base,
+                             size_t static_cap) {
   if (!p) return fail(QMC_E_INVAL, "NULL plan");
   if (!dev_mean || !dev_err) return fail(QMC_E_INVAL, "dev_mean and dev_err are required");
-  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  const bool in_static = static_base != nullptr;
+  if (!in_static && !p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  const bool with_bound = p->precision == QMC_PREC_FP32 && !p->cplx && !p->in_cal;
+  if (with_bound && !p->cal_valid) {
+    qmc_status r = fp32_calibrate(p, stream, static_base, static_cap);
+    if (r != QMC_OK) return r;
+  }
   const int tiles = p->m / p->tile;
   // lattice table
   __int128 total = 0;
@@ -671,14 +794,78 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
     b += nb;
   }
   p->begin[p->S] = b;
-  if ((size_t)b * p->tile * p->KC * 2 > p->partial_doubles)
-    return fail(QMC_E_NOMEM, "launch needs %lld workgroups, workspace holds %lld", (long long)b,
-                (long long)(p->partial_doubles / (2 * (size_t)p->tile * p->KC)));
   hipStream_t st = (hipStream_t)stream;
   int e;
-  const bool same = p->lat_valid && p->lat_uploaded.size() == p->lat.size() &&
-                    std::memcmp(p->lat_uploaded.data(), p->lat.data(),
-                                sizeof(LatticeDev) * p->lat.size()) == 0;
+  // device regions of this call: the plan's workspace, or a layout in the static scratch
+  char *r_sec, *r_coef, *r_coef32, *r_shift, *r_lat, *r_begin, *r_order, *r_q, *r_status, *r_sign,
+      *r_partial, *r_bound;
+  if (in_static) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+      char *at = static_base + o;
+      o = align256(o + bytes);
+      return at;
+    };
+    r_sec = take(sizeof(SectorDev) * p->S);
+    r_coef = take(sizeof(double) * p->coef.size());
+    r_coef32 = take(sizeof(float) * p->coef32.size());
+    r_shift = take(sizeof(double) * p->shifts.size());
+    r_lat = take(sizeof(LatticeDev) * p->S);
+    r_begin = take(sizeof(int64_t) * (p->S + 1));
+    r_order = take(sizeof(int32_t) * p->S);
+    r_q = dev_q ? nullptr : take(sizeof(double) * (size_t)p->S * p->m * p->KC);
+    r_status = take(256);
+    r_sign = p->cplx ? take(sizeof(unsigned long long) * (size_t)p->S) : nullptr;
+    r_bound = with_bound ? take(sizeof(double) * p->f32_bound.size()) : nullptr;
+    r_partial = take(sizeof(double) * 2 * (size_t)b * p->tile * p->KC);
+    if (o > static_cap)
+      return fail(QMC_E_NOMEM,
+                  "the call needs %zu bytes of static scratch (%lld workgroups), the library "
+                  "holds %zu; lower the launch target (qmc_set_launch_shape) or the shifts",
+                  o, (long long)b, static_cap);
+    auto up = [&](char *dst, const void *src, size_t bytes) {
+      return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    if ((e = up(r_sec, p->sec.data(), sizeof(SectorDev) * p->S)) ||
+        (e = up(r_coef, p->coef.data(), sizeof(double) * p->coef.size())) ||
+        (e = up(r_coef32, p->coef32.data(), sizeof(float) * p->coef32.size())) ||
+        (e = up(r_shift, p->shifts.data(), sizeof(double) * p->shifts.size())) ||
+        (e = up(r_lat, p->lat.data(), sizeof(LatticeDev) * p->S)) ||
+        (e = up(r_begin, p->begin.data(), sizeof(int64_t) * (p->S + 1))) ||
+        (e = up(r_order, p->order.data(), sizeof(int32_t) * p->S)) ||
+        (with_bound && (e = up(r_bound, p->f32_bound.data(), sizeof(double) * p->f32_bound.size()))))
+      return hip_fail(e, "upload tables to the static scratch");
+    p->static_status = (int32_t *)r_status;
+    p->static_sign = (unsigned long long *)r_sign;
+  } else {
+    if ((size_t)b * p->tile * p->KC * 2 > p->partial_doubles)
+      return fail(QMC_E_NOMEM, "launch needs %lld workgroups, workspace holds %lld", (long long)b,
+                  (long long)(p->partial_doubles / (2 * (size_t)p->tile * p->KC)));
+    r_sec = p->ws + p->off_sec;
+    r_coef = p->ws + p->off_coef;
+    r_coef32 = p->ws + p->off_coef32;
+    r_shift = p->ws + p->off_shift;
+    r_lat = p->ws + p->off_lat;
+    r_begin = p->ws + p->off_begin;
+    r_order = p->ws + p->off_order;
+    r_q = p->ws + p->off_q;
+    r_status = p->ws + p->off_status;
+    r_sign = p->ws + p->off_sign;
+    r_partial = p->ws + p->off_partial;
+    r_bound = with_bound ? p->ws + p->off_bound : nullptr;
+    if (with_bound && !p->bound_in_ws) {
+      if ((e = hipMemcpyAsync(r_bound, p->f32_bound.data(), sizeof(double) * p->f32_bound.size(),
+                              hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_fail(e, "upload the FP32 bound");
+      p->bound_in_ws = true;
+    }
+    p->static_status = nullptr;
+    p->static_sign = nullptr;
+  }
+  const bool same = in_static ||
+                    (p->lat_valid && p->lat_uploaded.size() == p->lat.size() &&
+                     std::memcmp(p->lat_uploaded.data(), p->lat.data(),
+                                 sizeof(LatticeDev) * p->lat.size()) == 0);
   if (!same) {
     if ((e = hipMemcpyAsync(p->ws + p->off_lat, p->lat.data(), sizeof(LatticeDev) * p->S,
                             hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -691,32 +878,35 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   }
   LaunchArgs la;
   std::memset(&la, 0, sizeof la);
-  la.sectors = (const SectorDev *)(p->ws + p->off_sec);
-  la.coef = (const double *)(p->ws + p->off_coef);
-  la.coef32 = (const float *)(p->ws + p->off_coef32);
-  la.shifts = (const double *)(p->ws + p->off_shift);
-  la.lat = (const LatticeDev *)(p->ws + p->off_lat);
-  la.block_begin = (const int64_t *)(p->ws + p->off_begin);
-  la.order = (const int32_t *)(p->ws + p->off_order);
+  la.sectors = (const SectorDev *)r_sec;
+  la.coef = (const double *)r_coef;
+  la.coef32 = (const float *)r_coef32;
+  la.shifts = (const double *)r_shift;
+  la.lat = (const LatticeDev *)r_lat;
+  la.block_begin = (const int64_t *)r_begin;
+  la.order = (const int32_t *)r_order;
   la.n_dim_launches = n_dl;
   for (int t = 0; t < n_dl; ++t) la.dims[t] = dl[t];
-  la.partial = (double *)(p->ws + p->off_partial);
-  la.q = dev_q ? dev_q : (double *)(p->ws + p->off_q);
+  la.partial = (double *)r_partial;
+  la.q = dev_q ? dev_q : (double *)r_q;
   la.mean = dev_mean;
   la.err = dev_err;
-  la.status = (int32_t *)(p->ws + p->off_status);
+  la.status = (int32_t *)r_status;
   la.n_sectors = p->S;
   la.m = p->m;
   la.K = p->KC;
   la.cplx = p->cplx;
-  la.sign_count = (unsigned long long *)(p->ws + p->off_sign);
+  la.sign_count = (unsigned long long *)r_sign;
+  la.sector_ticks = (p->ticks_on && !in_static) ? (unsigned long long *)(p->ws + p->off_ticks)
+                                                : nullptr;
+  la.f32_bound = (const double *)r_bound;
   la.shift_tile = p->tile;
   la.shifts_per_pass = p->spp;
   la.block = p->block;
   la.total_blocks = b;
   la.d_max = p->d_max;
   la.precision = p->precision;
-  if (p->timing) {
+  if (p->timing && !in_static) {
     if (p->ev_used + 2 > p->ev.size()) {
       if (p->ev.size() >= 2 * 4096) return fail(QMC_E_STATE, "timing record full; re-enable timing");
       for (int t = 0; t < 2; ++t) {
@@ -732,7 +922,9 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   if ((e = launch_status_reset(la.status, stream)) != hipSuccess) return hip_fail(e, "status reset");
   if (p->cplx && (e = launch_clear_u64(la.sign_count, p->S, stream)) != hipSuccess)
     return hip_fail(e, "sign-check counter reset");
-  if ((e = launch_integrate(la, stream, &p->side)) != hipSuccess) return hip_fail(e, "integrate launch");
+  // the static form runs every class launch on the caller's stream (no side streams)
+  if ((e = launch_integrate(la, stream, in_static ? nullptr : &p->side)) != hipSuccess)
+    return hip_fail(e, "integrate launch");
   return QMC_OK;
 }
 
@@ -957,10 +1149,11 @@ qmc_status qmc_query_status(qmc_plan_t p, void *stream, int32_t *sector, int32_t
                             int32_t *order) {
   g_last_error.clear();
   if (!p) return fail(QMC_E_INVAL, "NULL plan");
-  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (!p->ws && !p->static_status) return fail(QMC_E_STATE, "no workspace bound");
   int32_t code = 0;
   hipStream_t st = (hipStream_t)stream;
-  int e = hipMemcpyAsync(&code, p->ws + p->off_status, sizeof code, hipMemcpyDeviceToHost, st);
+  const void *at = p->static_status ? (const void *)p->static_status : p->ws + p->off_status;
+  int e = hipMemcpyAsync(&code, at, sizeof code, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "read status");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
   if (code == INT32_MAX) {
@@ -991,14 +1184,14 @@ int32_t qmc_plan_complex(qmc_plan_t p) { return p ? p->cplx : -1; }
 
 qmc_status qmc_sign_violations(qmc_plan_t p, void *stream, uint64_t *counts) {
   if (!p || !counts) return fail(QMC_E_INVAL, "NULL argument");
-  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (!p->ws && !p->static_status) return fail(QMC_E_STATE, "no workspace bound");
   if (!p->cplx) {
     for (int s = 0; s < p->S; ++s) counts[s] = 0;
     return QMC_OK;
   }
   hipStream_t st = (hipStream_t)stream;
-  int e = hipMemcpyAsync(counts, p->ws + p->off_sign, sizeof(uint64_t) * p->S,
-                         hipMemcpyDeviceToHost, st);
+  const void *at = p->static_sign ? (const void *)p->static_sign : p->ws + p->off_sign;
+  int e = hipMemcpyAsync(counts, at, sizeof(uint64_t) * p->S, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "read sign-check counters");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
   return QMC_OK;

@@ -695,10 +695,22 @@ __device__ __forceinline__ int find_sector(const int64_t *__restrict__ begin, in
 struct BlockWork {
   int64_t b, chunk_id;
   int s, l_begin, tile;
+  uint64_t t0;   // start on the constant clock (cost accounting)
 };
+
+// Cost accounting for the adaptive loop (the cost per evaluation of each sector is
+// measured while the evaluation runs, Sec. 2.1.3): with a.sector_ticks set, thread 0 of
+// a workgroup adds the workgroup's duration on the constant 100 MHz clock to its
+// sector's counter once the workgroup's partial is stored.
+__device__ __forceinline__ uint64_t ticks_now() { return __builtin_amdgcn_s_memrealtime(); }
+__device__ __forceinline__ void ticks_add(const LaunchArgs &a, int s, uint64_t t0) {
+  if (a.sector_ticks && threadIdx.x == 0)
+    atomicAdd(a.sector_ticks + s, (unsigned long long)(ticks_now() - t0));
+}
 
 __device__ __forceinline__ BlockWork block_work(const LaunchArgs &a, int64_t block_base) {
   BlockWork w;
+  w.t0 = ticks_now();
   w.b = block_base + blockIdx.x;
   w.s = a.order[find_sector(a.block_begin, a.n_sectors, w.b)];
   const LatticeDev *__restrict__ lt = a.lat + w.s;
@@ -724,6 +736,7 @@ __device__ __forceinline__ void block_store(const LaunchArgs &a, const BlockWork
     out[0] = r.s;
     out[1] = r.c;
   }
+  ticks_add(a, w.s, w.t0);
 }
 
 // Maximum shifts per workgroup and waves per workgroup (LDS staging of the partials).

@@ -292,6 +292,7 @@ qmc_status qmc_flow_attach(qmc_plan_t p, int32_t sector, const void *dev_flow, i
   sd.flow_cond = dev_flow ? n_cond : 0;
   for (int k = 0; k < kFlowMaxCond; ++k) sd.cond[k] = (dev_flow && k < n_cond) ? cond[k] : 0.0;
   plan_reorder(p);
+  p->cal_valid = false;   // the sector's integrand form changed
   hipStream_t st = (hipStream_t)stream;
   int e;
   if ((e = hipMemcpyAsync(p->ws + p->off_sec, p->sec.data(), sizeof(SectorDev) * p->S,

@@ -847,6 +847,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
   __shared__ double red[kMaxWaves][kMaxTile * 4][2];
   __shared__ FlowIntegrateLds L;
+  const uint64_t t0 = ticks_now();
   const int64_t b = block_base + blockIdx.x;
   const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
   const LatticeDev *__restrict__ lt = a.lat + s;
@@ -868,6 +869,7 @@ void qmc_flow_integrate_kernel(LaunchArgs a, int64_t block_base) {
     out[0] = r.s;
     out[1] = r.c;
   }
+  ticks_add(a, s, t0);
 }
 
 // The batched form's flow-transformed sectors (real contour): the round's work items
@@ -890,6 +892,7 @@ void qmc_persistent_flow_kernel(LaunchArgs a, AmpState *st) {
     __syncthreads();
     const int64_t b = item;
     if (b >= total) break;
+    const uint64_t t0 = ticks_now();
     const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
     if (s != staged) {
       stage_flow(a, s, L);
@@ -921,6 +924,7 @@ void qmc_persistent_flow_kernel(LaunchArgs a, AmpState *st) {
       out[0] = r.s;
       out[1] = r.c;
     }
+    ticks_add(a, s, t0);
   }
 }
 

@@ -108,6 +108,12 @@ struct LaunchArgs {
   int32_t n_dim_launches;
   int32_t cplx;                    // complex plan: K counts (re, im) columns, K = 2 n_orders
   unsigned long long *sign_count;  // complex plans: [S] sign-check violations
+  // adaptive loop: [S] workgroup durations per sector on the 100 MHz constant clock (the
+  // measured cost per evaluation), or NULL (not recorded)
+  unsigned long long *sector_ticks;
+  // FP32 plans: [S][K] bound on the rounding error of each sector's FP32 estimate,
+  // added to err by the statistics kernel; NULL: nothing added
+  const double *f32_bound;
   DimLaunch dims[4 * QMC_MAX_DIM];
 };
 
@@ -151,7 +157,15 @@ struct AmpArgs {
   const int32_t *int_ptr, *int_sec;   // sectors of integral c: int_sec[int_ptr[c] .. int_ptr[c+1]), ascending
   int32_t *lidx, *active, *unmet;
   double *want;
-  const double *tau, *c2, *cre, *cim;
+  double *tau;                     // [S] cost per evaluation the allocation uses
+  const double *c2, *cre, *cim;
+  // measured costs (Sec. 2.1.3: tau estimated while the evaluation runs): per-round
+  // workgroup ticks of each sector (the persistent kernels add, the round kernel drains),
+  // their running sums and the evaluations they cover; measure_tau = 0 keeps tau fixed.
+  unsigned long long *ticks;
+  double *tick_sum, *eval_sum;
+  int32_t measure_tau, trace_rows;
+  double *tau_trace;               // [trace_rows][S]: tau used by the allocation after each round
   double *I, *VI, *Are, *Aim, *Vre, *Vim;
   const double *mean, *err;
   const uint64_t *lattice_n, *lattice_a;

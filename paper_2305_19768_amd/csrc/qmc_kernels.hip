@@ -89,7 +89,7 @@ __global__ void qmc_stats_kernel(LaunchArgs a) {
   }
   const double var = m > 1 ? (ss.s + ss.c) / (double)(m - 1) : 0.0;
   a.mean[idx] = mean;
-  a.err[idx] = sqrt(var / (double)m);
+  a.err[idx] = sqrt(var / (double)m) + (a.f32_bound ? a.f32_bound[idx] : 0.0);
 }
 
 __global__ void qmc_status_reset_kernel(int32_t *status) {

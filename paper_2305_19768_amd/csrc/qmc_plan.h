@@ -57,7 +57,13 @@ struct qmc_plan_s {
   // workspace layout (byte offsets)
   size_t off_sec = 0, off_coef = 0, off_shift = 0, off_lat = 0, off_begin = 0, off_q = 0,
          off_status = 0, off_partial = 0, off_order = 0, off_mean = 0, off_err = 0, off_coef32 = 0, off_amp = 0, amp_bytes = 0, off_p2cand = 0, off_p2part = 0, off_p2vals = 0,
-         off_sign = 0, total = 0;
+         off_sign = 0, off_ticks = 0, total = 0;
+  bool ticks_on = false;   // record per-sector workgroup ticks (the adaptive loop's costs)
+  // FP32 plans: rounding-error bound per (sector, column) from the calibration lattice
+  // (fp32_calibrate), with the FP64 estimates there; valid until shifts or flows change
+  size_t off_cal = 0, off_bound = 0;
+  bool cal_valid = false, in_cal = false, bound_in_ws = false;
+  std::vector<double> f32_bound, cal_mean;
   int64_t max_blocks = 0;
   int64_t target_blocks = 16384;      // workgroups per launch the chunking aims at
   size_t partial_doubles = 0;         // capacity of the workgroup partial buffer
@@ -77,6 +83,11 @@ struct qmc_plan_s {
   qmc::SideStreams side{};
   // plan-specialised kernels (qmc_specialize)
   std::vector<qmc::GenKernel> gen;
+  // status word and sign-check counters of the last integration laid out in a caller's
+  // region instead of the workspace (integrate_sectors' static_base); NULL after any
+  // call that used the workspace
+  int32_t *static_status = nullptr;
+  unsigned long long *static_sign = nullptr;
   ~qmc_plan_s() {
     for (qmc::GenKernel &g : gen) (void)hipModuleUnload((hipModule_t)g.mod);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -97,7 +108,17 @@ namespace qmc {
 // current launch shape, if one was compiled for exactly the class's current sectors; 0
 // otherwise (the table-driven kernel runs).
 uint64_t gen_lookup(const qmc_plan_s *p, int d, bool f32);
+// With static_base set, every device region of the call (tables, lattice records,
+// workgroup partials, status) is laid out in that buffer of static_cap bytes instead of
+// the plan's workspace, and the tables are uploaded on `stream` first.
 qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n, const uint64_t *a,
                              const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
-                             double *dev_err, const uint64_t *zvec = nullptr);
+                             double *dev_err, const uint64_t *zvec = nullptr,
+                             char *static_base = nullptr, size_t static_cap = 0);
+// FP32 plans: bound the rounding error of the FP32 integrand form per (sector, order)
+// by integrating every sector on a small calibration lattice with the FP64 and with the
+// FP32 form (same points, same shifts) -- once per plan until its shifts or flows
+// change; synchronizes `stream`.  No-op for FP64 and complex plans.
+qmc_status fp32_calibrate(qmc_plan_s *p, void *stream, char *static_base = nullptr,
+                          size_t static_cap = 0);
 }  // namespace qmc

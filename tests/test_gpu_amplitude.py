@@ -268,3 +268,31 @@ def test_invalid_amplitude_arguments(qmc):
     with pytest.raises(qmc.QmcError, match="n_max"):
         plan.amp_evaluate([[1.0, 1.0, 1.0]], 1e-6, lattice_n=np.array([2**40 + 15], np.uint64),
                           lattice_a=np.ones((1, 8), np.uint64))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_measured_costs_parity(qmc, mode):
+    # tau measured while the loop runs (ticks per evaluation of every sector, Sec. 2.1.3):
+    # the oracle's loop, given the costs each allocation used, takes the same rounds and
+    # lattices and gives the same sums
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    coef = np.array([prob.amp_coef])
+    plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+    val, err, nfin, st = plan.amp_evaluate(coef, epsrel=1e-5, lattice_n=sizes, lattice_a=a_tab,
+                                           tau=None, n_presample=1009, mode=mode, return_tau=True)
+    taus = st["tau_used"]
+    print("rounds", st["rounds"], "converged", st["converged"], "tau rows", taus.shape, flush=True)
+    # one row per allocation: after every round but a converged last one
+    assert taus.shape[1] == len(prob.sectors)
+    assert taus.shape[0] == st["rounds"] - (1 if st["converged"] else 0)
+    assert np.all(taus > 0) and np.all(np.isfinite(taus))
+    d = np.array([s.d for s in prob.sectors])
+    # the cost per evaluation grows with the dimension (more monomials, more transforms)
+    assert np.median(taus[0][d == d.max()]) > np.median(taus[0][d == d.min()])
+    ov, oe, on, orounds, oconv = oracle.adaptive_amplitude(prob, coef, sizes, a_tab, taus,
+                                                           epsrel=1e-5, n_presample=1009)
+    assert st["rounds"] == orounds and bool(st["converged"]) == oconv
+    assert np.array_equal(nfin, on)
+    scale = np.abs(ov) + np.abs(oe)
+    assert np.all(np.abs(val - ov) <= 1e-12 * scale)

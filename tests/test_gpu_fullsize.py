@@ -77,9 +77,13 @@ def test_largest_sectors_at_full_size(qmc, two_loop, precision, tol):
         rel = np.abs(q[s, :2] - Qo) / np.maximum(np.abs(Qo), So)
         worst = max(worst, float(rel.max()))
         assert rel.max() <= tol, (s, rel)
+    shift_err = q.std(axis=1, ddof=1) / math.sqrt(prob.m)
     if precision == "fp32":
         assert worst > 1e-12   # the FP32 form ran
-    assert np.allclose(err, q.std(axis=1, ddof=1) / math.sqrt(prob.m), rtol=1e-9)
+        # the stated error adds the FP32 rounding bound to the shift error
+        assert np.all(err >= shift_err * (1 - 1e-9))
+    else:
+        assert np.allclose(err, shift_err, rtol=1e-9)
 
 
 def test_flow_integrated_d6_sector_at_its_own_size(qmc, two_loop):

@@ -208,6 +208,51 @@ def test_fp32_form_two_loop_parity(qmc):
     assert worst > 1e-12   # the FP32 form really ran (not the FP64 path)
 
 
+def test_fp32_form_states_its_error(qmc):
+    """The err output of an FP32 plan includes the FP32 form's rounding bound (measured on
+    the calibration lattice with both forms): the deviation of the FP32 estimate from the
+    FP64 oracle's is within err for every sector and order, the bound is above the
+    shift error where that is tiny, and a sector kept in FP64 (cancelling F) carries no
+    bound (its err equals the oracle's shift error)."""
+    prob = W.two_loop_integral(seed=0, n_sectors=12, n_scale=0.01)
+    cancel = W.custom_sector(4, [(1.0, (0, 0, 0, 0)), (0.5, (1, 0, 0, 0))],
+                             [(1.0, (0, 0, 0, 0)), (-0.3, (1, 1, 0, 0)), (0.2, (0, 0, 2, 0))],
+                             u_pow=1, f_pow2=-6, logc=[[1, 0, 0], [0, -2, 0], [0, 0, 2]],
+                             n=20011, a=5467, transform="korobov3")
+    prob.sectors.append(cancel)
+    prob.shifts.append(W.uniform_shifts(np.random.default_rng(9), prob.m, 4))
+    plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
+    q, mean, err = plan.integrate()
+    mean, err = mean.cpu().numpy(), err.cpu().numpy()
+    ratios = []
+    for s, sec in enumerate(prob.sectors):
+        Qo, So = oracle.sector_sums(sec, prob.shifts[s], threads=8)
+        mo, eo = oracle.estimate(Qo)
+        dev = np.abs(mean[s] - mo)
+        assert np.all(dev <= err[s]), (s, dev, err[s])
+        if s == len(prob.sectors) - 1:   # FP64 form: err is the shift error alone
+            assert np.allclose(err[s], eo, rtol=1e-9, atol=0)
+        else:
+            assert np.all(err[s] > eo)
+            ratios.append(float((dev / err[s]).max()))
+    print("deviation / stated error, FP32 sectors: max", max(ratios), flush=True)
+
+
+def test_fp32_amplitude_refuses_target_below_its_floor(qmc):
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    from test_oracle_adaptive import ladder
+    sizes, a_tab = ladder(seed=2)
+    plan = qmc.Plan(prob, n_max=int(sizes[-1]), precision=qmc.QMC_PREC_FP32)
+    for mode in (0, 1):
+        with pytest.raises(qmc.QmcError, match="rounding bound"):
+            plan.amp_evaluate(prob.amp_coef, epsrel=1e-11, lattice_n=sizes, lattice_a=a_tab,
+                              n_presample=1009, mode=mode)
+    # a target above the floor runs (and, on this ladder, converges)
+    val, err, nfin, st = plan.amp_evaluate(prob.amp_coef, epsrel=5e-4, lattice_n=sizes,
+                                           lattice_a=a_tab, n_presample=1009, mode=1)
+    assert st["converged"] == 1
+
+
 def test_fp32_form_keeps_fp64_for_cancelling_F(qmc):
     # F with a negative coefficient: not eligible, so it is evaluated in FP64 (1e-12 bar)
     sec = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
