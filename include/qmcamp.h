@@ -182,7 +182,7 @@ qmc_status qmc_bind_workspace(qmc_plan_t plan, void *dev_workspace, size_t bytes
  * qmc_set_shifts -- replace the shifts with caller values: host array
  * shifts[s][l][j], s < n_sectors, l < m, j < QMC_MAX_DIM (only j < d_s is read),
  * each in [0, 1).  Copied to the workspace on `stream` (without a bound workspace they
- * are kept on the host and uploaded when one is bound).
+ * are kept on the host for qmc_integrate_static).
  * Built-in shifts (used until this is called): Delta_{s,l,j} =
  * (splitmix64(seed, (s << 32) | (l << 8) | j) >> 11) * 2^-53, where splitmix64(seed, c)
  * is the (c+1)-th output of Steele-Lea-Flood's SplitMix64 started from state `seed`.
@@ -226,6 +226,31 @@ qmc_status qmc_integrate(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, 
  */
 qmc_status qmc_integrate_vec(qmc_plan_t plan, const uint64_t *n, const uint64_t *z, void *stream,
                              double *dev_q, double *dev_mean, double *dev_err);
+
+/*
+ * qmc_integrate_static -- qmc_integrate for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and launches as qmc_integrate, except where the device state
+ * of the call lives: the plan needs no bound workspace; its tables (sector records,
+ * coefficients, shifts) and the call's lattice records, workgroup partials, Q (when
+ * dev_q is NULL) and status word are placed in a device array that the library holds
+ * per GPU, QMC_STATIC_SCRATCH_BYTES long, uploaded to on `stream` at every call.  The
+ * caller passes the outputs (dev_q, dev_mean, dev_err) as before.  No device memory is
+ * allocated: no hipMalloc, no workspace; the array is the current device's (call with
+ * the device of `stream` current) and stays until the process ends.
+ * Errors: as qmc_integrate; QMC_E_NOMEM (before any launch) if the call needs more than
+ * QMC_STATIC_SCRATCH_BYTES (the partials take 16 B per workgroup, shift and column:
+ * lower the launch target with qmc_set_launch_shape).
+ * Sharing: every call on one GPU uses the same array, which keeps the last call's
+ * contents (the status word and sign-check counters are reset by each call; everything
+ * else is written before it is read).  Calls that overlap on one GPU (other streams,
+ * other threads, other plans) race: serialize them.  qmc_query_status and
+ * qmc_sign_violations after this call read the array, valid until the next static call
+ * on that GPU.  The class launches run one after another on `stream`.
+ */
+#define QMC_STATIC_SCRATCH_BYTES (16u << 20)
+qmc_status qmc_integrate_static(qmc_plan_t plan, const uint64_t *n, const uint64_t *a,
+                                void *stream, double *dev_q, double *dev_mean, double *dev_err);
 
 /*
  * Median QMC rule (Sec. 2.2, Eq. median): for every sector, the unshifted rank-1

@@ -55,7 +55,8 @@ class Plan:
 
     def __init__(self, problem, m: Optional[int] = None, precision: int = QMC_PREC_FP64,
                  seed: int = 0, n_max: int = 0, block: int = 0, shift_tile: int = 0,
-                 shifts_per_pass: int = 0, use_problem_shifts: bool = True, device=None):
+                 shifts_per_pass: int = 0, use_problem_shifts: bool = True, device=None,
+                 bind_workspace: bool = True):
         torch = _torch()
         self.problem = problem
         self.m = int(problem.m if m is None else m)
@@ -68,11 +69,13 @@ class Plan:
         self._h = h
         self.complex = bool(lib().qmc_plan_complex(h))
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
-        nbytes = int(lib().qmc_workspace_bytes(h))
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        _check(lib().qmc_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
-                                        ctypes.c_size_t(nbytes), _stream_ptr()),
-               "qmc_bind_workspace")
+        self.workspace = None
+        if bind_workspace:   # without one, only integrate_static runs (static device scratch)
+            nbytes = int(lib().qmc_workspace_bytes(h))
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _check(lib().qmc_bind_workspace(h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                            ctypes.c_size_t(nbytes), _stream_ptr()),
+                   "qmc_bind_workspace")
         if use_problem_shifts and getattr(problem, "shifts", None) is not None:
             self.set_shifts(problem.shifts)
 
@@ -132,6 +135,35 @@ class Plan:
                                        None if a_arr is None else a_arr.ctypes.data_as(u64p), st,
                                        dp(q.data_ptr()) if q is not None else None,
                                        dp(mean.data_ptr()), dp(err.data_ptr())), "qmc_integrate")
+        if check:
+            self.check_status(stream)
+        return q, mean, err
+
+    def integrate_static(self, n: Optional[Sequence[int]] = None,
+                         a: Optional[Sequence[int]] = None, out=None, stream=None,
+                         check: bool = True):
+        """integrate() through qmc_integrate_static: the call's device state lives in the
+        library's static scratch, so it needs no workspace.  Same outputs."""
+        torch = _torch()
+        tail = (2,) if self.complex else ()
+        if out is None:
+            q = torch.empty((self.S, self.m, self.K) + tail, dtype=torch.float64,
+                            device=self.device)
+            mean = torch.empty((self.S, self.K) + tail, dtype=torch.float64, device=self.device)
+            err = torch.empty((self.S, self.K) + tail, dtype=torch.float64, device=self.device)
+        else:
+            q, mean, err = out
+        n_arr = None if n is None else np.ascontiguousarray(n, dtype=np.uint64)
+        a_arr = None if a is None else np.ascontiguousarray(a, dtype=np.uint64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.c_void_p
+        _check(lib().qmc_integrate_static(self._h,
+                                          None if n_arr is None else n_arr.ctypes.data_as(u64p),
+                                          None if a_arr is None else a_arr.ctypes.data_as(u64p),
+                                          _stream_ptr(stream),
+                                          dp(q.data_ptr()) if q is not None else None,
+                                          dp(mean.data_ptr()), dp(err.data_ptr())),
+               "qmc_integrate_static")
         if check:
             self.check_status(stream)
         return q, mean, err

@@ -583,7 +583,7 @@ qmc_status qmc_set_shifts(qmc_plan_t p, const double *shifts, void *stream) {
         p->shifts[at] = j < p->dims[s] ? shifts[at] : 0.0;
       }
   p->cal_valid = false;
-  if (!p->ws) return QMC_OK;   // kept on the host until a workspace is bound
+  if (!p->ws) return QMC_OK;   // kept on the host (uploaded at bind, or by qmc_integrate_static)
   int e = hipMemcpyAsync(p->ws + p->off_shift, p->shifts.data(), sizeof(double) * p->shifts.size(),
                          hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "upload shifts");

@@ -83,9 +83,8 @@ struct qmc_plan_s {
   qmc::SideStreams side{};
   // plan-specialised kernels (qmc_specialize)
   std::vector<qmc::GenKernel> gen;
-  // status word and sign-check counters of the last integration laid out in a caller's
-  // region instead of the workspace (integrate_sectors' static_base); NULL after any
-  // call that used the workspace
+  // status word and sign-check counters of the last qmc_integrate_static call (in the
+  // library's static device scratch); NULL after any call that used the workspace
   int32_t *static_status = nullptr;
   unsigned long long *static_sign = nullptr;
   ~qmc_plan_s() {
