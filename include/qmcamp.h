@@ -487,9 +487,10 @@ qmc_status qmc_autotune(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, i
  * and F and the log-F polynomial of every order fixed, compile it for gfx950 with the
  * HIP run-time compiler and load it on the current device.  qmc_integrate then runs
  * these kernels for those classes; the results equal the table-driven kernels' up to
- * rounding order.  A class kernel is compiled for the shifts per pass of the launch
- * shape at the time of the call and for the sectors the class holds then; under a
- * different shape, or after a sector enters the class (a flow detached), that class
+ * rounding order.  Each class kernel is compiled for two and for four shifts per pass
+ * and for the shifts per pass of the launch shape at the time of the call (FP64 at
+ * d >= 7: one), and for the sectors the class holds then; under a shape with other
+ * shifts per pass, or after a sector enters the class (a flow detached), that class
  * runs the table-driven kernel until qmc_specialize is called again (kernels already
  * compiled are kept).  The amplitude evaluation's persistent kernels are unaffected.
  * flags: 0, QMC_SPEC_COMPILE_ONLY (generate and compile, load nothing: usable without

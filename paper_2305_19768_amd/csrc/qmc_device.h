@@ -314,7 +314,10 @@ __device__ __forceinline__ double recip(double v) {
 // Taylor series atanh(s) = s sum_k s^(2k)/(2k+1) through s^19 (remainder below 2.4e-17
 // relative); e ln 2 with ln 2 split into a 32-bit head (e * head exact) and a tail.
 // log(0) = -inf, log(+inf) = +inf, negative or NaN input gives NaN.
-__device__ __forceinline__ double log_f64(double x) {
+// log_pos: the same for x known to be positive and finite (F with non-negative
+// coefficients and a positive constant term, on the unit cube), without the special
+// cases (no compare-and-select, no divergent branch).
+__device__ __forceinline__ double log_pos(double x) {
   constexpr double kLn2Hi = 0x1.62e42ffp-1;
   constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
   double m = __builtin_amdgcn_frexp_mant(x);   // [0.5, 1) for finite non-zero x
@@ -335,7 +338,11 @@ __device__ __forceinline__ double log_f64(double x) {
   p = __builtin_fma(p, z, 1.0 / 3.0);
   const double logm = 2.0 * __builtin_fma(s * z, p, s);
   const double ed = (double)e;
-  double r = __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, logm));
+  return __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, logm));
+}
+
+__device__ __forceinline__ double log_f64(double x) {
+  const double r = log_pos(x);
   const bool ok = x > 0.0 && x < __builtin_inf();
   return ok ? r : (x == 0.0 ? -__builtin_inf() : (x > 0.0 ? x : __builtin_nan("")));
 }

@@ -191,9 +191,21 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   for (int k = 0; k < K; ++k)
     for (int m = 0; m <= p->M; ++m)
       if (sd.logc[k][m] != 0.0) mmax = std::max(mmax, m);
+  // F > 0 on the whole cube when its coefficients are non-negative and its constant
+  // term positive: then the logarithm needs no special cases
+  bool f_pos = false;
+  for (const Mono &mo : F) {
+    int g = 0;
+    for (int j = 0; j < D; ++j) g += mo.e[j];
+    if (mo.c < 0.0) {
+      f_pos = false;
+      break;
+    }
+    if (g == 0 && mo.c > 0.0) f_pos = true;
+  }
   if (mmax > 0) {
     em.line(f32 ? "const float L = __builtin_amdgcn_logf(F) * 0.693147180559945309f;"
-                : "const double L = qmc::log_f64(F);");
+                : f_pos ? "const double L = qmc::log_pos(F);" : "const double L = qmc::log_f64(F);");
     em.line(std::string("const ") + T + " BL0 = B;");
     for (int m = 1; m <= mmax; ++m)
       em.line(std::string("const ") + T + " BL" + std::to_string(m) + " = BL" +
@@ -338,13 +350,10 @@ bool gen_compile(const std::string &src, const std::string &name, std::vector<ch
   return true;
 }
 
-// Shifts per pass a class kernel runs with under the plan's launch shape (the rule of
-// the table-driven launches: FP64 at d >= 7 one shift per pass).
-int gen_spp(const qmc_plan_s *p, int D, bool f32) {
-  if (f32) return p->spp == 1 ? 1 : 2;
-  if (D >= 7) return 1;
-  return p->spp;
-}
+// Shifts per pass a class kernel runs with under a launch shape of `spp` shifts per
+// pass (FP64 at d >= 7 one shift per pass: two overflow the registers).
+int gen_spp_for(int spp, int D, bool f32) { return (!f32 && D >= 7) ? 1 : spp; }
+int gen_spp(const qmc_plan_s *p, int D, bool f32) { return gen_spp_for(p->spp, D, f32); }
 
 // The fast-path sectors of launch class (D, f32) of the plan.
 std::vector<int> gen_class_sectors(const qmc_plan_s *p, int D, bool f32) {
@@ -380,7 +389,8 @@ qmc_status qmc_gen_source(qmc_plan_t p, int32_t d, int32_t f32, char *buf, size_
   if (d < 1 || d > QMC_MAX_DIM) return fail(QMC_E_INVAL, "d = %d outside [1, %d]", d, QMC_MAX_DIM);
   const std::vector<int> secs = gen_class_sectors(p, d, f32 != 0);
   const std::string src =
-      secs.empty() ? std::string() : gen_class_source(p, d, f32 != 0, gen_spp(p, d, f32 != 0), secs);
+      secs.empty() ? std::string()
+                   : gen_class_source(p, d, f32 != 0, gen_spp(p, d, f32 != 0), secs);
   if (len) *len = src.size();
   if (buf && cap) {
     const size_t n = std::min(cap - 1, src.size());
@@ -410,22 +420,32 @@ qmc_status qmc_specialize(qmc_plan_t p, int32_t flags, double *seconds) {
     bool ok = false;
   };
   std::vector<Job> jobs;
+  // every class for the shifts per pass of the current launch shape and of the shapes
+  // the autotuner prefers (two and four), so that a change of shape keeps the
+  // specialised kernels
   for (int D = 1; D <= QMC_MAX_DIM; ++D)
     for (int f32 = 0; f32 <= 1; ++f32) {
       const std::vector<int> secs = gen_class_sectors(p, D, f32 != 0);
       if (secs.empty()) continue;
-      Job j;
-      j.d = D;
-      j.f32 = f32;
-      j.spp = gen_spp(p, D, f32 != 0);
-      bool have = false;
-      for (const GenKernel &g : p->gen)
-        have |= g.d == D && g.f32 == f32 && g.spp == j.spp && g.sectors == secs;
-      if (have) continue;
-      j.sectors = secs;
-      j.name = gen_kernel_name(D, f32 != 0, j.spp);
-      j.src = gen_class_source(p, D, f32 != 0, j.spp, secs);
-      jobs.push_back(std::move(j));
+      std::vector<int> spps;
+      for (int spp : {p->spp, 2, 4}) {
+        const int S = gen_spp_for(spp, D, f32 != 0);
+        if (std::find(spps.begin(), spps.end(), S) == spps.end()) spps.push_back(S);
+      }
+      for (int S : spps) {
+        bool have = false;
+        for (const GenKernel &g : p->gen)
+          have |= g.d == D && g.f32 == f32 && g.spp == S && g.sectors == secs;
+        if (have) continue;
+        Job j;
+        j.d = D;
+        j.f32 = f32;
+        j.spp = S;
+        j.sectors = secs;
+        j.name = gen_kernel_name(D, f32 != 0, S);
+        j.src = gen_class_source(p, D, f32 != 0, S, secs);
+        jobs.push_back(std::move(j));
+      }
     }
   // the classes compile concurrently (independent programs)
   std::vector<std::thread> th;
