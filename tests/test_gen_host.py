@@ -66,7 +66,7 @@ def _interpret(lines, x):
         m = re.fullmatch(r"\((.*)\) \* (qmc::recip\(\w+\)|r)", e)
         if m:
             return expr(m.group(1)) * (1.0 / env["den"])
-        m = re.fullmatch(r"qmc::log_f64\((\w+)\)", e)
+        m = re.fullmatch(r"qmc::log_(?:f64|pos)\((\w+)\)", e)
         if m:
             return math.log(env[m.group(1)])
         m = re.fullmatch(r"__builtin_amdgcn_logf\((\w+)\) \* .*", e)
@@ -201,3 +201,27 @@ def test_compile_only_every_dimension(q, precision):
     finally:
         q.lib().qmc_plan_free(h)
     assert t > 0.0
+
+
+def test_logarithm_form_follows_the_sign_of_F(q):
+    # F with non-negative coefficients and a positive constant is positive on the cube:
+    # the generated code takes the logarithm without special cases; an F with a negative
+    # coefficient keeps the checked form (non-finite sums are then reported)
+    logc = [[1, 0, 0], [0, -2, 0], [0, 0, 2]]
+    pos = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
+                          [(1.0, (0, 0, 0)), (0.3, (1, 1, 0)), (0.2, (0, 0, 2))], u_pow=1,
+                          f_pow2=-6, logc=logc, n=20011, a=5467, transform="korobov3")
+    neg = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
+                          [(1.0, (0, 0, 0)), (-0.3, (1, 1, 0)), (0.2, (0, 0, 2))], u_pow=1,
+                          f_pow2=-6, logc=logc, n=20011, a=5467, transform="korobov3")
+    rng = np.random.default_rng(3)
+    prob = W.Problem(sectors=[pos, neg], order_lo=-2, m=4,
+                     shifts=[W.uniform_shifts(rng, 4, 3) for _ in range(2)])
+    h = q.host_plan(prob)
+    try:
+        structs = _structs(q.gen_source(h, 3))
+    finally:
+        q.lib().qmc_plan_free(h)
+    body = {s: "\n".join(lines) for s, (_, lines) in structs.items()}
+    assert "qmc::log_pos(F)" in body[0] and "qmc::log_f64" not in body[0]
+    assert "qmc::log_f64(F)" in body[1] and "qmc::log_pos" not in body[1]
