@@ -348,6 +348,7 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
     plan32.enable_timing(False)
     viol32 = plan32.sign_violations()
     m32 = out[1].cpu().numpy()
+    e32 = out[2].cpu().numpy()   # stated error: shift error + the FP32 rounding bound
     c64 = m64[..., 0] + 1j * m64[..., 1]
     c32 = m32[..., 0] + 1j * m32[..., 1]
     err = np.hypot(e64[..., 0], e64[..., 1])
@@ -369,6 +370,8 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
                           "rel_dev_vs_fp64": {"median": float(np.median(rel)),
                                               "p99": float(np.quantile(rel, 0.99)),
                                               "max": float(rel.max())},
+                          "dev_over_stated_error_max": float(np.max(
+                              dev / np.maximum(np.hypot(e32[..., 0], e32[..., 1]), 1e-300))),
                           "dev_over_fp64_shift_error_max": float(np.max(dev / np.maximum(err, 1e-300))),
                           "sectors_violating_at_full_n": int(np.count_nonzero(viol32))}}
 

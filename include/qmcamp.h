@@ -130,13 +130,14 @@ typedef struct {
                                          logarithm and sign check from those in FP64
                                          (sign check margin 2^-20 |F| instead of 2^-40).
                                          Lattice points and sums are FP64 throughout.
-                                         Error of the FP32 form (real plans): the first
-                                         integration (and the first after qmc_set_shifts
-                                         or a flow change) integrates every sector on a
-                                         calibration lattice (n = 1021, Korobov parameter
-                                         of least P_2) with both forms and the plan's
-                                         shifts, synchronizing the stream once; per
-                                         (sector, order) the shift differences
+                                         Error of the FP32 form: the first integration
+                                         (and the first after qmc_set_shifts, a flow or a
+                                         deformation change) integrates every sector on
+                                         a calibration lattice (n = 1021, Korobov
+                                         parameter of least P_2) with both forms and the
+                                         plan's shifts, synchronizing the stream once;
+                                         per (sector, order) -- per real and imaginary
+                                         part in complex plans -- the shift differences
                                          D_l = Q32_l - Q64_l give the bound
                                          |mean D| + 3 x its standard error, which every
                                          err output of the plan then includes (0 for

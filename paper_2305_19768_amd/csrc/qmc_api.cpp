@@ -281,7 +281,8 @@ static bool fp32_range_ok(const SectorDev &sd, const std::vector<double> &coef, 
 // 4: attached flow transform, 5: deformed with the FP32 polynomial bulk, 6: deformed with
 // an attached flow transform.
 static int path_class(const qmc_plan_s *p, int s) {
-  if (p->cplx) return p->sec[s].flow ? 6 : (p->sec[s].flags & SF_CF32) ? 5 : 3;
+  if (p->cplx)
+    return p->sec[s].flow ? 6 : (p->precision == QMC_PREC_FP32 && (p->sec[s].flags & SF_CF32)) ? 5 : 3;
   if (p->sec[s].flow) return 4;
   const int f = p->sec[s].flags;
   if (!(f & SF_FAST)) return 0;
@@ -631,13 +632,14 @@ static uint64_t cal_korobov(int d) {
 }
 
 qmc_status fp32_calibrate(qmc_plan_s *p, void *stream, char *static_base, size_t static_cap) {
-  if (p->precision != QMC_PREC_FP32 || p->cplx) return QMC_OK;
+  if (p->precision != QMC_PREC_FP32) return QMC_OK;
   const size_t S = p->S, KC = p->KC, m = p->m;
   p->f32_bound.assign(S * KC, 0.0);
   p->cal_mean.assign(S * KC, 0.0);
-  bool any = false;
+  bool any = false;   // a sector with an FP32 form (real: the fast path; complex: FP32 bulk)
   for (size_t s = 0; s < S; ++s)
-    any = any || (!p->sec[s].flow && (p->sec[s].flags & SF_FAST) && (p->sec[s].flags & SF_F32OK));
+    any = any || (!p->sec[s].flow && (p->cplx ? (p->sec[s].flags & SF_CF32) != 0
+                                              : (p->sec[s].flags & SF_FAST) && (p->sec[s].flags & SF_F32OK)));
   if (!any) {
     p->cal_valid = true;
     return QMC_OK;
@@ -659,7 +661,7 @@ qmc_status fp32_calibrate(qmc_plan_s *p, void *stream, char *static_base, size_t
   for (size_t s = 0; s < S; ++s) a[s] = n_c == kCalN ? cal_korobov(p->dims[s]) : 1;
   const int prec = p->precision;
   const bool timing = p->timing;
-  p->in_cal = true;
+  p->bound_off = true;
   p->timing = false;
   p->precision = QMC_PREC_FP64;
   qmc_status r = integrate_sectors(p, n.data(), a.data(), nullptr, stream, q64, mean, err, nullptr,
@@ -668,7 +670,7 @@ qmc_status fp32_calibrate(qmc_plan_s *p, void *stream, char *static_base, size_t
   if (r == QMC_OK)
     r = integrate_sectors(p, n.data(), a.data(), nullptr, stream, q32, mean, err, nullptr,
                           static_base, cap);
-  p->in_cal = false;
+  p->bound_off = false;
   p->timing = timing;
   if (r != QMC_OK) return r;
   std::vector<double> h64(qn), h32(qn);
@@ -712,7 +714,7 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
   if (!dev_mean || !dev_err) return fail(QMC_E_INVAL, "dev_mean and dev_err are required");
   const bool in_static = static_base != nullptr;
   if (!in_static && !p->ws) return fail(QMC_E_STATE, "no workspace bound");
-  const bool with_bound = p->precision == QMC_PREC_FP32 && !p->cplx && !p->in_cal;
+  const bool with_bound = p->precision == QMC_PREC_FP32 && !p->bound_off;
   if (with_bound && !p->cal_valid) {
     qmc_status r = fp32_calibrate(p, stream, static_base, static_cap);
     if (r != QMC_OK) return r;
@@ -1206,6 +1208,7 @@ qmc_status qmc_set_deformation(qmc_plan_t p, const double *lambda, void *stream)
     if (!(lambda[s] >= 0.0) || !std::isfinite(lambda[s]))
       return fail(QMC_E_INVAL, "lambda[%d] must be finite and >= 0", s);
   for (int s = 0; s < p->S; ++s) p->sec[s].lambda = lambda[s];
+  p->cal_valid = false;   // the contour changed
   int e = hipMemcpyAsync(p->ws + p->off_sec, p->sec.data(), sizeof(SectorDev) * p->S,
                          hipMemcpyHostToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "upload sectors");
@@ -1240,7 +1243,9 @@ qmc_status qmc_choose_deformation(qmc_plan_t p, uint64_t n_pre, const uint64_t *
     if (!any) break;
     qmc_status st = qmc_set_deformation(p, lam.data(), stream);
     if (st != QMC_OK) return st;
+    p->bound_off = true;   // only the sign-check counts are wanted here
     st = integrate_sectors(p, n.data(), a.data(), active.data(), stream, nullptr, mean, err);
+    p->bound_off = false;
     if (st != QMC_OK) return st;
     if ((st = qmc_sign_violations(p, stream, cnt.data())) != QMC_OK) return st;
     for (int s = 0; s < S; ++s) {

@@ -308,6 +308,13 @@ __device__ __forceinline__ double recip(double v) {
   r = __builtin_fma(__builtin_fma(-v, r, 1.0), r, r);
   return r;
 }
+// One Newton step on the hardware reciprocal (about 2^-25 relative on gfx950): within
+// about 11 ulp of 1/v (measured over 4M random arguments; two steps: within half an ulp).
+// Used where a relative error of a few 1e-15 in a factor of the integrand is immaterial.
+__device__ __forceinline__ double recip1(double v) {
+  const double r = __builtin_amdgcn_rcp(v);
+  return __builtin_fma(__builtin_fma(-v, r, 1.0), r, r);
+}
 
 // Natural logarithm of log F, accurate to a few ulp.  x = m 2^e with m in
 // [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.1716, by the
@@ -339,6 +346,109 @@ __device__ __forceinline__ double log_pos(double x) {
   const double logm = 2.0 * __builtin_fma(s * z, p, s);
   const double ed = (double)e;
   return __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, logm));
+}
+
+// Logarithm by table reduction, for the plan-specialised kernels (x positive and
+// finite).  x = m 2^e with m in [1/2, 1); the top six bits of m's mantissa pick
+// c_i = (1 + (i + 1/2)/64)/2, the centre of m's bucket, so r = m / c_i - 1 lies within
+// +-1/129; log x = e ln 2 + ln c_i + log1p(r), with log1p(r) = r (1 - r/2 + ... + r^6/7)
+// (the next term, r^8/8, is below 2e-18).  kLogTab[i] = {RN(1/c_i), RN(ln c_i)}; r is
+// formed as fma(m, RN(1/c_i), -1).  Absolute error a few 1e-16 (relative accuracy near
+// x = 1 is not kept; the integrands use log x only multiplied into smooth terms).  The
+// table lives in LDS (LogTable, filled once per workgroup by fill_log_table).
+constexpr double kLogTab[64][2] = {
+    {0x1.fc07f01fc07f0p+0, -0x1.5ee82aa241920p-1},
+    {0x1.f44659e4a4271p+0, -0x1.5707a26bb8c66p-1},
+    {0x1.ecc07b301ecc0p+0, -0x1.4f45a835a4e19p-1},
+    {0x1.e573ac901e574p+0, -0x1.47a1527e8a2d3p-1},
+    {0x1.de5d6e3f8868ap+0, -0x1.4019c2125ca93p-1},
+    {0x1.d77b654b82c34p+0, -0x1.38ae2171976e7p-1},
+    {0x1.d0cb58f6ec074p+0, -0x1.315da4434068bp-1},
+    {0x1.ca4b3055ee191p+0, -0x1.2a2786d0ec107p-1},
+    {0x1.c3f8f01c3f8f0p+0, -0x1.230b0d8bebc98p-1},
+    {0x1.bdd2b899406f7p+0, -0x1.1c07849ae6007p-1},
+    {0x1.b7d6c3dda338bp+0, -0x1.151c3f6f29612p-1},
+    {0x1.b2036406c80d9p+0, -0x1.0e4898611cce1p-1},
+    {0x1.ac5701ac5701bp+0, -0x1.078bf0533c568p-1},
+    {0x1.a6d01a6d01a6dp+0, -0x1.00e5ae5b207abp-1},
+    {0x1.a16d3f97a4b02p+0, -0x1.f4aa7ee03192dp-2},
+    {0x1.9c2d14ee4a102p+0, -0x1.e7b42c3ddad73p-2},
+    {0x1.970e4f80cb872p+0, -0x1.dae75484c9616p-2},
+    {0x1.920fb49d0e229p+0, -0x1.ce42f18064743p-2},
+    {0x1.8d3018d3018d3p+0, -0x1.c1c60693fa39ep-2},
+    {0x1.886e5f0abb04ap+0, -0x1.b56fa04462909p-2},
+    {0x1.83c977ab2beddp+0, -0x1.a93ed3c8ad9e3p-2},
+    {0x1.7f405fd017f40p+0, -0x1.9d32bea15ed3bp-2},
+    {0x1.7ad2208e0ecc3p+0, -0x1.914a8635bf68ap-2},
+    {0x1.767dce434a9b1p+0, -0x1.85855776dcbfbp-2},
+    {0x1.724287f46debcp+0, -0x1.79e26687cfb3ep-2},
+    {0x1.6e1f76b4337c7p+0, -0x1.6e60ee6af1972p-2},
+    {0x1.6a13cd1537290p+0, -0x1.630030b3aac49p-2},
+    {0x1.661ec6a5122f9p+0, -0x1.57bf753c8d1fbp-2},
+    {0x1.623fa77016240p+0, -0x1.4c9e09e172c3cp-2},
+    {0x1.5e75bb8d015e7p+0, -0x1.419b423d5e8c7p-2},
+    {0x1.5ac056b015ac0p+0, -0x1.36b6776be1117p-2},
+    {0x1.571ed3c506b3ap+0, -0x1.2bef07cdc9354p-2},
+    {0x1.5390948f40febp+0, -0x1.214456d0eb8d4p-2},
+    {0x1.5015015015015p+0, -0x1.16b5ccbacfb73p-2},
+    {0x1.4cab88725af6ep+0, -0x1.0c42d676162e3p-2},
+    {0x1.49539e3b2d067p+0, -0x1.01eae5626c691p-2},
+    {0x1.460cbc7f5cf9ap+0, -0x1.ef5ade4dcffe6p-3},
+    {0x1.42d6625d51f87p+0, -0x1.db13db0d48940p-3},
+    {0x1.3fb013fb013fbp+0, -0x1.c6ffbc6f00f71p-3},
+    {0x1.3c995a47babe7p+0, -0x1.b31d8575bce3dp-3},
+    {0x1.3991c2c187f63p+0, -0x1.9f6c407089664p-3},
+    {0x1.3698df3de0748p+0, -0x1.8beafeb38fe8cp-3},
+    {0x1.33ae45b57bcb2p+0, -0x1.7898d85444c73p-3},
+    {0x1.30d190130d190p+0, -0x1.6574ebe8c133ap-3},
+    {0x1.2e025c04b8097p+0, -0x1.527e5e4a1b58dp-3},
+    {0x1.2b404ad012b40p+0, -0x1.3fb45a59928ccp-3},
+    {0x1.288b01288b013p+0, -0x1.2d1610c86813ap-3},
+    {0x1.25e22708092f1p+0, -0x1.1aa2b7e23f72ap-3},
+    {0x1.23456789abcdfp+0, -0x1.08598b59e3a07p-3},
+    {0x1.20b470c67c0d9p+0, -0x1.ec739830a1120p-4},
+    {0x1.1e2ef3b3fb874p+0, -0x1.c885801bc4b23p-4},
+    {0x1.1bb4a4046ed29p+0, -0x1.a4e7640b1bc38p-4},
+    {0x1.19453808ca29cp+0, -0x1.8197e2f40e3f0p-4},
+    {0x1.16e0689427379p+0, -0x1.5e95a4d9791cbp-4},
+    {0x1.1485f0e0acd3bp+0, -0x1.3bdf5a7d1ee64p-4},
+    {0x1.12358e75d3033p+0, -0x1.1973bd1465567p-4},
+    {0x1.0fef010fef011p+0, -0x1.eea31c006b87cp-5},
+    {0x1.0db20a88f4696p+0, -0x1.aaef2d0fb10fcp-5},
+    {0x1.0b7e6ec259dc8p+0, -0x1.67c94f2d4bb58p-5},
+    {0x1.0953f39010954p+0, -0x1.252f32f8d183fp-5},
+    {0x1.073260a47f7c6p+0, -0x1.c63d2ec14aaf2p-6},
+    {0x1.05197f7d73404p+0, -0x1.432a925980cc1p-6},
+    {0x1.03091b51f5e1ap+0, -0x1.82448a388a2aap-7},
+    {0x1.0101010101010p+0, -0x1.0080559588b35p-8},
+};
+struct LogTable {
+  double v[64][2];
+};
+__device__ __forceinline__ void fill_log_table(LogTable &t) {
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    t.v[i][0] = kLogTab[i][0];
+    t.v[i][1] = kLogTab[i][1];
+  }
+}
+__device__ __forceinline__ double log_tab(double x, const LogTable &t) {
+  constexpr double kLn2Hi = 0x1.62e42ffp-1;
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+  const double m = __builtin_amdgcn_frexp_mant(x);   // [1/2, 1)
+  const int e = __builtin_amdgcn_frexp_exp(x);
+  const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, m) >> 32);
+  const int i = (int)((hi >> 14) & 63u);             // top six mantissa bits
+  const double inv_c = t.v[i][0], log_c = t.v[i][1];
+  const double r = __builtin_fma(m, inv_c, -1.0);
+  double p = 1.0 / 7.0;
+  p = __builtin_fma(p, r, -1.0 / 6.0);
+  p = __builtin_fma(p, r, 1.0 / 5.0);
+  p = __builtin_fma(p, r, -1.0 / 4.0);
+  p = __builtin_fma(p, r, 1.0 / 3.0);
+  p = __builtin_fma(p, r, -0.5);
+  p = __builtin_fma(p, r, 1.0);
+  const double ed = (double)e;
+  return __builtin_fma(ed, kLn2Hi, __builtin_fma(ed, kLn2Lo, __builtin_fma(r, p, log_c)));
 }
 
 __device__ __forceinline__ double log_f64(double x) {
@@ -762,10 +872,10 @@ constexpr int kFold = 8;
 // instructions per point; the persistent kernel, tighter on registers, uses literals).
 //
 // GEN: a plan-specialised integrand (generated straight-line code for one sector,
-// compiled at run time) with static members f64<S>(x, f, C) and f32<S>(x, f, C) that give
-// the orders f_k of S korobov3-transformed samples, reading the sector's coefficients in
-// the order of use from C = coefficient table + gen_off; NoGen selects the table-driven
-// forms.
+// compiled at run time, its coefficients as literals) with static members
+// f64<S>(x, f, C, log_table) and f32<S>(x, f, C) that give the orders f_k of S
+// korobov3-transformed samples (C, the coefficient table + gen_off, is passed for
+// generators that read it); NoGen selects the table-driven forms.
 struct NoGen {};
 template <class T>
 struct IsGen {
@@ -797,6 +907,12 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
   // every lane runs the same number of iterations; lanes past i_end contribute 0
   const int64_t n_iter = (int64_t)((i_end - i_begin + B - 1) / B);
 
+  // the logarithm table of the generated FP64 integrands, in LDS for the workgroup
+  __shared__ LogTable log_table;
+  if constexpr (IsGen<GEN>::value && !F32) {
+    fill_log_table(log_table);
+    __syncthreads();
+  }
   KorobovConsts kc{35.0, -84.0, 70.0, -20.0};
   if constexpr (REGCONST) kc = korobov3_consts();
   // lattice state of this thread at its first point i0: k_j = i0 z_j mod n
@@ -875,7 +991,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
             }
           } else {
             korobov3_fast<D, S>(w_scale, kc, y, x, W);
-            GEN::template f64<S>(x, f, launder_after(cl + gen_off, W[0]));
+            GEN::template f64<S>(x, f, launder_after(cl + gen_off, W[0]), log_table);
           }
         } else if (F32) {
           float yf[S][D], xf[S][D], Wf[S], ff[S][K];

@@ -183,7 +183,7 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
       em.line("r = __builtin_fmaf(__builtin_fmaf(-den, r, 1.0f), r, r);");
       em.line("const float B = (" + num + ") * r;");
     } else {
-      em.line("const double B = (" + num + ") * qmc::recip(den);");
+      em.line("const double B = (" + num + ") * qmc::recip1(den);");
     }
   }
   // orders: f_k = sum_m logc[k][m] B L^m, from the terms BL_m = B L^m
@@ -205,7 +205,7 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   }
   if (mmax > 0) {
     em.line(f32 ? "const float L = __builtin_amdgcn_logf(F) * 0.693147180559945309f;"
-                : f_pos ? "const double L = qmc::log_pos(F);" : "const double L = qmc::log_f64(F);");
+                : f_pos ? "const double L = qmc::log_tab(F, lt);" : "const double L = qmc::log_f64(F);");
     em.line(std::string("const ") + T + " BL0 = B;");
     for (int m = 1; m <= mmax; ++m)
       em.line(std::string("const ") + T + " BL" + std::to_string(m) + " = BL" +
@@ -231,10 +231,11 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
                 "struct G%d {\n"
                 "  template <int S>\n"
                 "  __device__ static __forceinline__ void %s(const %s (&x)[S][%d], %s (&f)[S][%d],\n"
-                "                                          qmc::cptr<%s>) {\n"
+                "                                          qmc::cptr<%s>%s) {\n"
                 "#pragma unroll\n"
                 "    for (int u = 0; u < S; ++u) {\n",
-                s, f32 ? "f32" : "f64", T, D, T, K, T);
+                s, f32 ? "f32" : "f64", T, D, T, K, T,
+                f32 ? "" : ", const qmc::LogTable &lt");
   return std::string(head) + em.body + "    }\n  }\n};\n";
 }
 

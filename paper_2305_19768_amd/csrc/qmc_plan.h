@@ -62,7 +62,9 @@ struct qmc_plan_s {
   // FP32 plans: rounding-error bound per (sector, column) from the calibration lattice
   // (fp32_calibrate), with the FP64 estimates there; valid until shifts or flows change
   size_t off_cal = 0, off_bound = 0;
-  bool cal_valid = false, in_cal = false, bound_in_ws = false;
+  // bound_off: integrations that need no bound (the calibration itself, the presample
+  // choice of the deformation parameters)
+  bool cal_valid = false, bound_off = false, bound_in_ws = false;
   std::vector<double> f32_bound, cal_mean;
   int64_t max_blocks = 0;
   int64_t target_blocks = 16384;      // workgroups per launch the chunking aims at
@@ -114,10 +116,10 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n, const uint64_t *a
                              const uint8_t *active, void *stream, double *dev_q, double *dev_mean,
                              double *dev_err, const uint64_t *zvec = nullptr,
                              char *static_base = nullptr, size_t static_cap = 0);
-// FP32 plans: bound the rounding error of the FP32 integrand form per (sector, order)
-// by integrating every sector on a small calibration lattice with the FP64 and with the
-// FP32 form (same points, same shifts) -- once per plan until its shifts or flows
-// change; synchronizes `stream`.  No-op for FP64 and complex plans.
+// FP32 plans: bound the rounding error of the FP32 form per (sector, column) by
+// integrating every sector on a small calibration lattice with the FP64 and with the
+// FP32 form (same points, same shifts) -- once per plan until its shifts, flows or
+// deformation parameters change; synchronizes `stream`.  No-op for FP64 plans.
 qmc_status fp32_calibrate(qmc_plan_s *p, void *stream, char *static_base = nullptr,
                           size_t static_cap = 0);
 }  // namespace qmc

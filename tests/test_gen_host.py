@@ -63,10 +63,10 @@ def _interpret(lines, x):
         if m:
             a, b, c = _split_args(m.group(1))
             return expr(a) * expr(b) + expr(c)
-        m = re.fullmatch(r"\((.*)\) \* (qmc::recip\(\w+\)|r)", e)
+        m = re.fullmatch(r"\((.*)\) \* (qmc::recip1?\(\w+\)|r)", e)
         if m:
             return expr(m.group(1)) * (1.0 / env["den"])
-        m = re.fullmatch(r"qmc::log_(?:f64|pos)\((\w+)\)", e)
+        m = re.fullmatch(r"qmc::log_(?:f64|pos|tab)\((\w+)(?:, lt)?\)", e)
         if m:
             return math.log(env[m.group(1)])
         m = re.fullmatch(r"__builtin_amdgcn_logf\((\w+)\) \* .*", e)
@@ -205,7 +205,8 @@ def test_compile_only_every_dimension(q, precision):
 
 def test_logarithm_form_follows_the_sign_of_F(q):
     # F with non-negative coefficients and a positive constant is positive on the cube:
-    # the generated code takes the logarithm without special cases; an F with a negative
+    # the generated code takes the table-reduced logarithm without special cases; an F
+    # with a negative
     # coefficient keeps the checked form (non-finite sums are then reported)
     logc = [[1, 0, 0], [0, -2, 0], [0, 0, 2]]
     pos = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
@@ -223,5 +224,5 @@ def test_logarithm_form_follows_the_sign_of_F(q):
     finally:
         q.lib().qmc_plan_free(h)
     body = {s: "\n".join(lines) for s, (_, lines) in structs.items()}
-    assert "qmc::log_pos(F)" in body[0] and "qmc::log_f64" not in body[0]
-    assert "qmc::log_f64(F)" in body[1] and "qmc::log_pos" not in body[1]
+    assert "qmc::log_tab(F, lt)" in body[0] and "qmc::log_f64" not in body[0]
+    assert "qmc::log_f64(F)" in body[1] and "qmc::log_tab" not in body[1]

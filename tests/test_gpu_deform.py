@@ -207,7 +207,7 @@ def _compare32(qmc, prob, fp64_sectors=()):
     plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
     assert plan.complex
     q, mean, err = plan.integrate(check=False)
-    q = q.cpu().numpy()
+    q, mean, err = q.cpu().numpy(), mean.cpu().numpy(), err.cpu().numpy()
     viol = plan.sign_violations()
     worst = 0.0
     for s, sec in enumerate(prob.sectors):
@@ -216,6 +216,11 @@ def _compare32(qmc, prob, fp64_sectors=()):
         dev = np.abs(g - Q) / np.maximum(np.abs(Q), S)
         tol = TOL if s in fp64_sectors else TOL32
         assert np.all(dev <= tol), (s, float(dev.max()))
+        # the stated error (shift error + the calibrated FP32 bound) covers the FP32
+        # estimate's distance from the FP64 oracle's, part by part
+        mo = Q.mean(axis=0)
+        assert np.all(np.abs(mean[s, :, 0] - mo.real) <= err[s, :, 0]), s
+        assert np.all(np.abs(mean[s, :, 1] - mo.imag) <= err[s, :, 1]), s
         if s not in fp64_sectors:
             worst = max(worst, float(dev.max()))
         # FP32 sign check: violations above FP32 rounding (2^-20 |F|) only, so counts
