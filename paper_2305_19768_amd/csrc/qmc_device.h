@@ -885,6 +885,17 @@ template <>
 struct IsGen<NoGen> {
   static constexpr bool value = false;
 };
+// A generated integrand with finite = true is finite on the whole closed cube (F, and U
+// where it divides, positive there), so a sample of weight 0 contributes 0 without a
+// test and lanes past the chunk only need weight 0.
+template <class T>
+struct GenFinite {
+  static constexpr bool value = T::finite;
+};
+template <>
+struct GenFinite<NoGen> {
+  static constexpr bool value = false;
+};
 
 template <int D, int K, int S, bool FAST, bool F32, bool REGCONST = true, class GEN = NoGen>
 __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int l_begin, int tile,
@@ -974,6 +985,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
           for (int j = 0; j < D; ++j)
             y[u][j] = shifted(q[j], shl[(u < live ? u : 0) * QMC_MAX_DIM + j]);
         double f[S][K];
+        const bool valid = i < i_end;
         if constexpr (IsGen<GEN>::value) {
           if constexpr (F32) {
             float yf[S][D], xf[S][D], Wf[S], ff[S][K];
@@ -985,6 +997,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
             GEN::template f32<S>(xf, ff, launder_after_f(cl32 + gen_off, Wf[0]));
 #pragma unroll
             for (int u = 0; u < S; ++u) {
+              if constexpr (GenFinite<GEN>::value) Wf[u] = valid ? Wf[u] : 0.0f;
               W[u] = (double)Wf[u];
 #pragma unroll
               for (int kk = 0; kk < K; ++kk) f[u][kk] = (double)(Wf[u] * ff[u][kk]);
@@ -1015,13 +1028,26 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
           for (int u = 0; u < S; ++u) W[u] = apply_transform<D>(kind, w_scale, y[u], x[u]);
           integrand<D, K, S>(ss, (cptr<SectorDev>)sd, launder_after(cl, W[0]), x, f);
         }
-        const bool valid = i < i_end;
+        if constexpr (GenFinite<GEN>::value) {
 #pragma unroll
-        for (int u = 0; u < S; ++u) {
-          const bool use = valid && (W[u] != 0.0);
+          for (int u = 0; u < S; ++u) {
+            if constexpr (F32) {   // the weight (0 past the chunk) is in f already
 #pragma unroll
-          for (int kk = 0; kk < K; ++kk)
-            part[u][kk] += use ? (F32 ? f[u][kk] : W[u] * f[u][kk]) : 0.0;
+              for (int kk = 0; kk < K; ++kk) part[u][kk] += f[u][kk];
+            } else {
+              const double w = valid ? W[u] : 0.0;
+#pragma unroll
+              for (int kk = 0; kk < K; ++kk) part[u][kk] = __builtin_fma(w, f[u][kk], part[u][kk]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < S; ++u) {
+            const bool use = valid && (W[u] != 0.0);
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk)
+              part[u][kk] += use ? (F32 ? f[u][kk] : W[u] * f[u][kk]) : 0.0;
+          }
         }
       }
 #pragma unroll

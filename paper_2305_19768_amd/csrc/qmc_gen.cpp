@@ -145,6 +145,19 @@ struct Emitter {
   }
 };
 
+// Non-negative coefficients and a positive constant term: the polynomial is at least
+// that constant on [0, 1]^d.
+bool positive_on_cube(const std::vector<Mono> &P, int D) {
+  bool c0 = false;
+  for (const Mono &mo : P) {
+    if (mo.c < 0.0) return false;
+    int g = 0;
+    for (int j = 0; j < D; ++j) g += mo.e[j];
+    c0 = c0 || (g == 0 && mo.c > 0.0);
+  }
+  return c0;
+}
+
 std::string product(const std::string &base, int times, const std::string &one) {
   if (times == 0) return one;
   std::string s = base;
@@ -192,17 +205,10 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
     for (int m = 0; m <= p->M; ++m)
       if (sd.logc[k][m] != 0.0) mmax = std::max(mmax, m);
   // F > 0 on the whole cube when its coefficients are non-negative and its constant
-  // term positive: then the logarithm needs no special cases
-  bool f_pos = false;
-  for (const Mono &mo : F) {
-    int g = 0;
-    for (int j = 0; j < D; ++j) g += mo.e[j];
-    if (mo.c < 0.0) {
-      f_pos = false;
-      break;
-    }
-    if (g == 0 && mo.c > 0.0) f_pos = true;
-  }
+  // term positive: then the logarithm needs no special cases, and with U positive too
+  // (where it divides) the integrand is finite on the closed cube
+  const bool f_pos = positive_on_cube(F, D);
+  const bool finite = f_pos && (sd.u_den == 0 || positive_on_cube(U, D));
   if (mmax > 0) {
     em.line(f32 ? "const float L = __builtin_amdgcn_logf(F) * 0.693147180559945309f;"
                 : f_pos ? "const double L = qmc::log_tab(F, lt);" : "const double L = qmc::log_f64(F);");
@@ -229,12 +235,13 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   char head[512];
   std::snprintf(head, sizeof head,
                 "struct G%d {\n"
+                "  static constexpr bool finite = %s;\n"
                 "  template <int S>\n"
                 "  __device__ static __forceinline__ void %s(const %s (&x)[S][%d], %s (&f)[S][%d],\n"
                 "                                          qmc::cptr<%s>%s) {\n"
                 "#pragma unroll\n"
                 "    for (int u = 0; u < S; ++u) {\n",
-                s, f32 ? "f32" : "f64", T, D, T, K, T,
+                s, finite ? "true" : "false", f32 ? "f32" : "f64", T, D, T, K, T,
                 f32 ? "" : ", const qmc::LogTable &lt");
   return std::string(head) + em.body + "    }\n  }\n};\n";
 }

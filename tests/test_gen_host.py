@@ -220,9 +220,13 @@ def test_logarithm_form_follows_the_sign_of_F(q):
                      shifts=[W.uniform_shifts(rng, 4, 3) for _ in range(2)])
     h = q.host_plan(prob)
     try:
-        structs = _structs(q.gen_source(h, 3))
+        src = q.gen_source(h, 3)
     finally:
         q.lib().qmc_plan_free(h)
+    structs = _structs(src)
     body = {s: "\n".join(lines) for s, (_, lines) in structs.items()}
+    # finite on the closed cube (no weight-0 test needed) only where F is positive there
+    assert "struct G0 {\n  static constexpr bool finite = true;" in src
+    assert "struct G1 {\n  static constexpr bool finite = false;" in src
     assert "qmc::log_tab(F, lt)" in body[0] and "qmc::log_f64" not in body[0]
     assert "qmc::log_f64(F)" in body[1] and "qmc::log_tab" not in body[1]
