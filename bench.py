@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X published FP32 vector peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qmc_integrate_kernel_two_loop_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qmc_gen_class_kernels_two_loop_traffic.json")
 
 
 def algorithmic_flops(sec, m: int) -> float:
@@ -788,8 +788,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic,
-                     "kernel": ("qmc_gen_d{4,5,6}_f64_s2 (plan-specialised" if spec_s is not None
-                                else "qmc_integrate_kernel<D,3,2> (table-driven") +
+                     "kernel": (("qmc_gen_d{4,5,6}_f64_s%d (plan-specialised" % plan.launch_shape()["shifts_per_pass"])
+                                if spec_s is not None
+                                else "qmc_integrate_kernel<D,3,S> (table-driven") +
                                "; d = 4, 5, 6 concurrent launches, kernel_ms is their joint span)",
                      "kernel_ms": kernel_ms / max(launches, 1),
                      "algorithmic_flops_per_launch": flops_launch,
