@@ -195,6 +195,7 @@ def problem_struct(problem):
     K = problem.K
     M = problem.M
     rows_e, rows_c = [], []
+    rows = 0   # monomial rows packed so far
     desc = (SectorDesc * S)()
     for s, sec in enumerate(secs):
         d = int(sec.d)
@@ -203,16 +204,18 @@ def problem_struct(problem):
         D.integral = int(sec.integral)
         D.n_u = len(sec.u_coef)
         D.n_f = len(sec.f_coef)
-        D.u_off = sum(len(r) for r in rows_c)
+        D.u_off = rows
         ue = np.zeros((len(sec.u_coef), QMC_MAX_DIM), dtype=np.uint8)
         ue[:, :d] = np.asarray(sec.u_exp, dtype=np.uint8).reshape(-1, d)
         rows_e.append(ue)
         rows_c.append(np.asarray(sec.u_coef, dtype=np.float64))
-        D.f_off = sum(len(r) for r in rows_c)
+        rows += len(rows_c[-1])
+        D.f_off = rows
         fe = np.zeros((len(sec.f_coef), QMC_MAX_DIM), dtype=np.uint8)
         fe[:, :d] = np.asarray(sec.f_exp, dtype=np.uint8).reshape(-1, d)
         rows_e.append(fe)
         rows_c.append(np.asarray(sec.f_coef, dtype=np.float64))
+        rows += len(rows_c[-1])
         xp = np.zeros(QMC_MAX_DIM, dtype=np.int32)
         xp[:d] = np.asarray(sec.x_pow2, dtype=np.int32)
         for j in range(QMC_MAX_DIM):
