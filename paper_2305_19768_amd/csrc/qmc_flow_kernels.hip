@@ -30,20 +30,26 @@ __device__ __forceinline__ unsigned short bf_bits(float f) {
   return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
-// tanh in float32 to about 1e-6 relative: the odd Taylor series through x^9 for
-// |x| < 0.3 (truncation below 6e-8 relative), else 1 - 2 / (exp(2x) + 1) from the
-// hardware exponential and reciprocal (no cancellation there; saturates at both ends).
-// The results are rounded to bfloat16 (8 significant bits) before use.
+// tanh in float32, one formula for every argument: x P(x^2) / Q(x^2) with P, Q of degree
+// 4 and P(0) = Q(0) = 1, the argument clamped to [-9, 9] (tanh(9) rounds to the largest
+// float32 below 1).  The coefficients are a minimax fit on the relative error (csrc/fit_tanh.py:
+// 2.1e-8 in exact arithmetic, below 3.5e-7 evaluated in float32 with one reciprocal).  One
+// transcendental instruction per element and no divergent branch.  The results are rounded
+// to bfloat16 (8 significant bits) before use.
 __device__ __forceinline__ float tanh_f(float x) {
-  const float u = x * x;
-  float p = 62.0f / 2835.0f;
-  p = __builtin_fmaf(p, u, -17.0f / 315.0f);
-  p = __builtin_fmaf(p, u, 2.0f / 15.0f);
-  p = __builtin_fmaf(p, u, -1.0f / 3.0f);
-  const float small = __builtin_fmaf(x * u, p, x);
-  const float e = __expf(2.0f * x);
-  const float large = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-  return __builtin_fabsf(x) < 0.3f ? small : large;
+  const float c = __builtin_amdgcn_fmed3f(x, -9.0f, 9.0f);
+  const float t = c * c;
+  float p = 0x1.cd1634p-27f;
+  p = __builtin_fmaf(p, t, 0x1.5aa224p-16f);
+  p = __builtin_fmaf(p, t, 0x1.ca9e3ap-9f);
+  p = __builtin_fmaf(p, t, 0x1.121a86p-3f);
+  p = __builtin_fmaf(p, t, 1.0f);
+  float q = 0x1.a300fcp-21f;
+  q = __builtin_fmaf(q, t, 0x1.591658p-12f);
+  q = __builtin_fmaf(q, t, 0x1.a82f1cp-6f);
+  q = __builtin_fmaf(q, t, 0x1.de629p-2f);
+  q = __builtin_fmaf(q, t, 1.0f);
+  return (c * p) * __builtin_amdgcn_rcpf(q);
 }
 
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
@@ -181,11 +187,24 @@ __device__ __forceinline__ void put_input(unsigned short *zin, const double (&z)
   }
 }
 
+// tanh of a float32 network output in FP64 from one exponential: with e = exp(-2|o|),
+// tanh(o) = sign(o) (1 - e) / (1 + e).  The absolute error is a few units of 2^-53 (for
+// small |o| the cancellation in 1 - e costs relative accuracy only); the flow uses
+// s = tanh(o) / 4 as an exponent, where the absolute error is what matters.
+__device__ __forceinline__ double tanh_out(float o) {
+  const double e = exp(-2.0 * __builtin_fabs((double)o));
+  const double th = (1.0 - e) / (1.0 + e);
+  return o < 0.0f ? -th : th;
+}
+
+// The coupling moves each transformed coordinate by z <- (z - t) exp(-s) (dir 0) or
+// z exp(s) + t (dir 1); ssum accumulates s and jac multiplies the factors exp(-+s)
+// themselves (the Jacobian of the layer, exactly the factor the map applied).
 template <int DMAX>
 __device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBias &bs,
                                          FlowXchg &xc, int d, int c, const float (&cond)[kFlowMaxCond],
                                          int l, int dir, int lane, double (&z)[DMAX],
-                                         double &ssum) {
+                                         double &ssum, double &jac) {
   put_input<DMAX>(xc.zin + lane * kFlowIn, z, d, c, cond, l);
   wave_sync();
   v4f o[4];
@@ -199,10 +218,12 @@ __device__ __forceinline__ void coupling(const unsigned short *pk, const FlowBia
 #pragma unroll
   for (int j = 0; j < DMAX; ++j) {
     if (j >= d || conditioning(j, l)) continue;
-    const double s = 0.25 * tanh((double)xc.out[lane * kFlowOut + j]);
+    const double s = 0.25 * tanh_out(xc.out[lane * kFlowOut + j]);
     const double t = (double)xc.out[lane * kFlowOut + d + j];
-    z[j] = dir == 0 ? (z[j] - t) * exp(-s) : __builtin_fma(z[j], exp(s), t);
+    const double e = exp(dir == 0 ? -s : s);
+    z[j] = dir == 0 ? (z[j] - t) * e : __builtin_fma(z[j], e, t);
     ssum += s;
+    jac *= e;
   }
   wave_sync();
 }
@@ -269,20 +290,26 @@ __global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, i
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     a[j] = (valid && j < d) ? in[i * d + j] : 0.5;
-    z[j] = log(a[j]) - log1p(-a[j]);
-    if (j < d) lsum += log(a[j] * (1.0 - a[j]));
+    z[j] = 0.0;
+    if (j < d) {   // logit and log(a (1 - a)) from the same two logarithms
+      const double la = log(a[j]), lb = log(1.0 - a[j]);
+      z[j] = la - lb;
+      lsum += la + lb;
+    }
   }
-  double ssum = 0.0;
+  double ssum = 0.0, jac = 1.0;
   for (int step = 0; step < kFlowLayers; ++step) {
     const int l = dir == 0 ? kFlowLayers - 1 - step : step;
-    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], xc[wave], d, c, cf, l, dir, lane, z, ssum);
+    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], xc[wave], d, c, cf, l, dir, lane, z, ssum,
+                jac);
   }
   double rsum = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
+    if (j >= d) continue;
     const double r = 1.0 / (1.0 + exp(-z[j]));
-    if (valid && j < d) out[i * d + j] = r;
-    if (j < d) rsum += log(r * (1.0 - r));
+    if (valid) out[i * d + j] = r;
+    rsum += log(r * (1.0 - r));
   }
   if (valid) logdet[i] = dir == 0 ? rsum - lsum - ssum : rsum - lsum + ssum;
 }
@@ -360,23 +387,29 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
   double lx = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double xj = valid ? xs[j] : 0.5;
-    z[j] = log(xj) - log1p(-xj);
-    if (j < d) lx += log(xj * (1.0 - xj));
+    z[j] = 0.0;
+    if (j < d) {
+      const double xj = valid ? xs[j] : 0.5;
+      const double la = log(xj), lb = log(1.0 - xj);
+      z[j] = la - lb;
+      lx += la + lb;
+    }
   }
-  double ssum = 0.0;
+  double ssum = 0.0, jac = 1.0;
   for (int l = 0; l < kFlowLayers; ++l) {
     if (valid)
 #pragma unroll
       for (int j = 0; j < 8; ++j) a.zs[((int64_t)l * a.count + i) * 8 + j] = z[j];
-    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], X, d, c, cf, l, 1, lane, z, ssum);
+    coupling<8>(pk + (int64_t)l * kPackLayer, sb[l], X, d, c, cf, l, 1, lane, z, ssum, jac);
   }
   double uu[8];
   bool u_in = true;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
+    uu[j] = 0.5;
+    if (j >= d) continue;
     uu[j] = 1.0 / (1.0 + exp(-z[j]));
-    if (j < d) u_in = u_in && uu[j] > 0.0 && uu[j] < 1.0;
+    u_in = u_in && uu[j] > 0.0 && uu[j] < 1.0;
   }
   // a sample whose image rounds onto a face of the cube carries no weight either
   if (!u_in) wi = 0.0;
@@ -415,7 +448,7 @@ __global__ __launch_bounds__(256) void flow_grad_kernel(FlowTrainArgs a) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       if (j >= d || conditioning(j, l)) continue;
-      const double th = tanh((double)X.out[lane * kFlowOut + j]);
+      const double th = tanh_out(X.out[lane * kFlowOut + j]);
       const double es = exp(0.25 * th);
       const double ds = dz[j] * zl[j] * es - wi;       // log q carries + s
       dof[j] = (float)(ds * 0.25 * (1.0 - th * th));
@@ -769,29 +802,37 @@ __device__ __forceinline__ void flow_block(const LaunchArgs &a, int s, int l_beg
         y[j] = shifted(q, shl[j]);
       }
       const double Wk = apply_transform<D>(kind, w_scale, y, u);
+      // J_T(u) = prod_j x_j (1 - x_j) / (u_j (1 - u_j)) times the coupling factors; the two
+      // products are kept as mantissa in [1/2, 1) and binary exponent (no underflow)
       bool inside = true;
-      double z[D], lsum = 0.0;
+      double z[D], mu = 1.0;
+      int eu = 0;
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         inside = inside && u[j] > 0.0 && u[j] < 1.0;
         const double uj = (u[j] > 0.0 && u[j] < 1.0) ? u[j] : 0.5;
-        z[j] = log(uj) - log1p(-uj);
-        lsum += log(uj * (1.0 - uj));
+        z[j] = log(uj) - log(1.0 - uj);
+        const double v = mu * (uj * (1.0 - uj));
+        mu = __builtin_amdgcn_frexp_mant(v);
+        eu += __builtin_amdgcn_frexp_exp(v);
       }
-      double ssum = 0.0;
+      double ssum = 0.0, jac = 1.0;
       for (int step = 0; step < kFlowLayers; ++step) {
         const int l = kFlowLayers - 1 - step;
-        coupling<D>(L.pack[l], L.bias[l], L.xc[wave], D, fc, cf, l, 0, lane, z, ssum);
+        coupling<D>(L.pack[l], L.bias[l], L.xc[wave], D, fc, cf, l, 0, lane, z, ssum, jac);
       }
-      double x[1][D], rsum = 0.0;
+      double x[1][D], mx = 1.0;
+      int ex = 0;
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         const double r = 1.0 / (1.0 + exp(-z[j]));
         inside = inside && r > 0.0 && r < 1.0;
         x[0][j] = (r > 0.0 && r < 1.0) ? r : 0.5;
-        rsum += log(x[0][j] * (1.0 - x[0][j]));
+        const double v = mx * (x[0][j] * (1.0 - x[0][j]));
+        mx = __builtin_amdgcn_frexp_mant(v);
+        ex += __builtin_amdgcn_frexp_exp(v);
       }
-      const double W = Wk * exp(rsum - lsum - ssum);
+      const double W = Wk * __builtin_amdgcn_ldexp((mx / mu) * jac, ex - eu);
       const bool use = (i < i_end) && inside && (W != 0.0);
       if constexpr (CPLX) {
         C2 f[NK];
