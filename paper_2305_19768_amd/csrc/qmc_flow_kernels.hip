@@ -59,8 +59,9 @@ __device__ __forceinline__ v4f mfma32(v8b a, v8b b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// Biases of one layer staged as float: b1 [64], b2 [64], b3 [16] (zero beyond 2d).
-struct FlowBias {
+// Biases of one layer staged as float: b1 [64], b2 [64], b3 [16] (zero beyond 2d); read
+// four at a time (16-byte aligned).
+struct alignas(16) FlowBias {
   float b1[kFlowHidden], b2[kFlowHidden], b3[kFlowOut];
 };
 
@@ -88,7 +89,8 @@ __device__ __forceinline__ void flow_mlp(const unsigned short *pk, const FlowBia
                                          const unsigned short *zin, int lane, v4f (&o)[4],
                                          v4f (*h1)[4], v4f (*h2)[4]) {
   const int p = lane & 15, g = lane >> 4;
-  const v4f zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  // the biases enter as the accumulator operand of each layer's first product (the
+  // rows 16 rb + 4 g + i of the lane's result tiles)
   v4s B1[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) B1[q] = *(const v4s *)(zin + (16 * q + p) * kFlowIn + 4 * g);
@@ -96,8 +98,9 @@ __device__ __forceinline__ void flow_mlp(const unsigned short *pk, const FlowBia
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     const v4s A = *(const v4s *)(pk + kPackF1 + (rb * 64 + lane) * 4);
+    const v4f b = *(const v4f *)(bs.b1 + 16 * rb + 4 * g);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) C[q][rb] = mfma16(A, B1[q], zero);
+    for (int q = 0; q < 4; ++q) C[q][rb] = mfma16(A, B1[q], b);
   }
   v8b H[4][2];
 #pragma unroll
@@ -106,44 +109,37 @@ __device__ __forceinline__ void flow_mlp(const unsigned short *pk, const FlowBia
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float v = tanh_f(C[q][rb][i] + bs.b1[16 * rb + 4 * g + i]);
+        const float v = tanh_f(C[q][rb][i]);
         if (KEEP) h1[q][rb][i] = v;
         H[q][rb >> 1][(rb & 1) * 4 + i] = (__bf16)v;
       }
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) C[q][rb] = zero;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int rb = 0; rb < 4; ++rb) {
+    const v4f b = *(const v4f *)(bs.b2 + 16 * rb + 4 * g);
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const v8b A = *(const v8b *)(pk + kPackF2 + ((rb * 2 + ks) * 64 + lane) * 8);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) C[q][rb] = mfma32(A, H[q][ks], C[q][rb]);
+      for (int q = 0; q < 4; ++q) C[q][rb] = mfma32(A, H[q][ks], ks == 0 ? b : C[q][rb]);
     }
+  }
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float v = tanh_f(C[q][rb][i] + bs.b2[16 * rb + 4 * g + i]);
+        const float v = tanh_f(C[q][rb][i]);
         if (KEEP) h2[q][rb][i] = v;
         H[q][rb >> 1][(rb & 1) * 4 + i] = (__bf16)v;
       }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) o[q] = zero;
+  const v4f b3 = *(const v4f *)(bs.b3 + 4 * g);
 #pragma unroll
   for (int ks = 0; ks < 2; ++ks) {
     const v8b A = *(const v8b *)(pk + kPackF3 + (ks * 64 + lane) * 8);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = mfma32(A, H[q][ks], o[q]);
+    for (int q = 0; q < 4; ++q) o[q] = mfma32(A, H[q][ks], ks == 0 ? b3 : o[q]);
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) o[q][i] += bs.b3[4 * g + i];
 }
 
 // Per-wave LDS exchange areas: network input (bfloat16) and output (float).
