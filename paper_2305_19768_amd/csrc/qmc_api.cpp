@@ -1363,7 +1363,9 @@ qmc_status qmc_autotune(qmc_plan_t p, const uint64_t *n, const uint64_t *a, int3
         for (int tg : targets) {
           qmc_launch_shape c{bl, tile, spp, tg, 0.0};
           if (p->cplx && spp != 1) continue;
-          if (p->precision == QMC_PREC_FP32 && spp == 4) continue;   // FP32 kernels: 1 or 2
+          // FP32 at four shifts per pass: the specialised kernels take four, the
+          // table-driven ones run two (no FP32 table kernel is compiled for four)
+          if (p->precision == QMC_PREC_FP32 && spp == 4 && p->gen.empty()) continue;
           if (qmc_set_launch_shape(p, &c) != QMC_OK) continue;
           // warm-up (uploads the lattice table), then the timed repetitions
           if ((res = integrate_sectors(p, n, a, nullptr, stream, nullptr, mean, err)) != QMC_OK)

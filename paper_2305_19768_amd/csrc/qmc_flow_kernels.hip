@@ -265,7 +265,7 @@ __global__ void flow_pack_kernel(char *flow, int d, int c) {
 // ----------------------------------------------------------- transform alone
 
 // dir 0: u -> x = T(u) and log J_T(u); dir 1: x -> u = G(x) and log q(x).  Points with a
-// coordinate outside (0, 1) give NaN outputs.
+// coordinate outside (0, 1) get a NaN log-determinant.
 __global__ __launch_bounds__(256) void flow_transform_kernel(const char *flow, int d, int c,
                                                              const double *in, const double *cond,
                                                              int64_t count, double *out,

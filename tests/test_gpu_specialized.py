@@ -52,6 +52,20 @@ def test_specialized_two_loop_parity(qmc, precision, tol):
     _check(q.cpu().numpy(), prob, tol)
 
 
+def test_fp32_specialised_at_four_shifts_per_pass(qmc):
+    prob = W.two_loop_integral(seed=0, n_scale=0.01)
+    out = {}
+    for spp in (2, 4):
+        plan = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32, shifts_per_pass=spp)
+        plan.specialize()
+        assert plan.launch_shape()["shifts_per_pass"] == spp
+        out[spp] = plan.integrate()[0].cpu().numpy()
+    _check(out[4], prob, 1e-5)
+    # each shift's sum is formed by the same operations at either pass width
+    print("max |spp4 - spp2|", np.max(np.abs(out[4] - out[2])), flush=True)
+    assert np.array_equal(out[2], out[4])
+
+
 @pytest.mark.parametrize("d,K,M,u_pow,f_pow2", [(1, 1, 0, 0, -2), (3, 2, 1, -1, -4), (5, 3, 2, 2, -6),
                                                 (7, 4, 3, 1, -8), (8, 4, 1, 0, 4), (6, 3, 0, 3, 0)])
 def test_specialized_fast_path_shapes(qmc, d, K, M, u_pow, f_pow2):
