@@ -208,9 +208,7 @@ static hipError_t launch_d(const LaunchArgs &a, const DimLaunch &dl, hipStream_t
   if (!dl.fast) return launch_ds<D, 1, false, false>(a, dl, st);
   if (dl.f32) {
     if (a.shifts_per_pass == 1) return launch_ds<D, 1, true, true>(a, dl, st);
-    // table-driven FP32 kernels: 1 or 2 shifts per pass (4 runs as 2; the plan-specialised
-    // FP32 kernels take 4)
-    return launch_ds<D, 2, true, true>(a, dl, st);
+    return launch_ds<D, 2, true, true>(a, dl, st);   // FP32 kernels: 1 or 2 shifts per pass
   }
   // FP64 at d >= 7: one shift per pass whatever the shape asks (with two the lattice
   // state, both shifts' points and accumulators overflow the registers: spills and half
