@@ -535,7 +535,9 @@ def one_loop_leg(qmc, torch, steps: int = 3):
     """Throughput variant of the one-loop sector: the same integrand (x1^(1/2) U^-1
     F^(-1-eps), two orders, korobov3, 16 shifts) on a lattice of n = 2^31 - 1 points whose
     Korobov parameter minimises P_2 over 64 random candidates (device search, timed
-    separately).  The x1^(1/2) factor keeps it on the general integrand path, in FP64."""
+    separately), in FP64: first on the table-driven kernel (the general integrand path:
+    the x1^(1/2) factor), then on the plan-specialised one at the autotuner's launch shape
+    (compilation and the search, on a lattice of 2^26 points, outside the timing)."""
     import numpy as np
     import workloads
     n = 2 ** 31 - 1
@@ -545,26 +547,41 @@ def one_loop_leg(qmc, torch, steps: int = 3):
     t0 = time.perf_counter()
     a, p2 = plan.korobov_search(n, 3, [int(c) for c in prob.sectors[0].a_candidates])
     search_s = time.perf_counter() - t0
-    plan.integrate(n=[n], a=[a])                   # warm-up
-    times, kms = [], []
-    for _ in range(steps):
-        plan.enable_timing(True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, mean, err = plan.integrate(n=[n], a=[a], check=False)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t1)
-        kms.append(plan.read_timing()[0])
-        plan.enable_timing(False)
-    plan.check_status()
+
+    def measure():
+        plan.integrate(n=[n], a=[a])                   # warm-up
+        times, kms = [], []
+        for _ in range(steps):
+            plan.enable_timing(True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, mean, err = plan.integrate(n=[n], a=[a], check=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            kms.append(plan.read_timing()[0])
+            plan.enable_timing(False)
+        plan.check_status()
+        return (float(np.median(times)), float(np.median(kms)),
+                mean.cpu().numpy()[0], err.cpu().numpy()[0])
+
     evals = n * prob.m
-    mean, err = mean.cpu().numpy()[0], err.cpu().numpy()[0]
+    t_tab, k_tab, m_tab, e_tab = measure()
+    spec_s = plan.specialize()
+    n_tune = workloads.next_prime(1 << 26)
+    tune = plan.autotune(n=[n_tune], a=[12345], reps=3, use_cache=False)
+    t_gen, k_gen, mean, err = measure()
     return {"workload": "one_loop_sector: d = 3, n = 2^31 - 1, a = argmin P_2 over 64 random "
-                        "candidates, 16 shifts, 2 orders, korobov3, FP64 (general path)",
+                        "candidates, 16 shifts, 2 orders, korobov3, FP64",
             "a": a, "p2": p2, "p2_search_s": search_s,
-            "value": evals / float(np.median(times)), "unit": "evals/s",
-            "ms_per_step": float(np.median(times)) * 1e3,
-            "kernel_ms": float(np.median(kms)), "evals_per_step": evals,
+            "value": evals / t_gen, "unit": "evals/s", "ms_per_step": t_gen * 1e3,
+            "kernel_ms": k_gen, "evals_per_step": evals,
+            "kernel": "plan-specialised", "specialize_seconds": spec_s,
+            "launch": {k: tune[k] for k in ("block", "shift_tile", "shifts_per_pass",
+                                            "target_blocks")},
+            "table_driven": {"value": evals / t_tab, "ms_per_step": t_tab * 1e3,
+                             "kernel_ms": k_tab,
+                             "max_rel_diff_of_estimates": float(np.max(np.abs(m_tab - mean) /
+                                                                       np.abs(mean)))},
             "estimate": [float(v) for v in mean], "error": [float(v) for v in err]}
 
 

@@ -482,10 +482,12 @@ qmc_status qmc_autotune(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, i
 /*
  * qmc_specialize -- plan-specialised integrand kernels (the per-integral generated
  * code of Sec. 2.1, where pySecDec compiles each integrand with its constants fixed):
- * for every launch class of fast-path sectors (korobov3, integer powers of U and F, no
- * powers of x, real plans) write straight-line code that evaluates only the monomials
- * each sector has (multivariate Horner by greedy factorisation), with the powers of U
- * and F and the log-F polynomial of every order fixed, compile it for gfx950 with the
+ * for every launch class (dimension, precision) of the sectors of a real plan that have
+ * no flow attached (FP64: every such sector; FP32: those with an FP32 form) write
+ * straight-line code that evaluates only the monomials each sector has (multivariate
+ * Horner by greedy factorisation), with the integer and half-integer powers of x_j, U
+ * and F and the log-F polynomial of every order fixed (the sector's transform applied
+ * as in the table-driven kernels), compile it for gfx950 with the
  * HIP run-time compiler and load it on the current device.  qmc_integrate then runs
  * these kernels for those classes; the results equal the table-driven kernels' up to
  * rounding order.  Each class kernel is compiled for two and for four shifts per pass
@@ -505,8 +507,8 @@ qmc_status qmc_specialize(qmc_plan_t plan, int32_t flags, double *seconds);
 
 /*
  * qmc_gen_source -- the generated source of launch class (d, f32 != 0) of the plan as
- * qmc_specialize would compile it now (empty when the class has no fast-path
- * sectors): copied NUL-terminated into buf[cap] (truncated to cap - 1 bytes; buf may
+ * qmc_specialize would compile it now (empty when the class has no sector, and for
+ * complex plans): copied NUL-terminated into buf[cap] (truncated to cap - 1 bytes; buf may
  * be NULL), its full length in *len (may be NULL).  Host only.
  */
 qmc_status qmc_gen_source(qmc_plan_t plan, int32_t d, int32_t f32, char *buf, size_t cap,

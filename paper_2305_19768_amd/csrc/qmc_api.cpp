@@ -788,7 +788,7 @@ qmc_status integrate_sectors(qmc_plan_s *p, const uint64_t *n_in, const uint64_t
       dl[n_dl].deform = deform;
       dl[n_dl].flow = flow;
       dl[n_dl].pad = 0;
-      dl[n_dl].gen = (fast && !deform && !flow) ? gen_lookup(p, p->dims[s], f32 != 0) : 0;
+      dl[n_dl].gen = (!deform && !flow) ? gen_lookup(p, p->dims[s], f32 != 0) : 0;
       ++n_dl;
     }
     const int64_t nb = (int64_t)L.n_chunks * tiles;

@@ -874,8 +874,9 @@ constexpr int kFold = 8;
 // GEN: a plan-specialised integrand (generated straight-line code for one sector,
 // compiled at run time, its coefficients as literals) with static members
 // f64<S>(x, f, C, log_table) and f32<S>(x, f, C) that give the orders f_k of S
-// korobov3-transformed samples (C, the coefficient table + gen_off, is passed for
-// generators that read it); NoGen selects the table-driven forms.
+// transformed samples (C, the coefficient table + gen_off, is passed for generators
+// that read it) and `korobov3` (else the sector's transform runs through
+// apply_transform; FP32 sectors are korobov_3); NoGen selects the table-driven forms.
 struct NoGen {};
 template <class T>
 struct IsGen {
@@ -1003,7 +1004,12 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
               for (int kk = 0; kk < K; ++kk) f[u][kk] = (double)(Wf[u] * ff[u][kk]);
             }
           } else {
-            korobov3_fast<D, S>(w_scale, kc, y, x, W);
+            if constexpr (GEN::korobov3) {
+              korobov3_fast<D, S>(w_scale, kc, y, x, W);
+            } else {
+#pragma unroll
+              for (int u = 0; u < S; ++u) W[u] = apply_transform<D>(kind, w_scale, y[u], x[u]);
+            }
             GEN::template f64<S>(x, f, launder_after(cl + gen_off, W[0]), log_table);
           }
         } else if (F32) {

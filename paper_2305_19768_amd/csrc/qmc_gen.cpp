@@ -5,9 +5,9 @@
 // out of the point loop).  The table-driven kernels of this library instead evaluate
 // U and F by a dense nested Horner over every monomial slot of total degree <= 3,
 // which at d = 6 visits 84 slots for the 10-30 monomials F actually has.  This file
-// writes, for every sector on the fast path, straight-line code that evaluates only
-// its own monomials, with the epsilon-order polynomials in log F and the powers of U
-// and F fixed, and compiles it with hiprtc for the device the plan runs on: one kernel
+// writes, for every real-contour sector without a flow, straight-line code that
+// evaluates only its own monomials, with the epsilon-order polynomials in log F and the
+// powers of x_j, U and F (integer or half-integer) fixed, and compiles it with hiprtc for the device the plan runs on: one kernel
 // per (dimension, precision) launch class, a uniform switch over the class's sectors
 // choosing the sector's code (every workgroup holds one sector).  Everything else --
 // lattice points, transform, accumulation, reductions -- is the library's own block
@@ -165,8 +165,10 @@ std::string product(const std::string &base, int times, const std::string &one) 
   return s;
 }
 
-// The generated integrand of one fast-path sector: struct G<s> with f64<S> or f32<S>
-// giving the orders f_k (without the transform weight) of S samples.
+// The generated integrand of one sector: struct G<s> with f64<S> or f32<S> giving the
+// orders f_k (without the transform weight) of S transformed samples; `korobov3` tells
+// the block body which transform to apply (korobov_3 inline, the others through
+// apply_transform).
 std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   const SectorDev &sd = p->sec[s];
   const int D = sd.d, K = p->K;
@@ -180,12 +182,33 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   if (f.empty()) f = f32 ? "0.0f" : "0.0";
   em.line(std::string("const ") + T + " U = " + u + ";");
   em.line(std::string("const ") + T + " F = " + f + ";");
-  // B = U^u_num F^f_num / (U^u_den F^f_den)
-  std::string num, den;
-  if (sd.u_num) num = product("U", sd.u_num, one);
-  if (sd.f_num) num += (num.empty() ? "" : " * ") + product("F", sd.f_num, one);
-  if (sd.u_den) den = product("U", sd.u_den, one);
-  if (sd.f_den) den += (den.empty() ? "" : " * ") + product("F", sd.f_den, one);
+  // B = U^u_num F^f_num prod_j x_j^x_num / (U^u_den F^f_den prod_j x_j^x_den), times
+  // sqrt(hn / hd) = sqrt(hn hd) / hd for the half-integer exponents (hn: the factors with
+  // exponent +1/2, hd: those with -1/2); FP32 sectors have integer exponents of U and F only
+  std::string num, den, hn, hd;
+  auto mul = [](std::string &acc, const std::string &t) { acc += (acc.empty() ? "" : " * ") + t; };
+  if (sd.u_num) mul(num, product("U", sd.u_num, one));
+  if (sd.f_num) mul(num, product("F", sd.f_num, one));
+  if (sd.u_den) mul(den, product("U", sd.u_den, one));
+  if (sd.f_den) mul(den, product("F", sd.f_den, one));
+  bool neg_x = false;
+  for (int j = 0; j < D; ++j) {
+    const std::string xj = "x[u][" + std::to_string(j) + "]";
+    if (sd.x_num[j]) mul(num, product(xj, sd.x_num[j], one));
+    if (sd.x_den[j]) mul(den, product(xj, sd.x_den[j], one));
+    if (sd.x_half[j] > 0) mul(hn, xj);
+    if (sd.x_half[j] < 0) mul(hd, xj);
+    neg_x = neg_x || sd.x_den[j] != 0 || sd.x_half[j] < 0;
+  }
+  if (sd.f_half > 0) mul(hn, "F");
+  if (sd.f_half < 0) mul(hd, "F");
+  if (!hn.empty() || !hd.empty()) {
+    std::string h = hn;
+    if (!hd.empty()) mul(h, hd);
+    em.line("const double hs = __builtin_sqrt(" + h + ");");
+    mul(num, "hs");
+    if (!hd.empty()) mul(den, hd);
+  }
   if (num.empty()) num = one;
   if (den.empty()) {
     em.line(std::string("const ") + T + " B = " + num + ";");
@@ -208,7 +231,7 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   // term positive: then the logarithm needs no special cases, and with U positive too
   // (where it divides) the integrand is finite on the closed cube
   const bool f_pos = positive_on_cube(F, D);
-  const bool finite = f_pos && (sd.u_den == 0 || positive_on_cube(U, D));
+  const bool finite = f_pos && (sd.u_den == 0 || positive_on_cube(U, D)) && !neg_x;
   if (mmax > 0) {
     em.line(f32 ? "const float L = __builtin_amdgcn_logf(F) * 0.693147180559945309f;"
                 : f_pos ? "const double L = qmc::log_tab(F, lt);" : "const double L = qmc::log_f64(F);");
@@ -232,16 +255,19 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
     }
     em.line("f[u][" + std::to_string(k) + "] = " + (acc.empty() ? (f32 ? "0.0f" : "0.0") : acc) + ";");
   }
-  char head[512];
+  char head[600];
   std::snprintf(head, sizeof head,
                 "struct G%d {\n"
                 "  static constexpr bool finite = %s;\n"
+                "  static constexpr bool korobov3 = %s;\n"
                 "  template <int S>\n"
                 "  __device__ static __forceinline__ void %s(const %s (&x)[S][%d], %s (&f)[S][%d],\n"
                 "                                          qmc::cptr<%s>%s) {\n"
                 "#pragma unroll\n"
                 "    for (int u = 0; u < S; ++u) {\n",
-                s, finite ? "true" : "false", f32 ? "f32" : "f64", T, D, T, K, T,
+                s, finite ? "true" : "false",
+                sd.transform == QMC_TRANSFORM_KOROBOV3 ? "true" : "false", f32 ? "f32" : "f64", T,
+                D, T, K, T,
                 f32 ? "" : ", const qmc::LogTable &lt");
   return std::string(head) + em.body + "    }\n  }\n};\n";
 }
@@ -363,14 +389,16 @@ bool gen_compile(const std::string &src, const std::string &name, std::vector<ch
 int gen_spp_for(int spp, int D, bool f32) { return (!f32 && D >= 7) ? 1 : spp; }
 int gen_spp(const qmc_plan_s *p, int D, bool f32) { return gen_spp_for(p->spp, D, f32); }
 
-// The fast-path sectors of launch class (D, f32) of the plan.
+// The sectors of launch class (D, f32) of the plan: real-contour sectors without a flow;
+// FP32 takes the fast-path sectors with an FP32 form, FP64 every other one (fast path
+// and generic shape alike).
 std::vector<int> gen_class_sectors(const qmc_plan_s *p, int D, bool f32) {
   std::vector<int> out;
   if (p->cplx) return out;
   for (int s = 0; s < p->S; ++s) {
     const SectorDev &sd = p->sec[s];
-    if (sd.d != D || sd.flow || !(sd.flags & SF_FAST)) continue;
-    const bool s32 = p->precision == QMC_PREC_FP32 && (sd.flags & SF_F32OK);
+    if (sd.d != D || sd.flow) continue;
+    const bool s32 = p->precision == QMC_PREC_FP32 && (sd.flags & SF_FAST) && (sd.flags & SF_F32OK);
     if (s32 == f32) out.push_back(s);
   }
   return out;

@@ -63,6 +63,9 @@ def _interpret(lines, x):
         if m:
             a, b, c = _split_args(m.group(1))
             return expr(a) * expr(b) + expr(c)
+        m = re.fullmatch(r"__builtin_sqrt\((.*)\)", e)
+        if m:
+            return math.sqrt(expr(m.group(1)))
         m = re.fullmatch(r"\((.*)\) \* (qmc::recip1?\(\w+\)|r)", e)
         if m:
             return expr(m.group(1)) * (1.0 / env["den"])
@@ -130,7 +133,7 @@ def _check_generated(q, prob, precision, rtol):
 def test_generated_integrands_match_oracle_two_loop(q):
     prob = W.two_loop_integral(seed=0, n_scale=0.01)
     seen = _check_generated(q, prob, q.QMC_PREC_FP64, 1e-13)
-    assert seen == set(range(len(prob.sectors)))   # every fast-path sector has code
+    assert seen == set(range(len(prob.sectors)))   # every sector has code
 
 
 @pytest.mark.parametrize("d,K,M,u_pow,f_pow2", [(1, 1, 0, 0, -2), (3, 2, 1, -1, -4), (5, 3, 2, 2, -6),
@@ -178,13 +181,41 @@ def test_repeated_monomials_and_unit_coefficients(q):
     assert "-0x" not in "".join(ops) and "0x1.3333333333333p-2" not in "".join(ops)
 
 
-def test_non_fast_sectors_get_no_code(q):
+def test_one_loop_sector_gets_code(q):
+    # x_1^(1/2) U^-1 F^-1 and its log F order: one square root, U F as the denominator
     prob = W.one_loop_sector(seed=0, n=4099, m=4)
+    assert _check_generated(q, prob, q.QMC_PREC_FP64, 1e-13) == {0}
     h = q.host_plan(prob)
     try:
-        assert q.gen_source(h, 3) == ""   # x_1^(1/2) prefactor: table-driven kernel
+        src = q.gen_source(h, 3)
     finally:
         q.lib().qmc_plan_free(h)
+    body = _structs(src)[0][1]
+    assert "const double hs = __builtin_sqrt(x[u][0]);" in body
+    assert "static constexpr bool korobov3 = true;" in src
+
+
+@pytest.mark.parametrize("transform", ["none", "baker", "korobov1", "korobov3", "korobov6"])
+@pytest.mark.parametrize("x_pow2,u_pow,f_pow2", [([1, 0, 3], -2, -3), ([2, -1, 0], 1, 3),
+                                                 ([-3, 4, 1], 0, -1), ([0, 0, 0], -1, 5)])
+def test_generic_shapes_get_code(q, transform, x_pow2, u_pow, f_pow2):
+    # integer and half-integer powers of x_j (positive and negative), half-integer powers
+    # of F, every transform, log polynomials of degree above K - 1
+    sec = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0)), (0.25, (0, 1, 1))],
+                          [(0.3, (0, 0, 0)), (0.7, (1, 1, 0)), (0.2, (0, 0, 2)), (0.4, (1, 0, 1))],
+                          x_pow2=x_pow2, u_pow=u_pow, f_pow2=f_pow2,
+                          logc=[[1, 0, 0.5], [0.5, -1, 0]], n=20011, a=5467, transform=transform)
+    prob = W.single_problem(sec, m=4, seed=1)
+    assert _check_generated(q, prob, q.QMC_PREC_FP64, 1e-13) == {0}
+    h = q.host_plan(prob)
+    try:
+        src = q.gen_source(h, 3)
+    finally:
+        q.lib().qmc_plan_free(h)
+    assert ("static constexpr bool korobov3 = %s;" % ("true" if transform == "korobov3" else "false")) in src
+    # a negative power of some x_j makes the integrand infinite on a face of the cube
+    neg = any(e < 0 for e in x_pow2)
+    assert ("static constexpr bool finite = %s;" % ("false" if neg else "true")) in src
 
 
 @pytest.mark.slow

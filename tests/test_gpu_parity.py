@@ -385,6 +385,14 @@ def test_one_loop_throughput_size(qmc):
     g = _gauss_3d_one_loop(prob, 96)
     print("estimate", mean, "error", err, "gauss", g, flush=True)
     assert np.all(np.abs(mean - g) < 5 * err + 1e-12 * np.abs(g))
+    # the plan-specialised kernel at four shifts per pass: the same sums up to rounding
+    plan.specialize()
+    plan.set_launch_shape(256, 16, 4, 16384)
+    q2, mean2, _ = plan.integrate(n=[n], a=[a])
+    q2, mean2 = q2.cpu().numpy()[0], mean2.cpu().numpy()[0]
+    print("specialised", mean2, flush=True)
+    assert np.allclose(q2, q, rtol=1e-12, atol=0.0)
+    assert np.all(np.abs(mean2 - g) < 5 * err + 1e-12 * np.abs(g))
 
 
 def test_many_dimension_classes_run_concurrently(qmc):

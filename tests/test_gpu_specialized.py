@@ -84,6 +84,35 @@ def test_specialized_fast_path_shapes(qmc, d, K, M, u_pow, f_pow2):
         _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
 
 
+@pytest.mark.parametrize("transform", ["none", "baker", "korobov2", "korobov3", "korobov5"])
+@pytest.mark.parametrize("x_pow2,u_pow,f_pow2", [([1, 0, 3], -2, -3), ([-3, 4, 1], 0, -1),
+                                                 ([0, 2, 0], 1, 3)])
+def test_specialized_generic_shapes(qmc, transform, x_pow2, u_pow, f_pow2):
+    # integer and half-integer powers of x_j and F, every transform family, a log
+    # polynomial of degree above K - 1: the specialised kernel against the oracle at one,
+    # two and four shifts per pass
+    sec = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0)), (0.25, (0, 1, 1))],
+                          [(0.3, (0, 0, 0)), (0.7, (1, 1, 0)), (0.2, (0, 0, 2)), (0.4, (1, 0, 1))],
+                          x_pow2=x_pow2, u_pow=u_pow, f_pow2=f_pow2,
+                          logc=[[1, 0, 0.5], [0.5, -1, 0]], n=20011, a=5467, transform=transform)
+    prob = W.single_problem(sec, m=8, seed=1)
+    for spp in (1, 2, 4):
+        plan = qmc.Plan(prob, shifts_per_pass=spp)
+        plan.specialize()
+        print(f"{transform} x_pow2={x_pow2} spp={spp}", flush=True)
+        _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
+
+
+def test_one_loop_sector_specialised(qmc):
+    prob = W.one_loop_sector(seed=0, n=65521, m=16)
+    plan = qmc.Plan(prob)
+    q0 = plan.integrate()[0].cpu().numpy()
+    plan.specialize()
+    q1 = plan.integrate()[0].cpu().numpy()
+    assert np.allclose(q1, q0, rtol=1e-12, atol=0.0)
+    _check(q1, prob, TOL)
+
+
 def test_specialized_agrees_with_table_driven(qmc):
     prob = W.two_loop_integral(seed=7, n_sectors=12, n_scale=0.02)
     plan = qmc.Plan(prob)
