@@ -141,17 +141,24 @@ def test_unspecialised_shape_and_class_fall_back(qmc):
     _check(plan.integrate()[0].cpu().numpy(), prob, TOL)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", TOL), ("fp32", 1e-5)])
-def test_specialized_largest_sector_full_size(qmc, precision, tol):
+@pytest.mark.parametrize("precision,tol,shape", [("fp64", TOL, (256, 4, 4, 16384)),
+                                                 ("fp64", TOL, (256, 8, 4, 8192)),
+                                                 ("fp32", 1e-5, (256, 4, 2, 16384)),
+                                                 ("fp32", 1e-5, (256, 2, 2, 32768))])
+def test_specialized_largest_sector_full_size(qmc, precision, tol, shape):
+    # the launch shapes the autotuner picks for the benchmark's FP64 and FP32 plans
     prob = W.two_loop_integral(seed=0)
     prec = qmc.QMC_PREC_FP32 if precision == "fp32" else qmc.QMC_PREC_FP64
     plan = qmc.Plan(prob, precision=prec)
     a = [plan.korobov_search(s.n, s.d, [int(c) for c in s.a_candidates])[0] for s in prob.sectors]
-    plan.set_launch_shape(256, 2, 2, 32768)   # the benchmark's shape
+    plan.set_launch_shape(*shape)
     plan.specialize()
     q = plan.integrate(a=a)[0].cpu().numpy()
     assert np.all(np.isfinite(q))
-    s = int(np.argmax([sec.n for sec in prob.sectors]))
-    sec = dataclasses.replace(prob.sectors[s], a=int(a[s]))
-    one = dataclasses.replace(prob, sectors=[sec], shifts=[prob.shifts[s]])
-    _check(q[s:s + 1], one, tol, shift_range=(0, 2))
+    # the largest sector of every dimension class (one kernel each), on two shifts
+    for d in sorted({sec.d for sec in prob.sectors}):
+        s = max((i for i, sec in enumerate(prob.sectors) if sec.d == d),
+                key=lambda i: prob.sectors[i].n)
+        sec = dataclasses.replace(prob.sectors[s], a=int(a[s]))
+        one = dataclasses.replace(prob, sectors=[sec], shifts=[prob.shifts[s]])
+        _check(q[s:s + 1], one, tol, shift_range=(0, 2))
