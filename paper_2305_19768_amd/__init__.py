@@ -249,8 +249,9 @@ class Plan:
         _check(lib().qmc_set_launch_shape(self._h, ctypes.byref(sh)), "qmc_set_launch_shape")
 
     def specialize(self, off: bool = False) -> float:
-        """Compiles and loads plan-specialised integrand kernels for the fast-path launch
-        classes (see qmc_specialize); off=True unloads them.  Returns the seconds taken."""
+        """Compiles and loads plan-specialised integrand kernels for the launch classes of
+        the real-contour sectors without a flow (see qmc_specialize); off=True unloads
+        them.  Returns the seconds taken."""
         sec = ctypes.c_double()
         _check(lib().qmc_specialize(self._h, QMC_SPEC_OFF if off else 0, ctypes.byref(sec)),
                "qmc_specialize")
