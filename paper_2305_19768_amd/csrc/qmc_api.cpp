@@ -141,32 +141,13 @@ static int dense_pos(int D, const uint8_t *e, int *deg_out) {
   return -1;
 }
 
-// Position of a monomial of total degree <= 2 in the compact degree-2 layout
-// (c0; per j: c_j, then c_jk for k >= j), or -1.
-static int dense_pos2(int D, const int *e) {
-  int var[2], g = 0;
-  for (int j = 0; j < D; ++j)
-    for (int t = 0; t < e[j]; ++t) {
-      if (g >= 2) return -1;
-      var[g++] = j;
-    }
-  if (g == 0) return 0;
-  int p = 1;
-  for (int j = 0; j < D; ++j) {
-    if (g == 1 && var[0] == j) return p;
-    for (int k = j; k < D; ++k)
-      if (g == 2 && var[0] == j && var[1] == k) return p + 1 + (k - j);
-    p += 1 + D - j;
-  }
-  return -1;
-}
-
-// Complex plans: dense tables of dF/dx_a (degree 2, D tables) and d2F/dx_a dx_b for
-// b >= a (degree 1, D(D+1)/2 tables), differentiated monomial by monomial.
+// Complex plans: the gradient of F at x = 0 (dF/dx_a(0), D values; the device forms the
+// gradient at x from the Hessian by Euler's theorem) and dense tables of d2F/dx_a dx_b
+// for b >= a (degree 1, D(D+1)/2 tables), differentiated monomial by monomial.
 static void pack_derivatives(int D, const qmc_problem *prob, int64_t off, int32_t count,
                              std::vector<double> &coef, int32_t *grad_off, int32_t *hess_off) {
   const size_t gbase = coef.size();
-  const size_t hbase = gbase + (size_t)D * dense_len2(D);
+  const size_t hbase = gbase + (size_t)D;
   coef.resize(hbase + (size_t)(D * (D + 1) / 2) * dense_len1(D), 0.0);
   *grad_off = (int32_t)gbase;
   *hess_off = (int32_t)hbase;
@@ -174,15 +155,15 @@ static void pack_derivatives(int D, const qmc_problem *prob, int64_t off, int32_
     const uint8_t *er = prob->mono_exp + (size_t)(off + r) * QMC_MAX_DIM;
     const double c = prob->mono_coef[off + r];
     int e[QMC_MAX_DIM];
-    for (int j = 0; j < D; ++j) e[j] = er[j];
-    // first derivatives: c e_a x^(e - 1_a)
-    for (int a = 0; a < D; ++a) {
-      if (e[a] == 0) continue;
-      int ea[QMC_MAX_DIM];
-      for (int j = 0; j < D; ++j) ea[j] = e[j] - (j == a);
-      const int pos = dense_pos2(D, ea);   // degree <= 2 since F has degree <= 3
-      coef[gbase + (size_t)a * dense_len2(D) + pos] += c * e[a];
+    int deg = 0;
+    for (int j = 0; j < D; ++j) {
+      e[j] = er[j];
+      deg += e[j];
     }
+    // first derivatives at x = 0: only the monomials c x_a contribute (c)
+    if (deg == 1)
+      for (int a = 0; a < D; ++a)
+        if (e[a] == 1) coef[gbase + (size_t)a] += c;
     // second derivatives d2/dx_i dx_k, k >= i: c e_i (e_k - [i == k]) x^(e - 1_i - 1_k)
     int t = 0;
     for (int i = 0; i < D; ++i)

@@ -101,35 +101,6 @@ __device__ __forceinline__ C2 poly_c(cptr<double> c, int deg, const C2 (&z)[D], 
   return horner_c<D, 1>(c, z, ch);
 }
 
-// Real Horner over the compact degree-2 layout (c0, then per j: c_j, c_jk for k >= j).
-template <int D>
-__device__ __forceinline__ double horner2(cptr<double> c, const double (&x)[D], LoadChain &ch) {
-  c = ch.next(c);
-  double acc = c[0];
-  int p = 1;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    double g = c[p];
-#pragma unroll
-    for (int k = j; k < D; ++k) g = __builtin_fma(x[k], c[p + 1 + k - j], g);
-    p += 1 + D - j;
-    acc = __builtin_fma(x[j], g, acc);
-  }
-  ch.done(acc);
-  return acc;
-}
-
-// Real linear polynomial c0 + sum_j c_{j+1} x_j.
-template <int D>
-__device__ __forceinline__ double horner1(cptr<double> c, const double (&x)[D], LoadChain &ch) {
-  c = ch.next(c);
-  double acc = c[0];
-#pragma unroll
-  for (int j = 0; j < D; ++j) acc = __builtin_fma(c[1 + j], x[j], acc);
-  ch.done(acc);
-  return acc;
-}
-
 constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }   // lower triangle, j <= i
 
 // Elimination determinant of the complex symmetric matrix A (lower triangle, packed by
@@ -148,9 +119,10 @@ __device__ __forceinline__ C2 det_sym(C2 (&A)[D * (D + 1) / 2]) {
       for (int i = k + 1; i < D; ++i) {
         const C2 t = cmul(A[tri(i, k)], r);
 #pragma unroll
-        for (int j = k + 1; j <= i; ++j) {
-          const C2 u = cmul(t, A[tri(j, k)]);
-          A[tri(i, j)] = C2{A[tri(i, j)].r - u.r, A[tri(i, j)].i - u.i};
+        for (int j = k + 1; j <= i; ++j) {   // A_ij -= t A_jk, four fused operations
+          const C2 a = A[tri(j, k)], b = A[tri(i, j)];
+          A[tri(i, j)] = C2{__builtin_fma(-t.r, a.r, __builtin_fma(t.i, a.i, b.r)),
+                            __builtin_fma(-t.r, a.i, __builtin_fma(-t.i, a.r, b.i))};
         }
       }
     }
@@ -208,6 +180,59 @@ __device__ __forceinline__ void deform_finish(const SectorScalars &ss, cptr<Sect
   }
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The Hessian H_jk(x) = h0_jk + L_jk(x) of F (degree <= 3: L_jk is linear and homogeneous)
+// and the gradient from it by Euler's theorem on the homogeneous parts of F,
+// dF/dx_j = c_j + sum_k x_k (h0_jk + L_jk(x) / 2) with c_j = dF/dx_j at x = 0 (packed
+// by the plan): about a third of the operations of D dense gradient polynomials of
+// degree 2.  Fills A with I - i lambda (D1 + S H S) (lower
+// triangle) and g with the gradient.  T: the polynomial arithmetic (double or float).
+template <int D, class T, class P, class Chain>
+__device__ __forceinline__ void hessian_and_gradient(P coef, int grad_off, int hess_off,
+                                                     double lam, const double (&x)[D],
+                                                     const T (&xt)[D], Chain &ch, double (&g)[D],
+                                                     C2 (&A)[D * (D + 1) / 2]) {
+  double sq[D];
+  T gt[D];
+  {
+    const P cg = ch.next(coef + grad_off);
+#pragma unroll
+    for (int j = 0; j < D; ++j) gt[j] = cg[j];
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const double s = x[j] * (1.0 - x[j]);
+    // korobov3 evaluated with fused multiply-adds can round x a few ulp above 1 near
+    // y = 1, making s a tiny negative number; the symmetric scaling takes its root
+    sq[j] = sqrt(__builtin_fmax(s, 0.0));
+  }
+  int t = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+#pragma unroll
+    for (int k = j; k < D; ++k, ++t) {
+      const P c = ch.next(coef + hess_off + t * dense_len1(D));
+      T L = c[1] * xt[0];
+#pragma unroll
+      for (int l = 1; l < D; ++l) L = fma_t(c[1 + l], xt[l], L);
+      ch.done(L);
+      const T h0 = c[0];
+      const T w = fma_t((T)0.5, L, h0);
+      gt[j] = fma_t(xt[k], w, gt[j]);
+      if (k != j) gt[k] = fma_t(xt[j], w, gt[k]);
+      const double v = -lam * sq[j] * sq[k] * (double)(L + h0);
+      if (k == j) A[tri(j, j)] = C2{1.0, v};
+      else A[tri(k, j)] = C2{0.0, v};
+    }
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    g[j] = (double)gt[j];
+    A[tri(j, j)].i += -lam * (1.0 - 2.0 * x[j]) * g[j];
+  }
+}
+
 // J f_k(z(x)) for every order; returns whether the sample violates the sign check.
 template <int D, int NK>
 __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<SectorDev> sd,
@@ -215,30 +240,8 @@ __device__ __forceinline__ bool integrand_deform(const SectorScalars &ss, cptr<S
                                                  double lam, const double (&x)[D], C2 (&f)[NK]) {
   LoadChain ch{x[0], x[0]};
   double g[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) g[j] = horner2<D>(coef + grad_off + j * dense_len2(D), x, ch);
-  double sq[D];
   C2 A[D * (D + 1) / 2];
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    const double s = x[j] * (1.0 - x[j]);
-    // korobov3 evaluated with fused multiply-adds can round x a few ulp above 1 near
-    // y = 1, making s a tiny negative number; the symmetric scaling takes its root
-    sq[j] = sqrt(__builtin_fmax(s, 0.0));
-    A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
-  }
-  {
-    int t = 0;
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-#pragma unroll
-      for (int k = j; k < D; ++k, ++t) {
-        const double h = horner1<D>(coef + hess_off + t * dense_len1(D), x, ch);
-        const double v = -lam * sq[j] * sq[k] * h;
-        if (k == j) A[tri(j, j)].i += v;
-        else A[tri(k, j)] = C2{0.0, v};
-      }
-  }
+  hessian_and_gradient<D, double>(coef, grad_off, hess_off, lam, x, x, ch, g, A);
   const C2 det = det_sym<D>(A);
   // the contour point, formed after the elimination so that it is not live across it
   C2 z[D];
@@ -310,33 +313,6 @@ __device__ __forceinline__ C2f poly_cf(cptr<float> c, int deg, const C2f (&z)[D]
   return horner_cf<D, 1>(c, z, ch);
 }
 
-template <int D>
-__device__ __forceinline__ float horner2f(cptr<float> c, const float (&x)[D], LoadChainF &ch) {
-  c = ch.next(c);
-  float acc = c[0];
-  int p = 1;
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    float g = c[p];
-#pragma unroll
-    for (int k = j; k < D; ++k) g = __builtin_fmaf(x[k], c[p + 1 + k - j], g);
-    p += 1 + D - j;
-    acc = __builtin_fmaf(x[j], g, acc);
-  }
-  ch.done(acc);
-  return acc;
-}
-
-template <int D>
-__device__ __forceinline__ float horner1f(cptr<float> c, const float (&x)[D], LoadChainF &ch) {
-  c = ch.next(c);
-  float acc = c[0];
-#pragma unroll
-  for (int j = 0; j < D; ++j) acc = __builtin_fmaf(c[1 + j], x[j], acc);
-  ch.done(acc);
-  return acc;
-}
-
 // integrand_deform with the polynomial bulk in FP32.  The sign check uses the FP32
 // value of F(z) with a margin above FP32 rounding: Im F(z) > 2^-20 |F(z)|.
 template <int D, int NK>
@@ -349,29 +325,8 @@ __device__ __forceinline__ bool integrand_deform_f32(const SectorScalars &ss, cp
   for (int j = 0; j < D; ++j) xf[j] = (float)x[j];
   LoadChainF ch{xf[0]};
   double g[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j)
-    g[j] = (double)horner2f<D>(coef + grad_off + j * dense_len2(D), xf, ch);
-  double sq[D];
   C2 A[D * (D + 1) / 2];
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    const double s = x[j] * (1.0 - x[j]);
-    sq[j] = sqrt(__builtin_fmax(s, 0.0));
-    A[tri(j, j)] = C2{1.0, -lam * (1.0 - 2.0 * x[j]) * g[j]};
-  }
-  {
-    int t = 0;
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-#pragma unroll
-      for (int k = j; k < D; ++k, ++t) {
-        const double h = (double)horner1f<D>(coef + hess_off + t * dense_len1(D), xf, ch);
-        const double v = -lam * sq[j] * sq[k] * h;
-        if (k == j) A[tri(j, j)].i += v;
-        else A[tri(k, j)] = C2{0.0, v};
-      }
-  }
+  hessian_and_gradient<D, float>(coef, grad_off, hess_off, lam, x, xf, ch, g, A);
   const C2 det = det_sym<D>(A);
   C2 z[D];
   C2f zf[D];

@@ -19,10 +19,8 @@ constexpr int dense_len(int D) { return (D + 1) * (D + 2) * (D + 3) / 6; }
 
 constexpr int kMaxTile = 16;    // shifts per workgroup
 constexpr int kMaxWaves = 4;    // wavefronts per workgroup
-// The same layout truncated to total degree 2 (c0, then per j: c_j and the c_jk, k >= j;
-// length C(D+2, 2)) and to degree 1 (c0, c_0 .. c_{D-1}; length D + 1): the gradient
-// and Hessian tables of F in complex plans.
-constexpr int dense_len2(int D) { return (D + 1) * (D + 2) / 2; }
+// The same layout truncated to total degree 1 (c0, c_0 .. c_{D-1}; length D + 1): the
+// Hessian tables of F in complex plans.
 constexpr int dense_len1(int D) { return D + 1; }
 
 enum : int32_t {
