@@ -348,6 +348,25 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
     evals = prob.evals()
     m64 = out[1].cpu().numpy().copy()
     e64 = out[2].cpu().numpy().copy()
+    # the same scan in two calls on a fresh plan: the presample choice, then the
+    # integration with the sign-check fallback built in (qmc_integrate_deformed), which
+    # integrates the sectors that need no further halving once
+    del plan
+    plan_w = qmc.Plan(prob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan_w.choose_deformation(4099)
+    _, mw, _, lamw, halvw, rcw = plan_w.integrate_deformed(out=out)
+    torch.cuda.synchronize()
+    workflow_s = time.perf_counter() - t0
+    mw = mw.cpu().numpy()
+    workflow = {"choice_then_integration_s": choose_s + el / steps,
+                "presample_then_integrate_deformed_s": workflow_s,
+                "same_lambda": bool(np.array_equal(lamw, lam2)),
+                "max_rel_diff_of_estimates": float(np.max(
+                    np.abs((mw[..., 0] - m64[..., 0]) + 1j * (mw[..., 1] - m64[..., 1])) /
+                    np.maximum(np.hypot(m64[..., 0], m64[..., 1]), 1e-300)))}
+    del plan_w
     # FP32 bulk (gradient, Hessian, U(z), F(z) in FP32; Jacobian, log, powers and sums in
     # FP64) with the same deformation parameters
     plan32 = qmc.Plan(prob, precision=qmc.QMC_PREC_FP32)
@@ -380,6 +399,7 @@ def scan_leg(qmc, torch, n_points: int, steps: int):
             "sectors_lambda_halved_full_n": int(np.count_nonzero(halv2)),
             "sectors_unfixed": int(rc2 != 0),
             "sectors_violating_at_full_n": int(np.count_nonzero(viol)),
+            "scan_wall": workflow,
             "fp32_bulk": {"value": evals * steps / el32, "unit": "complex evals/s",
                           "ms_per_step": el32 / steps * 1e3, "kernel_ms": k32 / max(l32, 1),
                           "speedup_vs_fp64": el / el32,

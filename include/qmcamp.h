@@ -314,6 +314,28 @@ qmc_status qmc_choose_deformation(qmc_plan_t plan, uint64_t n_pre, const uint64_
                                   int32_t *halvings_out);
 
 /*
+ * qmc_integrate_deformed -- qmc_integrate of a complex plan with the sign-check fallback
+ * built in (the deformation parameter chosen by presampling, Sec. 3.1.3, may still let
+ * samples of the full lattice leave the F - i0 half plane): integrate every sector on
+ * lattices (n, a) as qmc_integrate does, then re-integrate every sector with a
+ * violating sample with its lambda halved, at most max_halvings times.  dev_q, dev_mean,
+ * dev_err (layout of qmc_integrate; dev_q may be NULL) hold, for every sector, the
+ * results at its final lambda: a sector keeps the sums of the last pass that integrated
+ * it.  The same results as qmc_choose_deformation on these lattices followed by
+ * qmc_integrate, without the second integration of the sectors that needed no halving.
+ * Writes the final parameters to lambda_out[n_sectors] and the halvings of this call to
+ * halvings_out[n_sectors] (either may be NULL) and leaves them set in the plan.
+ * Synchronous.  Errors: QMC_E_INVAL, QMC_E_STATE (real plan, no workspace),
+ * QMC_E_NONFINITE (a pass produced a non-finite sum; see qmc_query_status),
+ * QMC_E_SIGNCHECK (some sector still violates after max_halvings: every output still
+ * written), and those of qmc_integrate.
+ */
+qmc_status qmc_integrate_deformed(qmc_plan_t plan, const uint64_t *n, const uint64_t *a,
+                                  int32_t max_halvings, void *stream, double *dev_q,
+                                  double *dev_mean, double *dev_err, double *lambda_out,
+                                  int32_t *halvings_out);
+
+/*
  * qmc_korobov_p2 -- figure of merit of Korobov lattices on the device:
  *   dev_p2[c] = -1 + (1/n) sum_{k<n} prod_{j<d} [1 + 2 pi^2 B2({k a_c^j / n})],
  *   B2(x) = x^2 - x + 1/6,

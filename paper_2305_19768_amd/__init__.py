@@ -306,6 +306,37 @@ class Plan:
             _check(rc, "qmc_choose_deformation")
         return lam, halv, rc
 
+    def integrate_deformed(self, n: Optional[Sequence[int]] = None,
+                           a: Optional[Sequence[int]] = None, max_halvings: int = 16, out=None,
+                           stream=None):
+        """integrate() of a complex plan with the sign-check fallback (qmc_integrate_deformed):
+        sectors with a violating sample are re-integrated with lambda halved.  Returns
+        (q, mean, err, lambda [S], halvings [S], status) with status 0 or QMC_E_SIGNCHECK
+        (-6) if some sector could not be fixed (its results are still written)."""
+        torch = _torch()
+        if out is None:
+            q = torch.empty((self.S, self.m, self.K, 2), dtype=torch.float64, device=self.device)
+            mean = torch.empty((self.S, self.K, 2), dtype=torch.float64, device=self.device)
+            err = torch.empty((self.S, self.K, 2), dtype=torch.float64, device=self.device)
+        else:
+            q, mean, err = out
+        n_arr = None if n is None else np.ascontiguousarray(n, dtype=np.uint64)
+        a_arr = None if a is None else np.ascontiguousarray(a, dtype=np.uint64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.c_void_p
+        lam = np.zeros(self.S, dtype=np.float64)
+        halv = np.zeros(self.S, dtype=np.int32)
+        rc = lib().qmc_integrate_deformed(
+            self._h, None if n_arr is None else n_arr.ctypes.data_as(u64p),
+            None if a_arr is None else a_arr.ctypes.data_as(u64p), ctypes.c_int32(max_halvings),
+            _stream_ptr(stream), dp(q.data_ptr()) if q is not None else None,
+            dp(mean.data_ptr()), dp(err.data_ptr()),
+            lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            halv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if rc not in (0, -6):
+            _check(rc, "qmc_integrate_deformed")
+        return q, mean, err, lam, halv, rc
+
     def check_status(self, stream=None):
         sec, sh, order = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().qmc_query_status(self._h, _stream_ptr(stream), ctypes.byref(sec),

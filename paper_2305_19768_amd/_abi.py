@@ -129,6 +129,9 @@ def lib():
         L.qmc_choose_deformation.argtypes = [vp, ctypes.c_uint64, u64p, ctypes.c_int32, vp,
                                              ctypes.POINTER(ctypes.c_double), i32p]
         L.qmc_choose_deformation.restype = ctypes.c_int
+        L.qmc_integrate_deformed.argtypes = [vp, u64p, u64p, ctypes.c_int32, vp, vp, vp, vp,
+                                             ctypes.POINTER(ctypes.c_double), i32p]
+        L.qmc_integrate_deformed.restype = ctypes.c_int
         L.qmc_integrate_static.argtypes = [vp, u64p, u64p, vp, vp, vp, vp]
         L.qmc_integrate_static.restype = ctypes.c_int
         L.qmc_integrate_vec.argtypes = [vp, u64p, u64p, vp, vp, vp, vp]

@@ -1256,6 +1256,68 @@ qmc_status qmc_choose_deformation(qmc_plan_t p, uint64_t n_pre, const uint64_t *
   return QMC_OK;
 }
 
+qmc_status qmc_integrate_deformed(qmc_plan_t p, const uint64_t *n_in, const uint64_t *a_in,
+                                  int32_t max_halvings, void *stream, double *dev_q,
+                                  double *dev_mean, double *dev_err, double *lambda_out,
+                                  int32_t *halvings_out) {
+  g_last_error.clear();
+  if (!p) return fail(QMC_E_INVAL, "NULL plan");
+  if (!p->cplx) return fail(QMC_E_STATE, "the plan is real (no deformed sector)");
+  if (!p->ws) return fail(QMC_E_STATE, "no workspace bound");
+  if (!dev_mean || !dev_err) return fail(QMC_E_INVAL, "dev_mean and dev_err are required");
+  if (max_halvings < 0 || max_halvings > 60)
+    return fail(QMC_E_INVAL, "max_halvings = %d outside [0, 60]", max_halvings);
+  const int S = p->S;
+  std::vector<uint64_t> cnt(S);
+  std::vector<uint8_t> active(S, 1);   // the first pass integrates every sector
+  std::vector<int32_t> halv(S, 0);
+  std::vector<double> lam(S);
+  for (int s = 0; s < S; ++s) lam[s] = p->sec[s].lambda;
+  bool failed = false, changed = false;
+  int first_failed = -1;
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < S; ++s) any = any || active[s];
+    if (!any) break;
+    qmc_status st;
+    if (changed && (st = qmc_set_deformation(p, lam.data(), stream)) != QMC_OK) return st;
+    changed = false;
+    // a later pass re-integrates only the sectors whose lambda was halved: the others
+    // keep the sums (and, through the statistics over every sector, the errors) of the
+    // pass at their final lambda
+    st = integrate_sectors(p, n_in, a_in, active.data(), stream, dev_q, dev_mean, dev_err);
+    if (st != QMC_OK) return st;
+    int32_t sec = -1, shift = -1, order = -1;
+    st = qmc_query_status(p, stream, &sec, &shift, &order);
+    if (st == QMC_E_NONFINITE) return st;
+    g_last_error.clear();
+    if ((st = qmc_sign_violations(p, stream, cnt.data())) != QMC_OK) return st;
+    for (int s = 0; s < S; ++s) {
+      if (!active[s] || cnt[s] == 0) {
+        active[s] = 0;
+        continue;
+      }
+      if (halv[s] < max_halvings) {
+        lam[s] *= 0.5;
+        ++halv[s];
+        changed = true;
+      } else {
+        active[s] = 0;
+        if (!failed) first_failed = s;
+        failed = true;
+      }
+    }
+  }
+  for (int s = 0; s < S; ++s) {
+    if (lambda_out) lambda_out[s] = lam[s];
+    if (halvings_out) halvings_out[s] = halv[s];
+  }
+  if (failed)
+    return fail(QMC_E_SIGNCHECK, "sector %d: sign check still fails after %d halvings",
+                first_failed, max_halvings);
+  return QMC_OK;
+}
+
 // ------------------------------------------------------------------ autotuner
 
 static std::mutex g_tune_mu;

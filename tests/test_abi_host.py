@@ -132,6 +132,8 @@ def test_complex_plan_validation_and_shape(L):
                                  None) == -7
     assert "real" in _err()
     assert L.qmc_choose_deformation(h, 1009, None, 4, None, None, None) == -7
+    assert L.qmc_integrate_deformed(h, None, None, 4, None, None, None, None, None, None) == -7
+    assert "real" in _err()
     L.qmc_plan_free(h)
     assert L.qmc_plan_complex(None) == -1
     prob.sectors[1].deform_lambda = -0.5

@@ -287,3 +287,44 @@ def test_bubble_above_threshold_fp32_bulk(qmc):
     print("bubble FP32 bulk", mean, exact, flush=True)
     assert abs(mean[0] - exact.real) <= 1e-5 * abs(exact)
     assert abs(mean[1] - exact.imag) <= 1e-5 * abs(exact)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_integrate_deformed_equals_choice_then_integration(qmc, precision):
+    """qmc_integrate_deformed (integrate, then re-integrate the sectors with a violating
+    sample with lambda halved) gives what the full-lattice choice followed by an
+    integration gives, after the presample choice of the deformation parameters: the same
+    parameters, bit for bit the same sums for the sectors integrated once, and for the
+    re-integrated ones (a launch over fewer sectors splits their lattices into other
+    chunks, so the compensated sums may round differently) the same to 1e-13."""
+    prob = W.physical_scan(seed=0, n_points=2)
+    prec = qmc.QMC_PREC_FP32 if precision == "fp32" else qmc.QMC_PREC_FP64
+    ref = qmc.Plan(prob, precision=prec)
+    lam0, _, rc0 = ref.choose_deformation(4099)
+    assert rc0 == 0
+    lam_ref, halv_ref, rc_ref = ref.choose_deformation(prob.sectors[0].n)
+    q_ref, m_ref, e_ref = ref.integrate(check=False)
+    new = qmc.Plan(prob, precision=prec)
+    new.set_deformation(lam0)
+    q, m, e, lam, halv, rc = new.integrate_deformed()
+    print("sectors halved on the full lattice", int(np.count_nonzero(halv)), flush=True)
+    assert np.count_nonzero(halv) > 0          # the fallback was exercised
+    assert rc == rc_ref == 0
+    assert np.array_equal(lam, lam_ref) and np.array_equal(halv, halv_ref)
+    once = halv == 0
+    q, m, e = q.cpu().numpy(), m.cpu().numpy(), e.cpu().numpy()
+    q_ref, m_ref, e_ref = q_ref.cpu().numpy(), m_ref.cpu().numpy(), e_ref.cpu().numpy()
+    for a_, b_ in ((q, q_ref), (m, m_ref), (e, e_ref)):
+        assert np.array_equal(a_[once].view(np.uint64), b_[once].view(np.uint64))
+    # on the scale of each sector's largest sum (a real or imaginary part can be ~0; an
+    # error is a spread of the shift sums)
+    sq = np.abs(q_ref[~once]).max(axis=(1, 2, 3))[:, None, None, None]
+    sm = np.abs(m_ref[~once]).max(axis=(1, 2))[:, None, None]
+    print("re-integrated sectors: max |dq| / scale",
+          float((np.abs(q[~once] - q_ref[~once]) / sq).max()), flush=True)
+    assert np.all(np.abs(q[~once] - q_ref[~once]) <= 1e-13 * sq)
+    assert np.all(np.abs(m[~once] - m_ref[~once]) <= 1e-13 * sm)
+    assert np.all(np.abs(e[~once] - e_ref[~once]) <= 1e-13 * sm)
+    # no sample of the final contours violates the sign check
+    new.integrate(check=False)
+    assert not np.any(new.sign_violations())
