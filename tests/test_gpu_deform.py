@@ -328,3 +328,19 @@ def test_integrate_deformed_equals_choice_then_integration(qmc, precision):
     # no sample of the final contours violates the sign check
     new.integrate(check=False)
     assert not np.any(new.sign_violations())
+
+
+def test_integrate_deformed_without_halvings_reports_the_violation(qmc):
+    """max_halvings = 0: one integration at the given parameters, the violation reported
+    as QMC_E_SIGNCHECK with every output written (equal to a plain integration)."""
+    prob = W.physical_scan(seed=0, n_points=2)
+    plan = qmc.Plan(prob)
+    lam0, _, _ = plan.choose_deformation(4099)
+    q0, m0, e0 = plan.integrate(check=False)
+    q0 = q0.cpu().numpy()
+    viol = plan.sign_violations()
+    assert np.any(viol)
+    q, m, e, lam, halv, rc = plan.integrate_deformed(max_halvings=0)
+    assert rc == -6   # QMC_E_SIGNCHECK
+    assert np.array_equal(lam, lam0) and not np.any(halv)
+    assert np.array_equal(q.cpu().numpy().view(np.uint64), q0.view(np.uint64))
