@@ -1057,7 +1057,7 @@ qmc_status qmc_median_lattice(qmc_plan_t p, const uint64_t *n_in, int32_t r,
     if (n_dl == 0 || dl[n_dl - 1].d != p->dims[s] || dl[n_dl - 1].fast != fast ||
         dl[n_dl - 1].f32 != f32 || dl[n_dl - 1].flow != flow) {
       if (n_dl == 4 * QMC_MAX_DIM) return fail(QMC_E_STATE, "too many launch classes");
-      dl[n_dl] = DimLaunch{b, 0, p->dims[s], fast, f32, 0, flow, 0};
+      dl[n_dl] = DimLaunch{b, 0, p->dims[s], fast, f32, 0, flow, 0, 0};
       ++n_dl;
     }
     dl[n_dl - 1].blocks += L.n_chunks;

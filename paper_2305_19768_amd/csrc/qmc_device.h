@@ -905,14 +905,11 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
   const SectorDev *__restrict__ sd = a.sectors + s;
   const LatticeDev *__restrict__ lt = a.lat + s;
   const uint64_t n = lt->n;
-  const double n_d = lt->n_d, inv_n = lt->inv_n;
   const int64_t chunk = lt->chunk;
   const uint64_t i_begin = (uint64_t)(chunk_id * chunk);
   uint64_t i_end = i_begin + (uint64_t)chunk;
   if (i_end > n) i_end = n;
   const int kind = sd->transform;
-  const double w_scale = sd->w_scale;
-  const SectorScalars ss = load_scalars(sd);
   const uint64_t B = blockDim.x;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;

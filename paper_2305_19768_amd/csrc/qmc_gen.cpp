@@ -172,7 +172,7 @@ std::string product(const std::string &base, int times, const std::string &one) 
 std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
   const SectorDev &sd = p->sec[s];
   const int D = sd.d, K = p->K;
-  Emitter em{f32};
+  Emitter em{f32, std::string(), 0};
   const std::vector<Mono> U = sparse_monomials(p->coef.data() + sd.u_off, D);
   const std::vector<Mono> F = sparse_monomials(p->coef.data() + sd.f_off, D);
   const char *T = em.T();
