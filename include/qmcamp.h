@@ -326,9 +326,10 @@ qmc_status qmc_choose_deformation(qmc_plan_t plan, uint64_t n_pre, const uint64_
  * Writes the final parameters to lambda_out[n_sectors] and the halvings of this call to
  * halvings_out[n_sectors] (either may be NULL) and leaves them set in the plan.
  * Synchronous.  Errors: QMC_E_INVAL, QMC_E_STATE (real plan, no workspace),
- * QMC_E_NONFINITE (a pass produced a non-finite sum; see qmc_query_status),
- * QMC_E_SIGNCHECK (some sector still violates after max_halvings: every output still
- * written), and those of qmc_integrate.
+ * QMC_E_NONFINITE (a pass produced a non-finite sum, see qmc_query_status; the call
+ * stops there: the plan keeps the parameters of that pass and lambda_out/halvings_out
+ * are not written), QMC_E_SIGNCHECK (some sector still violates after max_halvings:
+ * every output still written), and those of qmc_integrate.
  */
 qmc_status qmc_integrate_deformed(qmc_plan_t plan, const uint64_t *n, const uint64_t *a,
                                   int32_t max_halvings, void *stream, double *dev_q,
