@@ -520,12 +520,19 @@ qmc_status qmc_autotune(qmc_plan_t plan, const uint64_t *n, const uint64_t *a, i
  * runs the table-driven kernel until qmc_specialize is called again (kernels already
  * compiled are kept).  The amplitude evaluation's persistent kernels are unaffected.
  * flags: 0, QMC_SPEC_COMPILE_ONLY (generate and compile, load nothing: usable without
- * a GPU) or QMC_SPEC_OFF (unload every specialised kernel of the plan).
+ * a GPU) or QMC_SPEC_OFF (unload every specialised kernel of the plan); with
+ * QMC_SPEC_PERSISTENT, instead of the class kernels, the persistent kernel of
+ * amp_evaluate's batched form (QMC_AMP_DEVICE) for the plan's sectors without a flow
+ * and its number of orders: one program holding every sector, its integrand a switch on
+ * the sector index inside the point loop (compiled in seconds for hundreds of sectors);
+ * the batched form runs it while the plan's sectors without a flow and orders are those
+ * it was compiled for.  Requires a real plan whose sectors have the batched form's
+ * shape, and in FP32 an FP32 form for each (QMC_E_INVAL otherwise).
  * *seconds (may be NULL): wall time of the call.  Synchronous, host-side (no stream
  * work).  Errors: QMC_E_INVAL, QMC_E_DEVICE (compiler or module-load failure; the
  * message carries the compiler log).
  */
-enum { QMC_SPEC_COMPILE_ONLY = 1, QMC_SPEC_OFF = 2 };
+enum { QMC_SPEC_COMPILE_ONLY = 1, QMC_SPEC_OFF = 2, QMC_SPEC_PERSISTENT = 4 };
 qmc_status qmc_specialize(qmc_plan_t plan, int32_t flags, double *seconds);
 
 /*

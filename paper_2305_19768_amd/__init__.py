@@ -16,7 +16,7 @@ import numpy as np
 
 from . import flow  # noqa: F401  (learned flow transform)
 from ._abi import (QMC_MAX_DIM, QMC_MAX_LOG, QMC_MAX_ORDERS, QMC_PREC_FP32, QMC_PREC_FP64,
-                   QMC_SPEC_COMPILE_ONLY, QMC_SPEC_OFF, TRANSFORMS, AmpOptions, AmpStats, Amplitude, LaunchShape, QmcError, lib,
+                   QMC_SPEC_COMPILE_ONLY, QMC_SPEC_OFF, QMC_SPEC_PERSISTENT, TRANSFORMS, AmpOptions, AmpStats, Amplitude, LaunchShape, QmcError, lib,
                    options_struct,
                    problem_struct)
 
@@ -248,13 +248,14 @@ class Plan:
         sh = LaunchShape(block, shift_tile, shifts_per_pass, target_blocks, 0.0)
         _check(lib().qmc_set_launch_shape(self._h, ctypes.byref(sh)), "qmc_set_launch_shape")
 
-    def specialize(self, off: bool = False) -> float:
+    def specialize(self, off: bool = False, persistent: bool = False) -> float:
         """Compiles and loads plan-specialised integrand kernels for the launch classes of
-        the real-contour sectors without a flow (see qmc_specialize); off=True unloads
+        the real-contour sectors without a flow (see qmc_specialize); persistent=True
+        compiles the batched amplitude form's persistent kernel instead; off=True unloads
         them.  Returns the seconds taken."""
         sec = ctypes.c_double()
-        _check(lib().qmc_specialize(self._h, QMC_SPEC_OFF if off else 0, ctypes.byref(sec)),
-               "qmc_specialize")
+        flags = QMC_SPEC_OFF if off else (QMC_SPEC_PERSISTENT if persistent else 0)
+        _check(lib().qmc_specialize(self._h, flags, ctypes.byref(sec)), "qmc_specialize")
         return sec.value
 
     def gen_source(self, d: int, f32: bool = False) -> str:

@@ -18,6 +18,7 @@ QMC_PREC_FP64 = 0
 QMC_PREC_FP32 = 1
 QMC_SPEC_COMPILE_ONLY = 1
 QMC_SPEC_OFF = 2
+QMC_SPEC_PERSISTENT = 4
 TRANSFORMS = {"none": 0, "baker": 1, "korobov1": 2, "korobov2": 3, "korobov3": 4,
               "korobov4": 5, "korobov5": 6, "korobov6": 7}
 

@@ -80,10 +80,27 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   for (int s = 0; s < S; ++s)
     all_f32 = all_f32 && (p->sec[s].flow || (p->sec[s].flags & SF_F32OK));
   const int variant = !f32 ? kPersistentF64 : all_f32 ? kPersistentF32 : kPersistentF32Mixed;
-  int &grid = p->persistent_grid[variant];
+  // the plan-specialised persistent kernel (qmc_specialize with QMC_SPEC_PERSISTENT), if
+  // it was compiled for these sectors and orders
+  std::vector<int> plain_secs;
+  for (int s = 0; s < S; ++s)
+    if (!p->sec[s].flow) plain_secs.push_back(s);
+  GenKernel *gk = variant == kPersistentF32Mixed ? nullptr : gen_persistent_lookup(p, f32, K, plain_secs);
+  int &grid = gk ? gk->grid : p->persistent_grid[variant];
   int e;
-  if (!grid && (e = persistent_grid(p->d_max, variant, K, p->block, &grid)) != hipSuccess)
-    return hip_fail(e, "occupancy query");
+  if (!grid) {
+    if (gk) {
+      int dev = 0, cus = 0, per = 0;
+      if ((e = hipGetDevice(&dev)) != hipSuccess ||
+          (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+          (e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per, (hipFunction_t)gk->fn,
+                                                                 p->block, 0)) != hipSuccess)
+        return hip_fail(e, "occupancy query");
+      grid = cus * (per > 0 ? per : 1);
+    } else if ((e = persistent_grid(p->d_max, variant, K, p->block, &grid)) != hipSuccess) {
+      return hip_fail(e, "occupancy query");
+    }
+  }
   int flow_grid = 0;
   if (n_plain < S && (e = persistent_flow_grid(p->block, &flow_grid)) != hipSuccess)
     return hip_fail(e, "occupancy query");
@@ -243,8 +260,16 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   for (;;) {
     for (int r = 0; r < 4; ++r) {   // queue a few rounds; finished rounds return at once
       if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");
-      if ((e = launch_persistent(la, dst, p->d_max, variant, (unsigned)grid, stream)) != hipSuccess)
-        return hip_fail(e, "persistent kernel");
+      if (gk) {
+        LaunchArgs la_k = la;
+        AmpState *st_k = dst;
+        void *params[] = {&la_k, &st_k};
+        e = hipModuleLaunchKernel((hipFunction_t)gk->fn, (unsigned)grid, 1, 1, (unsigned)p->block,
+                                  1, 1, 0, st, params, nullptr);
+      } else {
+        e = launch_persistent(la, dst, p->d_max, variant, (unsigned)grid, stream);
+      }
+      if (e != hipSuccess) return hip_fail(e, "persistent kernel");
       if (n_plain < S &&
           (e = launch_persistent_flow(la, dst, (unsigned)flow_grid, stream)) != hipSuccess)
         return hip_fail(e, "flow persistent kernel");

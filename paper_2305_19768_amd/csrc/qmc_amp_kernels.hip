@@ -6,7 +6,7 @@
 // (sector, chunk, shift tile) of every dimension from one atomic counter.  Every kernel
 // of a round returns at once when the state says the evaluation is finished, so the
 // host can queue several rounds and synchronise once.
-#include "qmc_device.h"
+#include "qmc_persist.h"
 
 namespace qmc {
 
@@ -282,13 +282,10 @@ __global__ __launch_bounds__(kRoundThreads) void qmc_amp_round_kernel(AmpArgs g)
 
 // -------------------------------------------------------- persistent kernel
 
-// Every sector of the fast path without a flow, all dimensions up to DMAX, in one launch:
-// each workgroup takes the next work item (sector, chunk, shift tile) from the round's
-// atomic counter until none is left, and writes its compensated partial exactly where
-// the per-dimension launch would, so the reduction and its order are unchanged.
-// F32 with FB: sectors without SF_F32OK fall back to the FP64 form; F32 without FB: every
-// sector of the launch has SF_F32OK, and the FP64 form (whose registers would set the
-// occupancy of the whole kernel) is not compiled in.
+// Every sector of the fast path without a flow, all dimensions up to DMAX, in one launch
+// (the loop: qmc_persist.h).  F32 with FB: sectors without SF_F32OK fall back to the FP64
+// form; F32 without FB: every sector of the launch has SF_F32OK, and the FP64 form (whose
+// registers would set the occupancy of the whole kernel) is not compiled in.
 template <int D, int K, int S, bool F32, bool FB>
 __device__ __forceinline__ void run_item(const LaunchArgs &a, int s, int l_begin, int T,
                                          int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
@@ -302,44 +299,12 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, int s, int l_begin
   }
 }
 
-// The work item is the same for every lane; make that explicit so that the sector's
-// tables stay in scalar registers.
-__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Waves per SIMD asked of the compiler: four (128 VGPRs) for the pure-FP32 and the FP64
-// (one shift per pass) forms up to d = 7, which fit with at most a few spills; no
-// constraint otherwise (the mixed form and d = 8 need more registers).
-template <int DMAX, bool F32, bool FB>
-constexpr int persistent_waves() {
-  return DMAX <= 7 && (!F32 || !FB) ? 4 : 1;
-}
-
+// One work item of the table-driven persistent kernel: the sector's dimension picks the
+// instantiation.
 template <int DMAX, int K, int S, bool F32, bool FB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<DMAX, F32, FB>())))
-void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
-  __shared__ double red[kMaxWaves][kMaxTile * 4][2];
-  __shared__ int64_t item;
-  if (st->done) return;
-  const int64_t total = st->plain_blocks;   // the flow sectors' items follow
-  const int T = a.shift_tile;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) item = (int64_t)atomicAdd(&st->work_counter, 1u);
-    __syncthreads();
-    const int64_t b = wave_uniform(item);
-    if (b >= total) break;
-    const uint64_t t0 = ticks_now();
-    const int s = a.order[find_sector(a.block_begin, a.n_sectors, b)];
-    const LatticeDev *__restrict__ lt = a.lat + s;
-    const int64_t local = b - lt->block_begin;
-    const int nch = lt->n_chunks;
-    const int tile_id = (int)(local / nch);
-    const int64_t chunk_id = local - (int64_t)tile_id * nch;
-    const int l_begin = tile_id * T;
+struct RunTable {
+  __device__ static __forceinline__ void run(const LaunchArgs &a, int s, int l_begin, int T,
+                                             int64_t chunk_id, double (*red)[kMaxTile * 4][2]) {
     switch (a.sectors[s].d) {
       case 1: run_item<1, K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
       case 2: if (DMAX >= 2) run_item<(DMAX >= 2 ? 2 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
@@ -350,17 +315,15 @@ void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
       case 7: if (DMAX >= 7) run_item<(DMAX >= 7 ? 7 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
       default: if (DMAX >= 8) run_item<(DMAX >= 8 ? 8 : 1), K, S, F32, FB>(a, s, l_begin, T, chunk_id, red); break;
     }
-    __syncthreads();
-    const int nwaves = blockDim.x >> 6;
-    if ((int)threadIdx.x < T * K) {
-      DD r{red[0][threadIdx.x][0], red[0][threadIdx.x][1]};
-      for (int w = 1; w < nwaves; ++w) r = dd_combine(r, DD{red[w][threadIdx.x][0], red[w][threadIdx.x][1]});
-      double *out = a.partial + (b * (T * K) + threadIdx.x) * 2;
-      out[0] = r.s;
-      out[1] = r.c;
-    }
-    ticks_add(a, s, t0);
   }
+};
+
+template <int DMAX, int K, int S, bool F32, bool FB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(persistent_waves<DMAX, F32, FB>())))
+void qmc_persistent_kernel(LaunchArgs a, AmpState *st) {
+  __shared__ double red[kMaxWaves][kMaxTile * 4][2];
+  __shared__ int64_t item;
+  persistent_loop<K, RunTable<DMAX, K, S, F32, FB>>(a, st, red, item);
 }
 
 // ------------------------------------------------------------------ launchers

@@ -1353,6 +1353,7 @@ qmc_status qmc_set_launch_shape(qmc_plan_t p, const qmc_launch_shape *sh) {
   p->spp = spp;
   p->target_blocks = sh->target_blocks;
   for (int &g : p->persistent_grid) g = 0;   // occupancy depends on the block size
+  for (GenKernel &g : p->gen) g.grid = 0;
   p->lat_valid = false;
   return QMC_OK;
 }

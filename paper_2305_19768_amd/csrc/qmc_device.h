@@ -871,12 +871,13 @@ constexpr int kFold = 8;
 // REGCONST: hold the korobov_3 coefficients in registers for the whole block (fewer
 // instructions per point; the persistent kernel, tighter on registers, uses literals).
 //
-// GEN: a plan-specialised integrand (generated straight-line code for one sector,
-// compiled at run time, its coefficients as literals) with static members
-// f64<S>(x, f, C, log_table) and f32<S>(x, f, C) that give the orders f_k of S
-// transformed samples (C, the coefficient table + gen_off, is passed for generators
-// that read it) and `korobov3` (else the sector's transform runs through
-// apply_transform; FP32 sectors are korobov_3); NoGen selects the table-driven forms.
+// GEN: a plan-specialised integrand (generated straight-line code, compiled at run time,
+// its coefficients as literals: one sector's, or a switch among several on the sector
+// index s) with static members f64<S>(x, f, C, log_table, s) and f32<S>(x, f, C, s) that
+// give the orders f_k of S transformed samples of sector s (C, the coefficient table +
+// gen_off, is passed for generators that read it) and `korobov3` (else the transform
+// runs through apply_transform; FP32 sectors are korobov_3); NoGen selects the
+// table-driven forms.
 struct NoGen {};
 template <class T>
 struct IsGen {
@@ -992,7 +993,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
 #pragma unroll
               for (int j = 0; j < D; ++j) yf[u][j] = (float)y[u][j];
             korobov3_f32<D, S>((float)w_scale, yf, xf, Wf);
-            GEN::template f32<S>(xf, ff, launder_after_f(cl32 + gen_off, Wf[0]));
+            GEN::template f32<S>(xf, ff, launder_after_f(cl32 + gen_off, Wf[0]), s);
 #pragma unroll
             for (int u = 0; u < S; ++u) {
               if constexpr (GenFinite<GEN>::value) Wf[u] = valid ? Wf[u] : 0.0f;
@@ -1007,7 +1008,7 @@ __device__ __forceinline__ void integrate_block(const LaunchArgs &a, int s, int 
 #pragma unroll
               for (int u = 0; u < S; ++u) W[u] = apply_transform<D>(kind, w_scale, y[u], x[u]);
             }
-            GEN::template f64<S>(x, f, launder_after(cl + gen_off, W[0]), log_table);
+            GEN::template f64<S>(x, f, launder_after(cl + gen_off, W[0]), log_table, s);
           }
         } else if (F32) {
           float yf[S][D], xf[S][D], Wf[S], ff[S][K];

@@ -169,7 +169,8 @@ std::string product(const std::string &base, int times, const std::string &one) 
 // orders f_k (without the transform weight) of S transformed samples; `korobov3` tells
 // the block body which transform to apply (korobov_3 inline, the others through
 // apply_transform).
-std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
+std::string sector_struct(const qmc_plan_s *p, int s, bool f32, bool *finite_out = nullptr,
+                          bool *korobov3_out = nullptr) {
   const SectorDev &sd = p->sec[s];
   const int D = sd.d, K = p->K;
   Emitter em{f32, std::string(), 0};
@@ -255,6 +256,8 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
     }
     em.line("f[u][" + std::to_string(k) + "] = " + (acc.empty() ? (f32 ? "0.0f" : "0.0") : acc) + ";");
   }
+  if (finite_out) *finite_out = finite;
+  if (korobov3_out) *korobov3_out = sd.transform == QMC_TRANSFORM_KOROBOV3;
   char head[600];
   std::snprintf(head, sizeof head,
                 "struct G%d {\n"
@@ -262,7 +265,7 @@ std::string sector_struct(const qmc_plan_s *p, int s, bool f32) {
                 "  static constexpr bool korobov3 = %s;\n"
                 "  template <int S>\n"
                 "  __device__ static __forceinline__ void %s(const %s (&x)[S][%d], %s (&f)[S][%d],\n"
-                "                                          qmc::cptr<%s>%s) {\n"
+                "                                          qmc::cptr<%s>%s, int) {\n"
                 "#pragma unroll\n"
                 "    for (int u = 0; u < S; ++u) {\n",
                 s, finite ? "true" : "false",
@@ -288,6 +291,10 @@ const char *kPrelude =
 }  // namespace
 
 namespace qmc {
+
+std::string gen_persistent_name(bool f32) {
+  return f32 ? "qmc_gen_persistent_f32" : "qmc_gen_persistent_f64";
+}
 
 std::string gen_kernel_name(int D, bool f32, int S) {
   char buf[64];
@@ -329,6 +336,106 @@ std::string gen_class_source(const qmc_plan_s *p, int D, bool f32, int S,
       "  qmc::block_store(a, w, red);\n"
       "}\n";
   return src;
+}
+
+// A struct whose integrand switches on the (wave-uniform) sector index among the
+// given sectors' generated integrands: the form a persistent kernel takes, where one
+// program holds every sector (the switch sits inside the point loop around the integrand
+// alone, so the lattice, transform and accumulation code is compiled once per
+// dimension, not once per sector).  Finite, or korobov_3, where every sector is.
+std::string gen_switch_struct(const qmc_plan_s *p, const std::string &name, int D, bool f32,
+                              const std::vector<int> &sectors, const std::vector<bool> &finite,
+                              const std::vector<bool> &korobov3) {
+  bool fin = true, k3 = true;
+  for (size_t i = 0; i < sectors.size(); ++i) {
+    fin = fin && finite[i];
+    k3 = k3 && korobov3[i];
+  }
+  const char *T = f32 ? "float" : "double";
+  char buf[768];
+  std::snprintf(buf, sizeof buf,
+                "struct %s {\n"
+                "  static constexpr bool finite = %s;\n"
+                "  static constexpr bool korobov3 = %s;\n"
+                "  template <int S>\n"
+                "  __device__ static __forceinline__ void %s(const %s (&x)[S][%d], %s (&f)[S][%d],\n"
+                "                                          qmc::cptr<%s> c%s, int s) {\n"
+                "    switch (s) {\n",
+                name.c_str(), fin ? "true" : "false", k3 ? "true" : "false", f32 ? "f32" : "f64",
+                T, D, T, p->K, T, f32 ? "" : ", const qmc::LogTable &lt");
+  std::string src = buf;
+  for (int s : sectors) {
+    std::snprintf(buf, sizeof buf, "      case %d: G%d::template %s<S>(x, f, c%s, s); break;\n", s,
+                  s, f32 ? "f32" : "f64", f32 ? "" : ", lt");
+    src += buf;
+  }
+  std::snprintf(buf, sizeof buf,
+                "      default:   // every work item of the launch is one of the sectors above\n"
+                "#pragma unroll\n"
+                "        for (int u = 0; u < S; ++u)\n"
+                "#pragma unroll\n"
+                "          for (int k = 0; k < %d; ++k) f[u][k] = 0;\n"
+                "    }\n"
+                "  }\n"
+                "};\n",
+                p->K);
+  return src + buf;
+}
+
+// Source of the batched form's persistent kernel specialised to the plan: the generated
+// integrands of the given sectors (every one without a flow), one switch struct per
+// dimension, and the persistent loop of the library (qmc_persist.h) with a work-item
+// runner that dispatches on the sector's dimension.  S shifts per pass (FP64 one, FP32
+// two, as the library's persistent kernels).
+std::string gen_persistent_source(const qmc_plan_s *p, bool f32, int S,
+                                  const std::vector<int> &sectors) {
+  std::string src = kPrelude;
+  src += "#include \"qmc_persist.h\"\n";
+  src += "namespace qmc_gen {\n";
+  int dmax = 1;
+  std::vector<std::vector<int>> by_d(QMC_MAX_DIM + 1);
+  std::vector<std::vector<bool>> fin_d(QMC_MAX_DIM + 1), k3_d(QMC_MAX_DIM + 1);
+  for (int s : sectors) {
+    bool fin = false, k3 = false;
+    src += sector_struct(p, s, f32, &fin, &k3);
+    const int d = p->sec[s].d;
+    by_d[d].push_back(s);
+    fin_d[d].push_back(fin);
+    k3_d[d].push_back(k3);
+    dmax = std::max(dmax, d);
+  }
+  for (int d = 1; d <= QMC_MAX_DIM; ++d)
+    if (!by_d[d].empty())
+      src += gen_switch_struct(p, "C" + std::to_string(d), d, f32, by_d[d], fin_d[d], k3_d[d]);
+  src += "}  // namespace qmc_gen\n\n";
+  char buf[512];
+  src +=
+      "struct RunGen {\n"
+      "  __device__ static __forceinline__ void run(const qmc::LaunchArgs &a, int s, int l_begin, "
+      "int T,\n"
+      "                                             int64_t chunk_id, double (*red)[qmc::kMaxTile * 4][2]) {\n"
+      "    switch (a.sectors[s].d) {\n";
+  for (int d = 1; d <= QMC_MAX_DIM; ++d) {
+    if (by_d[d].empty()) continue;
+    std::snprintf(buf, sizeof buf,
+                  "      case %d: qmc::integrate_block<%d, %d, %d, true, %s, false, qmc_gen::C%d>(a, s, "
+                  "l_begin, T, chunk_id, red); break;\n",
+                  d, d, p->K, S, f32 ? "true" : "false", d);
+    src += buf;
+  }
+  src += "      default: break;\n    }\n  }\n};\n\n";
+  char waves[96];   // the occupancy the library's persistent kernel of the same form asks
+  std::snprintf(waves, sizeof waves, "qmc::persistent_waves<%d, %s, false>()", dmax,
+                f32 ? "true" : "false");
+  std::snprintf(buf, sizeof buf,
+                "extern \"C\" __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu("
+                "%s))) void %s(qmc::LaunchArgs a, qmc::AmpState *st) {\n"
+                "  __shared__ double red[qmc::kMaxWaves][qmc::kMaxTile * 4][2];\n"
+                "  __shared__ int64_t item;\n"
+                "  qmc::persistent_loop<%d, RunGen>(a, st, red, item);\n"
+                "}\n",
+                waves, gen_persistent_name(f32).c_str(), p->K);
+  return src + buf;
 }
 
 // Code objects of sources compiled in this process (plans of the same problem share
@@ -404,11 +511,17 @@ std::vector<int> gen_class_sectors(const qmc_plan_s *p, int D, bool f32) {
   return out;
 }
 
+GenKernel *gen_persistent_lookup(qmc_plan_s *p, bool f32, int K, const std::vector<int> &sectors) {
+  for (GenKernel &g : p->gen)
+    if (g.persistent && g.f32 == (int)f32 && g.K == K && g.sectors == sectors) return &g;
+  return nullptr;
+}
+
 uint64_t gen_lookup(const qmc_plan_s *p, int D, bool f32) {
   if (p->gen.empty()) return 0;
   const int S = gen_spp(p, D, f32);
   for (const GenKernel &g : p->gen)
-    if (g.d == D && g.f32 == (int)f32 && g.spp == S)
+    if (!g.persistent && g.d == D && g.f32 == (int)f32 && g.spp == S)
       // a sector that joined the class later (a flow detached) has no case in the switch
       return g.sectors == gen_class_sectors(p, D, f32) ? (uint64_t)(uintptr_t)g.fn : 0;
   return 0;
@@ -439,7 +552,7 @@ qmc_status qmc_gen_source(qmc_plan_t p, int32_t d, int32_t f32, char *buf, size_
 qmc_status qmc_specialize(qmc_plan_t p, int32_t flags, double *seconds) {
   g_last_error.clear();
   if (!p) return fail(QMC_E_INVAL, "NULL plan");
-  if (flags & ~(QMC_SPEC_COMPILE_ONLY | QMC_SPEC_OFF))
+  if (flags & ~(QMC_SPEC_COMPILE_ONLY | QMC_SPEC_OFF | QMC_SPEC_PERSISTENT))
     return fail(QMC_E_INVAL, "unknown flags 0x%x", flags);
   const auto t0 = std::chrono::steady_clock::now();
   if (flags & QMC_SPEC_OFF) {
@@ -456,10 +569,39 @@ qmc_status qmc_specialize(qmc_plan_t p, int32_t flags, double *seconds) {
     bool ok = false;
   };
   std::vector<Job> jobs;
+  if (flags & QMC_SPEC_PERSISTENT) {
+    // the batched form's persistent kernel over every sector without a flow: real plans
+    // whose sectors have the common shape (as the batched form requires), FP64 or FP32
+    // with an FP32 form for every such sector
+    if (p->cplx) return fail(QMC_E_INVAL, "the batched form takes real plans");
+    const bool f32 = p->precision == QMC_PREC_FP32;
+    std::vector<int> secs;
+    for (int s = 0; s < p->S; ++s) {
+      const SectorDev &sd = p->sec[s];
+      if (sd.flow) continue;
+      if (!(sd.flags & SF_FAST))
+        return fail(QMC_E_INVAL, "sector %d does not have the common shape of the batched form", s);
+      if (f32 && !(sd.flags & SF_F32OK))
+        return fail(QMC_E_INVAL, "sector %d has no FP32 form: the FP32 plan is mixed", s);
+      secs.push_back(s);
+    }
+    if (secs.empty() || gen_persistent_lookup(p, f32, p->K, secs)) {
+      if (seconds) *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      return QMC_OK;
+    }
+    Job j;
+    j.d = 0;
+    j.f32 = f32;
+    j.spp = f32 ? 2 : 1;
+    j.sectors = secs;
+    j.name = gen_persistent_name(f32);
+    j.src = gen_persistent_source(p, f32, j.spp, secs);
+    jobs.push_back(std::move(j));
+  }
   // every class for the shifts per pass of the current launch shape and of the shapes
   // the autotuner prefers (two and four), so that a change of shape keeps the
   // specialised kernels
-  for (int D = 1; D <= QMC_MAX_DIM; ++D)
+  for (int D = 1; D <= QMC_MAX_DIM && !(flags & QMC_SPEC_PERSISTENT); ++D)
     for (int f32 = 0; f32 <= 1; ++f32) {
       const std::vector<int> secs = gen_class_sectors(p, D, f32 != 0);
       if (secs.empty()) continue;
@@ -495,6 +637,8 @@ qmc_status qmc_specialize(qmc_plan_t p, int32_t flags, double *seconds) {
       g.d = j.d;
       g.f32 = j.f32;
       g.spp = j.spp;
+      g.persistent = j.d == 0;
+      g.K = p->K;
       hipModule_t mod;
       hipFunction_t fn;
       int e = hipModuleLoadData(&mod, j.code.data());

@@ -27,12 +27,15 @@ constexpr size_t kP2PartialDoubles = 1 << 19;   // 4 MiB of P2 partial sums
 qmc_status p2_check_args(uint64_t n, int32_t d, const uint64_t *cand, int32_t n_cand);
 int64_t p2_chunks(uint64_t n, int32_t n_cand);
 
-// A plan-specialised class kernel (run-time compiled): launch class (d, f32) with spp
-// shifts per pass, covering exactly the listed sectors.
+// A plan-specialised kernel (run-time compiled): a class kernel of launch class (d, f32)
+// with spp shifts per pass, or (persistent = 1, d = 0) the batched form's persistent
+// kernel for K orders; covering exactly the listed sectors.
 struct GenKernel {
   int32_t d, f32, spp;
+  int32_t persistent, K;
   void *mod, *fn;                 // hipModule_t, hipFunction_t
   std::vector<int> sectors;
+  int32_t grid;                   // persistent: workgroups of the launch (0: not yet known)
 };
 
 }  // namespace qmc
@@ -109,6 +112,9 @@ namespace qmc {
 // current launch shape, if one was compiled for exactly the class's current sectors; 0
 // otherwise (the table-driven kernel runs).
 uint64_t gen_lookup(const qmc_plan_s *p, int d, bool f32);
+// The specialised persistent kernel for FP32 (f32) or FP64 and K orders whose sectors are
+// exactly `sectors`, or nullptr.
+GenKernel *gen_persistent_lookup(qmc_plan_s *p, bool f32, int K, const std::vector<int> &sectors);
 // With static_base set, every device region of the call (tables, lattice records,
 // workgroup partials, status) is laid out in that buffer of static_cap bytes instead of
 // the plan's workspace, and the tables are uploaded on `stream` first.

@@ -261,3 +261,44 @@ def test_logarithm_form_follows_the_sign_of_F(q):
     assert "struct G1 {\n  static constexpr bool finite = false;" in src
     assert "qmc::log_tab(F, lt)" in body[0] and "qmc::log_f64" not in body[0]
     assert "qmc::log_f64(F)" in body[1] and "qmc::log_tab" not in body[1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_compile_only_persistent_kernel(q, precision):
+    # the batched form's specialised persistent kernel: one program, every sector
+    import ctypes
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    prec = q.QMC_PREC_FP32 if precision == "fp32" else q.QMC_PREC_FP64
+    h = q.host_plan(prob, precision=prec)
+    try:
+        sec = ctypes.c_double()
+        rc = q.lib().qmc_specialize(h, q.QMC_SPEC_COMPILE_ONLY | q.QMC_SPEC_PERSISTENT,
+                                    ctypes.byref(sec))
+        assert rc == 0, q.lib().qmc_last_error()
+        assert sec.value > 0.0
+    finally:
+        q.lib().qmc_plan_free(h)
+
+
+def test_persistent_kernel_refuses_other_plans(q):
+    import ctypes
+    flags = q.QMC_SPEC_COMPILE_ONLY | q.QMC_SPEC_PERSISTENT
+    # a complex plan, and a sector outside the batched form's shape (x^(1/2))
+    for prob in (W.physical_scan(seed=0, n_points=1, n_sectors=2, d_lo=3, d_hi=4, n=1009, m=16),
+                 W.one_loop_sector(seed=0, n=4099, m=4)):
+        h = q.host_plan(prob)
+        try:
+            assert q.lib().qmc_specialize(h, flags, None) == -1
+        finally:
+            q.lib().qmc_plan_free(h)
+    # an FP32 plan with a sector that has no FP32 form
+    sec = W.custom_sector(3, [(1.0, (0, 0, 0)), (0.5, (1, 0, 0))],
+                          [(1.0, (0, 0, 0)), (-0.3, (1, 1, 0)), (0.2, (0, 0, 2))], u_pow=1,
+                          f_pow2=-6, logc=[[1, 0, 0], [0, -2, 0], [0, 0, 2]], n=20011, a=5467,
+                          transform="korobov3")
+    h = q.host_plan(W.single_problem(sec, m=4), precision=q.QMC_PREC_FP32)
+    try:
+        assert q.lib().qmc_specialize(h, flags, None) == -1
+        assert "FP32" in q.lib().qmc_last_error().decode()
+    finally:
+        q.lib().qmc_plan_free(h)

@@ -21,8 +21,10 @@ def qmc():
     return q
 
 
-def _compare(qmc, prob, coef, sizes, a_tab, tau, epsrel, n_presample, **kw):
+def _compare(qmc, prob, coef, sizes, a_tab, tau, epsrel, n_presample, persistent=False, **kw):
     plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+    if persistent:   # the batched form's persistent kernel specialised to the plan
+        plan.specialize(persistent=True)
     val, err, nfin, st = plan.amp_evaluate(coef, epsrel=epsrel, lattice_n=sizes, lattice_a=a_tab,
                                            tau=tau, n_presample=n_presample, **kw)
     ov, oe, on, orounds, oconv = oracle.adaptive_amplitude(prob, coef, sizes, a_tab, tau,
@@ -296,3 +298,63 @@ def test_measured_costs_parity(qmc, mode):
     assert np.array_equal(nfin, on)
     scale = np.abs(ov) + np.abs(oe)
     assert np.all(np.abs(val - ov) <= 1e-12 * scale)
+
+
+def test_specialised_persistent_kernel_parity(qmc):
+    # the batched form with its persistent kernel generated for the plan (the integrands
+    # of every sector behind a switch): same rounds, lattices and sums as the oracle's loop
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    coef = np.array([prob.amp_coef, prob.amp_coef * (0.5 - 1j)])
+    _compare(qmc, prob, coef, sizes, a_tab, tau, 2e-6, 1009, persistent=True, mode=1)
+
+
+def test_specialised_persistent_kernel_fp32(qmc):
+    # FP32 batched form, specialised against table-driven on the same ladder and costs:
+    # same rounds and final lattices, sums within the FP32 bar on their scale, and the
+    # specialised form against the FP64 oracle loop within that bar too
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=7, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    out = {}
+    for spec in (False, True):
+        plan = qmc.Plan(prob, n_max=int(sizes[-1]), precision=qmc.QMC_PREC_FP32)
+        if spec:
+            plan.specialize(persistent=True)
+        out[spec] = plan.amp_evaluate(prob.amp_coef, epsrel=5e-4, lattice_n=sizes,
+                                      lattice_a=a_tab, tau=tau, n_presample=1009, mode=1)
+        del plan
+    v0, e0, n0, s0 = out[False]
+    v1, e1, n1, s1 = out[True]
+    assert s1["converged"] == 1 and s1["rounds"] == s0["rounds"]
+    assert np.array_equal(n1, n0)
+    scale = np.abs(v0) + np.abs(e0)
+    print("max deviation specialised vs table-driven", float((np.abs(v1 - v0) / scale).max()),
+          flush=True)
+    assert np.all(np.abs(v1 - v0) <= 1e-5 * scale)
+    ov, oe, on, orounds, _ = oracle.adaptive_amplitude(prob, prob.amp_coef, sizes, a_tab, tau,
+                                                       epsrel=5e-4, n_presample=1009)
+    assert orounds == s1["rounds"] and np.array_equal(on, n1)
+    assert np.all(np.abs(v1 - ov) <= 1e-5 * (np.abs(ov) + np.abs(oe)))
+
+
+def test_specialised_persistent_kernel_follows_the_plan(qmc):
+    # attaching a flow changes the plan's sectors without a flow: the specialised kernel no
+    # longer matches and the batched form runs the library's own (same results as host mode)
+    from oracle import flow as OF
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    tau = np.array([float(s.d) for s in prob.sectors])
+    res = {}
+    for mode in (0, 1):
+        plan = qmc.Plan(prob, n_max=int(sizes[-1]))
+        plan.specialize(persistent=True)
+        d = prob.sectors[0].d
+        plan.attach_flow(0, qmc.flow.Flow(d, params=OF.flatten(OF.init_params(d, seed=3))))
+        res[mode] = plan.amp_evaluate(prob.amp_coef, epsrel=2e-6, lattice_n=sizes,
+                                      lattice_a=a_tab, tau=tau, n_presample=1009, mode=mode)
+        del plan
+    (v0, e0, n0, s0), (v1, e1, n1, s1) = res[0], res[1]
+    assert s0["rounds"] == s1["rounds"] and np.array_equal(n0, n1)
+    assert np.all(np.abs(v1 - v0) <= 1e-12 * (np.abs(v0) + np.abs(e0)))
