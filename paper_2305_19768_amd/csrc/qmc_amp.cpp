@@ -151,22 +151,29 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   }
   AmpState init;
   std::memset(&init, 0, sizeof init);
-  const std::vector<double> zeros(S, 0.0);
   hipStream_t st = (hipStream_t)stream;
-  auto up = [&](void *dst_, const void *src, size_t bytes) {
-    return bytes ? hipMemcpyAsync(dst_, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  // every table goes up in one copy: a host image of the region (the tables at their
+  // device offsets, zeros between and in the arrays the kernels write before they read)
+  std::vector<char> image(o, 0);
+  auto put = [&](void *dst_, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(image.data() + ((char *)dst_ - base), src, bytes);
   };
-  if ((e = up(dst, &init, sizeof init)) || (e = up(d_integral, integral.data(), 4 * S)) ||
-      (e = up(d_dims, p->dims.data(), 4 * S)) || (e = up(d_lidx, lidx.data(), 4 * S)) ||
-      (e = up(d_iptr, iptr.data(), 4 * (NI + 1))) || (e = up(d_isec, isec.data(), 4 * S)) ||
-      (e = up(d_order, order_dev.data(), 4 * S)) ||
-      (e = up(d_tau, tau.data(), 8 * S)) || (e = up(d_tick_sum, zeros.data(), 8 * S)) ||
-      (e = up(d_eval_sum, zeros.data(), 8 * S)) || (e = up(d_c2, c2.data(), 8 * c2.size())) ||
-      (e = up(d_cre, cre.data(), 8 * cre.size())) || (e = up(d_cim, cim.data(), 8 * cim.size())) ||
-      (e = up(d_ln, lad.data(), 8 * lad.size())) ||
-      (e = up(d_trace, opt->tau_used,
-              opt->tau_used ? 8 * (size_t)S * std::min(opt->max_rounds, QMC_AMP_TAU_ROWS) : 0)) ||
-      (e = up(d_la, opt->lattice_a, 8 * lad.size() * QMC_MAX_DIM)))
+  put(dst, &init, sizeof init);
+  put(d_integral, integral.data(), 4 * S);
+  put(d_dims, p->dims.data(), 4 * S);
+  put(d_lidx, lidx.data(), 4 * S);
+  put(d_iptr, iptr.data(), 4 * (NI + 1));
+  put(d_isec, isec.data(), 4 * S);
+  put(d_order, order_dev.data(), 4 * S);
+  put(d_tau, tau.data(), 8 * S);
+  put(d_c2, c2.data(), 8 * c2.size());
+  put(d_cre, cre.data(), 8 * cre.size());
+  put(d_cim, cim.data(), 8 * cim.size());
+  put(d_ln, lad.data(), 8 * lad.size());
+  put(d_trace, opt->tau_used,
+      opt->tau_used ? 8 * (size_t)S * std::min(opt->max_rounds, QMC_AMP_TAU_ROWS) : 0);
+  put(d_la, opt->lattice_a, 8 * lad.size() * QMC_MAX_DIM);
+  if ((e = hipMemcpyAsync(base, image.data(), o, hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "upload amplitude tables");
   AmpArgs g;
   std::memset(&g, 0, sizeof g);
@@ -289,11 +296,9 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
       break;
     }
   }
-  std::vector<double> Are(T * K), Aim(T * K), Vre(T * K), Vim(T * K);
-  if ((e = hipMemcpyAsync(Are.data(), d_Are, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
-      (e = hipMemcpyAsync(Aim.data(), d_Aim, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
-      (e = hipMemcpyAsync(Vre.data(), d_Vre, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
-      (e = hipMemcpyAsync(Vim.data(), d_Vim, 8 * T * K, hipMemcpyDeviceToHost, st)) ||
+  // the four result arrays are consecutive in the region: one copy
+  std::vector<char> res((char *)d_Vim - (char *)d_Are + 8 * T * K);
+  if ((e = hipMemcpyAsync(res.data(), d_Are, res.size(), hipMemcpyDeviceToHost, st)) ||
       (e = hipMemcpyAsync(lidx.data(), d_lidx, 4 * S, hipMemcpyDeviceToHost, st)))
     return hip_fail(e, "read results");
   // the trace rows the rounds could have written (the others still hold the caller's
@@ -304,11 +309,16 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
                           st)) != hipSuccess)
     return hip_fail(e, "read costs");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "read results");
+  auto result = [&](const double *at, int i) {
+    double v;
+    std::memcpy(&v, res.data() + ((const char *)at - (const char *)d_Are) + 8 * (size_t)i, 8);
+    return v;
+  };
   for (int i = 0; i < T * K; ++i) {
-    value[2 * i] = Are[i];
-    value[2 * i + 1] = Aim[i];
-    error[2 * i] = std::sqrt(Vre[i]);
-    error[2 * i + 1] = std::sqrt(Vim[i]);
+    value[2 * i] = result(d_Are, i);
+    value[2 * i + 1] = result(d_Aim, i);
+    error[2 * i] = std::sqrt(result(d_Vre, i));
+    error[2 * i + 1] = std::sqrt(result(d_Vim, i));
   }
   if (n_final)
     for (int s = 0; s < S; ++s) n_final[s] = lad[lidx[s]];
