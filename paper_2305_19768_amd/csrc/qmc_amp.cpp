@@ -283,11 +283,17 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
       if ((e = launch_reduce_stats(la, stream)) != hipSuccess) return hip_fail(e, "reduction");
     }
     if ((e = launch_amp_round(g, stream)) != hipSuccess) return hip_fail(e, "round kernel");
-    if ((e = hipMemcpyAsync(&hs, dst, sizeof hs, hipMemcpyDeviceToHost, st)) != hipSuccess)
+    // the state and the status word in one synchronisation; a non-finite sum is then
+    // reported by qmc_query_status
+    int32_t code = 0;
+    if ((e = hipMemcpyAsync(&hs, dst, sizeof hs, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&code, la.status, sizeof code, hipMemcpyDeviceToHost, st)) != hipSuccess)
       return hip_fail(e, "read state");
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "synchronize");
-    qmc_status r = qmc_query_status(p, stream, nullptr, nullptr, nullptr);
-    if (r != QMC_OK) return r;
+    if (code != INT32_MAX) {
+      qmc_status r = qmc_query_status(p, stream, nullptr, nullptr, nullptr);
+      if (r != QMC_OK) return r;
+    }
     if (hs.done) break;
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
