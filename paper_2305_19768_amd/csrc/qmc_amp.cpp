@@ -153,10 +153,21 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   std::memset(&init, 0, sizeof init);
   hipStream_t st = (hipStream_t)stream;
   // every table goes up in one copy: a host image of the region (the tables at their
-  // device offsets, zeros between and in the arrays the kernels write before they read)
-  std::vector<char> image(o, 0);
+  // device offsets, zeros between and in the arrays the kernels write before they read),
+  // in pinned memory kept by the plan, so that the copy is not staged or pinned per call
+  // (the previous call's copy has finished: every call synchronises before it returns)
+  if (p->amp_host_bytes < o) {
+    if (p->amp_host) (void)hipHostFree(p->amp_host);
+    p->amp_host = nullptr;
+    p->amp_host_bytes = 0;
+    if ((e = hipHostMalloc(&p->amp_host, o, hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "pinned host image of the amplitude tables");
+    p->amp_host_bytes = o;
+  }
+  char *image = (char *)p->amp_host;
+  std::memset(image, 0, o);
   auto put = [&](void *dst_, const void *src, size_t bytes) {
-    if (bytes) std::memcpy(image.data() + ((char *)dst_ - base), src, bytes);
+    if (bytes) std::memcpy(image + ((char *)dst_ - base), src, bytes);
   };
   put(dst, &init, sizeof init);
   put(d_integral, integral.data(), 4 * S);
@@ -173,7 +184,7 @@ qmc_status amp_device(qmc_plan_s *p, int T, int NI, int P, const std::vector<dou
   put(d_trace, opt->tau_used,
       opt->tau_used ? 8 * (size_t)S * std::min(opt->max_rounds, QMC_AMP_TAU_ROWS) : 0);
   put(d_la, opt->lattice_a, 8 * lad.size() * QMC_MAX_DIM);
-  if ((e = hipMemcpyAsync(base, image.data(), o, hipMemcpyHostToDevice, st)) != hipSuccess)
+  if ((e = hipMemcpyAsync(base, image, o, hipMemcpyHostToDevice, st)) != hipSuccess)
     return hip_fail(e, "upload amplitude tables");
   AmpArgs g;
   std::memset(&g, 0, sizeof g);

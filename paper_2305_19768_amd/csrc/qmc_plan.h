@@ -92,7 +92,11 @@ struct qmc_plan_s {
   // library's static device scratch); NULL after any call that used the workspace
   int32_t *static_status = nullptr;
   unsigned long long *static_sign = nullptr;
+  // pinned host image of the batched amplitude form's tables (grown as needed)
+  void *amp_host = nullptr;
+  size_t amp_host_bytes = 0;
   ~qmc_plan_s() {
+    if (amp_host) (void)hipHostFree(amp_host);
     for (qmc::GenKernel &g : gen) (void)hipModuleUnload((hipModule_t)g.mod);
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     for (int i = 0; i < side.n; ++i) {
