@@ -60,6 +60,32 @@ def test_synthetic_amplitude_parity(qmc, mode):
     _compare(qmc, prob, coef, sizes, a_tab, tau, 2e-6, 1009, mode=mode)
 
 
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_device_mode_repeated_calls_are_identical(qmc, fp32):
+    # the batched form builds its tables in a host image kept by the plan: a second call
+    # on the same plan, after a call on another plan with fewer sectors and sums, gives
+    # the same rounds, lattices, sums and errors bit for bit
+    prob = W.amplitude(seed=1, n_integrals=6, n_sectors=24, d_lo=3, d_hi=6, m=8, n0=1009)
+    small = W.amplitude(seed=4, n_integrals=3, n_sectors=9, d_lo=3, d_hi=5, m=8, n0=1009)
+    sizes, a_tab = ladder(seed=2)
+    prec = qmc.QMC_PREC_FP32 if fp32 else qmc.QMC_PREC_FP64
+    coef = np.array([prob.amp_coef, prob.amp_coef * (0.5 - 1j)])
+    tau = np.array([float(s.d) for s in prob.sectors])
+    plan = qmc.Plan(prob, precision=prec, n_max=int(sizes[-1]))
+    other = qmc.Plan(small, precision=prec, n_max=int(sizes[-1]))
+    kw = dict(epsrel=2e-6, lattice_n=sizes, lattice_a=a_tab, n_presample=1009, mode=1)
+    first = plan.amp_evaluate(coef, tau=tau, **kw)
+    o = other.amp_evaluate(np.array([small.amp_coef]),
+                           tau=np.array([float(s.d) for s in small.sectors]), **kw)
+    assert np.all(np.isfinite(o[0]))
+    second = plan.amp_evaluate(coef, tau=tau, **kw)
+    print("rounds", first[3]["rounds"], second[3]["rounds"], flush=True)
+    assert first[3]["rounds"] == second[3]["rounds"]
+    assert first[3]["evaluations"] == second[3]["evaluations"]
+    for a, b in zip(first[:3], second[:3]):
+        assert np.array_equal(a, b)
+
 def _series_coefficients(qmc, exprs, symbols, K):
     """Laurent terms of the coefficient expressions from the library's exact expansion,
     checked bit for bit against the oracle's exact rational functions."""
